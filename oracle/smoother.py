@@ -1,0 +1,110 @@
+"""The multiplicative vertex-patch smoother (Section 2.1, Algorithm 1).
+
+TEST INFRASTRUCTURE (oracle): see oracle/__init__.py.
+
+For every patch j, in a fixed order, with the global u updated after each
+patch (Section 2.1):
+    gather    u-bar_j = Pi-bar_j u, b_j = Pi_j b              (eq. gather)
+    evaluate  r_j = b_j - Pi_j A-bar_j u-bar_j                (eq. main:4)
+    solve     d_j ~ A~_j^{-1} r_j  (p-multigrid V-cycles)     (eq. main:5)
+    scatter   u += Pi_j^T d_j                                 (eq. scatter)
+
+Order: patches sit at the interior vertices v of the mesh.  Vertex v has
+colour sum_i 2^i (v_i mod 2); a forward sweep visits colours 0 .. 2^d-1 and,
+within a colour, vertices in lexicographic order (x fastest); a backward sweep
+visits the reverse order.  Two vertices of one colour differ by at least 2 in
+some coordinate, so the interior of one patch never meets the closure of the
+other; the patches of one colour can therefore be updated in any order with
+the same result.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .fem import Mesh, PatchGeometry, _multi, global_node, patch_closure_matrix
+from .pmg import LocalSolver
+from . import lanczos
+
+
+def vertex_color(v) -> int:
+    return sum(((v[i] % 2) << i) for i in range(len(v)))
+
+
+def interior_vertices(dim: int, n: int):
+    """Interior vertices in x-fastest order."""
+    return [tuple(t + 1 for t in v) for v in _multi(n - 1, dim)]
+
+
+def patch_order(dim: int, n: int):
+    """Forward sweep order: colours ascending, lexicographic within a colour."""
+    verts = interior_vertices(dim, n)
+    return [v for c in range(2 ** dim) for v in verts if vertex_color(v) == c]
+
+
+def patch_indices(v, p: int, n: int, dim: int):
+    """(closure global indices, interior global indices) of the patch around
+    interior vertex v at degree p: node offsets s in [0, 2p]^dim from
+    (v - 1) p, interior s in [1, 2p-1]^dim, both x-fastest."""
+    m = n * p + 1
+    clo, inn = [], []
+    for s in _multi(2 * p + 1, dim):
+        g = global_node([(v[i] - 1) * p + s[i] for i in range(dim)], m, dim)
+        clo.append(g)
+        if all(0 < s[i] < 2 * p for i in range(dim)):
+            inn.append(g)
+    return np.array(clo), np.array(inn)
+
+
+class PatchSmoother:
+    """All patches of one mesh with their local p-multigrid solvers.
+
+    bounds: "lanczos" (computed here with the given seed and step count), or a
+    dict {vertex: [(lam_min, lam_max) per smoothed level]}.
+    keep_closure: keep A-bar_j for the evaluate step (else only the interior
+    rows of the global operator are used, which are the same numbers; see
+    evaluate_rows).
+    """
+
+    def __init__(self, mesh: Mesh, p: int, levels, cheb_degree=3, n_vcycles=1,
+                 bounds="lanczos", lanczos_steps=12, seed=0, global_matrix=None):
+        self.mesh, self.p, self.levels = mesh, p, tuple(levels)
+        self.dim, self.n = mesh.dim, mesh.n
+        self.order = patch_order(self.dim, self.n)
+        self.solvers = {}
+        self.idx = {}
+        self.A = global_matrix
+        for v in self.order:
+            P = mesh.patch(v)
+            s = LocalSolver(P, self.levels, cheb_degree=cheb_degree, n_vcycles=n_vcycles)
+            if bounds == "lanczos":
+                vlin = sum(v[i] * (self.n + 1) ** i for i in range(self.dim))
+                b = [lanczos.bounds(s.A[l], s.dinv[l], lanczos_steps, seed, vlin, l)
+                     for l in range(len(self.levels) - 1)]
+            else:
+                b = bounds[v]
+            s.set_bounds(b)
+            self.solvers[v] = s
+            self.idx[v] = patch_indices(v, p, self.n, self.dim)
+
+    def local_residual(self, v, u, b):
+        """r_j = b_j - Pi_j A-bar_j u-bar_j (evaluate step)."""
+        clo, inn = self.idx[v]
+        if self.A is not None:
+            # rows of the global operator at the patch interior: every interior
+            # basis function is supported inside the patch, so these rows only
+            # see the patch cells and equal the interior rows of A-bar_j.
+            return b[inn] - self.A[inn] @ u
+        Abar = patch_closure_matrix(self.solvers[v].patch, self.p)
+        mask = self.solvers[v].patch.interior_mask(self.p)
+        return b[inn] - (Abar @ u[clo])[mask]
+
+    def sweep(self, u, b, direction=+1, exact=False):
+        """One multiplicative sweep; returns the updated copy of u."""
+        u = np.array(u, dtype=np.float64, copy=True)
+        order = self.order if direction > 0 else list(reversed(self.order))
+        for v in order:
+            r = self.local_residual(v, u, b)
+            s = self.solvers[v]
+            d = s.exact_solve(r) if exact else s.solve(r)
+            u[self.idx[v][1]] += d
+        return u

@@ -1,0 +1,381 @@
+"""Pins of the oracle's local p-multigrid, Chebyshev smoother, Lanczos bounds,
+patch sweep and global multigrid (no GPU)."""
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import synth
+from oracle import fe1d, fem, gmg, lanczos, pmg
+from oracle.smoother import PatchSmoother, patch_order, vertex_color
+
+
+def _patch(dim, alpha=0.2, mu_log10=(-2, 2), seed=0):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    X, mu = synth.make_random_patch(dim, alpha, mu_log10, rng)
+    return fem.PatchGeometry(X, mu)
+
+
+def _affine_patch(dim, seed=0):
+    # an affine image of the Cartesian patch (every cell a parallelogram)
+    rng = np.random.default_rng(seed)
+    B = np.eye(dim) + 0.3 * rng.uniform(-1, 1, (dim, dim))
+    g = np.array(np.meshgrid(*([np.arange(3)] * dim), indexing="ij"))
+    ref = np.stack([g[i].transpose(tuple(reversed(range(dim)))).reshape(-1)
+                    for i in range(dim)], axis=1) * 0.5
+    mu = 10.0 ** rng.uniform(-2, 2, 2 ** dim)
+    return fem.PatchGeometry(ref @ B.T + 0.1, mu)
+
+
+# ---------------------------------------------------------------------------
+# transfers and level operators
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("p,q,r", [(4, 2, 1), (7, 3, 1), (8, 4, 2), (6, 3, 2), (15, 7, 3)])
+def test_prolongation_nested(p, q, r):
+    # V_r < V_q < V_p: embedding r->p equals embedding q->p after r->q
+    A = pmg.prolongation_1d(p, q) @ pmg.prolongation_1d(q, r)
+    assert np.allclose(A, pmg.prolongation_1d(p, r), atol=1e-13)
+    if r >= 2:   # one-cell directions of boundary-cut patches
+        A1 = pmg.prolongation_1d(p, q, 1) @ pmg.prolongation_1d(q, r, 1)
+        assert np.allclose(A1, pmg.prolongation_1d(p, r, 1), atol=1e-13)
+
+
+@pytest.mark.parametrize("p,q", [(3, 2), (4, 2), (7, 3), (5, 1)])
+def test_prolongation_reproduces_piecewise_polynomials(p, q):
+    # the coarse function with nodal values f(x_t) of a cellwise degree-q
+    # polynomial f vanishing at the patch ends is reproduced at the fine nodes
+    xq, xp = fe1d.gll_nodes(q), fe1d.gll_nodes(p)
+    rng = np.random.default_rng(p * 10 + q)
+
+    def fvals(nodes, deg):
+        out = []
+        for s in range(1, 2 * deg):
+            c = min(s // deg, 1)
+            xi = nodes[s - c * deg]
+            out.append(cell_f(c, xi))
+        return np.array(out)
+    # cellwise polynomial of degree q with f(0)=f(2)=0 and continuity at 1:
+    # f_0(xi) = xi * g0(xi), f_1(xi) = (1 - xi) * g1(xi), with g0(1) = g1(0)
+    g0 = np.polynomial.Polynomial(rng.standard_normal(q))
+    g1 = np.polynomial.Polynomial(rng.standard_normal(q))
+    g1 = g1 - g1(0.0) + g0(1.0)
+    X = np.polynomial.Polynomial([0, 1])
+    f0, f1 = X * g0, (1 - X) * g1
+    def cell_f(c, xi):
+        return f0(xi) if c == 0 else f1(xi)
+    coarse = fvals(xq, q)
+    fine = fvals(xp, p)
+    assert np.allclose(pmg.prolongation_1d(p, q) @ coarse, fine, atol=1e-12)
+
+
+@pytest.mark.parametrize("dim,p,q", [(2, 3, 2), (2, 4, 2), (3, 2, 1), (3, 4, 2)])
+def test_galerkin_equals_rediscretisation_affine(dim, p, q):
+    # Section 3.1, level operators: P^T A_{j,p} P = A_{j,q} holds exactly on
+    # affine patches with piecewise constant mu (exact quadrature)
+    P = _affine_patch(dim, seed=p + q)
+    Ap, Aq = fem.patch_matrix(P, p), fem.patch_matrix(P, q)
+    Pr = pmg.prolongation(p, q, P.ncell)
+    assert np.abs(Pr.T @ Ap @ Pr - Aq).max() <= 1e-12 * np.abs(Aq).max()
+
+
+def test_galerkin_differs_on_distorted_patch():
+    # on a genuinely trilinear patch the two differ (quadrature of rational
+    # integrands); the method uses rediscretisation
+    P = _patch(2, alpha=0.3, mu_log10=None, seed=3)
+    Ap, Aq = fem.patch_matrix(P, 4), fem.patch_matrix(P, 2)
+    Pr = pmg.prolongation(4, 2, P.ncell)
+    assert np.abs(Pr.T @ Ap @ Pr - Aq).max() > 1e-8 * np.abs(Aq).max()
+
+
+def test_coarse_level_equals_galerkin_diagonal_affine():
+    # Section 3.1, coarse solver: the p = 1 scalar is the degree-one diagonal
+    # entry, equal to the Galerkin projection of the fine operator
+    P = _affine_patch(3, seed=5)
+    A1 = fem.patch_matrix(P, 1)
+    A3 = fem.patch_matrix(P, 3)
+    Pr = pmg.prolongation(3, 1, P.ncell)
+    assert A1.shape == (1, 1)
+    assert abs((Pr.T @ A3 @ Pr)[0, 0] - A1[0, 0]) <= 1e-12 * A1[0, 0]
+
+
+# ---------------------------------------------------------------------------
+# Chebyshev smoothing
+# ---------------------------------------------------------------------------
+
+def test_chebyshev_error_polynomial():
+    # e_k = tau_k(D^{-1}A) e_0, tau_k(lam) = T_k((theta - lam)/delta) / T_k(theta/delta)
+    A = fem.patch_matrix(_patch(2, seed=4), 3)
+    dinv = 1.0 / np.diag(A)
+    lam, V = sla.eigh(A, np.diag(np.diag(A)))      # A v = lam D v
+    rng = np.random.default_rng(0)
+    xstar = rng.standard_normal(A.shape[0])
+    f = A @ xstar
+    x0 = rng.standard_normal(A.shape[0])
+    a, b = 0.3, 1.1 * lam[-1]
+    theta, delta = (a + b) / 2, (b - a) / 2
+    for k in (1, 2, 3, 5):
+        xk = pmg.chebyshev(A, dinv, f, x0, a, b, k)
+        c0 = np.linalg.solve(V, xstar - x0)
+        ck = np.linalg.solve(V, xstar - xk)
+        Tk = np.polynomial.chebyshev.Chebyshev.basis(k)
+        tau = Tk((theta - lam) / delta) / Tk(theta / delta)
+        assert np.allclose(ck, tau * c0, atol=1e-9 * np.abs(c0).max())
+
+
+def test_chebyshev_degree_one_is_damped_jacobi():
+    # k = 1 on an interval with a + b = 4 is the paper's Jacobi step with
+    # omega = 1/2 (Section 3.1, smoothers; Section 3.2)
+    A = fem.patch_matrix(_patch(3, seed=2), 2)
+    dinv = 1.0 / np.diag(A)
+    rng = np.random.default_rng(1)
+    f, x0 = rng.standard_normal(A.shape[0]), rng.standard_normal(A.shape[0])
+    x1 = pmg.chebyshev(A, dinv, f, x0, 0.5, 3.5, 1)
+    assert np.allclose(x1, x0 + 0.5 * dinv * (f - A @ x0), atol=1e-14)
+
+
+def test_chebyshev_zero_start_skips_apply():
+    A = fem.patch_matrix(_patch(2, seed=8), 3)
+    dinv = 1.0 / np.diag(A)
+    f = np.random.default_rng(2).standard_normal(A.shape[0])
+    x_a = pmg.chebyshev(A, dinv, f, np.zeros_like(f), 0.2, 2.0, 3, x_is_zero=True)
+    x_b = pmg.chebyshev(A, dinv, f, np.zeros_like(f), 0.2, 2.0, 3)
+    assert np.allclose(x_a, x_b, atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# Lanczos bounds
+# ---------------------------------------------------------------------------
+
+def test_splitmix64_published_outputs():
+    # reference outputs of SplitMix64 seeded with 0 and with 1234567
+    assert [lanczos.splitmix64(0, i) for i in range(3)] == [
+        0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    assert [lanczos.splitmix64(1234567, i) for i in range(3)] == [
+        6457827717110365317, 3203168211198807973, 9817491932198370423]
+
+
+def test_start_vector_range_and_independence():
+    v = lanczos.start_vector(5, 100, 0, 4096)
+    assert v.min() >= -1.0 and v.max() < 1.0 and abs(v.mean()) < 0.05
+    w = lanczos.start_vector(5, 100, 1, 4096)
+    assert abs(np.corrcoef(v, w)[0, 1]) < 0.1
+
+
+@pytest.mark.parametrize("dim,q,m", [(2, 3, 12), (2, 4, 20), (3, 2, 12), (3, 2, 30)])
+def test_lanczos_inside_spectrum(dim, q, m):
+    A = fem.patch_matrix(_patch(dim, seed=q + m), q)
+    dinv = 1.0 / np.diag(A)
+    lo, hi = lanczos.bounds(A, dinv, m, seed=9, vertex=3, level=0)
+    ev = np.linalg.eigvals(dinv[:, None] * A).real
+    assert ev.min() - 1e-12 <= lo <= hi <= ev.max() + 1e-12
+    # Gershgorin bound of D^{-1} A
+    assert hi <= np.max(np.abs(A).sum(axis=1) * dinv) + 1e-12
+    # the largest Ritz value converges fast
+    assert hi >= 0.97 * ev.max()
+
+
+def test_lanczos_exact_when_steps_reach_dimension():
+    A = fem.patch_matrix(_patch(2, seed=1), 2)   # 9 x 9
+    dinv = 1.0 / np.diag(A)
+    lo, hi = lanczos.bounds(A, dinv, 9, seed=1, vertex=0, level=0)
+    ev = np.sort(np.linalg.eigvals(dinv[:, None] * A).real)
+    assert abs(lo - ev[0]) < 1e-10 and abs(hi - ev[-1]) < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# V-cycle
+# ---------------------------------------------------------------------------
+
+def _solver(dim, levels, seed=0, k=3, nmg=1):
+    P = _patch(dim, seed=seed)
+    s = pmg.LocalSolver(P, levels, cheb_degree=k, n_vcycles=nmg)
+    s.set_bounds([lanczos.bounds(s.A[l], s.dinv[l], 12, 1, seed, l) for l in range(len(levels) - 1)])
+    return s
+
+
+@pytest.mark.parametrize("dim,levels", [(2, (3, 2, 1)), (3, (4, 2, 1)), (3, (3, 1))])
+def test_vcycle_linear_and_symmetric(dim, levels):
+    s = _solver(dim, levels, seed=sum(levels))
+    n = s.A[0].shape[0]
+    rng = np.random.default_rng(3)
+    r1, r2 = rng.standard_normal(n), rng.standard_normal(n)
+    d1, d2 = s.solve(r1), s.solve(r2)
+    assert np.allclose(s.solve(2.0 * r1 - 3.0 * r2), 2.0 * d1 - 3.0 * d2, atol=1e-12 * np.abs(d1).max())
+    assert abs(r2 @ d1 - r1 @ d2) <= 1e-12 * abs(r1 @ d1)
+
+
+def test_two_level_error_operator():
+    # levels {p, 1}: the V-cycle error operator is S (I - P A_1^{-1} P^T A) S
+    # with S the Chebyshev error polynomial in D^{-1} A (Algorithm 2)
+    s = _solver(2, (3, 1), seed=4)
+    A, dinv = s.A[0], s.dinv[0]
+    n = A.shape[0]
+    a, b = s.intervals[0]
+    S = np.zeros((n, n))
+    for j in range(n):        # error propagation of one Chebyshev pass
+        e0 = np.eye(n)[j]
+        S[:, j] = e0 - pmg.chebyshev(A, dinv, A @ e0, np.zeros(n), a, b, 3, x_is_zero=True)
+    P = s.P[0]
+    C = np.eye(n) - P @ np.linalg.solve(s.A[1], P.T @ A)   # rediscretised coarse operator
+    E = S @ C @ S
+    Minv = np.column_stack([s.solve(A @ np.eye(n)[j]) for j in range(n)])
+    assert np.allclose(np.eye(n) - Minv, E, atol=1e-11)
+
+
+def test_many_vcycles_converge_to_lu():
+    s = _solver(3, (4, 2, 1), seed=2, nmg=40)
+    r = np.random.default_rng(5).standard_normal(s.A[0].shape[0])
+    d = s.solve(r)
+    x = s.exact_solve(r)
+    assert np.linalg.norm(d - x) <= 1e-8 * np.linalg.norm(x)
+
+
+def test_paper_single_patch_pcg_counts():
+    # Section 3.2: CG with one V-cycle (Jacobi, omega = 1/2, levels 1,3,7,15)
+    # as preconditioner on an undeformed Cartesian 2D patch needs about 10
+    # iterations at p = 3 and about 23 at p = 15 (to 1e-8).  omega = 1/2 is a
+    # degree-1 Chebyshev step on any interval with a + b = 4.
+    path = os.path.join(os.path.dirname(__file__), "golden", "single_patch_pcg.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    for d, p, iters in rows:
+        d, p, iters = int(d), int(p), int(iters)
+        levels = tuple(q for q in (15, 7, 3) if q < p) + (1,)
+        levels = (p,) + tuple(q for q in levels if q < p)
+        g = np.array(np.meshgrid(*([np.arange(3)] * d), indexing="ij"))
+        X = np.stack([g[i].transpose(tuple(reversed(range(d)))).reshape(-1) for i in range(d)], 1) * 0.5
+        s = pmg.LocalSolver(fem.PatchGeometry(X, np.ones(2 ** d)), levels, cheb_degree=1)
+        s.bounds = None
+        s.intervals = [(0.5, 3.5)] * (len(levels) - 1)
+        A = s.A[0]
+        b = np.random.default_rng(p).standard_normal(A.shape[0])
+        x = np.zeros_like(b)
+        r = b.copy()
+        z = s.solve(r)
+        dd = z.copy()
+        rz = r @ z
+        for k in range(1, 101):
+            Ad = A @ dd
+            al = rz / (dd @ Ad)
+            x += al * dd
+            r -= al * Ad
+            if np.linalg.norm(r) <= 1e-8 * np.linalg.norm(b):
+                break
+            z = s.solve(r)
+            rz, rz_old = r @ z, rz
+            dd = z + (rz / rz_old) * dd
+        assert 0.7 * iters <= k <= 1.3 * iters, (p, k)
+
+
+# ---------------------------------------------------------------------------
+# sweep
+# ---------------------------------------------------------------------------
+
+def test_colour_classes_disjoint():
+    from oracle.smoother import patch_indices
+    dim, n, p = 3, 5, 2
+    order = patch_order(dim, n)
+    for c in range(8):
+        vs = [v for v in order if vertex_color(v) == c]
+        for i, v in enumerate(vs):
+            clo_v, inn_v = patch_indices(v, p, n, dim)
+            for w in vs[i + 1:]:
+                clo_w, inn_w = patch_indices(w, p, n, dim)
+                assert not set(inn_v) & set(clo_w)
+                assert not set(inn_w) & set(clo_v)
+
+
+def test_sweep_order_within_colour_irrelevant():
+    w = synth.workload(1)
+    X, mu, _ = synth.make_case(w, n=4)
+    b = synth.make_rhs(3, 4, 2, 7)
+    mesh = fem.Mesh(3, 4, X, mu)
+    S = PatchSmoother(mesh, 2, (2, 1))
+    u0 = np.random.default_rng(0).standard_normal(b.shape) * fem.dirichlet_mask(3, 4, 2)
+    u1 = S.sweep(u0, b)
+    # permute patches inside each colour
+    S.order = [v for c in range(8) for v in reversed([x for x in S.order if vertex_color(x) == c])]
+    u2 = S.sweep(u0, b)
+    assert np.allclose(u1, u2, atol=1e-13 * np.abs(u1).max())
+
+
+def test_sweep_global_rows_equal_patch_closure():
+    w = synth.workload(1)
+    X, mu, _ = synth.make_case(w, n=3)
+    b = synth.make_rhs(3, 3, 2, 8)
+    mesh = fem.Mesh(3, 3, X, mu)
+    A = fem.dirichlet_operator(mesh, 2)
+    S1 = PatchSmoother(mesh, 2, (2, 1), global_matrix=A)
+    S2 = PatchSmoother(mesh, 2, (2, 1))
+    u0 = np.random.default_rng(1).standard_normal(b.shape) * fem.dirichlet_mask(3, 3, 2)
+    assert np.allclose(S1.sweep(u0, b), S2.sweep(u0, b), atol=1e-12)
+
+
+def test_one_patch_mesh_exact_solve():
+    # N = 2: one patch covers every interior node, so an exact local solve
+    # gives the discrete solution in one sweep
+    w = synth.workload(1)
+    X, mu, _ = synth.make_case(w, n=2)
+    b = synth.make_rhs(3, 2, 3, 9)
+    mesh = fem.Mesh(3, 2, X, mu)
+    A = fem.dirichlet_operator(mesh, 3)
+    S = PatchSmoother(mesh, 3, (3, 1))
+    u = S.sweep(np.zeros_like(b), b, exact=True)
+    m = fem.dirichlet_mask(3, 2, 3)
+    assert np.linalg.norm((b - A @ u)[m]) <= 1e-12 * np.linalg.norm(b)
+
+
+# ---------------------------------------------------------------------------
+# global multigrid and CG
+# ---------------------------------------------------------------------------
+
+def test_hierarchy_sizes():
+    assert gmg.hierarchy_sizes(8) == [2, 4, 8]
+    assert gmg.hierarchy_sizes(16) == [2, 4, 8, 16]
+    assert gmg.hierarchy_sizes(24) == [3, 6, 12, 24]
+    assert gmg.hierarchy_sizes(32) == [2, 4, 8, 16, 32]
+
+
+@pytest.mark.parametrize("dim,p", [(2, 3), (3, 2)])
+def test_h_prolongation_galerkin_cartesian(dim, p):
+    # on Cartesian meshes with constant mu the embedding is exact, so
+    # P^T A_fine P = A_coarse (Section 2, transfers)
+    nc = 2
+    def mesh_of(n):
+        g = np.array(np.meshgrid(*([np.arange(n + 1)] * dim), indexing="ij"))
+        X = np.stack([g[i].transpose(tuple(reversed(range(dim)))).reshape(-1)
+                      for i in range(dim)], axis=1) / n
+        return fem.Mesh(dim, n, X, np.ones(n ** dim))
+    Af = fem.dirichlet_operator(mesh_of(2 * nc), p)
+    Ac = fem.dirichlet_operator(mesh_of(nc), p)
+    P = gmg.prolongation_h(dim, nc, p)
+    assert abs(P.T @ Af @ P - Ac).max() <= 1e-12 * abs(Ac).max()
+
+
+def test_h_prolongation_reproduces_polynomials():
+    p, nc = 3, 3
+    P1 = gmg.prolongation_h_1d(nc, p)
+    x = fe1d.gll_nodes(p)
+    xc = np.concatenate([[(c + t) / nc for t in x[:-1]] for c in range(nc)] + [[1.0]])
+    xf = np.concatenate([[(c + t) / (2 * nc) for t in x[:-1]] for c in range(2 * nc)] + [[1.0]])
+    f = np.polynomial.Polynomial([0.3, -1.0, 2.0, 0.7])
+    assert np.allclose(P1 @ f(xc), f(xf), atol=1e-13)
+
+
+def test_gmg_cg_2d_converges_to_direct_solution():
+    w = synth.workload(0)
+    X, mu, b = synth.make_case(w)
+    mesh = fem.Mesh(w.dim, w.n, X, mu)
+    G = gmg.GMG(mesh, w.p, w.levels)
+    x, it, hist = G.cg(b, rtol=w.rtol)
+    m = fem.dirichlet_mask(w.dim, w.n, w.p)
+    A = G.A[-1].toarray()[np.ix_(m, m)]
+    xs = np.linalg.solve(A, b[m])
+    assert it <= 10
+    assert np.linalg.norm(x[m] - xs) <= 1e-8 * np.linalg.norm(xs)
+    # the preconditioner is symmetric (reversed sweep order after the coarse
+    # correction), which CG relies on
+    rng = np.random.default_rng(0)
+    r1, r2 = rng.standard_normal(b.shape) * m, rng.standard_normal(b.shape) * m
+    assert abs(r2 @ G.precondition(r1) - r1 @ G.precondition(r2)) <= 1e-11 * abs(r1 @ G.precondition(r1))
