@@ -1,0 +1,193 @@
+/*
+ * pmg.h -- C ABI of the MI355X (gfx950) vertex-patch smoother with nested
+ * matrix-free p-multigrid local solvers, and of the geometric-multigrid CG
+ * built on it.
+ *
+ * Method (arXiv 2510.17785):
+ *   problem      a(u,v) = int mu grad u . grad v on a structured quad/hex mesh,
+ *                continuous Q_p elements, homogeneous Dirichlet conditions
+ *                (Section 2, bilinear form and discrete problem)
+ *   smoother     multiplicative vertex-patch smoother: gather, evaluate the
+ *                local residual, solve locally, scatter-add (Section 2.1,
+ *                Algorithm 1; equations gather, main:4, main:5, scatter)
+ *   local solver p-multigrid V-cycle on the patch (Section 3.1, Algorithm 2):
+ *                embedding/transpose transfers, rediscretised level operators,
+ *                exact coarse solve at the lowest degree, Chebyshev-accelerated
+ *                Jacobi smoothing (damped Jacobi is its degree-1 case)
+ *   outer solver geometric multigrid V-cycle with one patch sweep per side
+ *                (Section 2, Section 4), used as CG preconditioner
+ *
+ * Conventions shared by every entry point:
+ *   - Global vectors are FP64, length (N p + 1)^dim, lexicographic with x
+ *     fastest, and hold 0 on Dirichlet nodes.  Vertices are
+ *     ((N+1)^dim x dim) FP64, x fastest; coefficients one FP64 per cell.
+ *   - "host" pointers are read during the call and never kept; "device"
+ *     pointers are device memory owned by the caller (for instance the
+ *     data_ptr() of a torch tensor) and are not kept after the call returns.
+ *   - Work is enqueued on opts.stream (a hipStream_t; NULL = the null stream)
+ *     and runs asynchronously unless stated otherwise.
+ *   - Every function returns a status: PMG_OK (0), a negative error code, or
+ *     PMG_WARN_NOT_CONVERGED (+1).  Nothing throws across the ABI.
+ *     pmg_last_error() returns the message of the last non-zero status of the
+ *     calling thread.
+ *   - Patches are numbered in sweep order: colours ascending, and within a
+ *     colour vertices in lexicographic order (x fastest).  The colour of
+ *     interior vertex v is sum_i 2^i (v_i mod 2).
+ */
+#ifndef PMG_H
+#define PMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define PMG_OK 0
+#define PMG_ERR_INVALID_ARG (-1)  /* null pointer, bad size, bad level list */
+#define PMG_ERR_UNSUPPORTED (-2)  /* valid request this build has no kernel for */
+#define PMG_ERR_DEGENERATE (-3)   /* a cell with det J <= 0 at a quadrature point */
+#define PMG_ERR_HIP (-4)          /* a HIP runtime call failed */
+#define PMG_ERR_OOM (-5)          /* device allocation failed */
+#define PMG_ERR_BREAKDOWN (-6)    /* CG breakdown: p^T A p <= 0 or NaN */
+#define PMG_WARN_NOT_CONVERGED 1  /* CG hit maxit; outputs are valid */
+
+/* precision of the local p-multigrid (global vectors stay FP64) */
+#define PMG_FP64 0
+#define PMG_FP32 1
+
+/* source of the Chebyshev eigenvalue bounds */
+#define PMG_BOUNDS_LANCZOS 0  /* per-patch Lanczos at setup */
+#define PMG_BOUNDS_FIXED 1    /* caller sets them with pmg_set_bounds */
+
+/* pmg_query keys */
+#define PMG_Q_N_PATCHES 0
+#define PMG_Q_N_COLORS 1
+#define PMG_Q_N_LEVELS 2
+#define PMG_Q_N_DOFS 3           /* (N p + 1)^dim */
+#define PMG_Q_N_INTERIOR_DOFS 4  /* (N p - 1)^dim */
+#define PMG_Q_DEVICE_BYTES 5
+#define PMG_Q_COLOR_OFFSET 16    /* + c: first patch of colour c, c <= n_colors */
+#define PMG_Q_LEVEL_DEGREE 32    /* + l: degree of local level l */
+#define PMG_Q_LEVEL_SIZE 48      /* + l: interior nodes per patch at level l */
+
+typedef struct pmg_handle pmg_handle; /* opaque; owns the device memory it allocates */
+typedef struct gmg_handle gmg_handle;
+
+/* Structured mesh of [0,1]^dim with n_cells cells per direction. */
+typedef struct pmg_mesh {
+  int32_t dim;            /* 2 or 3 */
+  int32_t n_cells;        /* N >= 2 */
+  const double* vertices; /* host, ((N+1)^dim x dim), x fastest */
+} pmg_mesh;
+
+typedef struct pmg_opts {
+  int32_t precision;     /* PMG_FP64 or PMG_FP32 */
+  int32_t n_levels;      /* number of local p-levels, 2..4 */
+  int32_t levels[8];     /* degrees, strictly descending, levels[0] = p, last = 1 */
+  int32_t cheb_degree;   /* Chebyshev steps per smoothing pass, 1..8 (default 3) */
+  int32_t n_vcycles;     /* local V-cycles per patch solve, N_MG >= 1 (default 1) */
+  int32_t bounds;        /* PMG_BOUNDS_LANCZOS or PMG_BOUNDS_FIXED */
+  int32_t lanczos_steps; /* Lanczos steps, 2..64 (default 12) */
+  double cheb_safety;    /* s: b = s lambda_max (default 1.1) */
+  double cheb_range;     /* rho: a = max(lambda_min, b / rho) (default 15) */
+  uint64_t seed;         /* seed of the Lanczos start vectors (default 0) */
+  void* stream;          /* hipStream_t, NULL = null stream */
+} pmg_opts;
+
+/* Fill *o with the defaults listed above (levels: p, floor halvings, 1 is
+ * not known without p, so n_levels = 0 means "p, p/2, ..., 1" at setup). */
+int pmg_default_opts(pmg_opts* o);
+
+/* Build the smoother for all interior vertex patches of a mesh at degree p
+ * (Section 2.1).  Uploads geometry and coefficients, computes the inverse
+ * diagonals of every level operator and, for PMG_BOUNDS_LANCZOS, the
+ * Chebyshev bounds.  mesh, coeff: host.  Synchronises opts->stream.
+ * Errors: INVALID_ARG (null, dim, N < 2, p outside 1..15, levels), DEGENERATE,
+ * UNSUPPORTED (a level list without a compiled kernel), OOM, HIP. */
+int pmg_patch_setup(const pmg_mesh* mesh, const double* coeff, int32_t p,
+                    const pmg_opts* opts, pmg_handle** out);
+
+/* One multiplicative sweep (Algorithm 1) over all patches: u += corrections.
+ * direction +1 visits colours ascending, -1 descending.  u: device in/out,
+ * b: device right-hand side (load vector), both FP64 global vectors; they
+ * must not overlap.  Asynchronous on the handle's stream. */
+int pmg_patch_smooth(pmg_handle* h, double* u, const double* b, int32_t direction);
+
+/* Same as pmg_patch_smooth restricted to colours [c_begin, c_end). */
+int pmg_patch_smooth_colors(pmg_handle* h, double* u, const double* b, int32_t c_begin,
+                            int32_t c_end);
+
+/* Evaluate step for all patches (equation main:4):
+ * r[j] = Pi_j b - Pi_j A-bar_j Pi-bar_j u, in the local precision.
+ * u, b: device global vectors; r: device, n_patches x (2p-1)^dim FP64, the
+ * patch interior in x-fastest order. */
+int pmg_patch_residual(pmg_handle* h, const double* u, const double* b, double* r);
+
+/* Batched level operators A_{j,q} (Section 3.1, level operators):
+ * y[j] = A_{j,q} x[j] for every patch, q = degree of level `level`.
+ * x, y: device, n_patches x (2q-1)^dim FP64, interior x-fastest. */
+int pmg_patch_apply(pmg_handle* h, int32_t level, const double* x, double* y);
+
+/* Batched local solves (equation main:5): d[j] = N_MG V-cycles (Algorithm 2)
+ * from zero on A_{j,p} d = r[j].  r, d: device, n_patches x (2p-1)^dim. */
+int pmg_patch_local_solve(pmg_handle* h, const double* r, double* d);
+
+/* Inverse diagonal of A_{j,q} at level `level`: out device, n_patches x (2q-1)^dim. */
+int pmg_get_inv_diag(const pmg_handle* h, int32_t level, double* out);
+
+/* Eigenvalue estimates of D^{-1} A_{j,q}: lam host, n_patches x (n_levels-1) x 2
+ * (lambda_min, lambda_max) per smoothed level.  Synchronises the stream. */
+int pmg_get_bounds(const pmg_handle* h, double* lam);
+
+/* Replace the bounds (same layout as pmg_get_bounds, host) and recompute the
+ * Chebyshev intervals.  Requires 0 < lambda_min <= lambda_max. */
+int pmg_set_bounds(pmg_handle* h, const double* lam);
+
+/* Linear vertex index sum_i v_i (N+1)^i of every patch, in patch order.
+ * out: host, n_patches int32. */
+int pmg_get_patch_vertices(const pmg_handle* h, int32_t* out);
+
+/* Sizes and counters; see the PMG_Q_* keys. */
+int pmg_query(const pmg_handle* h, int32_t what, int64_t* value);
+
+int pmg_patch_destroy(pmg_handle* h);
+
+/* Geometric multigrid over meshes with N, N/2, ... cells (halving while N
+ * stays even and the halved mesh has an interior vertex), degree p on every
+ * level.  Coarse vertices are the shared fine vertices; a coarse cell's
+ * coefficient is the mean of its children.  Smoothers on every level but the
+ * coarsest use opts; the coarsest level is solved exactly (dense Cholesky,
+ * FP64).  mesh, coeff: host.  Synchronises opts->stream. */
+int gmg_setup(const pmg_mesh* mesh, const double* coeff, int32_t p, const pmg_opts* opts,
+              gmg_handle** out);
+
+/* y = A x on the finest level (Dirichlet rows/columns removed).  Device FP64. */
+int gmg_apply(gmg_handle* g, const double* x, double* y);
+
+/* z = V-cycle(r) (Section 2 and Section 4: forward sweep, residual,
+ * restriction, recursion, prolongation, backward sweep).  Device FP64. */
+int gmg_vcycle(gmg_handle* g, const double* r, double* z);
+
+/* Preconditioned CG from x = 0 until ||r|| <= rtol ||b|| or maxit iterations.
+ * x, b: device FP64.  iters, relres: host (may be NULL).  Synchronous.
+ * Returns PMG_WARN_NOT_CONVERGED when maxit is hit, PMG_ERR_BREAKDOWN on
+ * breakdown. */
+int gmg_cg_solve(gmg_handle* g, double* x, const double* b, double rtol, int32_t maxit,
+                 int32_t* iters, double* relres);
+
+/* Number of mesh levels, or the smoother handle of level l (1 = coarsest
+ * smoothed level, n_levels-1 = finest); the handle stays owned by g. */
+int gmg_query(const gmg_handle* g, int32_t what, int64_t* value);
+int gmg_level_smoother(gmg_handle* g, int32_t level, pmg_handle** h);
+
+int gmg_destroy(gmg_handle* g);
+
+const char* pmg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PMG_H */

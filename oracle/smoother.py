@@ -60,18 +60,25 @@ class PatchSmoother:
 
     bounds: "lanczos" (computed here with the given seed and step count), or a
     dict {vertex: [(lam_min, lam_max) per smoothed level]}.
-    keep_closure: keep A-bar_j for the evaluate step (else only the interior
-    rows of the global operator are used, which are the same numbers; see
-    evaluate_rows).
+    global_matrix: if given, the evaluate step uses its rows at the patch
+    interior (the same numbers as the interior rows of A-bar_j); else A-bar_j
+    is assembled per patch, or taken from the cache when keep_closure is set.
+    vertices: restrict the smoother to these patches (sweep order kept), for
+    timing a sample of a large mesh.
     """
 
     def __init__(self, mesh: Mesh, p: int, levels, cheb_degree=3, n_vcycles=1,
-                 bounds="lanczos", lanczos_steps=12, seed=0, global_matrix=None):
+                 bounds="lanczos", lanczos_steps=12, seed=0, global_matrix=None,
+                 keep_closure=False, vertices=None):
         self.mesh, self.p, self.levels = mesh, p, tuple(levels)
         self.dim, self.n = mesh.dim, mesh.n
         self.order = patch_order(self.dim, self.n)
+        if vertices is not None:
+            keep = set(tuple(v) for v in vertices)
+            self.order = [v for v in self.order if v in keep]
         self.solvers = {}
         self.idx = {}
+        self.closure = {}
         self.A = global_matrix
         for v in self.order:
             P = mesh.patch(v)
@@ -85,6 +92,9 @@ class PatchSmoother:
             s.set_bounds(b)
             self.solvers[v] = s
             self.idx[v] = patch_indices(v, p, self.n, self.dim)
+            if keep_closure and global_matrix is None:
+                mask = P.interior_mask(p)
+                self.closure[v] = patch_closure_matrix(P, p)[mask]
 
     def local_residual(self, v, u, b):
         """r_j = b_j - Pi_j A-bar_j u-bar_j (evaluate step)."""
@@ -94,6 +104,8 @@ class PatchSmoother:
             # basis function is supported inside the patch, so these rows only
             # see the patch cells and equal the interior rows of A-bar_j.
             return b[inn] - self.A[inn] @ u
+        if v in self.closure:
+            return b[inn] - self.closure[v] @ u[clo]
         Abar = patch_closure_matrix(self.solvers[v].patch, self.p)
         mask = self.solvers[v].patch.interior_mask(self.p)
         return b[inn] - (Abar @ u[clo])[mask]

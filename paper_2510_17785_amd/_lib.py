@@ -1,0 +1,116 @@
+"""ctypes declarations of libpmg.so (include/pmg.h).  Argument marshalling
+only: every computation runs in the library's HIP kernels."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpmg.so")
+
+PMG_OK = 0
+PMG_ERR_INVALID_ARG = -1
+PMG_ERR_UNSUPPORTED = -2
+PMG_ERR_DEGENERATE = -3
+PMG_ERR_HIP = -4
+PMG_ERR_OOM = -5
+PMG_ERR_BREAKDOWN = -6
+PMG_WARN_NOT_CONVERGED = 1
+
+PMG_FP64 = 0
+PMG_FP32 = 1
+PMG_BOUNDS_LANCZOS = 0
+PMG_BOUNDS_FIXED = 1
+
+PMG_Q_N_PATCHES = 0
+PMG_Q_N_COLORS = 1
+PMG_Q_N_LEVELS = 2
+PMG_Q_N_DOFS = 3
+PMG_Q_N_INTERIOR_DOFS = 4
+PMG_Q_DEVICE_BYTES = 5
+PMG_Q_COLOR_OFFSET = 16
+PMG_Q_LEVEL_DEGREE = 32
+PMG_Q_LEVEL_SIZE = 48
+
+EXPORTS = [
+    "pmg_default_opts", "pmg_patch_setup", "pmg_patch_smooth", "pmg_patch_smooth_colors",
+    "pmg_patch_residual", "pmg_patch_apply", "pmg_patch_local_solve", "pmg_get_inv_diag",
+    "pmg_get_bounds", "pmg_set_bounds", "pmg_get_patch_vertices", "pmg_query",
+    "pmg_patch_destroy", "gmg_setup", "gmg_apply", "gmg_vcycle", "gmg_cg_solve", "gmg_query",
+    "gmg_level_smoother", "gmg_destroy", "pmg_last_error",
+]
+
+
+class PmgMesh(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n_cells", ctypes.c_int32),
+                ("vertices", ctypes.POINTER(ctypes.c_double))]
+
+
+class PmgOpts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("n_levels", ctypes.c_int32),
+                ("levels", ctypes.c_int32 * 8), ("cheb_degree", ctypes.c_int32),
+                ("n_vcycles", ctypes.c_int32), ("bounds", ctypes.c_int32),
+                ("lanczos_steps", ctypes.c_int32), ("cheb_safety", ctypes.c_double),
+                ("cheb_range", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("stream", ctypes.c_void_p)]
+
+
+class PmgError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"libpmg status {status}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libpmg.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2510_17785_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    D = ctypes.POINTER(ctypes.c_double)
+    i32 = ctypes.c_int32
+    sig = {
+        "pmg_default_opts": [ctypes.POINTER(PmgOpts)],
+        "pmg_patch_setup": [ctypes.POINTER(PmgMesh), D, i32, ctypes.POINTER(PmgOpts),
+                            ctypes.POINTER(P)],
+        "pmg_patch_smooth": [P, P, P, i32],
+        "pmg_patch_smooth_colors": [P, P, P, i32, i32],
+        "pmg_patch_residual": [P, P, P, P],
+        "pmg_patch_apply": [P, i32, P, P],
+        "pmg_patch_local_solve": [P, P, P],
+        "pmg_get_inv_diag": [P, i32, P],
+        "pmg_get_bounds": [P, D],
+        "pmg_set_bounds": [P, D],
+        "pmg_get_patch_vertices": [P, ctypes.POINTER(ctypes.c_int32)],
+        "pmg_query": [P, i32, ctypes.POINTER(ctypes.c_int64)],
+        "pmg_patch_destroy": [P],
+        "gmg_setup": [ctypes.POINTER(PmgMesh), D, i32, ctypes.POINTER(PmgOpts), ctypes.POINTER(P)],
+        "gmg_apply": [P, P, P],
+        "gmg_vcycle": [P, P, P],
+        "gmg_cg_solve": [P, P, P, ctypes.c_double, i32, ctypes.POINTER(i32),
+                         ctypes.POINTER(ctypes.c_double)],
+        "gmg_query": [P, i32, ctypes.POINTER(ctypes.c_int64)],
+        "gmg_level_smoother": [P, i32, ctypes.POINTER(P)],
+        "gmg_destroy": [P],
+        "pmg_last_error": [],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_char_p if name == "pmg_last_error" else ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def check(status: int) -> int:
+    if status < 0:
+        msg = load().pmg_last_error().decode(errors="replace")
+        raise PmgError(status, msg)
+    return status

@@ -1,0 +1,228 @@
+"""Thin Python interface to libpmg.so with the entry points of include/pmg.h.
+
+Torch is used only to hold device memory and to name the stream; every
+computation runs in the library's HIP kernels.  There is no CPU fallback:
+constructing any object without the built library, or without a GPU, raises.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _dptr(t: torch.Tensor) -> int:
+    if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError("expected a contiguous float64 device tensor")
+    return t.data_ptr()
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream or None
+
+
+def _opts(levels, precision, cheb_degree, n_vcycles, bounds, lanczos_steps, cheb_safety,
+          cheb_range, seed, stream) -> L.PmgOpts:
+    lib = L.load()
+    o = L.PmgOpts()
+    L.check(lib.pmg_default_opts(ctypes.byref(o)))
+    o.precision = {"fp64": L.PMG_FP64, "fp32": L.PMG_FP32}[precision]
+    lv = list(levels) if levels is not None else []
+    o.n_levels = len(lv)
+    for i, q in enumerate(lv):
+        o.levels[i] = int(q)
+    o.cheb_degree = int(cheb_degree)
+    o.n_vcycles = int(n_vcycles)
+    o.bounds = {"lanczos": L.PMG_BOUNDS_LANCZOS, "fixed": L.PMG_BOUNDS_FIXED}[bounds]
+    o.lanczos_steps = int(lanczos_steps)
+    o.cheb_safety = float(cheb_safety)
+    o.cheb_range = float(cheb_range)
+    o.seed = int(seed)
+    o.stream = _stream_handle(stream)
+    return o
+
+
+def _mesh(dim, n, vertices):
+    v = np.ascontiguousarray(vertices, dtype=np.float64)
+    if v.shape != ((n + 1) ** dim, dim):
+        raise ValueError(f"vertices must have shape {((n + 1) ** dim, dim)}, got {v.shape}")
+    m = L.PmgMesh(dim, n, v.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return m, v
+
+
+class PatchSmoother:
+    """pmg_patch_setup / pmg_patch_smooth and the batched local entry points."""
+
+    def __init__(self, dim: int, n: int, p: int, vertices, coeff, levels: Sequence[int] = None,
+                 precision: str = "fp64", cheb_degree: int = 3, n_vcycles: int = 1,
+                 bounds: str = "lanczos", lanczos_steps: int = 12, cheb_safety: float = 1.1,
+                 cheb_range: float = 15.0, seed: int = 0, stream=None, _handle=None, _owner=None):
+        self._lib = L.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("PatchSmoother needs a GPU")
+        self._owner = _owner
+        if _handle is not None:
+            self._h = _handle
+        else:
+            m, keep = _mesh(dim, n, vertices)
+            mu = np.ascontiguousarray(coeff, dtype=np.float64)
+            if mu.shape != (n ** dim,):
+                raise ValueError("one coefficient per cell expected")
+            o = _opts(levels, precision, cheb_degree, n_vcycles, bounds, lanczos_steps, cheb_safety,
+                      cheb_range, seed, stream)
+            h = ctypes.c_void_p()
+            L.check(self._lib.pmg_patch_setup(ctypes.byref(m), mu.ctypes.data_as(
+                ctypes.POINTER(ctypes.c_double)), int(p), ctypes.byref(o), ctypes.byref(h)))
+            self._h = h
+            del keep
+        q = self.query
+        self.dim = dim
+        self.n_patches = q(L.PMG_Q_N_PATCHES)
+        self.n_colors = q(L.PMG_Q_N_COLORS)
+        self.n_levels = q(L.PMG_Q_N_LEVELS)
+        self.levels = [q(L.PMG_Q_LEVEL_DEGREE + l) for l in range(self.n_levels)]
+        self.level_sizes = [q(L.PMG_Q_LEVEL_SIZE + l) for l in range(self.n_levels)]
+        self.color_offsets = [q(L.PMG_Q_COLOR_OFFSET + c) for c in range(self.n_colors + 1)]
+        self.n_dofs = q(L.PMG_Q_N_DOFS)
+        self.n_interior_dofs = q(L.PMG_Q_N_INTERIOR_DOFS)
+
+    def query(self, what: int) -> int:
+        v = ctypes.c_int64()
+        L.check(self._lib.pmg_query(self._h, int(what), ctypes.byref(v)))
+        return v.value
+
+    @property
+    def device_bytes(self) -> int:
+        return self.query(L.PMG_Q_DEVICE_BYTES)
+
+    def patch_vertices(self) -> np.ndarray:
+        out = np.zeros(self.n_patches, dtype=np.int32)
+        L.check(self._lib.pmg_get_patch_vertices(self._h, out.ctypes.data_as(
+            ctypes.POINTER(ctypes.c_int32))))
+        return out
+
+    def smooth(self, u: torch.Tensor, b: torch.Tensor, direction: int = 1):
+        L.check(self._lib.pmg_patch_smooth(self._h, _dptr(u), _dptr(b), int(direction)))
+
+    def smooth_colors(self, u, b, c_begin, c_end):
+        L.check(self._lib.pmg_patch_smooth_colors(self._h, _dptr(u), _dptr(b), int(c_begin),
+                                                  int(c_end)))
+
+    def residual(self, u: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
+        r = torch.empty((self.n_patches, self.level_sizes[0]), dtype=torch.float64, device=u.device)
+        L.check(self._lib.pmg_patch_residual(self._h, _dptr(u), _dptr(b), _dptr(r)))
+        return r
+
+    def apply(self, level: int, x: torch.Tensor) -> torch.Tensor:
+        y = torch.empty_like(x)
+        if tuple(x.shape) != (self.n_patches, self.level_sizes[level]):
+            raise ValueError("x must have shape (n_patches, level size)")
+        L.check(self._lib.pmg_patch_apply(self._h, int(level), _dptr(x), _dptr(y)))
+        return y
+
+    def local_solve(self, r: torch.Tensor) -> torch.Tensor:
+        if tuple(r.shape) != (self.n_patches, self.level_sizes[0]):
+            raise ValueError("r must have shape (n_patches, top level size)")
+        d = torch.empty_like(r)
+        L.check(self._lib.pmg_patch_local_solve(self._h, _dptr(r), _dptr(d)))
+        return d
+
+    def inv_diag(self, level: int) -> torch.Tensor:
+        out = torch.empty((self.n_patches, self.level_sizes[level]), dtype=torch.float64,
+                          device="cuda")
+        L.check(self._lib.pmg_get_inv_diag(self._h, int(level), _dptr(out)))
+        return out
+
+    def bounds(self) -> np.ndarray:
+        out = np.zeros((self.n_patches, self.n_levels - 1, 2))
+        L.check(self._lib.pmg_get_bounds(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def set_bounds(self, lam) -> None:
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        if lam.shape != (self.n_patches, self.n_levels - 1, 2):
+            raise ValueError("bounds must have shape (n_patches, n_levels - 1, 2)")
+        L.check(self._lib.pmg_set_bounds(self._h, lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._owner is None:
+            L.check(self._lib.pmg_patch_destroy(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class GMGSolver:
+    """gmg_setup / gmg_cg_solve: geometric multigrid with patch smoothers as the
+    CG preconditioner."""
+
+    def __init__(self, dim: int, n: int, p: int, vertices, coeff, levels: Sequence[int] = None,
+                 precision: str = "fp64", cheb_degree: int = 3, n_vcycles: int = 1,
+                 bounds: str = "lanczos", lanczos_steps: int = 12, cheb_safety: float = 1.1,
+                 cheb_range: float = 15.0, seed: int = 0, stream=None):
+        self._lib = L.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("GMGSolver needs a GPU")
+        m, keep = _mesh(dim, n, vertices)
+        mu = np.ascontiguousarray(coeff, dtype=np.float64)
+        o = _opts(levels, precision, cheb_degree, n_vcycles, bounds, lanczos_steps, cheb_safety,
+                  cheb_range, seed, stream)
+        h = ctypes.c_void_p()
+        L.check(self._lib.gmg_setup(ctypes.byref(m), mu.ctypes.data_as(
+            ctypes.POINTER(ctypes.c_double)), int(p), ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        del keep
+        v = ctypes.c_int64()
+        L.check(self._lib.gmg_query(self._h, 0, ctypes.byref(v)))
+        self.n_mesh_levels = v.value
+        self.sizes = []
+        for l in range(self.n_mesh_levels):
+            L.check(self._lib.gmg_query(self._h, 16 + l, ctypes.byref(v)))
+            self.sizes.append(v.value)
+        self.dim, self.p = dim, p
+
+    def smoother(self, level: int) -> PatchSmoother:
+        h = ctypes.c_void_p()
+        L.check(self._lib.gmg_level_smoother(self._h, int(level), ctypes.byref(h)))
+        return PatchSmoother(self.dim, self.sizes[level], self.p, None, None, _handle=h, _owner=self)
+
+    def apply(self, x: torch.Tensor) -> torch.Tensor:
+        y = torch.empty_like(x)
+        L.check(self._lib.gmg_apply(self._h, _dptr(x), _dptr(y)))
+        return y
+
+    def vcycle(self, r: torch.Tensor) -> torch.Tensor:
+        z = torch.empty_like(r)
+        L.check(self._lib.gmg_vcycle(self._h, _dptr(r), _dptr(z)))
+        return z
+
+    def cg(self, b: torch.Tensor, rtol: float = 1e-8, maxit: int = 100):
+        """Returns (x, iterations, relative residual); iterations = maxit + 1
+        when CG did not converge."""
+        x = torch.empty_like(b)
+        it = ctypes.c_int32()
+        rel = ctypes.c_double()
+        L.check(self._lib.gmg_cg_solve(self._h, _dptr(x), _dptr(b), float(rtol), int(maxit),
+                                       ctypes.byref(it), ctypes.byref(rel)))
+        return x, it.value, rel.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            L.check(self._lib.gmg_destroy(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,1014 @@
+// C ABI of the patch smoother and the GMG-CG solver: validation, handle
+// lifetime, setup orchestration and the host loops of the outer solver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fe_tables.hpp"
+#include "internal.hpp"
+
+using namespace pmgi;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(e_ == hipErrorOutOfMemory ? PMG_ERR_OOM : PMG_ERR_HIP, "%s: %s (%s:%d)", \
+                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                   \
+  } while (0)
+
+#define PMG_TRY(expr)         \
+  do {                        \
+    int s_ = (expr);          \
+    if (s_ < 0) return s_;    \
+  } while (0)
+
+int ipow(int b, int e) {
+  int r = 1;
+  for (int i = 0; i < e; ++i) r *= b;
+  return r;
+}
+
+template <typename P>
+int dev_alloc(P** ptr, size_t bytes, size_t* counter) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess)
+    return fail(e == hipErrorOutOfMemory ? PMG_ERR_OOM : PMG_ERR_HIP, "hipMalloc(%zu): %s", bytes,
+                hipGetErrorString(e));
+  *ptr = reinterpret_cast<P*>(p);
+  if (counter) *counter += bytes;
+  return PMG_OK;
+}
+
+// det J > 0 at the corners and Gauss points of every cell (the paper excludes
+// degenerate patches, Section 3.2)
+int check_mesh(int dim, int N, const double* X, int p) {
+  std::vector<double> xg, wg;
+  gauss_rule(p + 1, xg, wg);
+  std::vector<double> pts = {0.0, 1.0};
+  pts.insert(pts.end(), xg.begin(), xg.end());
+  const int N1 = N + 1;
+  const int ncell = ipow(N, dim);
+  for (int e = 0; e < ncell; ++e) {
+    const int ex = e % N, ey = (e / N) % N, ez = dim == 3 ? e / (N * N) : 0;
+    double C[8][3];
+    for (int c = 0; c < (1 << dim); ++c) {
+      int g = (ex + (c & 1)) + (ey + ((c >> 1) & 1)) * N1;
+      if (dim == 3) g += (ez + ((c >> 2) & 1)) * N1 * N1;
+      for (int r = 0; r < dim; ++r) C[c][r] = X[g * dim + r];
+    }
+    const int np = (int)pts.size();
+    for (int kz = 0; kz < (dim == 3 ? np : 1); ++kz)
+      for (int ky = 0; ky < np; ++ky)
+        for (int kx = 0; kx < np; ++kx) {
+          double xi[3] = {pts[kx], pts[ky], dim == 3 ? pts[kz] : 0.0};
+          double J[3][3] = {{0}};
+          for (int c = 0; c < (1 << dim); ++c)
+            for (int s = 0; s < dim; ++s) {
+              double d = 1.0;
+              for (int i = 0; i < dim; ++i) {
+                const int b = (c >> i) & 1;
+                d *= (i == s) ? (b ? 1.0 : -1.0) : (b ? xi[i] : 1.0 - xi[i]);
+              }
+              for (int r = 0; r < dim; ++r) J[r][s] += C[c][r] * d;
+            }
+          double det = dim == 2 ? J[0][0] * J[1][1] - J[0][1] * J[1][0]
+                                : J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                                      J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                                      J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+          if (!(det > 0.0))
+            return fail(PMG_ERR_DEGENERATE, "cell %d (%d,%d,%d) has det J = %g at a quadrature point",
+                        e, ex, ey, ez, det);
+        }
+  }
+  return PMG_OK;
+}
+
+}  // namespace
+
+struct pmg_handle {
+  int dim = 0, N = 0, p = 0, precision = 0, L = 0;
+  int levels[kMaxLevels] = {0};
+  int cheb_degree = 3, n_vcycles = 1, bounds_kind = PMG_BOUNDS_LANCZOS, lanczos_steps = 12;
+  double safety = 1.1, range = 15.0;
+  uint64_t seed = 0;
+  hipStream_t stream = nullptr;
+  const PatchVariant* var = nullptr;
+  int n_patches = 0, n_colors = 0;
+  std::vector<int> color_off;
+  int max_color = 0;
+  size_t device_bytes = 0;
+  bool bounds_valid = false;
+  // device memory
+  double* verts = nullptr;
+  double* mu = nullptr;
+  int32_t* patch_vertex = nullptr;
+  double* tab64 = nullptr;
+  void* tab = nullptr;
+  double* invdiag64[kMaxLevels] = {nullptr};
+  void* invdiag[kMaxLevels] = {nullptr};
+  void* cheb = nullptr;
+  void* vec_scratch = nullptr;
+  int64_t vec_bytes = 0;  // bytes per block slot of vec_scratch
+  int64_t vec_blocks = 0;
+  std::vector<double> bounds;  // host copy, n_patches x (L-1) x 2
+  int level_size(int l) const { return ipow(2 * levels[l] - 1, dim); }
+  size_t tsize() const { return precision == PMG_FP64 ? sizeof(double) : sizeof(float); }
+  PatchArgs args() const {
+    PatchArgs a{};
+    a.verts = verts;
+    a.mu = mu;
+    a.patch_vertex = patch_vertex;
+    a.N = N;
+    a.p = p;
+    a.tab = tab;
+    a.tab64 = tab64;
+    for (int l = 0; l < kMaxLevels; ++l) {
+      a.invdiag[l] = invdiag[l];
+      a.invdiag64[l] = invdiag64[l];
+    }
+    a.cheb = cheb;
+    a.cheb_degree = cheb_degree;
+    a.n_vcycles = n_vcycles;
+    a.vec_scratch = vec_scratch;
+    a.vec_stride = vec_bytes / (int64_t)tsize();
+    a.lanczos_steps = lanczos_steps;
+    a.seed = seed;
+    return a;
+  }
+};
+
+namespace {
+
+void free_handle(pmg_handle* h) {
+  if (!h) return;
+  void* ptrs[] = {h->verts, h->mu, h->patch_vertex, h->tab64, h->cheb, h->vec_scratch};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (h->tab && h->tab != h->tab64) (void)hipFree(h->tab);  // FP64 handles share the tables
+  for (int l = 0; l < kMaxLevels; ++l) {
+    if (h->invdiag64[l]) (void)hipFree(h->invdiag64[l]);
+    if (h->invdiag[l] && h->invdiag[l] != h->invdiag64[l]) (void)hipFree(h->invdiag[l]);
+  }
+  delete h;
+}
+
+// launch a per-patch kernel over patches [begin, end) in chunks that fit the
+// vector scratch
+int launch_chunks(pmg_handle* h, int mode, PatchArgs a, int begin, int end) {
+  const int chunk = h->vec_blocks > 0 ? (int)h->vec_blocks : (end - begin);
+  for (int s = begin; s < end; s += std::max(chunk, 1)) {
+    a.patch_begin = s;
+    a.n_patch = std::min(chunk, end - s);
+    HIP_TRY(h->var->launch(mode, a, h->stream));
+  }
+  return PMG_OK;
+}
+
+int set_cheb(pmg_handle* h) {
+  const int nl = h->L - 1;
+  std::vector<double> c64((size_t)h->n_patches * nl * 2);
+  for (int j = 0; j < h->n_patches; ++j)
+    for (int l = 0; l < nl; ++l) {
+      const double lo = h->bounds[((size_t)j * nl + l) * 2], hi = h->bounds[((size_t)j * nl + l) * 2 + 1];
+      if (!(lo > 0.0) || !(hi >= lo) || !std::isfinite(hi))
+        return fail(PMG_ERR_INVALID_ARG, "patch %d level %d: bad bounds (%g, %g)", j, l, lo, hi);
+      // interval [a, b]: b = s lambda_max, a = max(lambda_min, b / rho)
+      const double b = h->safety * hi;
+      const double a = std::max(lo, b / h->range);
+      c64[((size_t)j * nl + l) * 2] = 0.5 * (b + a);
+      c64[((size_t)j * nl + l) * 2 + 1] = 0.5 * (b - a);
+    }
+  if (h->precision == PMG_FP64) {
+    HIP_TRY(hipMemcpyAsync(h->cheb, c64.data(), c64.size() * sizeof(double), hipMemcpyHostToDevice,
+                           h->stream));
+  } else {
+    std::vector<float> c32(c64.begin(), c64.end());
+    HIP_TRY(hipMemcpyAsync(h->cheb, c32.data(), c32.size() * sizeof(float), hipMemcpyHostToDevice,
+                           h->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  h->bounds_valid = true;
+  return PMG_OK;
+}
+
+int patch_setup_impl(const pmg_mesh* mesh, const double* coeff, int p, const pmg_opts* o,
+                     pmg_handle** out) {
+  if (!mesh || !coeff || !o || !out || !mesh->vertices)
+    return fail(PMG_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  const int dim = mesh->dim, N = mesh->n_cells;
+  if (dim != 2 && dim != 3) return fail(PMG_ERR_INVALID_ARG, "dim must be 2 or 3, got %d", dim);
+  if (N < 2) return fail(PMG_ERR_INVALID_ARG, "need at least 2 cells per direction, got %d", N);
+  if (p < 1 || p > kMaxDegree) return fail(PMG_ERR_INVALID_ARG, "degree %d outside 1..15", p);
+  if (o->precision != PMG_FP64 && o->precision != PMG_FP32)
+    return fail(PMG_ERR_INVALID_ARG, "unknown precision %d", o->precision);
+  if (o->cheb_degree < 1 || o->cheb_degree > 8)
+    return fail(PMG_ERR_INVALID_ARG, "Chebyshev degree %d outside 1..8", o->cheb_degree);
+  if (o->n_vcycles < 1) return fail(PMG_ERR_INVALID_ARG, "n_vcycles must be >= 1");
+  if (o->bounds != PMG_BOUNDS_LANCZOS && o->bounds != PMG_BOUNDS_FIXED)
+    return fail(PMG_ERR_INVALID_ARG, "unknown bounds source %d", o->bounds);
+  if (o->lanczos_steps < 2 || o->lanczos_steps > 64)
+    return fail(PMG_ERR_INVALID_ARG, "lanczos_steps %d outside 2..64", o->lanczos_steps);
+  if (!(o->cheb_safety >= 1.0) || !(o->cheb_range > 1.0))
+    return fail(PMG_ERR_INVALID_ARG, "cheb_safety must be >= 1 and cheb_range > 1");
+  int levels[kMaxLevels] = {0};
+  int L = o->n_levels;
+  if (L == 0) {
+    int q = p;
+    while (true) {
+      if (L >= kMaxLevels) return fail(PMG_ERR_UNSUPPORTED, "default halving needs > %d levels", kMaxLevels);
+      levels[L++] = q;
+      if (q == 1) break;
+      q = q / 2;
+    }
+  } else {
+    if (L < 2 || L > kMaxLevels) return fail(PMG_ERR_INVALID_ARG, "n_levels %d outside 2..%d", L, kMaxLevels);
+    for (int l = 0; l < L; ++l) levels[l] = o->levels[l];
+  }
+  if (levels[0] != p) return fail(PMG_ERR_INVALID_ARG, "levels[0] = %d must equal p = %d", levels[0], p);
+  if (levels[L - 1] != 1) return fail(PMG_ERR_INVALID_ARG, "last level must be degree 1");
+  for (int l = 1; l < L; ++l)
+    if (levels[l] >= levels[l - 1]) return fail(PMG_ERR_INVALID_ARG, "levels must strictly decrease");
+  const PatchVariant* var = find_variant(o->precision, dim, L, levels);
+  if (!var)
+    return fail(PMG_ERR_UNSUPPORTED, "no kernel compiled for this level list (available: %s)",
+                list_variants().c_str());
+  PMG_TRY(check_mesh(dim, N, mesh->vertices, p));
+
+  pmg_handle* h = new pmg_handle();
+  h->dim = dim;
+  h->N = N;
+  h->p = p;
+  h->precision = o->precision;
+  h->L = L;
+  for (int l = 0; l < L; ++l) h->levels[l] = levels[l];
+  h->cheb_degree = o->cheb_degree;
+  h->n_vcycles = o->n_vcycles;
+  h->bounds_kind = o->bounds;
+  h->lanczos_steps = o->lanczos_steps;
+  h->safety = o->cheb_safety;
+  h->range = o->cheb_range;
+  h->seed = o->seed;
+  h->stream = reinterpret_cast<hipStream_t>(o->stream);
+  h->var = var;
+  auto cleanup = [&](int s) {
+    free_handle(h);
+    return s;
+  };
+
+  // patches in sweep order: colour sum_i 2^i (v_i mod 2), lexicographic within
+  const int N1 = N + 1;
+  std::vector<int32_t> order;
+  h->n_colors = 1 << dim;
+  h->color_off.assign(h->n_colors + 1, 0);
+  for (int col = 0; col < h->n_colors; ++col) {
+    h->color_off[col] = (int)order.size();
+    for (int vz = (dim == 3 ? 1 : 0); vz < (dim == 3 ? N : 1); ++vz)
+      for (int vy = 1; vy < N; ++vy)
+        for (int vx = 1; vx < N; ++vx) {
+          int c = (vx & 1) | ((vy & 1) << 1) | (dim == 3 ? ((vz & 1) << 2) : 0);
+          if (c != col) continue;
+          order.push_back(vx + vy * N1 + (dim == 3 ? vz * N1 * N1 : 0));
+        }
+    h->max_color = std::max(h->max_color, (int)order.size() - h->color_off[col]);
+  }
+  h->color_off[h->n_colors] = (int)order.size();
+  h->n_patches = (int)order.size();
+
+  const size_t nv = (size_t)ipow(N1, dim), nc = (size_t)ipow(N, dim);
+  int s;
+  if ((s = dev_alloc(&h->verts, nv * dim * sizeof(double), &h->device_bytes)) < 0) return cleanup(s);
+  if ((s = dev_alloc(&h->mu, nc * sizeof(double), &h->device_bytes)) < 0) return cleanup(s);
+  if ((s = dev_alloc(&h->patch_vertex, order.size() * sizeof(int32_t), &h->device_bytes)) < 0)
+    return cleanup(s);
+  hipError_t e;
+  if ((e = hipMemcpy(h->verts, mesh->vertices, nv * dim * sizeof(double), hipMemcpyHostToDevice)) ||
+      (e = hipMemcpy(h->mu, coeff, nc * sizeof(double), hipMemcpyHostToDevice)) ||
+      (e = hipMemcpy(h->patch_vertex, order.data(), order.size() * sizeof(int32_t),
+                     hipMemcpyHostToDevice)))
+    return cleanup(fail(PMG_ERR_HIP, "upload: %s", hipGetErrorString(e)));
+  for (size_t i = 0; i < nc; ++i)
+    if (!(coeff[i] > 0.0) || !std::isfinite(coeff[i]))
+      return cleanup(fail(PMG_ERR_INVALID_ARG, "coefficient of cell %zu is %g", i, coeff[i]));
+
+  // 1D tables: per level B, Dc, D, xg, wg; per transfer the patch prolongation
+  std::vector<double> tab(kTabSize, 0.0);
+  for (int l = 0; l < L; ++l) {
+    DegreeTables t = degree_tables(levels[l]);
+    const int n = t.n;
+    double* dst = tab.data() + l * kTabLevelStride;
+    std::copy(t.B.begin(), t.B.end(), dst);
+    std::copy(t.Dc.begin(), t.Dc.end(), dst + n * n);
+    std::copy(t.D.begin(), t.D.end(), dst + 2 * n * n);
+    std::copy(t.xg.begin(), t.xg.end(), dst + 3 * n * n);
+    std::copy(t.wg.begin(), t.wg.end(), dst + 3 * n * n + n);
+  }
+  for (int l = 0; l + 1 < L; ++l) {
+    std::vector<double> P = patch_prolongation_1d(levels[l], levels[l + 1], 2);
+    std::copy(P.begin(), P.end(), tab.data() + kMaxLevels * kTabLevelStride + l * kTabTransferStride);
+  }
+  if ((s = dev_alloc(&h->tab64, tab.size() * sizeof(double), &h->device_bytes)) < 0) return cleanup(s);
+  if ((e = hipMemcpy(h->tab64, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice)))
+    return cleanup(fail(PMG_ERR_HIP, "upload: %s", hipGetErrorString(e)));
+  if (h->precision == PMG_FP64) {
+    h->tab = h->tab64;
+  } else {
+    std::vector<float> t32(tab.begin(), tab.end());
+    if ((s = dev_alloc(&h->tab, t32.size() * sizeof(float), &h->device_bytes)) < 0) return cleanup(s);
+    if ((e = hipMemcpy(h->tab, t32.data(), t32.size() * sizeof(float), hipMemcpyHostToDevice)))
+      return cleanup(fail(PMG_ERR_HIP, "upload: %s", hipGetErrorString(e)));
+  }
+
+  // vector scratch when the level vectors do not fit in LDS (sized for the
+  // larger of the working-precision and FP64 layouts)
+  {
+    const int64_t e1 = var->vec_scratch_elems() * (int64_t)h->tsize();
+    const int64_t e2 = var->vec_scratch_elems64() * (int64_t)sizeof(double);
+    const int64_t bytes_per_block = std::max(e1, e2);
+    if (bytes_per_block > 0) {
+      h->vec_blocks = h->max_color;
+      h->vec_bytes = bytes_per_block;
+      if ((s = dev_alloc(&h->vec_scratch, (size_t)bytes_per_block * h->vec_blocks, &h->device_bytes)) < 0)
+        return cleanup(s);
+    }
+  }
+
+  // inverse diagonals of every level (FP64), then the working-precision copy
+  for (int l = 0; l < L; ++l) {
+    const size_t cnt = (size_t)h->n_patches * h->level_size(l);
+    if ((s = dev_alloc(&h->invdiag64[l], cnt * sizeof(double), &h->device_bytes)) < 0) return cleanup(s);
+    if (h->precision == PMG_FP64) {
+      h->invdiag[l] = h->invdiag64[l];
+    } else if ((s = dev_alloc(&h->invdiag[l], cnt * sizeof(float), &h->device_bytes)) < 0) {
+      return cleanup(s);
+    }
+  }
+  {
+    PatchArgs a = h->args();
+    a.vec_stride = h->vec_bytes / (int64_t)sizeof(double);  // FP64 setup kernels
+    const int chunk = h->vec_blocks > 0 ? (int)h->vec_blocks : h->n_patches;
+    for (int b = 0; b < h->n_patches; b += chunk) {
+      a.patch_begin = b;
+      a.n_patch = std::min(chunk, h->n_patches - b);
+      if ((e = var->launch_diag(a, h->stream)))
+        return cleanup(fail(PMG_ERR_HIP, "diagonal kernel (%d patches, LDS %zu bytes of FP64 layout): %s",
+                            a.n_patch, var->lds_bytes(-1), hipGetErrorString(e)));
+    }
+    if (h->precision == PMG_FP32)
+      for (int l = 0; l < L; ++l)
+        if ((e = launch_convert_to_float((int64_t)h->n_patches * h->level_size(l), h->invdiag64[l],
+                                         reinterpret_cast<float*>(h->invdiag[l]), h->stream)))
+          return cleanup(fail(PMG_ERR_HIP, "convert: %s", hipGetErrorString(e)));
+  }
+  const size_t ncheb = (size_t)h->n_patches * (L - 1) * 2;
+  if ((s = dev_alloc(&h->cheb, ncheb * h->tsize(), &h->device_bytes)) < 0) return cleanup(s);
+  h->bounds.assign(ncheb, 0.0);
+
+  if (h->bounds_kind == PMG_BOUNDS_LANCZOS) {
+    double* dbounds = nullptr;
+    double* basis = nullptr;
+    const int chunk = std::min(h->n_patches, 4096);
+    const size_t basis_elems = (size_t)chunk * h->lanczos_steps * h->level_size(0);
+    if ((s = dev_alloc(&dbounds, ncheb * sizeof(double), nullptr)) < 0) return cleanup(s);
+    if ((s = dev_alloc(&basis, basis_elems * sizeof(double), nullptr)) < 0) {
+      (void)hipFree(dbounds);
+      return cleanup(s);
+    }
+    PatchArgs a = h->args();
+    a.vec_stride = h->vec_bytes / (int64_t)sizeof(double);  // FP64 setup kernels
+    a.lanczos_basis = basis;
+    a.bounds_out = dbounds;
+    int st = PMG_OK;
+    for (int l = 0; l + 1 < L && st == PMG_OK; ++l) {
+      for (int b = 0; b < h->n_patches; b += chunk) {
+        // the vector scratch (if any) has vec_blocks slots
+        const int c2 = h->vec_blocks > 0 ? std::min<int>(chunk, (int)h->vec_blocks) : chunk;
+        for (int b2 = b; b2 < std::min(b + chunk, h->n_patches); b2 += c2) {
+          a.patch_begin = b2;
+          a.n_patch = std::min(c2, std::min(b + chunk, h->n_patches) - b2);
+          if ((e = var->launch_lanczos(a, l, h->stream))) {
+            st = fail(PMG_ERR_HIP, "lanczos kernel: %s", hipGetErrorString(e));
+            break;
+          }
+        }
+      }
+    }
+    if (st == PMG_OK) {
+      if ((e = hipMemcpyAsync(h->bounds.data(), dbounds, ncheb * sizeof(double), hipMemcpyDeviceToHost,
+                              h->stream)) ||
+          (e = hipStreamSynchronize(h->stream)))
+        st = fail(PMG_ERR_HIP, "bounds: %s", hipGetErrorString(e));
+    }
+    (void)hipFree(dbounds);
+    (void)hipFree(basis);
+    if (st != PMG_OK) return cleanup(st);
+    if ((s = set_cheb(h)) < 0) return cleanup(s);
+  } else {
+    if ((e = hipStreamSynchronize(h->stream)))
+      return cleanup(fail(PMG_ERR_HIP, "setup: %s", hipGetErrorString(e)));
+  }
+  *out = h;
+  return PMG_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// GMG
+// ---------------------------------------------------------------------------
+
+struct gmg_handle {
+  int dim = 0, p = 0, nlev = 0;
+  hipStream_t stream = nullptr;
+  std::vector<int> sizes;             // cells per direction, coarsest first
+  std::vector<pmg_handle*> smoother;  // [0] unused
+  std::vector<double*> verts, mu;     // per level
+  std::vector<double*> f, u, t, cellbuf;
+  std::vector<int*> hfirst;           // per transfer (coarse level l -> l+1)
+  std::vector<double*> hw;
+  double* tab64 = nullptr;
+  double* tbuf[2] = {nullptr, nullptr};  // transfer intermediates (finest size)
+  double* coarse_inv = nullptr;
+  double* cpack[2] = {nullptr, nullptr};
+  int coarse_n = 0;
+  double *x = nullptr, *r = nullptr, *z = nullptr, *d = nullptr, *Ad = nullptr;
+  double* partial = nullptr;
+  double* scal = nullptr;  // device scalars
+  double* hscal = nullptr; // pinned host scalars
+  int64_t len(int l) const {
+    int64_t M = (int64_t)sizes[l] * p + 1;
+    return dim == 3 ? M * M * M : M * M;
+  }
+  int M(int l) const { return sizes[l] * p + 1; }
+};
+
+namespace {
+
+void free_gmg(gmg_handle* g) {
+  if (!g) return;
+  for (pmg_handle* h : g->smoother)
+    if (h) free_handle(h);
+  auto fr = [](void* p) {
+    if (p) (void)hipFree(p);
+  };
+  for (auto* p : g->verts) fr(p);
+  for (auto* p : g->mu) fr(p);
+  for (auto* p : g->f) fr(p);
+  for (auto* p : g->u) fr(p);
+  for (auto* p : g->t) fr(p);
+  for (auto* p : g->cellbuf) fr(p);
+  for (auto* p : g->hfirst) fr(p);
+  for (auto* p : g->hw) fr(p);
+  fr(g->tab64);
+  fr(g->tbuf[0]);
+  fr(g->tbuf[1]);
+  fr(g->coarse_inv);
+  fr(g->cpack[0]);
+  fr(g->cpack[1]);
+  fr(g->x);
+  fr(g->r);
+  fr(g->z);
+  fr(g->d);
+  fr(g->Ad);
+  fr(g->partial);
+  fr(g->scal);
+  if (g->hscal) (void)hipHostFree(g->hscal);
+  delete g;
+}
+
+int global_apply(gmg_handle* g, int l, const double* x, double* y) {
+  CellArgs a{g->verts[l], g->mu[l], g->sizes[l], g->p, g->dim, g->tab64};
+  HIP_TRY(launch_cell_apply(a, x, g->cellbuf[l], g->stream));
+  HIP_TRY(launch_cell_gather(g->dim, g->sizes[l], g->p, g->cellbuf[l], y, g->stream));
+  return PMG_OK;
+}
+
+// out (fine level l+1) = P in (coarse level l), or its transpose
+int h_transfer(gmg_handle* g, int l, const double* in, double* out, bool transpose) {
+  const int Mc = g->M(l), Mf = g->M(l + 1), dim = g->dim;
+  int cur[3] = {transpose ? Mf : Mc, transpose ? Mf : Mc, dim == 3 ? (transpose ? Mf : Mc) : 1};
+  const double* src = in;
+  for (int axis = 0; axis < dim; ++axis) {
+    int nxt[3] = {cur[0], cur[1], cur[2]};
+    nxt[axis] = transpose ? Mc : Mf;
+    double* dst = axis == dim - 1 ? out : g->tbuf[axis & 1];
+    HIP_TRY(launch_h_prolong_axis(dim, axis, cur, nxt, g->hfirst[l], g->hw[l], g->p, src, dst,
+                                  transpose ? 1 : 0, g->stream));
+    src = dst;
+    for (int i = 0; i < 3; ++i) cur[i] = nxt[i];
+  }
+  HIP_TRY(launch_mask_dirichlet(dim, transpose ? Mc : Mf, out, g->stream));
+  return PMG_OK;
+}
+
+int vcycle(gmg_handle* g, int l, const double* f, double* u) {
+  const int dim = g->dim;
+  if (l == 0) {
+    HIP_TRY(launch_gather_interior(dim, g->M(0), f, g->cpack[0], g->stream));
+    HIP_TRY(launch_gemv(g->coarse_n, g->coarse_inv, g->cpack[0], g->cpack[1], g->stream));
+    HIP_TRY(hipMemsetAsync(u, 0, g->len(0) * sizeof(double), g->stream));
+    HIP_TRY(launch_scatter_interior(dim, g->M(0), g->cpack[1], u, g->stream));
+    return PMG_OK;
+  }
+  pmg_handle* S = g->smoother[l];
+  HIP_TRY(hipMemsetAsync(u, 0, g->len(l) * sizeof(double), g->stream));
+  PMG_TRY(pmg_patch_smooth(S, u, f, +1));
+  // residual r = f - A u, restricted to level l-1
+  double* t = g->t[l];
+  PMG_TRY(global_apply(g, l, u, t));
+  HIP_TRY(launch_axpby(g->len(l), 1.0, f, -1.0, t, g->stream));
+  PMG_TRY(h_transfer(g, l - 1, t, g->f[l - 1], true));
+  PMG_TRY(vcycle(g, l - 1, g->f[l - 1], g->u[l - 1]));
+  PMG_TRY(h_transfer(g, l - 1, g->u[l - 1], t, false));
+  HIP_TRY(launch_axpby(g->len(l), 1.0, t, 1.0, u, g->stream));
+  PMG_TRY(pmg_patch_smooth(S, u, f, -1));
+  return PMG_OK;
+}
+
+int dot(gmg_handle* g, const double* x, const double* y, int slot) {
+  const int64_t n = g->len(g->nlev - 1);
+  HIP_TRY(launch_dot_partial(n, x, y, g->partial, kDotBlocks, g->stream));
+  HIP_TRY(launch_dot_final(g->partial, kDotBlocks, g->scal + slot, g->stream));
+  return PMG_OK;
+}
+
+// dense SPD inverse through the Cholesky factor (host, FP64)
+int spd_inverse(std::vector<double>& A, int n) {
+  // A = L L^T (lower, in place)
+  for (int j = 0; j < n; ++j) {
+    double d = A[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) d -= A[(size_t)j * n + k] * A[(size_t)j * n + k];
+    if (!(d > 0.0)) return fail(PMG_ERR_BREAKDOWN, "coarse matrix not SPD at row %d", j);
+    d = std::sqrt(d);
+    A[(size_t)j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double s = A[(size_t)i * n + j];
+      const double* ai = &A[(size_t)i * n];
+      const double* aj = &A[(size_t)j * n];
+      for (int k = 0; k < j; ++k) s -= ai[k] * aj[k];
+      A[(size_t)i * n + j] = s / d;
+    }
+  }
+  // W = L^{-1} (lower), then A^{-1} = W^T W
+  std::vector<double> W((size_t)n * n, 0.0);
+  for (int c = 0; c < n; ++c) {
+    W[(size_t)c * n + c] = 1.0 / A[(size_t)c * n + c];
+    for (int i = c + 1; i < n; ++i) {
+      double s = 0;
+      for (int k = c; k < i; ++k) s -= A[(size_t)i * n + k] * W[(size_t)k * n + c];
+      W[(size_t)i * n + c] = s / A[(size_t)i * n + i];
+    }
+  }
+  std::vector<double> inv((size_t)n * n, 0.0);
+  for (int k = 0; k < n; ++k) {
+    const double* wk = &W[(size_t)k * n];
+    for (int i = 0; i <= k; ++i) {
+      const double wki = wk[i];
+      if (wki == 0.0) continue;
+      double* row = &inv[(size_t)i * n];
+      for (int j = 0; j <= k; ++j) row[j] += wki * wk[j];
+    }
+  }
+  A.swap(inv);
+  return PMG_OK;
+}
+
+int gmg_setup_impl(const pmg_mesh* mesh, const double* coeff, int p, const pmg_opts* o,
+                   gmg_handle** out) {
+  if (!mesh || !coeff || !o || !out || !mesh->vertices) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  const int dim = mesh->dim;
+  if (dim != 2 && dim != 3) return fail(PMG_ERR_INVALID_ARG, "dim must be 2 or 3");
+  if (p < 1 || p > kMaxDegree) return fail(PMG_ERR_INVALID_ARG, "degree %d outside 1..15", p);
+  // hierarchy: halve while even and the halved mesh keeps an interior vertex
+  std::vector<int> sizes = {mesh->n_cells};
+  while (sizes.back() % 2 == 0 && sizes.back() / 2 >= 2) sizes.push_back(sizes.back() / 2);
+  if (sizes.size() < 2) return fail(PMG_ERR_INVALID_ARG, "mesh with %d cells cannot be coarsened", mesh->n_cells);
+  std::reverse(sizes.begin(), sizes.end());
+  gmg_handle* g = new gmg_handle();
+  g->dim = dim;
+  g->p = p;
+  g->nlev = (int)sizes.size();
+  g->sizes = sizes;
+  g->stream = reinterpret_cast<hipStream_t>(o->stream);
+  auto cleanup = [&](int s) {
+    free_gmg(g);
+    return s;
+  };
+  const int L = g->nlev;
+  // level geometry: shared vertices, mean coefficients of the children
+  std::vector<std::vector<double>> V(L), Mu(L);
+  V[L - 1].assign(mesh->vertices, mesh->vertices + (size_t)ipow(mesh->n_cells + 1, dim) * dim);
+  Mu[L - 1].assign(coeff, coeff + (size_t)ipow(mesh->n_cells, dim));
+  for (int l = L - 2; l >= 0; --l) {
+    const int Nc = sizes[l], Nf = sizes[l + 1];
+    const int Nc1 = Nc + 1, Nf1 = Nf + 1;
+    V[l].assign((size_t)ipow(Nc1, dim) * dim, 0.0);
+    Mu[l].assign((size_t)ipow(Nc, dim), 0.0);
+    for (int v = 0; v < ipow(Nc1, dim); ++v) {
+      const int vx = v % Nc1, vy = (v / Nc1) % Nc1, vz = dim == 3 ? v / (Nc1 * Nc1) : 0;
+      const int f = 2 * vx + 2 * vy * Nf1 + (dim == 3 ? 2 * vz * Nf1 * Nf1 : 0);
+      for (int r = 0; r < dim; ++r) V[l][(size_t)v * dim + r] = V[l + 1][(size_t)f * dim + r];
+    }
+    for (int e = 0; e < ipow(Nc, dim); ++e) {
+      const int ex = e % Nc, ey = (e / Nc) % Nc, ez = dim == 3 ? e / (Nc * Nc) : 0;
+      double s = 0;
+      for (int c = 0; c < (1 << dim); ++c) {
+        int f = (2 * ex + (c & 1)) + (2 * ey + ((c >> 1) & 1)) * Nf;
+        if (dim == 3) f += (2 * ez + ((c >> 2) & 1)) * Nf * Nf;
+        s += Mu[l + 1][f];
+      }
+      Mu[l][e] = s / (1 << dim);
+    }
+  }
+  g->smoother.assign(L, nullptr);
+  g->verts.assign(L, nullptr);
+  g->mu.assign(L, nullptr);
+  g->f.assign(L, nullptr);
+  g->u.assign(L, nullptr);
+  g->t.assign(L, nullptr);
+  g->cellbuf.assign(L, nullptr);
+  int s;
+  hipError_t e;
+  for (int l = 0; l < L; ++l) {
+    const int N = sizes[l];
+    const size_t nv = (size_t)ipow(N + 1, dim), nc = (size_t)ipow(N, dim);
+    if ((s = dev_alloc(&g->verts[l], nv * dim * sizeof(double), nullptr)) < 0) return cleanup(s);
+    if ((s = dev_alloc(&g->mu[l], nc * sizeof(double), nullptr)) < 0) return cleanup(s);
+    if ((e = hipMemcpy(g->verts[l], V[l].data(), nv * dim * sizeof(double), hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(g->mu[l], Mu[l].data(), nc * sizeof(double), hipMemcpyHostToDevice)))
+      return cleanup(fail(PMG_ERR_HIP, "upload: %s", hipGetErrorString(e)));
+    const size_t len = (size_t)g->len(l);
+    if ((s = dev_alloc(&g->f[l], len * sizeof(double), nullptr)) < 0) return cleanup(s);
+    if ((s = dev_alloc(&g->u[l], len * sizeof(double), nullptr)) < 0) return cleanup(s);
+    if ((s = dev_alloc(&g->t[l], len * sizeof(double), nullptr)) < 0) return cleanup(s);
+    if ((s = dev_alloc(&g->cellbuf[l], nc * ipow(p + 1, dim) * sizeof(double), nullptr)) < 0)
+      return cleanup(s);
+    if (l > 0) {
+      pmg_mesh m{dim, N, V[l].data()};
+      pmg_handle* h = nullptr;
+      if ((s = patch_setup_impl(&m, Mu[l].data(), p, o, &h)) < 0) return cleanup(s);
+      g->smoother[l] = h;
+    }
+  }
+  for (int l = 0; l + 1 < L; ++l) {
+    std::vector<int> first;
+    std::vector<double> w;
+    h_prolongation_1d(sizes[l], p, first, w);
+    int* df = nullptr;
+    double* dw = nullptr;
+    if ((s = dev_alloc(&df, first.size() * sizeof(int), nullptr)) < 0) return cleanup(s);
+    g->hfirst.push_back(df);
+    if ((s = dev_alloc(&dw, w.size() * sizeof(double), nullptr)) < 0) return cleanup(s);
+    g->hw.push_back(dw);
+    if ((e = hipMemcpy(df, first.data(), first.size() * sizeof(int), hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(dw, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice)))
+      return cleanup(fail(PMG_ERR_HIP, "upload: %s", hipGetErrorString(e)));
+  }
+  {
+    DegreeTables t = degree_tables(p);
+    const int n = t.n;
+    std::vector<double> tab(3 * n * n + 2 * n);
+    std::copy(t.B.begin(), t.B.end(), tab.begin());
+    std::copy(t.Dc.begin(), t.Dc.end(), tab.begin() + n * n);
+    std::copy(t.D.begin(), t.D.end(), tab.begin() + 2 * n * n);
+    std::copy(t.xg.begin(), t.xg.end(), tab.begin() + 3 * n * n);
+    std::copy(t.wg.begin(), t.wg.end(), tab.begin() + 3 * n * n + n);
+    if ((s = dev_alloc(&g->tab64, tab.size() * sizeof(double), nullptr)) < 0) return cleanup(s);
+    if ((e = hipMemcpy(g->tab64, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice)))
+      return cleanup(fail(PMG_ERR_HIP, "upload: %s", hipGetErrorString(e)));
+  }
+  const size_t lf = (size_t)g->len(L - 1);
+  for (int i = 0; i < 2; ++i)
+    if ((s = dev_alloc(&g->tbuf[i], lf * sizeof(double), nullptr)) < 0) return cleanup(s);
+  for (double** v : {&g->x, &g->r, &g->z, &g->d, &g->Ad})
+    if ((s = dev_alloc(v, lf * sizeof(double), nullptr)) < 0) return cleanup(s);
+  if ((s = dev_alloc(&g->partial, kDotBlocks * sizeof(double), nullptr)) < 0) return cleanup(s);
+  if ((s = dev_alloc(&g->scal, 8 * sizeof(double), nullptr)) < 0) return cleanup(s);
+  if ((e = hipHostMalloc((void**)&g->hscal, 8 * sizeof(double), hipHostMallocDefault)))
+    return cleanup(fail(PMG_ERR_HIP, "hipHostMalloc: %s", hipGetErrorString(e)));
+
+  // coarsest level: element matrices on the GPU, dense assembly and Cholesky
+  // inverse on the host (FP64), inverse kept on the device for a GEMV solve
+  {
+    const int Nc = sizes[0], n = p + 1, npt = ipow(n, dim), ncell = ipow(Nc, dim);
+    const int Mc = Nc * p + 1, mi = Mc - 2;
+    const int nint = ipow(mi, dim);
+    g->coarse_n = nint;
+    double* dKe = nullptr;
+    if ((s = dev_alloc(&dKe, (size_t)ncell * npt * npt * sizeof(double), nullptr)) < 0) return cleanup(s);
+    CellArgs a{g->verts[0], g->mu[0], Nc, p, dim, g->tab64};
+    std::vector<double> Ke((size_t)ncell * npt * npt);
+    if ((e = launch_element_matrices(a, dKe, g->stream)) ||
+        (e = hipMemcpyAsync(Ke.data(), dKe, Ke.size() * sizeof(double), hipMemcpyDeviceToHost, g->stream)) ||
+        (e = hipStreamSynchronize(g->stream))) {
+      (void)hipFree(dKe);
+      return cleanup(fail(PMG_ERR_HIP, "coarse element matrices: %s", hipGetErrorString(e)));
+    }
+    (void)hipFree(dKe);
+    std::vector<double> A((size_t)nint * nint, 0.0);
+    std::vector<int> loc(npt);
+    for (int c = 0; c < ncell; ++c) {
+      const int ex = c % Nc, ey = (c / Nc) % Nc, ez = dim == 3 ? c / (Nc * Nc) : 0;
+      for (int k = 0; k < npt; ++k) {
+        const int ax = k % n, ay = (k / n) % n, az = dim == 3 ? k / (n * n) : 0;
+        const int gx = ex * p + ax, gy = ey * p + ay, gz = ez * p + az;
+        bool bd = gx == 0 || gx == Mc - 1 || gy == 0 || gy == Mc - 1;
+        if (dim == 3) bd = bd || gz == 0 || gz == Mc - 1;
+        loc[k] = bd ? -1 : (gx - 1) + (gy - 1) * mi + (dim == 3 ? (gz - 1) * mi * mi : 0);
+      }
+      for (int i = 0; i < npt; ++i) {
+        if (loc[i] < 0) continue;
+        for (int j = 0; j < npt; ++j)
+          if (loc[j] >= 0) A[(size_t)loc[i] * nint + loc[j]] += Ke[((size_t)c * npt + i) * npt + j];
+      }
+    }
+    if ((s = spd_inverse(A, nint)) < 0) return cleanup(s);
+    if ((s = dev_alloc(&g->coarse_inv, A.size() * sizeof(double), nullptr)) < 0) return cleanup(s);
+    for (int i = 0; i < 2; ++i)
+      if ((s = dev_alloc(&g->cpack[i], (size_t)nint * sizeof(double), nullptr)) < 0) return cleanup(s);
+    if ((e = hipMemcpy(g->coarse_inv, A.data(), A.size() * sizeof(double), hipMemcpyHostToDevice)))
+      return cleanup(fail(PMG_ERR_HIP, "upload: %s", hipGetErrorString(e)));
+  }
+  *out = g;
+  return PMG_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// exported functions
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+int pmg_default_opts(pmg_opts* o) {
+  if (!o) return fail(PMG_ERR_INVALID_ARG, "null opts");
+  std::memset(o, 0, sizeof(*o));
+  o->precision = PMG_FP64;
+  o->n_levels = 0;
+  o->cheb_degree = 3;
+  o->n_vcycles = 1;
+  o->bounds = PMG_BOUNDS_LANCZOS;
+  o->lanczos_steps = 12;
+  o->cheb_safety = 1.1;
+  o->cheb_range = 15.0;
+  o->seed = 0;
+  o->stream = nullptr;
+  return PMG_OK;
+}
+
+int pmg_patch_setup(const pmg_mesh* mesh, const double* coeff, int32_t p, const pmg_opts* opts,
+                    pmg_handle** out) {
+  return patch_setup_impl(mesh, coeff, p, opts, out);
+}
+
+int pmg_patch_smooth_colors(pmg_handle* h, double* u, const double* b, int32_t c_begin,
+                            int32_t c_end) {
+  if (!h || !u || !b) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  if (!h->bounds_valid) return fail(PMG_ERR_INVALID_ARG, "Chebyshev bounds not set");
+  if (c_begin < 0 || c_end > h->n_colors || c_begin > c_end)
+    return fail(PMG_ERR_INVALID_ARG, "colour range [%d, %d) outside [0, %d)", c_begin, c_end, h->n_colors);
+  PatchArgs a = h->args();
+  a.u = u;
+  a.b = b;
+  for (int c = c_begin; c < c_end; ++c) PMG_TRY(launch_chunks(h, kModeSmooth, a, h->color_off[c], h->color_off[c + 1]));
+  return PMG_OK;
+}
+
+int pmg_patch_smooth(pmg_handle* h, double* u, const double* b, int32_t direction) {
+  if (!h || !u || !b) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  if (direction != 1 && direction != -1) return fail(PMG_ERR_INVALID_ARG, "direction must be +1 or -1");
+  if (direction > 0) return pmg_patch_smooth_colors(h, u, b, 0, h->n_colors);
+  for (int c = h->n_colors - 1; c >= 0; --c) PMG_TRY(pmg_patch_smooth_colors(h, u, b, c, c + 1));
+  return PMG_OK;
+}
+
+int pmg_patch_residual(pmg_handle* h, const double* u, const double* b, double* r) {
+  if (!h || !u || !b || !r) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  PatchArgs a = h->args();
+  a.u = const_cast<double*>(u);
+  a.b = b;
+  a.out = r;
+  if (!h->bounds_valid) {
+    // the evaluate step reads no Chebyshev data; keep the kernel's loads valid
+  }
+  return launch_chunks(h, kModeResidual, a, 0, h->n_patches);
+}
+
+int pmg_patch_apply(pmg_handle* h, int32_t level, const double* x, double* y) {
+  if (!h || !x || !y) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  if (level < 0 || level >= h->L) return fail(PMG_ERR_INVALID_ARG, "level %d outside 0..%d", level, h->L - 1);
+  PatchArgs a = h->args();
+  a.in = x;
+  a.out = y;
+  a.level = level;
+  return launch_chunks(h, kModeApply, a, 0, h->n_patches);
+}
+
+int pmg_patch_local_solve(pmg_handle* h, const double* r, double* d) {
+  if (!h || !r || !d) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  if (!h->bounds_valid) return fail(PMG_ERR_INVALID_ARG, "Chebyshev bounds not set");
+  PatchArgs a = h->args();
+  a.in = r;
+  a.out = d;
+  return launch_chunks(h, kModeSolve, a, 0, h->n_patches);
+}
+
+int pmg_get_inv_diag(const pmg_handle* h, int32_t level, double* out) {
+  if (!h || !out) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  if (level < 0 || level >= h->L) return fail(PMG_ERR_INVALID_ARG, "level %d outside 0..%d", level, h->L - 1);
+  HIP_TRY(hipMemcpyAsync(out, h->invdiag64[level], (size_t)h->n_patches * h->level_size(level) * sizeof(double),
+                         hipMemcpyDeviceToDevice, h->stream));
+  return PMG_OK;
+}
+
+int pmg_get_bounds(const pmg_handle* h, double* lam) {
+  if (!h || !lam) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  std::copy(h->bounds.begin(), h->bounds.end(), lam);
+  return PMG_OK;
+}
+
+int pmg_set_bounds(pmg_handle* h, const double* lam) {
+  if (!h || !lam) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  std::vector<double> old = h->bounds;
+  std::copy(lam, lam + h->bounds.size(), h->bounds.begin());
+  int s = set_cheb(h);
+  if (s < 0) h->bounds = old;
+  return s;
+}
+
+int pmg_get_patch_vertices(const pmg_handle* h, int32_t* out) {
+  if (!h || !out) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  HIP_TRY(hipMemcpy(out, h->patch_vertex, (size_t)h->n_patches * sizeof(int32_t), hipMemcpyDeviceToHost));
+  return PMG_OK;
+}
+
+int pmg_query(const pmg_handle* h, int32_t what, int64_t* value) {
+  if (!h || !value) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  const int64_t M = (int64_t)h->N * h->p + 1;
+  switch (what) {
+    case PMG_Q_N_PATCHES: *value = h->n_patches; return PMG_OK;
+    case PMG_Q_N_COLORS: *value = h->n_colors; return PMG_OK;
+    case PMG_Q_N_LEVELS: *value = h->L; return PMG_OK;
+    case PMG_Q_N_DOFS: *value = h->dim == 3 ? M * M * M : M * M; return PMG_OK;
+    case PMG_Q_N_INTERIOR_DOFS: *value = h->dim == 3 ? (M - 2) * (M - 2) * (M - 2) : (M - 2) * (M - 2); return PMG_OK;
+    case PMG_Q_DEVICE_BYTES: *value = (int64_t)h->device_bytes; return PMG_OK;
+    default: break;
+  }
+  if (what >= PMG_Q_COLOR_OFFSET && what <= PMG_Q_COLOR_OFFSET + h->n_colors) {
+    *value = h->color_off[what - PMG_Q_COLOR_OFFSET];
+    return PMG_OK;
+  }
+  if (what >= PMG_Q_LEVEL_DEGREE && what < PMG_Q_LEVEL_DEGREE + h->L) {
+    *value = h->levels[what - PMG_Q_LEVEL_DEGREE];
+    return PMG_OK;
+  }
+  if (what >= PMG_Q_LEVEL_SIZE && what < PMG_Q_LEVEL_SIZE + h->L) {
+    *value = h->level_size(what - PMG_Q_LEVEL_SIZE);
+    return PMG_OK;
+  }
+  return fail(PMG_ERR_INVALID_ARG, "unknown query %d", what);
+}
+
+int pmg_patch_destroy(pmg_handle* h) {
+  if (!h) return PMG_OK;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  else (void)hipDeviceSynchronize();
+  free_handle(h);
+  return PMG_OK;
+}
+
+int gmg_setup(const pmg_mesh* mesh, const double* coeff, int32_t p, const pmg_opts* opts,
+              gmg_handle** out) {
+  return gmg_setup_impl(mesh, coeff, p, opts, out);
+}
+
+int gmg_apply(gmg_handle* g, const double* x, double* y) {
+  if (!g || !x || !y) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  return global_apply(g, g->nlev - 1, x, y);
+}
+
+int gmg_vcycle(gmg_handle* g, const double* r, double* z) {
+  if (!g || !r || !z) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  return vcycle(g, g->nlev - 1, r, z);
+}
+
+int gmg_cg_solve(gmg_handle* g, double* x, const double* b, double rtol, int32_t maxit, int32_t* iters,
+                 double* relres) {
+  if (!g || !x || !b) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  if (!(rtol > 0.0) || maxit < 1) return fail(PMG_ERR_INVALID_ARG, "need rtol > 0 and maxit >= 1");
+  const int lf = g->nlev - 1;
+  const int64_t n = g->len(lf);
+  hipStream_t s = g->stream;
+  auto fetch = [&](int k) -> int {
+    HIP_TRY(hipMemcpyAsync(g->hscal, g->scal, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    (void)k;
+    return PMG_OK;
+  };
+  // x = 0, r = b (Dirichlet entries of b are ignored)
+  HIP_TRY(hipMemsetAsync(x, 0, n * sizeof(double), s));
+  HIP_TRY(hipMemcpyAsync(g->r, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(launch_mask_dirichlet(g->dim, g->M(lf), g->r, s));
+  PMG_TRY(dot(g, g->r, g->r, 0));
+  PMG_TRY(vcycle(g, lf, g->r, g->z));
+  HIP_TRY(hipMemcpyAsync(g->d, g->z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  PMG_TRY(dot(g, g->r, g->z, 1));
+  PMG_TRY(fetch(0));
+  const double nb = std::sqrt(g->hscal[0]);
+  double rz = g->hscal[1];
+  if (nb == 0.0) {
+    if (iters) *iters = 0;
+    if (relres) *relres = 0.0;
+    return PMG_OK;
+  }
+  double rel = 1.0;
+  for (int k = 1; k <= maxit; ++k) {
+    PMG_TRY(global_apply(g, lf, g->d, g->Ad));
+    PMG_TRY(dot(g, g->d, g->Ad, 2));
+    PMG_TRY(fetch(k));
+    const double dAd = g->hscal[2];
+    if (!(dAd > 0.0) || !std::isfinite(dAd)) {
+      if (iters) *iters = k;
+      if (relres) *relres = rel;
+      return fail(PMG_ERR_BREAKDOWN, "CG breakdown at iteration %d: d^T A d = %g", k, dAd);
+    }
+    const double alpha = rz / dAd;
+    HIP_TRY(launch_axpby(n, alpha, g->d, 1.0, x, s));
+    HIP_TRY(launch_axpby(n, -alpha, g->Ad, 1.0, g->r, s));
+    PMG_TRY(dot(g, g->r, g->r, 3));
+    PMG_TRY(fetch(k));
+    rel = std::sqrt(g->hscal[3]) / nb;
+    if (rel <= rtol) {
+      if (iters) *iters = k;
+      if (relres) *relres = rel;
+      return PMG_OK;
+    }
+    PMG_TRY(vcycle(g, lf, g->r, g->z));
+    PMG_TRY(dot(g, g->r, g->z, 4));
+    PMG_TRY(fetch(k));
+    const double rz_new = g->hscal[4];
+    HIP_TRY(launch_xpay_to(n, g->z, rz_new / rz, g->d, g->d, s));
+    rz = rz_new;
+  }
+  if (iters) *iters = maxit + 1;
+  if (relres) *relres = rel;
+  g_last_error = "CG did not converge within maxit iterations";
+  return PMG_WARN_NOT_CONVERGED;
+}
+
+int gmg_query(const gmg_handle* g, int32_t what, int64_t* value) {
+  if (!g || !value) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  if (what == 0) {
+    *value = g->nlev;
+    return PMG_OK;
+  }
+  if (what >= 16 && what < 16 + g->nlev) {
+    *value = g->sizes[what - 16];
+    return PMG_OK;
+  }
+  return fail(PMG_ERR_INVALID_ARG, "unknown query %d", what);
+}
+
+int gmg_level_smoother(gmg_handle* g, int32_t level, pmg_handle** h) {
+  if (!g || !h) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  if (level < 1 || level >= g->nlev) return fail(PMG_ERR_INVALID_ARG, "level %d outside 1..%d", level, g->nlev - 1);
+  *h = g->smoother[level];
+  return PMG_OK;
+}
+
+int gmg_destroy(gmg_handle* g) {
+  if (!g) return PMG_OK;
+  if (g->stream) (void)hipStreamSynchronize(g->stream);
+  else (void)hipDeviceSynchronize();
+  free_gmg(g);
+  return PMG_OK;
+}
+
+const char* pmg_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

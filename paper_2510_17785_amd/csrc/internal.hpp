@@ -1,0 +1,104 @@
+// Internal declarations shared by the host API and the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pmg.h"
+
+namespace pmgi {
+
+constexpr int kThreads = 256;        // threads per patch workgroup
+constexpr int kMaxLevels = 4;        // local p-levels per patch
+constexpr int kTabLevelStride = 3 * 256 + 2 * 16;  // B, Dc, D (n x n) + xg, wg (n), n <= 16
+constexpr int kTabTransferStride = 29 * 29;        // (2p-1) x (2q-1), p <= 15
+constexpr int kTabSize = kMaxLevels * kTabLevelStride + (kMaxLevels - 1) * kTabTransferStride;
+
+// Kernel modes of the patch kernel.
+enum PatchMode : int {
+  kModeSmooth = 0,    // gather, evaluate, local solve, scatter-add
+  kModeResidual = 1,  // gather, evaluate, write the local residual
+  kModeSolve = 2,     // read local residuals, local solve, write corrections
+  kModeApply = 3,     // read interior vectors, apply one level operator
+};
+
+// Arguments of every per-patch kernel.  Pointers to T-valued arrays are
+// void* here and cast inside the kernel.
+struct PatchArgs {
+  const double* verts;       // (N+1)^dim x dim
+  const double* mu;          // N^dim
+  const int32_t* patch_vertex;  // per patch (sweep order): linear vertex index
+  int32_t N, p;
+  int32_t patch_begin;       // first patch of this launch (sweep order)
+  int32_t n_patch;           // patches in this launch (= grid size)
+  const void* tab;           // T tables, kTabSize
+  const double* tab64;       // FP64 tables, kTabSize
+  const void* invdiag[kMaxLevels];      // T, n_patches_total x size_l
+  const double* invdiag64[kMaxLevels];  // FP64, same layout
+  const void* cheb;          // T, n_patches_total x (L-1) x 2: theta, delta
+  int32_t cheb_degree, n_vcycles;
+  double* u;                 // global vector (smooth)
+  const double* b;           // global right-hand side (smooth, residual)
+  const double* in;          // batched local input (solve, apply)
+  double* out;               // batched local output (residual, solve, apply, diag)
+  int32_t level;             // level index (apply, diag)
+  void* vec_scratch;         // per-block vector storage when it does not fit in LDS
+  int64_t vec_stride;        // elements per block in vec_scratch
+  // Lanczos
+  int32_t lanczos_steps;
+  uint64_t seed;
+  double* lanczos_basis;     // per block: m x size_l doubles
+  double* bounds_out;        // n_patches_total x (L-1) x 2
+};
+
+// One compiled (precision, dim, levels) variant of the patch kernels.
+struct PatchVariant {
+  int precision, dim, n_levels;
+  int levels[kMaxLevels];
+  // launch one patch kernel in `mode` over args.n_patch patches
+  hipError_t (*launch)(int mode, const PatchArgs& a, hipStream_t s);
+  // dynamic LDS bytes of `mode`, and per-block vector-scratch elements needed
+  // when vectors do not fit in LDS (0 if they do)
+  size_t (*lds_bytes)(int mode);
+  int64_t (*vec_scratch_elems)();
+  int64_t (*vec_scratch_elems64)();  // same for the FP64 layout of the setup kernels
+  // FP64 setup kernels (inverse diagonals of every level; Lanczos bounds)
+  hipError_t (*launch_diag)(const PatchArgs& a, hipStream_t s);
+  hipError_t (*launch_lanczos)(const PatchArgs& a, int level, hipStream_t s);
+};
+
+const PatchVariant* find_variant(int precision, int dim, int n_levels, const int* levels);
+std::string list_variants();
+
+// Global (h-level) FP64 kernels.
+struct CellArgs {
+  const double* verts;
+  const double* mu;
+  int32_t N, p, dim;
+  const double* tab64;  // tables of degree p at level slot 0
+};
+hipError_t launch_cell_apply(const CellArgs& a, const double* x, double* cellbuf, hipStream_t s);
+hipError_t launch_cell_gather(int dim, int N, int p, const double* cellbuf, double* y, hipStream_t s);
+hipError_t launch_element_matrices(const CellArgs& a, double* Ke, hipStream_t s);
+hipError_t launch_h_prolong_axis(int dim, int axis, const int* sizes_in, const int* sizes_out,
+                                 const int* first, const double* w, int p, const double* in,
+                                 double* out, int transpose, hipStream_t s);
+hipError_t launch_mask_dirichlet(int dim, int M, double* x, hipStream_t s);
+hipError_t launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);
+hipError_t launch_xpay_to(int64_t n, const double* x, double a, const double* y, double* z,
+                          hipStream_t s);
+hipError_t launch_dot_partial(int64_t n, const double* x, const double* y, double* partial,
+                              int nblocks, hipStream_t s);
+hipError_t launch_dot_final(const double* partial, int nblocks, double* out, hipStream_t s);
+hipError_t launch_gemv(int n, const double* A, const double* x, double* y, hipStream_t s);
+hipError_t launch_gather_interior(int dim, int M, const double* full, double* packed,
+                                  hipStream_t s);
+hipError_t launch_scatter_interior(int dim, int M, const double* packed, double* full,
+                                   hipStream_t s);
+hipError_t launch_convert_to_float(int64_t n, const double* in, float* out, hipStream_t s);
+constexpr int kDotBlocks = 512;
+
+}  // namespace pmgi

@@ -1,0 +1,1460 @@
+// Per-patch kernels of the vertex-patch smoother with a nested p-multigrid
+// local solver (arXiv 2510.17785, Section 2.1 and Section 3.1), for CDNA4.
+//
+// One workgroup of kThreads threads owns one patch at a time.  Everything the
+// local solver touches lives in LDS: the 1D tables, the patch geometry (3^d
+// vertices relative to the patch centre and 2^d coefficients), the closure
+// input of the operator, its interior output, the sum-factorisation slab
+// buffers and, when they fit, the level vectors.  Global memory is touched
+// only to gather u and b, to read the per-patch inverse diagonals and
+// Chebyshev intervals, and to scatter-add the FP64 correction.
+//
+// Level operator (Section 3.1, level operators; Section 2, bilinear form):
+//   A_{j,q} x = sum over the 2^d cells of B^T G B x in sum-factorised form.
+// The patch is treated as one tensor-product object with 2 cells per
+// direction: a closure line of 2q+1 nodes maps to 2(q+1) Gauss points (q+1
+// per cell) through a block-structured 1D matrix, so the node shared by the
+// two cells of a line is handled once and the transposed contraction sums the
+// contributions of both cells without any atomics.  Gradients at the Gauss
+// points use the collocation derivative on the Gauss points.  The metric
+// G = mu w det J J^{-1} J^{-T} is recomputed at every quadrature point from
+// the multilinear cell map (the paper's matrix-free local solver keeps only
+// O(p^d) data per patch, Section 1 and Section 3.1).  In 3D the work is split
+// into two slabs (the two cell layers in z) to bound the LDS footprint.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <type_traits>
+
+#include "internal.hpp"
+
+namespace pmgi {
+namespace {
+
+constexpr __host__ __device__ int ipow(int b, int e) {
+  int r = 1;
+  for (int i = 0; i < e; ++i) r *= b;
+  return r;
+}
+constexpr __host__ __device__ int round_up(int x, int a) { return (x + a - 1) / a * a; }
+
+template <int... Qs>
+struct Levels {
+  static constexpr int count = sizeof...(Qs);
+  static constexpr int q[kMaxLevels] = {Qs...};
+};
+
+template <int DIM, int Q>
+struct Sh {
+  static constexpr int n = Q + 1;       // nodes / Gauss points per cell per direction
+  static constexpr int m = 2 * Q + 1;   // closure nodes per direction
+  static constexpr int mi = 2 * Q - 1;  // interior nodes per direction
+  static constexpr int NQ = 2 * n;      // Gauss points per direction over the patch
+  static constexpr int closure = ipow(m, DIM);
+  static constexpr int interior = ipow(mi, DIM);
+  static constexpr int S = DIM == 3 ? n * NQ * NQ : n * NQ;  // one slab buffer
+};
+
+constexpr __host__ __device__ int tab_size(int q) { return 3 * (q + 1) * (q + 1) + 2 * (q + 1); }
+
+// LDS layout (in elements of T) of one patch workgroup.
+template <typename T, int DIM, class LV>
+struct Layout {
+  static constexpr int L = LV::count;
+  using S0 = Sh<DIM, LV::q[0]>;
+  static constexpr int tab_level_off(int l) {
+    int o = 0;
+    for (int i = 0; i < l; ++i) o += tab_size(LV::q[i]);
+    return o;
+  }
+  static constexpr int tab_transfer_off(int t) {
+    int o = tab_level_off(L);
+    for (int i = 0; i < t; ++i) o += (2 * LV::q[i] - 1) * (2 * LV::q[i + 1] - 1);
+    return o;
+  }
+  static constexpr int tab_total = tab_transfer_off(L - 1);
+  static constexpr int geo_off = round_up(tab_total, 4);
+  static constexpr int nvert = ipow(3, DIM);
+  // per cell: DIM Jacobian columns x DIM components x 2^(DIM-1) multilinear coefficients
+  static constexpr int njc = ipow(2, DIM) * DIM * DIM * ipow(2, DIM - 1);
+  static constexpr int jc_rel = nvert * DIM + ipow(2, DIM) + 2 * kMaxLevels;
+  static constexpr int geo_size = jc_rel + njc;
+  static constexpr int X_off = round_up(geo_off + geo_size, 4);
+  static constexpr int Out_off = round_up(X_off + S0::closure, 4);
+  static constexpr int abuf_off = round_up(Out_off + S0::interior, 4);
+  static constexpr int base_total = round_up(abuf_off + 4 * S0::S, 4);
+  static constexpr int level_size(int l) { return ipow(2 * LV::q[l] - 1, DIM); }
+  // vectors: r_l, d_l, dinv_l per level, then res and z at the top size
+  static constexpr int vec_r(int l) {
+    int o = 0;
+    for (int i = 0; i < l; ++i) o += 3 * level_size(i);
+    return o;
+  }
+  static constexpr int vec_d(int l) { return vec_r(l) + level_size(l); }
+  static constexpr int vec_dinv(int l) { return vec_r(l) + 2 * level_size(l); }
+  static constexpr int vec_res = vec_r(L);
+  static constexpr int vec_z = vec_res + level_size(0);
+  static constexpr int vec_total = vec_z + level_size(0);
+  // metric G at every Gauss point of every level, structure of arrays
+  static constexpr int NG = DIM == 3 ? 6 : 3;
+  static constexpr int npts(int l) { return ipow(2 * (LV::q[l] + 1), DIM); }
+  static constexpr int G_rel(int l) {
+    int o = 0;
+    for (int i = 0; i < l; ++i) o += NG * npts(i);
+    return o;
+  }
+  static constexpr int G_total = G_rel(L);
+  static constexpr int kBudget = 80 * 1024;
+  // keep the metric in LDS when everything fits the budget; else keep the
+  // vectors in LDS if they fit; else vectors go to global scratch
+  static constexpr bool cache_G = (base_total + G_total + vec_total) * (int)sizeof(T) <= kBudget;
+  static constexpr bool vec_in_lds = cache_G || (base_total + vec_total) * (int)sizeof(T) <= kBudget;
+  static constexpr int G_off = base_total;
+  static constexpr int vec_off = base_total + (cache_G ? G_total : 0);
+  static constexpr int lds_elems = vec_off + (vec_in_lds ? vec_total : 0);
+};
+
+// ---------------------------------------------------------------------------
+// geometry: G = scale * det J J^{-1} J^{-T} = scale * adj(J) adj(J)^T / det J
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__device__ __forceinline__ void metric3(const T* __restrict__ V, int cx, int cy, int cz, T x,
+                                        T y, T z, T scale, T* G) {
+  // V: 27 patch vertices x 3, vertex (i,j,k) at ((k*3 + j)*3 + i)*3
+  const T* c = V + ((cz * 3 + cy) * 3 + cx) * 3;
+  auto P = [&](int i, int j, int k, int r) { return c[((k * 3 + j) * 3 + i) * 3 + r]; };
+  const T x0 = T(1) - x, y0 = T(1) - y, z0 = T(1) - z;
+  T J[3][3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    J[r][0] = y0 * z0 * (P(1, 0, 0, r) - P(0, 0, 0, r)) + y * z0 * (P(1, 1, 0, r) - P(0, 1, 0, r)) +
+              y0 * z * (P(1, 0, 1, r) - P(0, 0, 1, r)) + y * z * (P(1, 1, 1, r) - P(0, 1, 1, r));
+    J[r][1] = x0 * z0 * (P(0, 1, 0, r) - P(0, 0, 0, r)) + x * z0 * (P(1, 1, 0, r) - P(1, 0, 0, r)) +
+              x0 * z * (P(0, 1, 1, r) - P(0, 0, 1, r)) + x * z * (P(1, 1, 1, r) - P(1, 0, 1, r));
+    J[r][2] = x0 * y0 * (P(0, 0, 1, r) - P(0, 0, 0, r)) + x * y0 * (P(1, 0, 1, r) - P(1, 0, 0, r)) +
+              x0 * y * (P(0, 1, 1, r) - P(0, 1, 0, r)) + x * y * (P(1, 1, 1, r) - P(1, 1, 0, r));
+  }
+  T a[3][3];  // adjugate
+  a[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+  a[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+  a[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+  a[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+  a[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+  a[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+  a[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+  a[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+  a[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  const T det = J[0][0] * a[0][0] + J[0][1] * a[1][0] + J[0][2] * a[2][0];
+  const T s = scale / det;
+  G[0] = s * (a[0][0] * a[0][0] + a[0][1] * a[0][1] + a[0][2] * a[0][2]);
+  G[1] = s * (a[0][0] * a[1][0] + a[0][1] * a[1][1] + a[0][2] * a[1][2]);
+  G[2] = s * (a[0][0] * a[2][0] + a[0][1] * a[2][1] + a[0][2] * a[2][2]);
+  G[3] = s * (a[1][0] * a[1][0] + a[1][1] * a[1][1] + a[1][2] * a[1][2]);
+  G[4] = s * (a[1][0] * a[2][0] + a[1][1] * a[2][1] + a[1][2] * a[2][2]);
+  G[5] = s * (a[2][0] * a[2][0] + a[2][1] * a[2][1] + a[2][2] * a[2][2]);
+}
+
+template <typename T>
+__device__ __forceinline__ void metric2(const T* __restrict__ V, int cx, int cy, T x, T y,
+                                        T scale, T* G) {
+  // V: 9 patch vertices x 2, vertex (i,j) at (j*3 + i)*2
+  const T* c = V + (cy * 3 + cx) * 2;
+  auto P = [&](int i, int j, int r) { return c[(j * 3 + i) * 2 + r]; };
+  const T x0 = T(1) - x, y0 = T(1) - y;
+  T J[2][2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    J[r][0] = y0 * (P(1, 0, r) - P(0, 0, r)) + y * (P(1, 1, r) - P(0, 1, r));
+    J[r][1] = x0 * (P(0, 1, r) - P(0, 0, r)) + x * (P(1, 1, r) - P(1, 0, r));
+  }
+  const T det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  // adj = [[J11, -J01], [-J10, J00]]
+  const T s = scale / det;
+  G[0] = s * (J[1][1] * J[1][1] + J[0][1] * J[0][1]);
+  G[1] = -s * (J[1][1] * J[1][0] + J[0][1] * J[0][0]);
+  G[2] = s * (J[1][0] * J[1][0] + J[0][0] * J[0][0]);
+}
+
+// The Jacobian columns of a multilinear cell are multilinear in the other
+// reference coordinates: column 0 of a hex is a + b y + c z + d y z (per
+// component).  These coefficients are formed once per patch (jc, per cell:
+// [column][component][4] in 3D, [column][component][2] in 2D), so the metric
+// costs about 60 instructions per Gauss point.
+template <typename T>
+__device__ __forceinline__ void metric3c(const T* __restrict__ jc, T x, T y, T z, T scale, T* G) {
+  T J[3][3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const T* c0 = jc + (0 * 3 + r) * 4;
+    const T* c1 = jc + (1 * 3 + r) * 4;
+    const T* c2 = jc + (2 * 3 + r) * 4;
+    J[r][0] = c0[0] + c0[1] * y + z * (c0[2] + c0[3] * y);
+    J[r][1] = c1[0] + c1[1] * x + z * (c1[2] + c1[3] * x);
+    J[r][2] = c2[0] + c2[1] * x + y * (c2[2] + c2[3] * x);
+  }
+  T a[3][3];
+  a[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+  a[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+  a[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+  a[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+  a[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+  a[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+  a[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+  a[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+  a[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  const T det = J[0][0] * a[0][0] + J[0][1] * a[1][0] + J[0][2] * a[2][0];
+  const T s = scale / det;
+  G[0] = s * (a[0][0] * a[0][0] + a[0][1] * a[0][1] + a[0][2] * a[0][2]);
+  G[1] = s * (a[0][0] * a[1][0] + a[0][1] * a[1][1] + a[0][2] * a[1][2]);
+  G[2] = s * (a[0][0] * a[2][0] + a[0][1] * a[2][1] + a[0][2] * a[2][2]);
+  G[3] = s * (a[1][0] * a[1][0] + a[1][1] * a[1][1] + a[1][2] * a[1][2]);
+  G[4] = s * (a[1][0] * a[2][0] + a[1][1] * a[2][1] + a[1][2] * a[2][2]);
+  G[5] = s * (a[2][0] * a[2][0] + a[2][1] * a[2][1] + a[2][2] * a[2][2]);
+}
+
+template <typename T>
+__device__ __forceinline__ void metric2c(const T* __restrict__ jc, T x, T y, T scale, T* G) {
+  T J[2][2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const T* c0 = jc + (0 * 2 + r) * 2;
+    const T* c1 = jc + (1 * 2 + r) * 2;
+    J[r][0] = c0[0] + c0[1] * y;
+    J[r][1] = c1[0] + c1[1] * x;
+  }
+  const T det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  const T s = scale / det;
+  G[0] = s * (J[1][1] * J[1][1] + J[0][1] * J[0][1]);
+  G[1] = -s * (J[1][1] * J[1][0] + J[0][1] * J[0][0]);
+  G[2] = s * (J[1][0] * J[1][0] + J[0][0] * J[0][0]);
+}
+
+// multilinear coefficients of the Jacobian columns of every cell of the patch
+template <typename T, int DIM>
+__device__ void jacobian_coefficients(const T* __restrict__ V, T* __restrict__ jc) {
+  constexpr int ncell = ipow(2, DIM);
+  constexpr int per = DIM * DIM * ipow(2, DIM - 1);
+  for (int i = threadIdx.x; i < ncell * DIM * DIM; i += kThreads) {
+    const int r = i % DIM, col = (i / DIM) % DIM, cell = i / (DIM * DIM);
+    const int cx = cell & 1, cy = (cell >> 1) & 1, cz = (cell >> 2) & 1;
+    T* out = jc + cell * per + (col * DIM + r) * ipow(2, DIM - 1);
+    if constexpr (DIM == 3) {
+      auto P = [&](int i0, int j0, int k0) {
+        return V[(((cz + k0) * 3 + (cy + j0)) * 3 + (cx + i0)) * 3 + r];
+      };
+      // e[b][c]: difference along the column direction at the corners (b, c)
+      // of the other two directions, in increasing axis order
+      T e[2][2];
+      for (int b = 0; b < 2; ++b)
+        for (int cc = 0; cc < 2; ++cc) {
+          if (col == 0) e[b][cc] = P(1, b, cc) - P(0, b, cc);
+          else if (col == 1) e[b][cc] = P(b, 1, cc) - P(b, 0, cc);
+          else e[b][cc] = P(b, cc, 1) - P(b, cc, 0);
+        }
+      out[0] = e[0][0];
+      out[1] = e[1][0] - e[0][0];
+      out[2] = e[0][1] - e[0][0];
+      out[3] = e[1][1] - e[1][0] - e[0][1] + e[0][0];
+    } else {
+      auto P = [&](int i0, int j0) { return V[((cy + j0) * 3 + (cx + i0)) * 2 + r]; };
+      T e0, e1;
+      if (col == 0) {
+        e0 = P(1, 0) - P(0, 0);
+        e1 = P(1, 1) - P(0, 1);
+      } else {
+        e0 = P(0, 1) - P(0, 0);
+        e1 = P(1, 1) - P(1, 0);
+      }
+      out[0] = e0;
+      out[1] = e1 - e0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-workgroup context
+// ---------------------------------------------------------------------------
+
+template <typename T, int DIM, class LV>
+struct Ctx {
+  using Lay = Layout<T, DIM, LV>;
+  T* lds;
+  T* vec;  // vector storage (LDS or global scratch)
+  __device__ const T* tabB(int l) const { return lds + Lay::tab_level_off(l); }
+  __device__ const T* tabDc(int l) const {
+    const int n = LV::q[l] + 1;
+    return lds + Lay::tab_level_off(l) + n * n;
+  }
+  __device__ const T* tabD(int l) const {
+    const int n = LV::q[l] + 1;
+    return lds + Lay::tab_level_off(l) + 2 * n * n;
+  }
+  __device__ const T* tabXg(int l) const {
+    const int n = LV::q[l] + 1;
+    return lds + Lay::tab_level_off(l) + 3 * n * n;
+  }
+  __device__ const T* tabWg(int l) const {
+    const int n = LV::q[l] + 1;
+    return lds + Lay::tab_level_off(l) + 3 * n * n + n;
+  }
+  __device__ const T* tabP(int t) const { return lds + Lay::tab_transfer_off(t); }
+  __device__ T* geo() const { return lds + Lay::geo_off; }
+  __device__ T* mu() const { return lds + Lay::geo_off + Lay::nvert * DIM; }
+  __device__ T* cheb() const { return lds + Lay::geo_off + Lay::nvert * DIM + ipow(2, DIM); }
+  __device__ T* jc() const { return lds + Lay::geo_off + Lay::jc_rel; }
+  __device__ T* Gc(int l) const { return lds + Lay::G_off + Lay::G_rel(l); }
+  __device__ T* X() const { return lds + Lay::X_off; }
+  __device__ T* Out() const { return lds + Lay::Out_off; }
+  __device__ T* abuf() const { return lds + Lay::abuf_off; }
+  __device__ T* r(int l) const { return vec + Lay::vec_r(l); }
+  __device__ T* d(int l) const { return vec + Lay::vec_d(l); }
+  __device__ T* dinv(int l) const { return vec + Lay::vec_dinv(l); }
+  __device__ T* res() const { return vec + Lay::vec_res; }
+  __device__ T* z() const { return vec + Lay::vec_z; }
+};
+
+// ---------------------------------------------------------------------------
+// sum-factorised level operator
+//   X  : closure values (2Q+1)^DIM, x fastest (boundary entries included)
+//   Out: interior rows (2Q-1)^DIM of A-bar X
+// ---------------------------------------------------------------------------
+
+template <typename T, int Q, bool CACHE>
+__device__ __noinline__ void apply3(const T* __restrict__ X, T* __restrict__ Out, T* __restrict__ ab,
+                       const T* __restrict__ Bt, const T* __restrict__ Dc, const T* __restrict__ xg,
+                       const T* __restrict__ wg, const T* __restrict__ jc, const T* __restrict__ mu,
+                       const T* __restrict__ Gc) {
+  using SH = Sh<3, Q>;
+  constexpr int n = SH::n, m = SH::m, mi = SH::mi, NQ = SH::NQ, S = SH::S;
+  T* A = ab;
+  T* Bf = ab + S;
+  T* C = ab + 2 * S;
+  T* Dd = ab + 3 * S;
+  const int tid = threadIdx.x;
+#pragma unroll 1
+  for (int cz = 0; cz < 2; ++cz) {
+    // x: A[zl][y][QX] = sum_a B[kx][a] X[cz Q + zl][y][cx Q + a]
+#pragma unroll 1
+    for (int idx = tid; idx < n * m * NQ; idx += kThreads) {
+      const int QX = idx % NQ, t = idx / NQ, y = t % m, zl = t / m;
+      const int cx = QX >= n, kx = QX - cx * n;
+      const T* xr = X + ((cz * Q + zl) * m + y) * m + cx * Q;
+      const T* br = Bt + kx * n;
+      T acc = 0;
+#pragma unroll
+      for (int a = 0; a < n; ++a) acc += br[a] * xr[a];
+      A[idx] = acc;
+    }
+    __syncthreads();
+    // y: Bf[zl][QY][QX] = sum_a B[ky][a] A[zl][cy Q + a][QX]
+#pragma unroll 1
+    for (int idx = tid; idx < S; idx += kThreads) {
+      const int QX = idx % NQ, t = idx / NQ, QY = t % NQ, zl = t / NQ;
+      const int cy = QY >= n, ky = QY - cy * n;
+      const T* ar = A + (zl * m + cy * Q) * NQ + QX;
+      const T* br = Bt + ky * n;
+      T acc = 0;
+#pragma unroll
+      for (int a = 0; a < n; ++a) acc += br[a] * ar[a * NQ];
+      Bf[idx] = acc;
+    }
+    __syncthreads();
+    // z: C[kz][QY][QX] = sum_zl B[kz][zl] Bf[zl][QY][QX]   (values at Gauss points)
+#pragma unroll 1
+    for (int idx = tid; idx < S; idx += kThreads) {
+      const int kz = idx / (NQ * NQ), rem = idx % (NQ * NQ);
+      const T* br = Bt + kz * n;
+      T acc = 0;
+#pragma unroll
+      for (int a = 0; a < n; ++a) acc += br[a] * Bf[a * NQ * NQ + rem];
+      C[idx] = acc;
+    }
+    __syncthreads();
+    // reference gradients by collocation, then the flux G grad
+#pragma unroll 1
+    for (int idx = tid; idx < S; idx += kThreads) {
+      const int QX = idx % NQ, t = idx / NQ, QY = t % NQ, kz = t / NQ;
+      const int cx = QX >= n, kx = QX - cx * n, cy = QY >= n, ky = QY - cy * n;
+      const T* dx = Dc + kx * n;
+      const T* dy = Dc + ky * n;
+      const T* dz = Dc + kz * n;
+      const T* cxr = C + (kz * NQ + QY) * NQ + cx * n;
+      const T* cyr = C + (kz * NQ + cy * n) * NQ + QX;
+      const T* czr = C + QY * NQ + QX;
+      T gx = 0, gy = 0, gz = 0;
+#pragma unroll
+      for (int a = 0; a < n; ++a) {
+        gx += dx[a] * cxr[a];
+        gy += dy[a] * cyr[a * NQ];
+        gz += dz[a] * czr[a * NQ * NQ];
+      }
+      T G[6];
+      if constexpr (CACHE) {
+        const int gp = cz * S + idx;  // (QZ NQ + QY) NQ + QX with QZ = cz n + kz
+#pragma unroll
+        for (int c = 0; c < 6; ++c) G[c] = Gc[c * 2 * S + gp];
+      } else {
+        const int cell = cz * 4 + cy * 2 + cx;
+        metric3c<T>(jc + cell * 36, xg[kx], xg[ky], xg[kz], mu[cell] * wg[kx] * wg[ky] * wg[kz], G);
+      }
+      A[idx] = G[0] * gx + G[1] * gy + G[2] * gz;
+      Bf[idx] = G[1] * gx + G[3] * gy + G[4] * gz;
+      Dd[idx] = G[2] * gx + G[4] * gy + G[5] * gz;
+    }
+    __syncthreads();
+    // transposed collocation: C = Dc^T F
+#pragma unroll 1
+    for (int idx = tid; idx < S; idx += kThreads) {
+      const int QX = idx % NQ, t = idx / NQ, QY = t % NQ, kz = t / NQ;
+      const int cx = QX >= n, kx = QX - cx * n, cy = QY >= n, ky = QY - cy * n;
+      const T* fx = A + (kz * NQ + QY) * NQ + cx * n;
+      const T* fy = Bf + (kz * NQ + cy * n) * NQ + QX;
+      const T* fz = Dd + QY * NQ + QX;
+      T acc = 0;
+#pragma unroll
+      for (int a = 0; a < n; ++a) {
+        acc += Dc[a * n + kx] * fx[a];
+        acc += Dc[a * n + ky] * fy[a * NQ];
+        acc += Dc[a * n + kz] * fz[a * NQ * NQ];
+      }
+      C[idx] = acc;
+    }
+    __syncthreads();
+    // z^T: A[zl][QY][QX] = sum_kz B[kz][zl] C[kz][QY][QX]
+#pragma unroll 1
+    for (int idx = tid; idx < S; idx += kThreads) {
+      const int zl = idx / (NQ * NQ), rem = idx % (NQ * NQ);
+      T acc = 0;
+#pragma unroll
+      for (int k = 0; k < n; ++k) acc += Bt[k * n + zl] * C[k * NQ * NQ + rem];
+      A[idx] = acc;
+    }
+    __syncthreads();
+    // y^T onto interior rows: Bf[zl][yi][QX], y = yi + 1
+#pragma unroll 1
+    for (int idx = tid; idx < n * mi * NQ; idx += kThreads) {
+      const int QX = idx % NQ, t = idx / NQ, yi = t % mi, zl = t / mi;
+      const int y = yi + 1;
+      T acc = 0;
+      if (y <= Q) {
+        const T* ar = A + (zl * NQ) * NQ + QX;
+#pragma unroll
+        for (int k = 0; k < n; ++k) acc += Bt[k * n + y] * ar[k * NQ];
+      }
+      if (y >= Q) {
+        const T* ar = A + (zl * NQ + n) * NQ + QX;
+#pragma unroll
+        for (int k = 0; k < n; ++k) acc += Bt[k * n + (y - Q)] * ar[k * NQ];
+      }
+      Bf[idx] = acc;
+    }
+    __syncthreads();
+    // x^T onto interior columns and the interior z-planes of this slab
+    const int zl0 = cz == 0 ? 1 : 0;
+    constexpr int nz = Q;  // interior planes per slab: z = 1..Q or Q..2Q-1
+#pragma unroll 1
+    for (int idx = tid; idx < nz * mi * mi; idx += kThreads) {
+      const int xi = idx % mi, t = idx / mi, yi = t % mi, zl = zl0 + t / mi;
+      const int x = xi + 1;
+      const T* br = Bf + (zl * mi + yi) * NQ;
+      T acc = 0;
+      if (x <= Q) {
+#pragma unroll
+        for (int k = 0; k < n; ++k) acc += Bt[k * n + x] * br[k];
+      }
+      if (x >= Q) {
+#pragma unroll
+        for (int k = 0; k < n; ++k) acc += Bt[k * n + (x - Q)] * br[n + k];
+      }
+      const int zz = cz * Q + zl - 1;
+      T* o = Out + (zz * mi + yi) * mi + xi;
+      if (cz == 1 && zl == 0)
+        *o += acc;
+      else
+        *o = acc;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, int Q, bool CACHE>
+__device__ __noinline__ void apply2(const T* __restrict__ X, T* __restrict__ Out, T* __restrict__ ab,
+                       const T* __restrict__ Bt, const T* __restrict__ Dc, const T* __restrict__ xg,
+                       const T* __restrict__ wg, const T* __restrict__ jc, const T* __restrict__ mu,
+                       const T* __restrict__ Gc) {
+  using SH = Sh<2, Q>;
+  constexpr int n = SH::n, m = SH::m, mi = SH::mi, NQ = SH::NQ;
+  T* A = ab;
+  T* Bf = ab + SH::S;
+  T* C = ab + 2 * SH::S;
+  const int tid = threadIdx.x;
+#pragma unroll 1
+  for (int cy = 0; cy < 2; ++cy) {
+    // x: A[yl][QX] = sum_a B[kx][a] X[cy Q + yl][cx Q + a]
+#pragma unroll 1
+    for (int idx = tid; idx < n * NQ; idx += kThreads) {
+      const int QX = idx % NQ, yl = idx / NQ;
+      const int cx = QX >= n, kx = QX - cx * n;
+      const T* xr = X + (cy * Q + yl) * m + cx * Q;
+      T acc = 0;
+#pragma unroll
+      for (int a = 0; a < n; ++a) acc += Bt[kx * n + a] * xr[a];
+      A[idx] = acc;
+    }
+    __syncthreads();
+    // y: C[ky][QX] = sum_yl B[ky][yl] A[yl][QX]
+#pragma unroll 1
+    for (int idx = tid; idx < n * NQ; idx += kThreads) {
+      const int QX = idx % NQ, ky = idx / NQ;
+      T acc = 0;
+#pragma unroll
+      for (int a = 0; a < n; ++a) acc += Bt[ky * n + a] * A[a * NQ + QX];
+      C[idx] = acc;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int idx = tid; idx < n * NQ; idx += kThreads) {
+      const int QX = idx % NQ, ky = idx / NQ;
+      const int cx = QX >= n, kx = QX - cx * n;
+      T gx = 0, gy = 0;
+#pragma unroll
+      for (int a = 0; a < n; ++a) {
+        gx += Dc[kx * n + a] * C[ky * NQ + cx * n + a];
+        gy += Dc[ky * n + a] * C[a * NQ + QX];
+      }
+      T G[3];
+      if constexpr (CACHE) {
+        const int gp = cy * SH::S + idx;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) G[c] = Gc[c * 2 * SH::S + gp];
+      } else {
+        const int cell = cy * 2 + cx;
+        metric2c<T>(jc + cell * 8, xg[kx], xg[ky], mu[cell] * wg[kx] * wg[ky], G);
+      }
+      A[idx] = G[0] * gx + G[1] * gy;
+      Bf[idx] = G[1] * gx + G[2] * gy;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int idx = tid; idx < n * NQ; idx += kThreads) {
+      const int QX = idx % NQ, ky = idx / NQ;
+      const int cx = QX >= n, kx = QX - cx * n;
+      T acc = 0;
+#pragma unroll
+      for (int a = 0; a < n; ++a) {
+        acc += Dc[a * n + kx] * A[ky * NQ + cx * n + a];
+        acc += Dc[a * n + ky] * Bf[a * NQ + QX];
+      }
+      C[idx] = acc;
+    }
+    __syncthreads();
+    // y^T: A[yl][QX] = sum_ky B[ky][yl] C[ky][QX]
+#pragma unroll 1
+    for (int idx = tid; idx < n * NQ; idx += kThreads) {
+      const int QX = idx % NQ, yl = idx / NQ;
+      T acc = 0;
+#pragma unroll
+      for (int k = 0; k < n; ++k) acc += Bt[k * n + yl] * C[k * NQ + QX];
+      A[idx] = acc;
+    }
+    __syncthreads();
+    const int yl0 = cy == 0 ? 1 : 0;
+#pragma unroll 1
+    for (int idx = tid; idx < Q * mi; idx += kThreads) {
+      const int xi = idx % mi, yl = yl0 + idx / mi;
+      const int x = xi + 1;
+      const T* ar = A + yl * NQ;
+      T acc = 0;
+      if (x <= Q) {
+#pragma unroll
+        for (int k = 0; k < n; ++k) acc += Bt[k * n + x] * ar[k];
+      }
+      if (x >= Q) {
+#pragma unroll
+        for (int k = 0; k < n; ++k) acc += Bt[k * n + (x - Q)] * ar[n + k];
+      }
+      const int yy = cy * Q + yl - 1;
+      T* o = Out + yy * mi + xi;
+      if (cy == 1 && yl == 0)
+        *o += acc;
+      else
+        *o = acc;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, int DIM, class LV, int L>
+__device__ __forceinline__ void apply_level(const Ctx<T, DIM, LV>& c) {
+  constexpr int Q = LV::q[L];
+  constexpr bool CACHE = Layout<T, DIM, LV>::cache_G;
+  if constexpr (DIM == 3)
+    apply3<T, Q, CACHE>(c.X(), c.Out(), c.abuf(), c.tabB(L), c.tabDc(L), c.tabXg(L), c.tabWg(L),
+                        c.jc(), c.mu(), c.Gc(L));
+  else
+    apply2<T, Q, CACHE>(c.X(), c.Out(), c.abuf(), c.tabB(L), c.tabDc(L), c.tabXg(L), c.tabWg(L),
+                        c.jc(), c.mu(), c.Gc(L));
+}
+
+// Metric at every Gauss point of every level (when cached in LDS) and the
+// per-cell Jacobian coefficients; requires the geometry to be loaded.
+template <typename T, int DIM, class LV>
+__device__ void prepare_geometry(const Ctx<T, DIM, LV>& c) {
+  using Lay = Layout<T, DIM, LV>;
+  jacobian_coefficients<T, DIM>(c.geo(), c.jc());
+  __syncthreads();
+  if constexpr (Lay::cache_G) {
+    for (int l = 0; l < LV::count; ++l) {
+      const int n = LV::q[l] + 1, NQ = 2 * n;
+      const int NP = ipow(NQ, DIM);
+      const T* xg = c.tabXg(l);
+      const T* wg = c.tabWg(l);
+      T* Gl = c.Gc(l);
+      for (int pt = threadIdx.x; pt < NP; pt += kThreads) {
+        const int QX = pt % NQ, QY = (pt / NQ) % NQ, QZ = DIM == 3 ? pt / (NQ * NQ) : 0;
+        const int cx = QX >= n, cy = QY >= n, cz = QZ >= n;
+        const int kx = QX - cx * n, ky = QY - cy * n, kz = QZ - cz * n;
+        if constexpr (DIM == 3) {
+          const int cell = cz * 4 + cy * 2 + cx;
+          T G[6];
+          metric3c<T>(c.jc() + cell * 36, xg[kx], xg[ky], xg[kz],
+                      c.mu()[cell] * wg[kx] * wg[ky] * wg[kz], G);
+          for (int g = 0; g < 6; ++g) Gl[g * NP + pt] = G[g];
+        } else {
+          const int cell = cy * 2 + cx;
+          T G[3];
+          metric2c<T>(c.jc() + cell * 8, xg[kx], xg[ky], c.mu()[cell] * wg[kx] * wg[ky], G);
+          for (int g = 0; g < 3; ++g) Gl[g * NP + pt] = G[g];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// X <- closure layout of an interior vector (zero on the patch boundary)
+template <typename T, int DIM, int Q>
+__device__ __forceinline__ void load_closure(T* __restrict__ X, const T* __restrict__ v) {
+  using SH = Sh<DIM, Q>;
+  constexpr int m = SH::m, mi = SH::mi;
+#pragma unroll 1
+  for (int idx = threadIdx.x; idx < SH::closure; idx += kThreads) {
+    const int x = idx % m, t = idx / m, y = t % m;
+    const int zc = DIM == 3 ? t / m : 0;
+    bool in = x > 0 && x < m - 1 && y > 0 && y < m - 1;
+    if (DIM == 3) in = in && zc > 0 && zc < m - 1;
+    int ii = (y - 1) * mi + (x - 1);
+    if (DIM == 3) ii += (zc - 1) * mi * mi;
+    X[idx] = in ? v[ii] : T(0);
+  }
+  __syncthreads();
+}
+
+// Out = A_{j,q} v
+template <typename T, int DIM, class LV, int L>
+__device__ __forceinline__ void apply_vec(const Ctx<T, DIM, LV>& c, const T* v) {
+  load_closure<T, DIM, LV::q[L]>(c.X(), v);
+  apply_level<T, DIM, LV, L>(c);
+}
+
+// Chebyshev-accelerated Jacobi on A_{j,q} x = f over [theta - delta, theta + delta]
+// (Saad, Iterative Methods for Sparse Linear Systems, Algorithm 12.1, with
+// D^{-1} applied to the residuals).  Degree 1 on an interval with
+// theta = 2 is the paper's damped Jacobi step with omega = 1/2.
+template <typename T, int DIM, class LV, int L>
+__device__ __noinline__ void chebyshev(const Ctx<T, DIM, LV>& c, int k, bool x_zero) {
+  constexpr int N = Layout<T, DIM, LV>::level_size(L);
+  T* f = c.r(L);
+  T* x = c.d(L);
+  T* res = c.res();
+  T* z = c.z();
+  const T* dinv = c.dinv(L);
+  const T* Out = c.Out();
+  const T theta = c.cheb()[2 * L], delta = c.cheb()[2 * L + 1];
+  const T sigma = theta / delta;
+  T rho = T(1) / sigma;
+  const int tid = threadIdx.x;
+  if (x_zero) {
+    for (int i = tid; i < N; i += kThreads) {
+      res[i] = f[i];
+      z[i] = dinv[i] * f[i] / theta;
+      x[i] = 0;
+    }
+  } else {
+    apply_vec<T, DIM, LV, L>(c, x);
+    for (int i = tid; i < N; i += kThreads) {
+      const T ri = f[i] - Out[i];
+      res[i] = ri;
+      z[i] = dinv[i] * ri / theta;
+    }
+  }
+  __syncthreads();
+  for (int it = 0; it < k; ++it) {
+    for (int i = tid; i < N; i += kThreads) x[i] += z[i];
+    if (it == k - 1) break;
+    __syncthreads();
+    apply_vec<T, DIM, LV, L>(c, z);
+    const T rho_new = T(1) / (T(2) * sigma - rho);
+    const T c1 = rho_new * rho, c2 = T(2) * rho_new / delta;
+    for (int i = tid; i < N; i += kThreads) {
+      const T ri = res[i] - Out[i];
+      res[i] = ri;
+      z[i] = c1 * z[i] + c2 * dinv[i] * ri;
+    }
+    rho = rho_new;
+    __syncthreads();
+  }
+  __syncthreads();
+}
+
+// 1D contraction helpers for the Kronecker transfers.  P1: (mf x mc)
+// row-major (fine rows, coarse columns).
+
+// restriction: rc = (P1^T (x) ... (x) P1^T) rf
+template <typename T, int DIM, int QF, int QC>
+__device__ __noinline__ void restrict_vec(const T* __restrict__ rf, T* __restrict__ rc, const T* __restrict__ P1,
+                             T* __restrict__ ab) {
+  constexpr int mf = 2 * QF - 1, mc = 2 * QC - 1;
+  const int tid = threadIdx.x;
+  if constexpr (DIM == 3) {
+    T* t1 = ab;                       // [c][b][i]: mf*mf*mc
+    T* t2 = ab + mf * mf * mc;        // [c][j][i]: mf*mc*mc
+#pragma unroll 1
+    for (int idx = tid; idx < mf * mf * mc; idx += kThreads) {
+      const int i = idx % mc, cb = idx / mc;
+      T acc = 0;
+      for (int a = 0; a < mf; ++a) acc += P1[a * mc + i] * rf[cb * mf + a];
+      t1[idx] = acc;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int idx = tid; idx < mf * mc * mc; idx += kThreads) {
+      const int i = idx % mc, t = idx / mc, j = t % mc, cc = t / mc;
+      T acc = 0;
+      for (int b = 0; b < mf; ++b) acc += P1[b * mc + j] * t1[(cc * mf + b) * mc + i];
+      t2[idx] = acc;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int idx = tid; idx < mc * mc * mc; idx += kThreads) {
+      const int ji = idx % (mc * mc), k = idx / (mc * mc);
+      T acc = 0;
+      for (int cc = 0; cc < mf; ++cc) acc += P1[cc * mc + k] * t2[cc * mc * mc + ji];
+      rc[idx] = acc;
+    }
+  } else {
+    T* t1 = ab;  // [b][i]: mf*mc
+#pragma unroll 1
+    for (int idx = tid; idx < mf * mc; idx += kThreads) {
+      const int i = idx % mc, b = idx / mc;
+      T acc = 0;
+      for (int a = 0; a < mf; ++a) acc += P1[a * mc + i] * rf[b * mf + a];
+      t1[idx] = acc;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int idx = tid; idx < mc * mc; idx += kThreads) {
+      const int i = idx % mc, j = idx / mc;
+      T acc = 0;
+      for (int b = 0; b < mf; ++b) acc += P1[b * mc + j] * t1[b * mc + i];
+      rc[idx] = acc;
+    }
+  }
+  __syncthreads();
+}
+
+// prolongation and correction: df += (P1 (x) ... (x) P1) dc
+template <typename T, int DIM, int QF, int QC>
+__device__ __noinline__ void prolong_add(const T* __restrict__ dc, T* __restrict__ df, const T* __restrict__ P1,
+                            T* __restrict__ ab) {
+  constexpr int mf = 2 * QF - 1, mc = 2 * QC - 1;
+  const int tid = threadIdx.x;
+  if constexpr (DIM == 3) {
+    T* t1 = ab;                  // [k][j][a]: mc*mc*mf
+    T* t2 = ab + mc * mc * mf;   // [k][b][a]: mc*mf*mf
+#pragma unroll 1
+    for (int idx = tid; idx < mc * mc * mf; idx += kThreads) {
+      const int a = idx % mf, kj = idx / mf;
+      T acc = 0;
+      for (int i = 0; i < mc; ++i) acc += P1[a * mc + i] * dc[kj * mc + i];
+      t1[idx] = acc;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int idx = tid; idx < mc * mf * mf; idx += kThreads) {
+      const int a = idx % mf, t = idx / mf, b = t % mf, k = t / mf;
+      T acc = 0;
+      for (int j = 0; j < mc; ++j) acc += P1[b * mc + j] * t1[(k * mc + j) * mf + a];
+      t2[idx] = acc;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int idx = tid; idx < mf * mf * mf; idx += kThreads) {
+      const int ba = idx % (mf * mf), cc = idx / (mf * mf);
+      T acc = 0;
+      for (int k = 0; k < mc; ++k) acc += P1[cc * mc + k] * t2[k * mf * mf + ba];
+      df[idx] += acc;
+    }
+  } else {
+    T* t1 = ab;  // [j][a]: mc*mf
+#pragma unroll 1
+    for (int idx = tid; idx < mc * mf; idx += kThreads) {
+      const int a = idx % mf, j = idx / mf;
+      T acc = 0;
+      for (int i = 0; i < mc; ++i) acc += P1[a * mc + i] * dc[j * mc + i];
+      t1[idx] = acc;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int idx = tid; idx < mf * mf; idx += kThreads) {
+      const int a = idx % mf, b = idx / mf;
+      T acc = 0;
+      for (int j = 0; j < mc; ++j) acc += P1[b * mc + j] * t1[j * mf + a];
+      df[idx] += acc;
+    }
+  }
+  __syncthreads();
+}
+
+// V-cycle at level L (Algorithm 2): pre-smooth, residual, restrict, recurse,
+// prolongate and correct, post-smooth; the coarsest level is solved exactly.
+template <typename T, int DIM, class LV, int L>
+__device__ void vcycle(const Ctx<T, DIM, LV>& c, int k, bool d_zero) {
+  constexpr int N = Layout<T, DIM, LV>::level_size(L);
+  const int tid = threadIdx.x;
+  if constexpr (L == LV::count - 1) {
+    // coarsest level of an interior patch: a 1x1 matrix, inverse = 1 / diagonal
+    static_assert(N == 1, "coarsest interior level must have one node");
+    T* d = c.d(L);
+    const T* r = c.r(L);
+    const T* dinv = c.dinv(L);
+    if (tid == 0) d[0] = dinv[0] * r[0];
+    __syncthreads();
+  } else {
+    constexpr int QF = LV::q[L], QC = LV::q[L + 1];
+    chebyshev<T, DIM, LV, L>(c, k, d_zero);          // pre-smoothing
+    apply_vec<T, DIM, LV, L>(c, c.d(L));              // residual
+    T* res = c.res();
+    const T* f = c.r(L);
+    const T* Out = c.Out();
+    for (int i = tid; i < N; i += kThreads) res[i] = f[i] - Out[i];
+    __syncthreads();
+    restrict_vec<T, DIM, QF, QC>(res, c.r(L + 1), c.tabP(L), c.abuf());  // restriction
+    vcycle<T, DIM, LV, L + 1>(c, k, true);                               // recursion
+    prolong_add<T, DIM, QF, QC>(c.d(L + 1), c.d(L), c.tabP(L), c.abuf());  // correction
+    chebyshev<T, DIM, LV, L>(c, k, false);           // post-smoothing
+  }
+}
+
+// ---------------------------------------------------------------------------
+// the patch kernel
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__device__ __forceinline__ const T* tptr(const void* p) {
+  return reinterpret_cast<const T*>(p);
+}
+
+// Global node of closure offset s of the patch at vertex v (top degree p).
+template <int DIM>
+__device__ __forceinline__ void patch_base(int vlin, int N, int p, int& base, int& M) {
+  const int N1 = N + 1;
+  M = N * p + 1;
+  const int vx = vlin % N1, vy = (vlin / N1) % N1;
+  base = (vx - 1) * p + (vy - 1) * p * M;
+  if (DIM == 3) {
+    const int vz = vlin / (N1 * N1);
+    base += (vz - 1) * p * M * M;
+  }
+}
+
+template <typename T, int DIM, class LV>
+__device__ void load_patch(const Ctx<T, DIM, LV>& c, const PatchArgs& a, int patch) {
+  using Lay = Layout<T, DIM, LV>;
+  constexpr int L = LV::count;
+  const int tid = threadIdx.x;
+  // tables
+  const T* tab = tptr<T>(a.tab);
+  for (int l = 0; l < L; ++l) {
+    const int sz = tab_size(LV::q[l]);
+    for (int i = tid; i < sz; i += kThreads) c.lds[Lay::tab_level_off(l) + i] = tab[l * kTabLevelStride + i];
+  }
+  for (int t = 0; t + 1 < L; ++t) {
+    const int sz = (2 * LV::q[t] - 1) * (2 * LV::q[t + 1] - 1);
+    for (int i = tid; i < sz; i += kThreads)
+      c.lds[Lay::tab_transfer_off(t) + i] =
+          tab[kMaxLevels * kTabLevelStride + t * kTabTransferStride + i];
+  }
+  // geometry: 3^d vertices relative to the patch centre, 2^d coefficients
+  const int vlin = a.patch_vertex[patch];
+  const int N1 = a.N + 1;
+  const int vx = vlin % N1, vy = (vlin / N1) % N1, vz = DIM == 3 ? vlin / (N1 * N1) : 0;
+  for (int i = tid; i < Lay::nvert * DIM; i += kThreads) {
+    const int r = i % DIM, t = i / DIM;
+    const int tx = t % 3, ty = (t / 3) % 3, tz = DIM == 3 ? t / 9 : 0;
+    int g = (vx - 1 + tx) + (vy - 1 + ty) * N1;
+    if (DIM == 3) g += (vz - 1 + tz) * N1 * N1;
+    const double centre = a.verts[vlin * DIM + r];
+    c.geo()[i] = T(a.verts[g * DIM + r] - centre);
+  }
+  for (int i = tid; i < ipow(2, DIM); i += kThreads) {
+    const int cx = i & 1, cy = (i >> 1) & 1, cz = (i >> 2) & 1;
+    int g = (vx - 1 + cx) + (vy - 1 + cy) * a.N;
+    if (DIM == 3) g += (vz - 1 + cz) * a.N * a.N;
+    c.mu()[i] = T(a.mu[g]);
+  }
+  const T* cheb = tptr<T>(a.cheb);
+  for (int i = tid; i < 2 * (L - 1); i += kThreads) c.cheb()[i] = cheb[(int64_t)patch * 2 * (L - 1) + i];
+  for (int l = 0; l < L; ++l) {
+    const int sz = Lay::level_size(l);
+    const T* src = tptr<T>(a.invdiag[l]) + (int64_t)patch * sz;
+    T* dst = c.dinv(l);
+    for (int i = tid; i < sz; i += kThreads) dst[i] = src[i];
+  }
+  __syncthreads();
+}
+
+template <typename T, int DIM, class LV, int MODE>
+__global__ __launch_bounds__(kThreads) void patch_kernel(PatchArgs a) {
+  using Lay = Layout<T, DIM, LV>;
+  using S0 = Sh<DIM, LV::q[0]>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  Ctx<T, DIM, LV> c;
+  c.lds = reinterpret_cast<T*>(smem_raw);
+  c.vec = Lay::vec_in_lds ? c.lds + Lay::vec_off
+                          : reinterpret_cast<T*>(a.vec_scratch) + (int64_t)blockIdx.x * a.vec_stride;
+  const int patch = a.patch_begin + blockIdx.x;
+  const int tid = threadIdx.x;
+  load_patch<T, DIM, LV>(c, a, patch);
+  prepare_geometry<T, DIM, LV>(c);
+  constexpr int N0 = S0::interior;
+  constexpr int m = S0::m, mi = S0::mi;
+
+  if constexpr (MODE == kModeApply) {
+    // y = A_{j,q} x for the requested level
+    auto run = [&](auto Lc) {
+      constexpr int L = decltype(Lc)::value;
+      constexpr int NL = Lay::level_size(L);
+      T* v = c.z();
+      const double* in = a.in + (int64_t)patch * NL;
+      for (int i = tid; i < NL; i += kThreads) v[i] = T(in[i]);
+      __syncthreads();
+      apply_vec<T, DIM, LV, L>(c, v);
+      double* out = a.out + (int64_t)patch * NL;
+      for (int i = tid; i < NL; i += kThreads) out[i] = double(c.Out()[i]);
+    };
+    if (a.level == 0) run(std::integral_constant<int, 0>{});
+    if constexpr (LV::count > 1)
+      if (a.level == 1) run(std::integral_constant<int, 1>{});
+    if constexpr (LV::count > 2)
+      if (a.level == 2) run(std::integral_constant<int, 2>{});
+    if constexpr (LV::count > 3)
+      if (a.level == 3) run(std::integral_constant<int, 3>{});
+    return;
+  } else {
+    T* r0 = c.r(0);
+    int base = 0, M = 0;
+    if constexpr (MODE == kModeSmooth || MODE == kModeResidual) {
+      // gather u-bar_j (closure) and b_j (interior): equation gather
+      patch_base<DIM>(a.patch_vertex[patch], a.N, a.p, base, M);
+      T* X = c.X();
+  #pragma unroll 1
+    for (int idx = tid; idx < S0::closure; idx += kThreads) {
+        const int x = idx % m, t = idx / m, y = t % m, z = DIM == 3 ? t / m : 0;
+        X[idx] = T(a.u[base + x + y * M + (int64_t)z * M * M]);
+      }
+  #pragma unroll 1
+    for (int idx = tid; idx < N0; idx += kThreads) {
+        const int x = idx % mi + 1, t = idx / mi, y = t % mi + 1, z = DIM == 3 ? t / mi + 1 : 0;
+        r0[idx] = T(a.b[base + x + y * M + (int64_t)z * M * M]);
+      }
+      __syncthreads();
+      // evaluate: r_j = b_j - Pi_j A-bar_j u-bar_j (equation main:4)
+      apply_level<T, DIM, LV, 0>(c);
+      for (int i = tid; i < N0; i += kThreads) r0[i] -= c.Out()[i];
+      __syncthreads();
+      if constexpr (MODE == kModeResidual) {
+        double* out = a.out + (int64_t)patch * N0;
+        for (int i = tid; i < N0; i += kThreads) out[i] = double(r0[i]);
+        return;
+      }
+    } else {
+      const double* in = a.in + (int64_t)patch * N0;
+      for (int i = tid; i < N0; i += kThreads) r0[i] = T(in[i]);
+      __syncthreads();
+    }
+    // local solve: N_MG V-cycles from zero (equation main:5)
+    for (int it = 0; it < a.n_vcycles; ++it) vcycle<T, DIM, LV, 0>(c, a.cheb_degree, it == 0);
+    const T* d0 = c.d(0);
+    if constexpr (MODE == kModeSmooth) {
+      // scatter-add in FP64 (equation scatter); interiors of one colour are disjoint
+  #pragma unroll 1
+    for (int idx = tid; idx < N0; idx += kThreads) {
+        const int x = idx % mi + 1, t = idx / mi, y = t % mi + 1, z = DIM == 3 ? t / mi + 1 : 0;
+        a.u[base + x + y * M + (int64_t)z * M * M] += double(d0[idx]);
+      }
+    } else {
+      double* out = a.out + (int64_t)patch * N0;
+      for (int i = tid; i < N0; i += kThreads) out[i] = double(d0[i]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// setup: inverse diagonals of every level operator (FP64)
+//   diag_a = sum over cells and Gauss points of grad phi_a^T G grad phi_a
+// ---------------------------------------------------------------------------
+
+template <int DIM, class LV>
+__global__ __launch_bounds__(kThreads) void diag_kernel(PatchArgs a) {
+  using T = double;
+  using Lay = Layout<T, DIM, LV>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  Ctx<T, DIM, LV> c;
+  c.lds = reinterpret_cast<T*>(smem_raw);
+  c.vec = Lay::vec_in_lds ? c.lds + Lay::vec_off
+                          : reinterpret_cast<T*>(a.vec_scratch) + (int64_t)blockIdx.x * a.vec_stride;
+  const int patch = a.patch_begin + blockIdx.x;
+  const int tid = threadIdx.x;
+  // load tables and geometry only (the inverse diagonals are the output)
+  {
+    const T* tab = a.tab64;
+    for (int l = 0; l < LV::count; ++l) {
+      const int sz = tab_size(LV::q[l]);
+      for (int i = tid; i < sz; i += kThreads) c.lds[Lay::tab_level_off(l) + i] = tab[l * kTabLevelStride + i];
+    }
+    const int vlin = a.patch_vertex[patch];
+    const int N1 = a.N + 1;
+    const int vx = vlin % N1, vy = (vlin / N1) % N1, vz = DIM == 3 ? vlin / (N1 * N1) : 0;
+    for (int i = tid; i < Lay::nvert * DIM; i += kThreads) {
+      const int r = i % DIM, t = i / DIM;
+      const int tx = t % 3, ty = (t / 3) % 3, tz = DIM == 3 ? t / 9 : 0;
+      int g = (vx - 1 + tx) + (vy - 1 + ty) * N1;
+      if (DIM == 3) g += (vz - 1 + tz) * N1 * N1;
+      c.geo()[i] = a.verts[g * DIM + r] - a.verts[vlin * DIM + r];
+    }
+    for (int i = tid; i < ipow(2, DIM); i += kThreads) {
+      const int cx = i & 1, cy = (i >> 1) & 1, cz = (i >> 2) & 1;
+      int g = (vx - 1 + cx) + (vy - 1 + cy) * a.N;
+      if (DIM == 3) g += (vz - 1 + cz) * a.N * a.N;
+      c.mu()[i] = a.mu[g];
+    }
+    __syncthreads();
+  }
+  auto run = [&](auto Lc) {
+    constexpr int L = decltype(Lc)::value;
+    constexpr int Q = LV::q[L];
+    constexpr int n = Q + 1, m = 2 * Q + 1, mi = 2 * Q - 1;
+    constexpr int ncell = ipow(2, DIM), npt = ipow(n, DIM);
+    T* dg = c.X();      // closure diagonal
+    T* G = c.abuf();    // metric at the Gauss points of one cell
+    constexpr int NG = DIM == 3 ? 6 : 3;
+    const T* B = c.tabB(L);
+    const T* D = c.tabD(L);
+    const T* xg = c.tabXg(L);
+    const T* wg = c.tabWg(L);
+    for (int i = tid; i < ipow(m, DIM); i += kThreads) dg[i] = 0;
+    __syncthreads();
+    for (int cell = 0; cell < ncell; ++cell) {
+      const int cx = cell & 1, cy = (cell >> 1) & 1, cz = (cell >> 2) & 1;
+      for (int k = tid; k < npt; k += kThreads) {
+        const int kx = k % n, ky = (k / n) % n, kz = DIM == 3 ? k / (n * n) : 0;
+        if constexpr (DIM == 3)
+          metric3<T>(c.geo(), cx, cy, cz, xg[kx], xg[ky], xg[kz],
+                     c.mu()[cell] * wg[kx] * wg[ky] * wg[kz], G + NG * k);
+        else
+          metric2<T>(c.geo(), cx, cy, xg[kx], xg[ky], c.mu()[cell] * wg[kx] * wg[ky], G + NG * k);
+      }
+      __syncthreads();
+      for (int aidx = tid; aidx < npt; aidx += kThreads) {
+        const int ax = aidx % n, ay = (aidx / n) % n, az = DIM == 3 ? aidx / (n * n) : 0;
+        T acc = 0;
+        for (int k = 0; k < npt; ++k) {
+          const int kx = k % n, ky = (k / n) % n, kz = DIM == 3 ? k / (n * n) : 0;
+          const T* g = G + NG * k;
+          if constexpr (DIM == 3) {
+            const T bx = B[kx * n + ax], by = B[ky * n + ay], bz = B[kz * n + az];
+            const T g0 = D[kx * n + ax] * by * bz, g1 = bx * D[ky * n + ay] * bz,
+                    g2 = bx * by * D[kz * n + az];
+            acc += g[0] * g0 * g0 + g[3] * g1 * g1 + g[5] * g2 * g2 +
+                   T(2) * (g[1] * g0 * g1 + g[2] * g0 * g2 + g[4] * g1 * g2);
+          } else {
+            const T bx = B[kx * n + ax], by = B[ky * n + ay];
+            const T g0 = D[kx * n + ax] * by, g1 = bx * D[ky * n + ay];
+            acc += g[0] * g0 * g0 + g[2] * g1 * g1 + T(2) * g[1] * g0 * g1;
+          }
+        }
+        int s = (cx * Q + ax) + (cy * Q + ay) * m;
+        if (DIM == 3) s += (cz * Q + az) * m * m;
+        dg[s] += acc;
+      }
+      __syncthreads();
+    }
+    constexpr int NL = Lay::level_size(L);
+    double* out = const_cast<double*>(a.invdiag64[L]) + (int64_t)patch * NL;
+    for (int i = tid; i < NL; i += kThreads) {
+      const int x = i % mi + 1, t = i / mi, y = t % mi + 1, z = DIM == 3 ? t / mi + 1 : 0;
+      out[i] = 1.0 / dg[x + y * m + z * m * m];
+    }
+    __syncthreads();
+  };
+  run(std::integral_constant<int, 0>{});
+  if constexpr (LV::count > 1) run(std::integral_constant<int, 1>{});
+  if constexpr (LV::count > 2) run(std::integral_constant<int, 2>{});
+  if constexpr (LV::count > 3) run(std::integral_constant<int, 3>{});
+}
+
+// ---------------------------------------------------------------------------
+// setup: Lanczos on D^{-1/2} A_{j,q} D^{-1/2} (FP64), extreme Ritz values
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t n) {
+  // n-th output of the SplitMix64 stream seeded with `seed` (Steele, Lea and
+  // Flood, OOPSLA 2014): mix(seed + (n+1) * golden gamma)
+  uint64_t z = seed + (n + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ double block_sum(double v, double* red) {
+  // wavefront shuffle reduction, then across the waves of the block
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0;
+  for (int w = 0; w < kThreads / 64; ++w) s += red[w];
+  __syncthreads();
+  return s;
+}
+
+// number of eigenvalues of the symmetric tridiagonal (al, be) below x
+__device__ int sturm_count(const double* al, const double* be, int n, double x) {
+  int cnt = 0;
+  double q = al[0] - x;
+  if (q < 0) ++cnt;
+  for (int i = 1; i < n; ++i) {
+    if (q == 0) q = 1e-300;
+    q = al[i] - x - be[i - 1] * be[i - 1] / q;
+    if (q < 0) ++cnt;
+  }
+  return cnt;
+}
+
+__device__ double tridiag_eig(const double* al, const double* be, int n, int k) {
+  // k-th smallest eigenvalue by bisection inside the Gershgorin interval
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < n; ++i) {
+    double r = (i > 0 ? fabs(be[i - 1]) : 0.0) + (i < n - 1 ? fabs(be[i]) : 0.0);
+    lo = fmin(lo, al[i] - r);
+    hi = fmax(hi, al[i] + r);
+  }
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (sturm_count(al, be, n, mid) > k)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+template <int DIM, class LV, int L>
+__device__ void lanczos_level(Ctx<double, DIM, LV>& c, const PatchArgs& a, int patch) {
+  using T = double;
+  using Lay = Layout<T, DIM, LV>;
+  constexpr int NL = Lay::level_size(L);
+  const int tid = threadIdx.x;
+  const int m = min(a.lanczos_steps, NL);
+  double* Vb = a.lanczos_basis + (int64_t)blockIdx.x * (int64_t)a.lanczos_steps * NL;
+  T* w = c.res();
+  T* s = c.z();   // s = sqrt(dinv) * v, the operator input
+  __shared__ double red[kThreads / 64];
+  __shared__ double al[64], be[64], coef[64];
+  const T* dinv = c.dinv(L);
+  // start vector: entry i of patch vertex v at smoothed level L
+  const uint64_t vlin = (uint64_t)a.patch_vertex[patch];
+  const uint64_t base = ((vlin * 16u + (uint64_t)L) << 24);
+  double nrm = 0;
+  for (int i = tid; i < NL; i += kThreads) {
+    const double x = (double)(splitmix64(a.seed, base + (uint64_t)i) >> 11) * 0x1.0p-52 - 1.0;
+    Vb[i] = x;
+    nrm += x * x;
+  }
+  nrm = sqrt(block_sum(nrm, red));
+  for (int i = tid; i < NL; i += kThreads) Vb[i] /= nrm;
+  __syncthreads();
+  double b_prev = 0;
+  int steps = 0;
+  for (int j = 0; j < m; ++j) {
+    const double* v = Vb + (int64_t)j * NL;
+    for (int i = tid; i < NL; i += kThreads) s[i] = sqrt(dinv[i]) * v[i];
+    __syncthreads();
+    apply_vec<T, DIM, LV, L>(c, s);
+    double dot = 0;
+    for (int i = tid; i < NL; i += kThreads) {
+      double wi = sqrt(dinv[i]) * c.Out()[i];
+      if (j > 0) wi -= b_prev * Vb[(int64_t)(j - 1) * NL + i];
+      w[i] = wi;
+      dot += wi * v[i];
+    }
+    const double alpha = block_sum(dot, red);
+    for (int i = tid; i < NL; i += kThreads) w[i] -= alpha * v[i];
+    __syncthreads();
+    // full reorthogonalisation (classical Gram-Schmidt, twice)
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int q = 0; q <= j; ++q) {
+        const double* vq = Vb + (int64_t)q * NL;
+        double cq = 0;
+        for (int i = tid; i < NL; i += kThreads) cq += vq[i] * w[i];
+        cq = block_sum(cq, red);
+        if (tid == 0) coef[q] = cq;
+      }
+      __syncthreads();
+      for (int i = tid; i < NL; i += kThreads) {
+        double wi = w[i];
+        for (int q = 0; q <= j; ++q) wi -= coef[q] * Vb[(int64_t)q * NL + i];
+        w[i] = wi;
+      }
+      __syncthreads();
+    }
+    if (tid == 0) al[j] = alpha;
+    double bn = 0;
+    for (int i = tid; i < NL; i += kThreads) bn += w[i] * w[i];
+    bn = sqrt(block_sum(bn, red));
+    steps = j + 1;
+    if (j == m - 1 || bn < 1e-12 * fabs(alpha)) break;
+    if (tid == 0) be[j] = bn;
+    double* vn = Vb + (int64_t)(j + 1) * NL;
+    for (int i = tid; i < NL; i += kThreads) vn[i] = w[i] / bn;
+    b_prev = bn;
+    __syncthreads();
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double lo, hi;
+    if (steps == 1) {
+      lo = hi = al[0];
+    } else {
+      lo = tridiag_eig(al, be, steps, 0);
+      hi = tridiag_eig(al, be, steps, steps - 1);
+    }
+    double* o = a.bounds_out + ((int64_t)patch * (LV::count - 1) + L) * 2;
+    o[0] = lo;
+    o[1] = hi;
+  }
+  __syncthreads();
+}
+
+template <int DIM, class LV>
+__global__ __launch_bounds__(kThreads) void lanczos_kernel(PatchArgs a) {
+  using T = double;
+  using Lay = Layout<T, DIM, LV>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  Ctx<T, DIM, LV> c;
+  c.lds = reinterpret_cast<T*>(smem_raw);
+  c.vec = Lay::vec_in_lds ? c.lds + Lay::vec_off
+                          : reinterpret_cast<T*>(a.vec_scratch) + (int64_t)blockIdx.x * a.vec_stride;
+  const int patch = a.patch_begin + blockIdx.x;
+  {
+    // load_patch without the Chebyshev parameters
+    const int tid = threadIdx.x;
+    const T* tab = a.tab64;
+    for (int l = 0; l < LV::count; ++l) {
+      const int sz = tab_size(LV::q[l]);
+      for (int i = tid; i < sz; i += kThreads) c.lds[Lay::tab_level_off(l) + i] = tab[l * kTabLevelStride + i];
+    }
+    const int vlin = a.patch_vertex[patch];
+    const int N1 = a.N + 1;
+    const int vx = vlin % N1, vy = (vlin / N1) % N1, vz = DIM == 3 ? vlin / (N1 * N1) : 0;
+    for (int i = tid; i < Lay::nvert * DIM; i += kThreads) {
+      const int r = i % DIM, t = i / DIM;
+      const int tx = t % 3, ty = (t / 3) % 3, tz = DIM == 3 ? t / 9 : 0;
+      int g = (vx - 1 + tx) + (vy - 1 + ty) * N1;
+      if (DIM == 3) g += (vz - 1 + tz) * N1 * N1;
+      c.geo()[i] = a.verts[g * DIM + r] - a.verts[vlin * DIM + r];
+    }
+    for (int i = tid; i < ipow(2, DIM); i += kThreads) {
+      const int cx = i & 1, cy = (i >> 1) & 1, cz = (i >> 2) & 1;
+      int g = (vx - 1 + cx) + (vy - 1 + cy) * a.N;
+      if (DIM == 3) g += (vz - 1 + cz) * a.N * a.N;
+      c.mu()[i] = a.mu[g];
+    }
+    for (int l = 0; l < LV::count; ++l) {
+      const int sz = Lay::level_size(l);
+      const double* src = a.invdiag64[l] + (int64_t)patch * sz;
+      for (int i = tid; i < sz; i += kThreads) c.dinv(l)[i] = src[i];
+    }
+    __syncthreads();
+  }
+  prepare_geometry<T, DIM, LV>(c);
+  if (a.level == 0) lanczos_level<DIM, LV, 0>(c, a, patch);
+  if constexpr (LV::count > 2)
+    if (a.level == 1) lanczos_level<DIM, LV, 1>(c, a, patch);
+  if constexpr (LV::count > 3)
+    if (a.level == 2) lanczos_level<DIM, LV, 2>(c, a, patch);
+}
+
+// ---------------------------------------------------------------------------
+// launchers and registry
+// ---------------------------------------------------------------------------
+
+// Workgroups may use more than 64 KB of LDS on gfx950 (160 KB per CU); ask
+// for it explicitly before the first launch of a kernel that needs it.
+template <typename K>
+hipError_t allow_lds(K kernel, size_t bytes) {
+  if (bytes == 0) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) {
+    int dev = 0, lim = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    fprintf(stderr, "libpmg: cannot grant %zu bytes of LDS (device limit %d): %s\n", bytes, lim,
+            hipGetErrorString(e));
+  }
+  return e;
+}
+
+// On a failed launch, print what the runtime knows about the kernel.
+template <typename K>
+hipError_t report_launch(K kernel, const char* what, dim3 grid, size_t lds) {
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) return e;
+  hipFuncAttributes fa{};
+  hipError_t e2 = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kernel));
+  fprintf(stderr,
+          "libpmg: launch of %s failed: %s (grid %u, block %d, dynamic LDS %zu); attributes "
+          "(%s): maxThreads %d, static LDS %zu, max dynamic LDS %d, regs %d, local %zu\n",
+          what, hipGetErrorString(e), grid.x, kThreads, lds, hipGetErrorString(e2),
+          fa.maxThreadsPerBlock, fa.sharedSizeBytes, fa.maxDynamicSharedSizeBytes, fa.numRegs,
+          fa.localSizeBytes);
+  return e;
+}
+
+template <typename T, int DIM, class LV>
+struct Variant {
+  using Lay = Layout<T, DIM, LV>;
+  static size_t lds_bytes(int) { return (size_t)Lay::lds_elems * sizeof(T); }
+  static int64_t vec_elems() { return Lay::vec_in_lds ? 0 : (int64_t)Lay::vec_total; }
+  static hipError_t launch(int mode, const PatchArgs& a, hipStream_t s) {
+    if (a.n_patch <= 0) return hipSuccess;
+    const size_t lds = lds_bytes(mode);
+    dim3 grid(a.n_patch), block(kThreads);
+    hipError_t e = hipSuccess;
+    switch (mode) {
+      case kModeSmooth:
+        if ((e = allow_lds(patch_kernel<T, DIM, LV, kModeSmooth>, lds))) return e;
+        (void)hipGetLastError();  // clear a stale error of an earlier call
+        hipLaunchKernelGGL((patch_kernel<T, DIM, LV, kModeSmooth>), grid, block, lds, s, a);
+        return report_launch(patch_kernel<T, DIM, LV, kModeSmooth>, "patch", grid, lds);
+      case kModeResidual:
+        if ((e = allow_lds(patch_kernel<T, DIM, LV, kModeResidual>, lds))) return e;
+        (void)hipGetLastError();  // clear a stale error of an earlier call
+        hipLaunchKernelGGL((patch_kernel<T, DIM, LV, kModeResidual>), grid, block, lds, s, a);
+        return report_launch(patch_kernel<T, DIM, LV, kModeResidual>, "patch", grid, lds);
+      case kModeSolve:
+        if ((e = allow_lds(patch_kernel<T, DIM, LV, kModeSolve>, lds))) return e;
+        (void)hipGetLastError();  // clear a stale error of an earlier call
+        hipLaunchKernelGGL((patch_kernel<T, DIM, LV, kModeSolve>), grid, block, lds, s, a);
+        return report_launch(patch_kernel<T, DIM, LV, kModeSolve>, "patch", grid, lds);
+      case kModeApply:
+        if ((e = allow_lds(patch_kernel<T, DIM, LV, kModeApply>, lds))) return e;
+        (void)hipGetLastError();  // clear a stale error of an earlier call
+        hipLaunchKernelGGL((patch_kernel<T, DIM, LV, kModeApply>), grid, block, lds, s, a);
+        return report_launch(patch_kernel<T, DIM, LV, kModeApply>, "patch", grid, lds);
+      default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
+  static hipError_t launch_diag(const PatchArgs& a, hipStream_t s) {
+    using L64 = Layout<double, DIM, LV>;
+    if (a.n_patch <= 0) return hipSuccess;
+    const size_t lds = (size_t)L64::lds_elems * sizeof(double);
+    hipError_t e = allow_lds(diag_kernel<DIM, LV>, lds);
+    if (e != hipSuccess) return e;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL((diag_kernel<DIM, LV>), dim3(a.n_patch), dim3(kThreads), lds, s, a);
+    return report_launch(diag_kernel<DIM, LV>, "diag", dim3(a.n_patch), lds);
+  }
+  static hipError_t launch_lanczos(const PatchArgs& a, int level, hipStream_t s) {
+    using L64 = Layout<double, DIM, LV>;
+    if (a.n_patch <= 0) return hipSuccess;
+    PatchArgs b = a;
+    b.level = level;
+    const size_t lds = (size_t)L64::lds_elems * sizeof(double);
+    hipError_t e = allow_lds(lanczos_kernel<DIM, LV>, lds);
+    if (e != hipSuccess) return e;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL((lanczos_kernel<DIM, LV>), dim3(a.n_patch), dim3(kThreads), lds, s, b);
+    return report_launch(lanczos_kernel<DIM, LV>, "lanczos", dim3(a.n_patch), lds);
+  }
+};
+
+template <typename T, int DIM, int... Qs>
+PatchVariant make_variant() {
+  using LV = Levels<Qs...>;
+  using V = Variant<T, DIM, LV>;
+  PatchVariant v{};
+  v.precision = std::is_same<T, double>::value ? PMG_FP64 : PMG_FP32;
+  v.dim = DIM;
+  v.n_levels = LV::count;
+  const int q[] = {Qs...};
+  for (int i = 0; i < kMaxLevels; ++i) v.levels[i] = i < LV::count ? q[i] : 0;
+  v.launch = &V::launch;
+  v.lds_bytes = &V::lds_bytes;
+  v.vec_scratch_elems = &V::vec_elems;
+  v.vec_scratch_elems64 = &Variant<double, DIM, LV>::vec_elems;
+  // the FP64 setup kernels use the FP64 layout of the same level list
+  v.launch_diag = &Variant<double, DIM, LV>::launch_diag;
+  v.launch_lanczos = &Variant<double, DIM, LV>::launch_lanczos;
+  return v;
+}
+
+#define PMG_VARIANTS(T)                                                                        \
+  make_variant<T, 2, 2, 1>(), make_variant<T, 2, 3, 1>(), make_variant<T, 2, 3, 2, 1>(),       \
+      make_variant<T, 2, 4, 2, 1>(), make_variant<T, 2, 7, 3, 1>(), make_variant<T, 3, 2, 1>(), \
+      make_variant<T, 3, 3, 1>(), make_variant<T, 3, 3, 2, 1>(), make_variant<T, 3, 4, 2, 1>(), \
+      make_variant<T, 3, 6, 3, 1>(), make_variant<T, 3, 7, 3, 1>(), make_variant<T, 3, 8, 4, 2, 1>()
+
+const PatchVariant* registry(size_t* count) {
+  static const PatchVariant table[] = {PMG_VARIANTS(double), PMG_VARIANTS(float)};
+  *count = sizeof(table) / sizeof(table[0]);
+  return table;
+}
+
+}  // namespace
+
+const PatchVariant* find_variant(int precision, int dim, int n_levels, const int* levels) {
+  size_t n = 0;
+  const PatchVariant* t = registry(&n);
+  for (size_t i = 0; i < n; ++i) {
+    if (t[i].precision != precision || t[i].dim != dim || t[i].n_levels != n_levels) continue;
+    bool same = true;
+    for (int l = 0; l < n_levels; ++l) same = same && t[i].levels[l] == levels[l];
+    if (same) return &t[i];
+  }
+  return nullptr;
+}
+
+std::string list_variants() {
+  size_t n = 0;
+  const PatchVariant* t = registry(&n);
+  std::string s;
+  for (size_t i = 0; i < n; ++i) {
+    if (t[i].precision != PMG_FP64) continue;
+    s += std::to_string(t[i].dim) + "D:";
+    for (int l = 0; l < t[i].n_levels; ++l) s += (l ? "," : "") + std::to_string(t[i].levels[l]);
+    s += " ";
+  }
+  return s;
+}
+
+}  // namespace pmgi

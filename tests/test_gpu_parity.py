@@ -1,0 +1,147 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances: FP64 results agree with the oracle to 1e-11 relative (max-norm
+over all entries, relative to the largest reference entry); the quantities
+are linear maps of O(1) inputs evaluated with O(p^d) terms, so 1e-11 leaves
+three orders of margin over the rounding of either side.  FP32 results agree
+to 2e-5 relative for single operator applications and to 1e-4 for a full
+local solve (about 10 applications and Chebyshev updates, each with a
+relative rounding of 6e-8 amplified by the condition of the level operator).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import fem  # noqa: E402
+from oracle.smoother import patch_indices, patch_order  # noqa: E402
+
+from gpu_common import case, oracle_solver, rel_err, vlin  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # (workload, mesh cells, degree, levels)
+    ("2d-n8-q3", 8, 3, (3, 2, 1)),
+    ("3d-n16-q4", 4, 4, (4, 2, 1)),
+    ("3d-n32-q7-jump", 3, 7, (7, 3, 1)),
+    ("3d-n32-q6-learned", 3, 6, (6, 3, 1)),
+]
+TOL = {"fp64": 1e-11, "fp32": 2e-5}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def _setup(name, n, p, levels, precision):
+    from paper_2510_17785_amd import PatchSmoother
+    w, p, levels, X, mu, b = case(name, n, p, levels)
+    S = PatchSmoother(w.dim, w.n, p, X, mu, levels=levels, precision=precision)
+    mesh = fem.Mesh(w.dim, w.n, X, mu)
+    return w, p, levels, X, mu, b, S, mesh
+
+
+@pytest.mark.parametrize("name,n,p,levels", CASES)
+def test_patch_order_matches(dev, name, n, p, levels):
+    w, p, levels, X, mu, b, S, mesh = _setup(name, n, p, levels, "fp64")
+    ref = [vlin(v, w.n) for v in patch_order(w.dim, w.n)]
+    assert list(S.patch_vertices()) == ref
+    assert S.n_patches == (w.n - 1) ** w.dim
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("name,n,p,levels", CASES)
+def test_level_apply_and_diagonal(dev, name, n, p, levels, precision):
+    # matrix-free A_{j,q} x equals the assembled patch matrix times x
+    w, p, levels, X, mu, b, S, mesh = _setup(name, n, p, levels, precision)
+    order = patch_order(w.dim, w.n)
+    rng = np.random.default_rng(5)
+    k = 3 if p >= 6 else 8   # the oracle's dense patch matrices are slow at high degree
+    sample = list(rng.choice(S.n_patches, min(k, S.n_patches), replace=False))
+    for l, q in enumerate(levels):
+        x = rng.standard_normal((S.n_patches, S.level_sizes[l]))
+        y = S.apply(l, torch.tensor(x, device=dev)).cpu().numpy()
+        dg = S.inv_diag(l).cpu().numpy()
+        for j in sample:
+            A = fem.patch_matrix(mesh.patch(order[j]), q)
+            assert rel_err(y[j], A @ x[j]) <= TOL[precision], (l, j)
+            assert rel_err(dg[j], 1.0 / np.diag(A)) <= 1e-11, (l, j)
+
+
+@pytest.mark.parametrize("name,n,p,levels", CASES)
+def test_lanczos_bounds(dev, name, n, p, levels):
+    w, p, levels, X, mu, b, S, mesh = _setup(name, n, p, levels, "fp64")
+    order = patch_order(w.dim, w.n)
+    lam = S.bounds()
+    for j in range(min(S.n_patches, 3 if p >= 6 else 6)):
+        s = oracle_solver(mesh, order[j], levels)
+        for l in range(len(levels) - 1):
+            assert np.allclose(lam[j, l], s.bounds[l], rtol=1e-9, atol=0), (j, l, lam[j, l], s.bounds[l])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("name,n,p,levels", CASES)
+def test_residual_and_local_solve(dev, name, n, p, levels, precision):
+    w, p, levels, X, mu, b, S, mesh = _setup(name, n, p, levels, precision)
+    order = patch_order(w.dim, w.n)
+    rng = np.random.default_rng(7)
+    mask = fem.dirichlet_mask(w.dim, w.n, p)
+    u = rng.standard_normal(b.shape) * mask
+    r = S.residual(torch.tensor(u, device=dev), torch.tensor(b, device=dev)).cpu().numpy()
+    rr = rng.standard_normal((S.n_patches, S.level_sizes[0]))
+    d = S.local_solve(torch.tensor(rr, device=dev)).cpu().numpy()
+    tol_solve = 1e-10 if precision == "fp64" else 1e-4
+    for j in range(min(S.n_patches, 2 if p >= 6 else 6)):
+        v = order[j]
+        s = oracle_solver(mesh, v, levels)
+        clo, inn = patch_indices(v, p, w.n, w.dim)
+        Abar = fem.patch_closure_matrix(mesh.patch(v), p)
+        m = mesh.patch(v).interior_mask(p)
+        ref = b[inn] - (Abar @ u[clo])[m]
+        assert rel_err(r[j], ref) <= 50 * TOL[precision], j
+        assert rel_err(d[j], s.solve(rr[j])) <= tol_solve, j
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("name,n,p,levels", CASES[:2])
+def test_sweep(dev, name, n, p, levels, precision):
+    # one forward and one backward multiplicative sweep equal the oracle's
+    # sequential sweeps (Algorithm 1) in the same colour order
+    from oracle.smoother import PatchSmoother as OracleSmoother
+    w, p, levels, X, mu, b, S, mesh = _setup(name, n, p, levels, precision)
+    rng = np.random.default_rng(11)
+    u0 = rng.standard_normal(b.shape) * fem.dirichlet_mask(w.dim, w.n, p)
+    O = OracleSmoother(mesh, p, levels)
+    ref = O.sweep(O.sweep(u0, b, +1), b, -1)
+    ut = torch.tensor(u0, device=dev)
+    bt = torch.tensor(b, device=dev)
+    S.smooth(ut, bt, +1)
+    S.smooth(ut, bt, -1)
+    tol = 1e-11 if precision == "fp64" else 1e-4
+    assert rel_err(ut.cpu().numpy(), ref) <= tol
+
+
+@pytest.mark.parametrize("name,n", [("2d-n8-q3", 8), ("3d-n16-q4", 4), ("3d-n16-q4", 8)])
+def test_gmg_cg(dev, name, n):
+    # outer CG with the GMG preconditioner: equal iteration counts, solutions
+    # within 1e-10 relative (FP64)
+    from oracle import gmg as ogmg
+    from paper_2510_17785_amd import GMGSolver
+    w, p, levels, X, mu, b = case(name, n)
+    mesh = fem.Mesh(w.dim, w.n, X, mu)
+    G0 = ogmg.GMG(mesh, p, levels)
+    xo, ito, _ = G0.cg(b, rtol=w.rtol)
+    G = GMGSolver(w.dim, w.n, p, X, mu, levels=levels)
+    bt = torch.tensor(b, device=dev)
+    # the operator and one V-cycle first
+    xr = np.random.default_rng(3).standard_normal(b.shape) * fem.dirichlet_mask(w.dim, w.n, p)
+    assert rel_err(G.apply(torch.tensor(xr, device=dev)).cpu().numpy(), G0.A[-1] @ xr) <= 1e-12
+    assert rel_err(G.vcycle(bt).cpu().numpy(), G0.precondition(b)) <= 1e-10
+    x, it, rel = G.cg(bt, rtol=w.rtol)
+    assert it == ito
+    assert rel <= w.rtol
+    assert rel_err(x.cpu().numpy(), xo) <= 1e-10
