@@ -257,6 +257,16 @@ int patch_setup_impl(const pmg_mesh* mesh, const double* coeff, int p, const pmg
     return fail(PMG_ERR_UNSUPPORTED, "no kernel compiled for this level list (available: %s)",
                 list_variants().c_str());
   PMG_TRY(check_mesh(dim, N, mesh->vertices, p));
+  {
+    // the per-degree tables in constant memory, once per device
+    static int initialised_device = -1;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (initialised_device != dev) {
+      HIP_TRY(init_constant_tables());
+      initialised_device = dev;
+    }
+  }
 
   pmg_handle* h = new pmg_handle();
   h->dim = dim;

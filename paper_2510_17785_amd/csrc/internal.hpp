@@ -71,6 +71,8 @@ struct PatchVariant {
 };
 
 const PatchVariant* find_variant(int precision, int dim, int n_levels, const int* levels);
+// Fill the per-degree 1D tables in constant memory of the current device.
+hipError_t init_constant_tables();
 std::string list_variants();
 
 // Global (h-level) FP64 kernels.

@@ -27,7 +27,10 @@
 #include <cstring>
 #include <string>
 #include <type_traits>
+#include <vector>
+#include <algorithm>
 
+#include "fe_tables.hpp"
 #include "internal.hpp"
 
 namespace pmgi {
@@ -39,6 +42,38 @@ constexpr __host__ __device__ int ipow(int b, int e) {
   return r;
 }
 constexpr __host__ __device__ int round_up(int x, int a) { return (x + a - 1) / a * a; }
+
+// Address-space-qualified pointers: out-of-line device functions only get
+// ds_read/ds_write (not flat accesses) for LDS when the pointer type says so.
+#define LDSP __attribute__((address_space(3)))
+template <typename T>
+__device__ __forceinline__ LDSP T* lds_cast(T* p) {
+  return (LDSP T*)p;
+}
+template <typename T>
+__device__ __forceinline__ const LDSP T* lds_cast(const T* p) {
+  return (const LDSP T*)p;
+}
+
+// 1D tables of every degree 1..kMaxDegree, B (n x n), Dc (n x n), D (n x n),
+// Gauss points and weights, in constant memory: they depend on the degree
+// only, and reads at compile-time offsets become scalar loads.
+constexpr __host__ __device__ int ctab_size(int q) { return 3 * (q + 1) * (q + 1) + 2 * (q + 1); }
+constexpr __host__ __device__ int ctab_off(int q) {
+  int o = 0;
+  for (int r = 1; r < q; ++r) o += ctab_size(r);
+  return o;
+}
+constexpr int kConstTab = ctab_off(kMaxDegree + 1);
+__constant__ float c_tab32[kConstTab];
+__constant__ double c_tab64[kConstTab];
+template <typename T>
+__device__ __forceinline__ const T* ctab() {
+  if constexpr (std::is_same<T, double>::value)
+    return c_tab64;
+  else
+    return c_tab32;
+}
 
 template <int... Qs>
 struct Levels {
@@ -84,7 +119,15 @@ struct Layout {
   static constexpr int X_off = round_up(geo_off + geo_size, 4);
   static constexpr int Out_off = round_up(X_off + S0::closure, 4);
   static constexpr int abuf_off = round_up(Out_off + S0::interior, 4);
-  static constexpr int base_total = round_up(abuf_off + 4 * S0::S, 4);
+  // 3D levels use the segment-form operator when its four Gauss-point
+  // buffers fit 40 KB at the top degree (else the two-slab form)
+  static constexpr int P0 = ipow(2 * (LV::q[0] + 1), DIM);
+  static constexpr bool seg_top = DIM == 3 && 4 * P0 * (int)sizeof(T) <= 40 * 1024;
+  static constexpr int abuf_elems = seg_top ? 4 * P0 : 4 * S0::S;
+  static constexpr bool use_seg(int l) {
+    return DIM == 3 && 4 * ipow(2 * (LV::q[l] + 1), DIM) <= abuf_elems;
+  }
+  static constexpr int base_total = round_up(abuf_off + abuf_elems, 4);
   static constexpr int level_size(int l) { return ipow(2 * LV::q[l] - 1, DIM); }
   // vectors: r_l, d_l, dinv_l per level, then res and z at the top size
   static constexpr int vec_r(int l) {
@@ -183,14 +226,14 @@ __device__ __forceinline__ void metric2(const T* __restrict__ V, int cx, int cy,
 // component).  These coefficients are formed once per patch (jc, per cell:
 // [column][component][4] in 3D, [column][component][2] in 2D), so the metric
 // costs about 60 instructions per Gauss point.
-template <typename T>
-__device__ __forceinline__ void metric3c(const T* __restrict__ jc, T x, T y, T z, T scale, T* G) {
+template <typename T, typename PJ>
+__device__ __forceinline__ void metric3c(PJ jc, T x, T y, T z, T scale, T* G) {
   T J[3][3];
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
-    const T* c0 = jc + (0 * 3 + r) * 4;
-    const T* c1 = jc + (1 * 3 + r) * 4;
-    const T* c2 = jc + (2 * 3 + r) * 4;
+    const auto c0 = jc + (0 * 3 + r) * 4;
+    const auto c1 = jc + (1 * 3 + r) * 4;
+    const auto c2 = jc + (2 * 3 + r) * 4;
     J[r][0] = c0[0] + c0[1] * y + z * (c0[2] + c0[3] * y);
     J[r][1] = c1[0] + c1[1] * x + z * (c1[2] + c1[3] * x);
     J[r][2] = c2[0] + c2[1] * x + y * (c2[2] + c2[3] * x);
@@ -215,13 +258,13 @@ __device__ __forceinline__ void metric3c(const T* __restrict__ jc, T x, T y, T z
   G[5] = s * (a[2][0] * a[2][0] + a[2][1] * a[2][1] + a[2][2] * a[2][2]);
 }
 
-template <typename T>
-__device__ __forceinline__ void metric2c(const T* __restrict__ jc, T x, T y, T scale, T* G) {
+template <typename T, typename PJ>
+__device__ __forceinline__ void metric2c(PJ jc, T x, T y, T scale, T* G) {
   T J[2][2];
 #pragma unroll
   for (int r = 0; r < 2; ++r) {
-    const T* c0 = jc + (0 * 2 + r) * 2;
-    const T* c1 = jc + (1 * 2 + r) * 2;
+    const auto c0 = jc + (0 * 2 + r) * 2;
+    const auto c1 = jc + (1 * 2 + r) * 2;
     J[r][0] = c0[0] + c0[1] * y;
     J[r][1] = c1[0] + c1[1] * x;
   }
@@ -282,7 +325,13 @@ template <typename T, int DIM, class LV>
 struct Ctx {
   using Lay = Layout<T, DIM, LV>;
   T* lds;
-  T* vec;  // vector storage (LDS or global scratch)
+  T* vec;          // vector storage (LDS or global scratch)
+  const T* gtab;   // the same 1D tables in global memory (read with scalar loads)
+  __device__ const T* gB(int l) const { return gtab + l * kTabLevelStride; }
+  __device__ const T* gDc(int l) const {
+    const int n = LV::q[l] + 1;
+    return gtab + l * kTabLevelStride + n * n;
+  }
   __device__ const T* tabB(int l) const { return lds + Lay::tab_level_off(l); }
   __device__ const T* tabDc(int l) const {
     const int n = LV::q[l] + 1;
@@ -480,6 +529,285 @@ __device__ __noinline__ void apply3(const T* __restrict__ X, T* __restrict__ Out
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// 3D level operator in segment form
+//
+// Every contraction phase works on line segments: a work item reads the n =
+// q+1 values of one cell segment of a line, multiplies them by the n x n 1D
+// matrix (uniform across the wavefront, so it sits in scalar registers) and
+// writes n values.  Intermediate results use a cell-local layout per
+// direction (index c n + a for local node a of cell c), in which the node
+// shared by the two cells of a line appears twice; the transposed
+// contractions therefore never add into a shared node, and the duplicates
+// are summed once in the final assembly of the interior rows.  An input with
+// a zero patch boundary (a level vector) is read in interior layout directly.
+// ---------------------------------------------------------------------------
+
+template <typename T, int Q>
+struct Seg3 {
+  static constexpr int n = Q + 1, m = 2 * Q + 1, mi = 2 * Q - 1, NQ = 2 * n;
+  static constexpr int P = NQ * NQ * NQ;  // one buffer
+  static constexpr int NB = 2 * n - 2;    // cell-local indices of interior nodes
+};
+
+// Epilogues: what to do with row i of A x (fused into the last phase).
+// PT is the pointer type of the vectors: LDS-qualified when they live in LDS.
+template <typename T, class PT>
+struct EpiStore {  // out = A x
+  PT out;
+  __device__ __forceinline__ void operator()(int i, T v) const { out[i] = v; }
+};
+template <typename T, class PT>
+struct EpiResidual {  // res = f - A x
+  PT f, res;
+  __device__ __forceinline__ void operator()(int i, T v) const { res[i] = f[i] - v; }
+};
+template <typename T, class PT>
+struct EpiChebStart {  // res = f - A x, z = D^{-1} res / theta
+  PT f, res, z, dinv;
+  T inv_theta;
+  __device__ __forceinline__ void operator()(int i, T v) const {
+    const T r = f[i] - v;
+    res[i] = r;
+    z[i] = dinv[i] * r * inv_theta;
+  }
+};
+template <typename T, class PT>
+struct EpiChebStep {  // x += z, res -= A z, z = c1 z + c2 D^{-1} res
+  PT x, res, z, dinv;
+  T c1, c2;
+  __device__ __forceinline__ void operator()(int i, T v) const {
+    const T zi = z[i];
+    x[i] += zi;
+    const T r = res[i] - v;
+    res[i] = r;
+    z[i] = c1 * zi + c2 * dinv[i] * r;
+  }
+};
+
+template <typename T, int Q, bool CLOSURE_IN, bool CACHE, class Epi>
+__device__ __noinline__ void apply3seg(const LDSP T* __restrict__ in, Epi epi,
+                                       LDSP T* __restrict__ ab, const LDSP T* __restrict__ Dcl,
+                                       const LDSP T* __restrict__ jc, const LDSP T* __restrict__ mu,
+                                       const LDSP T* __restrict__ Gc) {
+  using SG = Seg3<T, Q>;
+  constexpr int n = SG::n, m = SG::m, mi = SG::mi, NQ = SG::NQ, P = SG::P;
+  const T* gB = ctab<T>() + ctab_off(Q);
+  const T* gDc = gB + n * n;
+  const T* xg = gB + 3 * n * n;
+  const T* wg = xg + n;
+  constexpr int R0 = CLOSURE_IN ? 0 : 1;   // first node row held by the input
+  constexpr int NR = CLOSURE_IN ? m : mi;  // node rows held per direction
+  constexpr int NQ2 = NQ * NQ;
+  LDSP T* A = ab;
+  LDSP T* Bb = ab + P;
+  LDSP T* C = ab + 2 * P;
+  LDSP T* D = ab + 3 * P;
+  const int tid = threadIdx.x;
+
+  // 1. x: A[zr][yr][QX] = sum_a B[k][a] in[zr][yr][cx q + a]
+#pragma unroll 1
+  for (int it = tid; it < 2 * NR * NR; it += kThreads) {
+    const int line = it % (NR * NR), cx = it / (NR * NR);
+    const LDSP T* src = in + line * NR;
+    T v[n];
+#pragma unroll
+    for (int a = 0; a < n; ++a) {
+      const int x = cx * Q + a;
+      v[a] = (CLOSURE_IN || (x >= 1 && x <= m - 2)) ? src[x - R0] : T(0);
+    }
+    LDSP T* dst = A + line * NQ + cx * n;
+#pragma unroll
+    for (int k = 0; k < n; ++k) {
+      T acc = 0;
+#pragma unroll
+      for (int a = 0; a < n; ++a) acc += gB[k * n + a] * v[a];
+      dst[k] = acc;
+    }
+  }
+  __syncthreads();
+  // 2. y: Bb[zr][QY][QX] = sum_a B[k][a] A[zr][cy q + a][QX]
+#pragma unroll 1
+  for (int it = tid; it < 2 * NR * NQ; it += kThreads) {
+    const int QX = it % NQ, r = it / NQ, zr = r % NR, cy = r / NR;
+    T v[n];
+#pragma unroll
+    for (int a = 0; a < n; ++a) {
+      const int y = cy * Q + a;
+      v[a] = (CLOSURE_IN || (y >= 1 && y <= m - 2)) ? A[(zr * NR + (y - R0)) * NQ + QX] : T(0);
+    }
+    LDSP T* dst = Bb + (zr * NQ + cy * n) * NQ + QX;
+#pragma unroll
+    for (int k = 0; k < n; ++k) {
+      T acc = 0;
+#pragma unroll
+      for (int a = 0; a < n; ++a) acc += gB[k * n + a] * v[a];
+      dst[k * NQ] = acc;
+    }
+  }
+  __syncthreads();
+  // 3. z: C[QZ][QY][QX] = sum_a B[k][a] Bb[cz q + a][QY][QX]   (values at Gauss points)
+#pragma unroll 1
+  for (int it = tid; it < 2 * NQ2; it += kThreads) {
+    const int col = it % NQ2, cz = it / NQ2;
+    T v[n];
+#pragma unroll
+    for (int a = 0; a < n; ++a) {
+      const int z = cz * Q + a;
+      v[a] = (CLOSURE_IN || (z >= 1 && z <= m - 2)) ? Bb[(z - R0) * NQ2 + col] : T(0);
+    }
+    LDSP T* dst = C + cz * n * NQ2 + col;
+#pragma unroll
+    for (int k = 0; k < n; ++k) {
+      T acc = 0;
+#pragma unroll
+      for (int a = 0; a < n; ++a) acc += gB[k * n + a] * v[a];
+      dst[k * NQ2] = acc;
+    }
+  }
+  __syncthreads();
+  // 4. reference gradients by collocation and the flux G grad; a thread owns
+  //    one local Gauss point (kx, ky, kz) of the four cells of layer cz
+  constexpr int n3 = n * n * n;
+#pragma unroll 1
+  for (int t = tid; t < 2 * n3; t += kThreads) {
+    const int k3 = t % n3, cz = t / n3;
+    const int kx = k3 % n, ky = (k3 / n) % n, kz = k3 / (n * n);
+    T dx[n], dy[n], dz[n];
+#pragma unroll
+    for (int a = 0; a < n; ++a) {
+      dx[a] = Dcl[kx * n + a];
+      dy[a] = Dcl[ky * n + a];
+      dz[a] = Dcl[kz * n + a];
+    }
+    const int QZ = cz * n + kz;
+#pragma unroll 2
+    for (int cc = 0; cc < 4; ++cc) {
+      const int cx = cc & 1, cy = cc >> 1;
+      const int QY = cy * n + ky, QX = cx * n + kx;
+      const int pt = (QZ * NQ + QY) * NQ + QX;
+      const LDSP T* rx = C + (QZ * NQ + QY) * NQ + cx * n;
+      const LDSP T* ry = C + (QZ * NQ + cy * n) * NQ + QX;
+      const LDSP T* rz = C + (cz * n * NQ + QY) * NQ + QX;
+      T gx = 0, gy = 0, gz = 0;
+#pragma unroll
+      for (int a = 0; a < n; ++a) {
+        gx += dx[a] * rx[a];
+        gy += dy[a] * ry[a * NQ];
+        gz += dz[a] * rz[a * NQ2];
+      }
+      T G[6];
+      if constexpr (CACHE) {
+#pragma unroll
+        for (int g = 0; g < 6; ++g) G[g] = Gc[g * P + pt];
+      } else {
+        const int cell = cz * 4 + cy * 2 + cx;
+        metric3c<T>(jc + cell * 36, xg[kx], xg[ky], xg[kz], mu[cell] * wg[kx] * wg[ky] * wg[kz], G);
+      }
+      A[pt] = G[0] * gx + G[1] * gy + G[2] * gz;
+      Bb[pt] = G[1] * gx + G[3] * gy + G[4] * gz;
+      D[pt] = G[2] * gx + G[4] * gy + G[5] * gz;
+    }
+  }
+  __syncthreads();
+  // 5. transposed collocation W = Dc^T F along one full Gauss-point column
+  //    (both cells), then z^T onto the interior z nodes, summing the two
+  //    cells at the shared node: C[zi][QY][QX], zi = z - 1
+#pragma unroll 1
+  for (int col = tid; col < NQ2; col += kThreads) {
+    const int QX = col % NQ, QY = col / NQ;
+    const int cx = QX >= n, kx = QX - cx * n, cy = QY >= n, ky = QY - cy * n;
+    T ex[n], ey[n];
+#pragma unroll
+    for (int a = 0; a < n; ++a) {
+      ex[a] = Dcl[a * n + kx];
+      ey[a] = Dcl[a * n + ky];
+    }
+    T acc_z[mi];
+#pragma unroll
+    for (int zi = 0; zi < mi; ++zi) acc_z[zi] = 0;
+#pragma unroll
+    for (int cz = 0; cz < 2; ++cz) {
+      T f2[n];
+#pragma unroll
+      for (int a = 0; a < n; ++a) f2[a] = D[(cz * n + a) * NQ2 + col];
+      T w[n];
+#pragma unroll
+      for (int k = 0; k < n; ++k) {
+        const int QZ = cz * n + k;
+        const LDSP T* fx = A + (QZ * NQ + QY) * NQ + cx * n;
+        const LDSP T* fy = Bb + (QZ * NQ + cy * n) * NQ + QX;
+        T acc = 0;
+#pragma unroll
+        for (int a = 0; a < n; ++a) acc += ex[a] * fx[a] + ey[a] * fy[a * NQ] + gDc[a * n + k] * f2[a];
+        w[k] = acc;
+      }
+      // z^T of this cell: node z = cz q + a, interior when 1 <= z <= m - 2
+#pragma unroll
+      for (int a = 0; a < n; ++a) {
+        const int zi = cz * Q + a - 1;
+        if (zi < 0 || zi >= mi) continue;
+        T acc = 0;
+#pragma unroll
+        for (int k = 0; k < n; ++k) acc += gB[k * n + a] * w[k];
+        acc_z[zi] += acc;
+      }
+    }
+#pragma unroll
+    for (int zi = 0; zi < mi; ++zi) C[zi * NQ2 + col] = acc_z[zi];
+  }
+  __syncthreads();
+  // 6. y^T onto interior y nodes (both cells of a line): A[zi][yi][QX]
+#pragma unroll 1
+  for (int it = tid; it < mi * NQ; it += kThreads) {
+    const int QX = it % NQ, zi = it / NQ;
+    const LDSP T* src = C + zi * NQ2 + QX;
+    T v[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) v[k] = src[k * NQ];
+#pragma unroll
+    for (int yi = 0; yi < mi; ++yi) {
+      const int y = yi + 1;
+      T acc = 0;
+      if (y <= Q) {
+#pragma unroll
+        for (int k = 0; k < n; ++k) acc += gB[k * n + y] * v[k];
+      }
+      if (y >= Q) {
+#pragma unroll
+        for (int k = 0; k < n; ++k) acc += gB[k * n + (y - Q)] * v[n + k];
+      }
+      A[(zi * mi + yi) * NQ + QX] = acc;
+    }
+  }
+  __syncthreads();
+  // 7. x^T onto interior x nodes: the interior rows, handed to the epilogue
+  //    with their interior index (the caller's vector update is fused here)
+#pragma unroll 1
+  for (int line = tid; line < mi * mi; line += kThreads) {
+    const LDSP T* src = A + line * NQ;
+    T v[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) v[k] = src[k];
+#pragma unroll
+    for (int xi = 0; xi < mi; ++xi) {
+      const int x = xi + 1;
+      T acc = 0;
+      if (x <= Q) {
+#pragma unroll
+        for (int k = 0; k < n; ++k) acc += gB[k * n + x] * v[k];
+      }
+      if (x >= Q) {
+#pragma unroll
+        for (int k = 0; k < n; ++k) acc += gB[k * n + (x - Q)] * v[n + k];
+      }
+      epi(line * mi + xi, acc);
+    }
+  }
+  __syncthreads();
+}
+
 template <typename T, int Q, bool CACHE>
 __device__ __noinline__ void apply2(const T* __restrict__ X, T* __restrict__ Out, T* __restrict__ ab,
                        const T* __restrict__ Bt, const T* __restrict__ Dc, const T* __restrict__ xg,
@@ -591,7 +919,11 @@ template <typename T, int DIM, class LV, int L>
 __device__ __forceinline__ void apply_level(const Ctx<T, DIM, LV>& c) {
   constexpr int Q = LV::q[L];
   constexpr bool CACHE = Layout<T, DIM, LV>::cache_G;
-  if constexpr (DIM == 3)
+  if constexpr (Layout<T, DIM, LV>::use_seg(L))
+    apply3seg<T, Q, true, CACHE>(lds_cast(c.X()), EpiStore<T, LDSP T*>{lds_cast(c.Out())},
+                                 lds_cast(c.abuf()), lds_cast(c.tabDc(L)), lds_cast(c.jc()),
+                                 lds_cast(c.mu()), lds_cast(c.Gc(L)));
+  else if constexpr (DIM == 3)
     apply3<T, Q, CACHE>(c.X(), c.Out(), c.abuf(), c.tabB(L), c.tabDc(L), c.tabXg(L), c.tabWg(L),
                         c.jc(), c.mu(), c.Gc(L));
   else
@@ -654,10 +986,36 @@ __device__ __forceinline__ void load_closure(T* __restrict__ X, const T* __restr
 }
 
 // Out = A_{j,q} v
+// Vector pointer type of a layout: LDS-qualified when the vectors live in LDS.
+template <typename T, int DIM, class LV>
+using VecPtr = typename std::conditional<Layout<T, DIM, LV>::vec_in_lds, LDSP T*, T*>::type;
+template <typename T, int DIM, class LV>
+__device__ __forceinline__ VecPtr<T, DIM, LV> vp(T* p) {
+  return (VecPtr<T, DIM, LV>)p;
+}
+
+// epi(i, (A_{j,q} v)_i) for every interior row i; v has a zero patch boundary
+template <typename T, int DIM, class LV, int L, class Epi>
+__device__ __forceinline__ void apply_vec_epi(const Ctx<T, DIM, LV>& c, const T* v, Epi epi) {
+  constexpr int Q = LV::q[L];
+  using Lay = Layout<T, DIM, LV>;
+  if constexpr (Lay::use_seg(L) && Lay::vec_in_lds) {
+    apply3seg<T, Q, false, Lay::cache_G>(lds_cast(v), epi, lds_cast(c.abuf()), lds_cast(c.tabDc(L)),
+                                         lds_cast(c.jc()), lds_cast(c.mu()), lds_cast(c.Gc(L)));
+  } else {
+    load_closure<T, DIM, Q>(c.X(), v);
+    apply_level<T, DIM, LV, L>(c);
+    constexpr int N = Lay::level_size(L);
+#pragma unroll 1
+    for (int i = threadIdx.x; i < N; i += kThreads) epi(i, c.Out()[i]);
+    __syncthreads();
+  }
+}
+
+// Out = A_{j,q} v
 template <typename T, int DIM, class LV, int L>
 __device__ __forceinline__ void apply_vec(const Ctx<T, DIM, LV>& c, const T* v) {
-  load_closure<T, DIM, LV::q[L]>(c.X(), v);
-  apply_level<T, DIM, LV, L>(c);
+  apply_vec_epi<T, DIM, LV, L>(c, v, EpiStore<T, VecPtr<T, DIM, LV>>{vp<T, DIM, LV>(c.Out())});
 }
 
 // Chebyshev-accelerated Jacobi on A_{j,q} x = f over [theta - delta, theta + delta]
@@ -665,48 +1023,40 @@ __device__ __forceinline__ void apply_vec(const Ctx<T, DIM, LV>& c, const T* v) 
 // D^{-1} applied to the residuals).  Degree 1 on an interval with
 // theta = 2 is the paper's damped Jacobi step with omega = 1/2.
 template <typename T, int DIM, class LV, int L>
-__device__ __noinline__ void chebyshev(const Ctx<T, DIM, LV>& c, int k, bool x_zero) {
+__device__ __forceinline__ void chebyshev(const Ctx<T, DIM, LV>& c, int k, bool x_zero) {
   constexpr int N = Layout<T, DIM, LV>::level_size(L);
-  T* f = c.r(L);
-  T* x = c.d(L);
-  T* res = c.res();
-  T* z = c.z();
-  const T* dinv = c.dinv(L);
-  const T* Out = c.Out();
+  using PT = VecPtr<T, DIM, LV>;
+  PT f = vp<T, DIM, LV>(c.r(L));
+  PT x = vp<T, DIM, LV>(c.d(L));
+  PT res = vp<T, DIM, LV>(c.res());
+  PT z = vp<T, DIM, LV>(c.z());
+  PT dinv = vp<T, DIM, LV>(c.dinv(L));
   const T theta = c.cheb()[2 * L], delta = c.cheb()[2 * L + 1];
   const T sigma = theta / delta;
   T rho = T(1) / sigma;
   const int tid = threadIdx.x;
   if (x_zero) {
+    // r_0 = f, z_0 = D^{-1} f / theta, x = 0
+#pragma unroll 1
     for (int i = tid; i < N; i += kThreads) {
       res[i] = f[i];
       z[i] = dinv[i] * f[i] / theta;
       x[i] = 0;
     }
+    __syncthreads();
   } else {
-    apply_vec<T, DIM, LV, L>(c, x);
-    for (int i = tid; i < N; i += kThreads) {
-      const T ri = f[i] - Out[i];
-      res[i] = ri;
-      z[i] = dinv[i] * ri / theta;
-    }
+    // r_0 = f - A x, z_0 = D^{-1} r_0 / theta
+    apply_vec_epi<T, DIM, LV, L>(c, c.d(L), EpiChebStart<T, PT>{f, res, z, dinv, T(1) / theta});
   }
-  __syncthreads();
-  for (int it = 0; it < k; ++it) {
-    for (int i = tid; i < N; i += kThreads) x[i] += z[i];
-    if (it == k - 1) break;
-    __syncthreads();
-    apply_vec<T, DIM, LV, L>(c, z);
+  for (int it = 0; it + 1 < k; ++it) {
+    // x += z_i, r_{i+1} = r_i - A z_i, z_{i+1} = c1 z_i + c2 D^{-1} r_{i+1}
     const T rho_new = T(1) / (T(2) * sigma - rho);
-    const T c1 = rho_new * rho, c2 = T(2) * rho_new / delta;
-    for (int i = tid; i < N; i += kThreads) {
-      const T ri = res[i] - Out[i];
-      res[i] = ri;
-      z[i] = c1 * z[i] + c2 * dinv[i] * ri;
-    }
+    apply_vec_epi<T, DIM, LV, L>(c, c.z(),
+                                 EpiChebStep<T, PT>{x, res, z, dinv, rho_new * rho, T(2) * rho_new / delta});
     rho = rho_new;
-    __syncthreads();
   }
+#pragma unroll 1
+  for (int i = tid; i < N; i += kThreads) x[i] += z[i];
   __syncthreads();
 }
 
@@ -715,7 +1065,7 @@ __device__ __noinline__ void chebyshev(const Ctx<T, DIM, LV>& c, int k, bool x_z
 
 // restriction: rc = (P1^T (x) ... (x) P1^T) rf
 template <typename T, int DIM, int QF, int QC>
-__device__ __noinline__ void restrict_vec(const T* __restrict__ rf, T* __restrict__ rc, const T* __restrict__ P1,
+__device__ __forceinline__ void restrict_vec(const T* __restrict__ rf, T* __restrict__ rc, const T* __restrict__ P1,
                              T* __restrict__ ab) {
   constexpr int mf = 2 * QF - 1, mc = 2 * QC - 1;
   const int tid = threadIdx.x;
@@ -768,7 +1118,7 @@ __device__ __noinline__ void restrict_vec(const T* __restrict__ rf, T* __restric
 
 // prolongation and correction: df += (P1 (x) ... (x) P1) dc
 template <typename T, int DIM, int QF, int QC>
-__device__ __noinline__ void prolong_add(const T* __restrict__ dc, T* __restrict__ df, const T* __restrict__ P1,
+__device__ __forceinline__ void prolong_add(const T* __restrict__ dc, T* __restrict__ df, const T* __restrict__ P1,
                             T* __restrict__ ab) {
   constexpr int mf = 2 * QF - 1, mc = 2 * QC - 1;
   const int tid = threadIdx.x;
@@ -835,13 +1185,11 @@ __device__ void vcycle(const Ctx<T, DIM, LV>& c, int k, bool d_zero) {
     __syncthreads();
   } else {
     constexpr int QF = LV::q[L], QC = LV::q[L + 1];
+    using PT = VecPtr<T, DIM, LV>;
     chebyshev<T, DIM, LV, L>(c, k, d_zero);          // pre-smoothing
-    apply_vec<T, DIM, LV, L>(c, c.d(L));              // residual
     T* res = c.res();
-    const T* f = c.r(L);
-    const T* Out = c.Out();
-    for (int i = tid; i < N; i += kThreads) res[i] = f[i] - Out[i];
-    __syncthreads();
+    apply_vec_epi<T, DIM, LV, L>(c, c.d(L),           // residual
+                                 EpiResidual<T, PT>{vp<T, DIM, LV>(c.r(L)), vp<T, DIM, LV>(res)});
     restrict_vec<T, DIM, QF, QC>(res, c.r(L + 1), c.tabP(L), c.abuf());  // restriction
     vcycle<T, DIM, LV, L + 1>(c, k, true);                               // recursion
     prolong_add<T, DIM, QF, QC>(c.d(L + 1), c.d(L), c.tabP(L), c.abuf());  // correction
@@ -926,6 +1274,7 @@ __global__ __launch_bounds__(kThreads) void patch_kernel(PatchArgs a) {
   c.lds = reinterpret_cast<T*>(smem_raw);
   c.vec = Lay::vec_in_lds ? c.lds + Lay::vec_off
                           : reinterpret_cast<T*>(a.vec_scratch) + (int64_t)blockIdx.x * a.vec_stride;
+  c.gtab = tptr<T>(a.tab);
   const int patch = a.patch_begin + blockIdx.x;
   const int tid = threadIdx.x;
   load_patch<T, DIM, LV>(c, a, patch);
@@ -1017,6 +1366,7 @@ __global__ __launch_bounds__(kThreads) void diag_kernel(PatchArgs a) {
   c.lds = reinterpret_cast<T*>(smem_raw);
   c.vec = Lay::vec_in_lds ? c.lds + Lay::vec_off
                           : reinterpret_cast<T*>(a.vec_scratch) + (int64_t)blockIdx.x * a.vec_stride;
+  c.gtab = a.tab64;
   const int patch = a.patch_begin + blockIdx.x;
   const int tid = threadIdx.x;
   // load tables and geometry only (the inverse diagonals are the output)
@@ -1261,6 +1611,7 @@ __global__ __launch_bounds__(kThreads) void lanczos_kernel(PatchArgs a) {
   c.lds = reinterpret_cast<T*>(smem_raw);
   c.vec = Lay::vec_in_lds ? c.lds + Lay::vec_off
                           : reinterpret_cast<T*>(a.vec_scratch) + (int64_t)blockIdx.x * a.vec_stride;
+  c.gtab = a.tab64;
   const int patch = a.patch_begin + blockIdx.x;
   {
     // load_patch without the Chebyshev parameters
@@ -1431,6 +1782,24 @@ const PatchVariant* registry(size_t* count) {
 }
 
 }  // namespace
+
+hipError_t init_constant_tables() {
+  std::vector<double> t64(kConstTab, 0.0);
+  for (int q = 1; q <= kMaxDegree; ++q) {
+    DegreeTables t = degree_tables(q);
+    const int n = t.n;
+    double* dst = t64.data() + ctab_off(q);
+    std::copy(t.B.begin(), t.B.end(), dst);
+    std::copy(t.Dc.begin(), t.Dc.end(), dst + n * n);
+    std::copy(t.D.begin(), t.D.end(), dst + 2 * n * n);
+    std::copy(t.xg.begin(), t.xg.end(), dst + 3 * n * n);
+    std::copy(t.wg.begin(), t.wg.end(), dst + 3 * n * n + n);
+  }
+  std::vector<float> t32(t64.begin(), t64.end());
+  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_tab64), t64.data(), t64.size() * sizeof(double));
+  if (e != hipSuccess) return e;
+  return hipMemcpyToSymbol(HIP_SYMBOL(c_tab32), t32.data(), t32.size() * sizeof(float));
+}
 
 const PatchVariant* find_variant(int precision, int dim, int n_levels, const int* levels) {
   size_t n = 0;
