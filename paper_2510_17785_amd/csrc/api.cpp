@@ -129,6 +129,8 @@ struct pmg_handle {
   void* tab = nullptr;
   double* invdiag64[kMaxLevels] = {nullptr};
   void* invdiag[kMaxLevels] = {nullptr};
+  double* dense64[kMaxLevels] = {nullptr};
+  void* dense[kMaxLevels] = {nullptr};
   void* cheb = nullptr;
   void* vec_scratch = nullptr;
   int64_t vec_bytes = 0;  // bytes per block slot of vec_scratch
@@ -148,6 +150,8 @@ struct pmg_handle {
     for (int l = 0; l < kMaxLevels; ++l) {
       a.invdiag[l] = invdiag[l];
       a.invdiag64[l] = invdiag64[l];
+      a.dense[l] = dense[l];
+      a.dense64[l] = dense64[l];
     }
     a.cheb = cheb;
     a.cheb_degree = cheb_degree;
@@ -171,6 +175,8 @@ void free_handle(pmg_handle* h) {
   for (int l = 0; l < kMaxLevels; ++l) {
     if (h->invdiag64[l]) (void)hipFree(h->invdiag64[l]);
     if (h->invdiag[l] && h->invdiag[l] != h->invdiag64[l]) (void)hipFree(h->invdiag[l]);
+    if (h->dense64[l]) (void)hipFree(h->dense64[l]);
+    if (h->dense[l] && h->dense[l] != h->dense64[l]) (void)hipFree(h->dense[l]);
   }
   delete h;
 }
@@ -392,6 +398,39 @@ int patch_setup_impl(const pmg_mesh* mesh, const double* coeff, int p, const pmg
         if ((e = launch_convert_to_float((int64_t)h->n_patches * h->level_size(l), h->invdiag64[l],
                                          reinterpret_cast<float*>(h->invdiag[l]), h->stream)))
           return cleanup(fail(PMG_ERR_HIP, "convert: %s", hipGetErrorString(e)));
+  }
+  // dense matrices of the small levels (formed with the FP64 matrix-free operator)
+  {
+    bool any = false;
+    for (int l = 0; l < L; ++l) {
+      if (!var->dense_level[l]) continue;
+      any = true;
+      const size_t cnt = (size_t)h->n_patches * h->level_size(l) * h->level_size(l);
+      if ((s = dev_alloc(&h->dense64[l], cnt * sizeof(double), &h->device_bytes)) < 0) return cleanup(s);
+      if (h->precision == PMG_FP64) {
+        h->dense[l] = h->dense64[l];
+      } else if ((s = dev_alloc(&h->dense[l], cnt * sizeof(float), &h->device_bytes)) < 0) {
+        return cleanup(s);
+      }
+    }
+    if (any) {
+      PatchArgs a = h->args();
+      a.vec_stride = h->vec_bytes / (int64_t)sizeof(double);  // FP64 setup kernels
+      const int chunk = h->vec_blocks > 0 ? (int)h->vec_blocks : h->n_patches;
+      for (int b = 0; b < h->n_patches; b += chunk) {
+        a.patch_begin = b;
+        a.n_patch = std::min(chunk, h->n_patches - b);
+        if ((e = var->launch_dense(a, h->stream)))
+          return cleanup(fail(PMG_ERR_HIP, "dense level kernel: %s", hipGetErrorString(e)));
+      }
+      if (h->precision == PMG_FP32)
+        for (int l = 0; l < L; ++l)
+          if (var->dense_level[l] &&
+              (e = launch_convert_to_float((int64_t)h->n_patches * h->level_size(l) * h->level_size(l),
+                                           h->dense64[l], reinterpret_cast<float*>(h->dense[l]),
+                                           h->stream)))
+            return cleanup(fail(PMG_ERR_HIP, "convert: %s", hipGetErrorString(e)));
+    }
   }
   const size_t ncheb = (size_t)h->n_patches * (L - 1) * 2;
   if ((s = dev_alloc(&h->cheb, ncheb * h->tsize(), &h->device_bytes)) < 0) return cleanup(s);

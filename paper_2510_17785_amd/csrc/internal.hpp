@@ -52,6 +52,9 @@ struct PatchArgs {
   uint64_t seed;
   double* lanczos_basis;     // per block: m x size_l doubles
   double* bounds_out;        // n_patches_total x (L-1) x 2
+  // small levels held as dense matrices (see PatchVariant::dense_level)
+  const void* dense[kMaxLevels];   // T, n_patches_total x size_l^2, row-major
+  double* dense64[kMaxLevels];     // FP64 copies, written by the setup kernel
 };
 
 // One compiled (precision, dim, levels) variant of the patch kernels.
@@ -68,6 +71,10 @@ struct PatchVariant {
   // FP64 setup kernels (inverse diagonals of every level; Lanczos bounds)
   hipError_t (*launch_diag)(const PatchArgs& a, hipStream_t s);
   hipError_t (*launch_lanczos)(const PatchArgs& a, int level, hipStream_t s);
+  // levels applied as a stored dense matrix (1) instead of by sum factorisation,
+  // and the FP64 setup kernel that forms them from the matrix-free operator
+  int dense_level[kMaxLevels];
+  hipError_t (*launch_dense)(const PatchArgs& a, hipStream_t s);
 };
 
 const PatchVariant* find_variant(int precision, int dim, int n_levels, const int* levels);

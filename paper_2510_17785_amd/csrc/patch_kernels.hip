@@ -140,6 +140,18 @@ struct Layout {
   static constexpr int vec_res = vec_r(L);
   static constexpr int vec_z = vec_res + level_size(0);
   static constexpr int vec_total = vec_z + level_size(0);
+  // Levels below the top with at most 32 interior nodes (degree 2 in 3D) and
+  // not the coarsest are applied as a stored dense matrix: their sum
+  // factorisation is all fixed per-phase cost.
+  static constexpr bool dense_level(int l) {
+    return l > 0 && l < L - 1 && level_size(l) <= 32;
+  }
+  static constexpr int dense_rel(int l) {
+    int o = 0;
+    for (int i = 0; i < l; ++i) o += dense_level(i) ? level_size(i) * level_size(i) : 0;
+    return o;
+  }
+  static constexpr int dense_total = dense_rel(L);
   // metric G at every Gauss point of every level, structure of arrays
   static constexpr int NG = DIM == 3 ? 6 : 3;
   static constexpr int npts(int l) { return ipow(2 * (LV::q[l] + 1), DIM); }
@@ -156,7 +168,8 @@ struct Layout {
   static constexpr bool vec_in_lds = cache_G || (base_total + vec_total) * (int)sizeof(T) <= kBudget;
   static constexpr int G_off = base_total;
   static constexpr int vec_off = base_total + (cache_G ? G_total : 0);
-  static constexpr int lds_elems = vec_off + (vec_in_lds ? vec_total : 0);
+  static constexpr int dense_off = round_up(vec_off + (vec_in_lds ? vec_total : 0), 4);
+  static constexpr int lds_elems = dense_off + dense_total;
 };
 
 // ---------------------------------------------------------------------------
@@ -355,6 +368,8 @@ struct Ctx {
   __device__ T* cheb() const { return lds + Lay::geo_off + Lay::nvert * DIM + ipow(2, DIM); }
   __device__ T* jc() const { return lds + Lay::geo_off + Lay::jc_rel; }
   __device__ T* Gc(int l) const { return lds + Lay::G_off + Lay::G_rel(l); }
+  __device__ T* dense(int l) const { return lds + Lay::dense_off + Lay::dense_rel(l); }
+  bool dense_ok = false;  // dense level matrices loaded (not in the setup kernels)
   __device__ T* X() const { return lds + Lay::X_off; }
   __device__ T* Out() const { return lds + Lay::Out_off; }
   __device__ T* abuf() const { return lds + Lay::abuf_off; }
@@ -999,6 +1014,20 @@ template <typename T, int DIM, class LV, int L, class Epi>
 __device__ __forceinline__ void apply_vec_epi(const Ctx<T, DIM, LV>& c, const T* v, Epi epi) {
   constexpr int Q = LV::q[L];
   using Lay = Layout<T, DIM, LV>;
+  if constexpr (Lay::dense_level(L)) {
+    if (c.dense_ok) {
+      constexpr int N = Lay::level_size(L);
+      const T* M = c.dense(L);
+      for (int i = threadIdx.x; i < N; i += kThreads) {
+        T acc = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) acc += M[i * N + j] * v[j];
+        epi(i, acc);
+      }
+      __syncthreads();
+      return;
+    }
+  }
   if constexpr (Lay::use_seg(L) && Lay::vec_in_lds) {
     apply3seg<T, Q, false, Lay::cache_G>(lds_cast(v), epi, lds_cast(c.abuf()), lds_cast(c.tabDc(L)),
                                          lds_cast(c.jc()), lds_cast(c.mu()), lds_cast(c.Gc(L)));
@@ -1262,6 +1291,13 @@ __device__ void load_patch(const Ctx<T, DIM, LV>& c, const PatchArgs& a, int pat
     T* dst = c.dinv(l);
     for (int i = tid; i < sz; i += kThreads) dst[i] = src[i];
   }
+  for (int l = 0; l < L; ++l) {
+    if (!Lay::dense_level(l)) continue;
+    const int sz = Lay::level_size(l) * Lay::level_size(l);
+    const T* src = tptr<T>(a.dense[l]) + (int64_t)patch * sz;
+    T* dst = c.dense(l);
+    for (int i = tid; i < sz; i += kThreads) dst[i] = src[i];
+  }
   __syncthreads();
 }
 
@@ -1278,6 +1314,7 @@ __global__ __launch_bounds__(kThreads) void patch_kernel(PatchArgs a) {
   const int patch = a.patch_begin + blockIdx.x;
   const int tid = threadIdx.x;
   load_patch<T, DIM, LV>(c, a, patch);
+  c.dense_ok = true;
   prepare_geometry<T, DIM, LV>(c);
   constexpr int N0 = S0::interior;
   constexpr int m = S0::m, mi = S0::mi;
@@ -1653,6 +1690,69 @@ __global__ __launch_bounds__(kThreads) void lanczos_kernel(PatchArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// setup: dense matrices of the small levels, A_{j,q} e_j column by column
+// with the matrix-free FP64 operator
+// ---------------------------------------------------------------------------
+
+template <int DIM, class LV>
+__global__ __launch_bounds__(kThreads) void dense_kernel(PatchArgs a) {
+  using T = double;
+  using Lay = Layout<T, DIM, LV>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  Ctx<T, DIM, LV> c;
+  c.lds = reinterpret_cast<T*>(smem_raw);
+  c.vec = Lay::vec_in_lds ? c.lds + Lay::vec_off
+                          : reinterpret_cast<T*>(a.vec_scratch) + (int64_t)blockIdx.x * a.vec_stride;
+  c.gtab = a.tab64;
+  const int patch = a.patch_begin + blockIdx.x;
+  const int tid = threadIdx.x;
+  {
+    const T* tab = a.tab64;
+    for (int l = 0; l < LV::count; ++l) {
+      const int sz = tab_size(LV::q[l]);
+      for (int i = tid; i < sz; i += kThreads) c.lds[Lay::tab_level_off(l) + i] = tab[l * kTabLevelStride + i];
+    }
+    const int vlin = a.patch_vertex[patch];
+    const int N1 = a.N + 1;
+    const int vx = vlin % N1, vy = (vlin / N1) % N1, vz = DIM == 3 ? vlin / (N1 * N1) : 0;
+    for (int i = tid; i < Lay::nvert * DIM; i += kThreads) {
+      const int r = i % DIM, t = i / DIM;
+      const int tx = t % 3, ty = (t / 3) % 3, tz = DIM == 3 ? t / 9 : 0;
+      int g = (vx - 1 + tx) + (vy - 1 + ty) * N1;
+      if (DIM == 3) g += (vz - 1 + tz) * N1 * N1;
+      c.geo()[i] = a.verts[g * DIM + r] - a.verts[vlin * DIM + r];
+    }
+    for (int i = tid; i < ipow(2, DIM); i += kThreads) {
+      const int cx = i & 1, cy = (i >> 1) & 1, cz = (i >> 2) & 1;
+      int g = (vx - 1 + cx) + (vy - 1 + cy) * a.N;
+      if (DIM == 3) g += (vz - 1 + cz) * a.N * a.N;
+      c.mu()[i] = a.mu[g];
+    }
+    __syncthreads();
+  }
+  prepare_geometry<T, DIM, LV>(c);
+  auto run = [&](auto Lc) {
+    constexpr int L = decltype(Lc)::value;
+    if constexpr (Lay::dense_level(L)) {
+      constexpr int N = Lay::level_size(L);
+      double* M = a.dense64[L] + (int64_t)patch * N * N;
+      T* e = c.z();
+      for (int j = 0; j < N; ++j) {
+        for (int i = tid; i < N; i += kThreads) e[i] = i == j ? 1.0 : 0.0;
+        __syncthreads();
+        apply_vec<T, DIM, LV, L>(c, e);
+        for (int i = tid; i < N; i += kThreads) M[i * N + j] = c.Out()[i];
+        __syncthreads();
+      }
+    }
+  };
+  run(std::integral_constant<int, 0>{});
+  if constexpr (LV::count > 1) run(std::integral_constant<int, 1>{});
+  if constexpr (LV::count > 2) run(std::integral_constant<int, 2>{});
+  if constexpr (LV::count > 3) run(std::integral_constant<int, 3>{});
+}
+
+// ---------------------------------------------------------------------------
 // launchers and registry
 // ---------------------------------------------------------------------------
 
@@ -1735,6 +1835,16 @@ struct Variant {
     hipLaunchKernelGGL((diag_kernel<DIM, LV>), dim3(a.n_patch), dim3(kThreads), lds, s, a);
     return report_launch(diag_kernel<DIM, LV>, "diag", dim3(a.n_patch), lds);
   }
+  static hipError_t launch_dense(const PatchArgs& a, hipStream_t s) {
+    using L64 = Layout<double, DIM, LV>;
+    if (a.n_patch <= 0) return hipSuccess;
+    const size_t lds = (size_t)L64::lds_elems * sizeof(double);
+    hipError_t e = allow_lds(dense_kernel<DIM, LV>, lds);
+    if (e != hipSuccess) return e;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL((dense_kernel<DIM, LV>), dim3(a.n_patch), dim3(kThreads), lds, s, a);
+    return report_launch(dense_kernel<DIM, LV>, "dense", dim3(a.n_patch), lds);
+  }
   static hipError_t launch_lanczos(const PatchArgs& a, int level, hipStream_t s) {
     using L64 = Layout<double, DIM, LV>;
     if (a.n_patch <= 0) return hipSuccess;
@@ -1766,6 +1876,9 @@ PatchVariant make_variant() {
   // the FP64 setup kernels use the FP64 layout of the same level list
   v.launch_diag = &Variant<double, DIM, LV>::launch_diag;
   v.launch_lanczos = &Variant<double, DIM, LV>::launch_lanczos;
+  v.launch_dense = &Variant<double, DIM, LV>::launch_dense;
+  for (int l = 0; l < kMaxLevels; ++l)
+    v.dense_level[l] = l < LV::count && Layout<T, DIM, LV>::dense_level(l) ? 1 : 0;
   return v;
 }
 
