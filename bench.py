@@ -58,6 +58,25 @@ def algorithmic_per_patch(dim, levels, k, tsize):
     return F, B
 
 
+def measured_traffic(workload):
+    """HBM bytes per launch of the FP32 patch kernel from the committed
+    rocprofv3 counter summary, or None when the kernel source has changed
+    since the counters were taken."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", f"patch_kernel_fp32_{workload}.md")
+    src = os.path.join(ROOT, "paper_2510_17785_amd", "csrc", "patch_kernels.hip")
+    if not os.path.exists(prof):
+        return None
+    text = open(prof).read()
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if f"`{digest}`" not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith("TRAFFIC_BYTES_PER_LAUNCH"):
+            return float(line.split("=")[1])
+    return None
+
+
 def time_sweeps(S, u, b, steps, warmup, torch):
     """Per-colour launch times (ms) over `steps` forward sweeps, recorded with
     events on the stream the kernels run on."""
@@ -125,7 +144,22 @@ def main(argv=None):
     ap.add_argument("--workload", default="3d-n16-q4")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-cg", action="store_true", help="skip the outer CG iteration check")
+    ap.add_argument("--only", choices=["fp32", "fp64"], default=None,
+                    help="time one precision only (for profiler runs; prints no JSON line)")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run a device-to-device copy of this many bytes, 5 times (a "
+                         "known-size kernel for calibrating the HBM byte counters)")
     args = ap.parse_args(argv)
+    if args.copy_bytes:
+        import torch
+        n = args.copy_bytes // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(f"# copied {n * 8} bytes 5 times", file=sys.stderr)
+        return 0
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the smoother is measured on one MI355X "
               "(a multi-GPU run would need a halo exchange per colour, which this build "
@@ -146,7 +180,7 @@ def main(argv=None):
     b = torch.tensor(bh, device=dev)
 
     res = {}
-    for prec in ("fp32", "fp64"):
+    for prec in ((args.only,) if args.only else ("fp32", "fp64")):
         t0 = time.perf_counter()
         S = PatchSmoother(w.dim, w.n, w.p, X, mu, levels=w.levels, precision=prec)
         torch.cuda.synchronize()
@@ -158,6 +192,8 @@ def main(argv=None):
         print(f"# {prec}: sweep {sweep_ms:.4f} ms, setup {setup_s:.2f} s, "
               f"{S.n_interior_dofs * 1e3 / sweep_ms:.3e} DoF/s", file=sys.stderr, flush=True)
 
+    if args.only:
+        return 0
     cg = {}
     if not args.no_cg:
         for prec in ("fp64", "fp32"):
@@ -210,7 +246,7 @@ def main(argv=None):
             "peak": VALU_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / VALU_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(w.name),
             "kernel": "patch_kernel<float,3,Levels<4,2,1>,smooth>",
             "algorithmic_flops_per_patch": F,
             "algorithmic_bytes_per_patch": B,
