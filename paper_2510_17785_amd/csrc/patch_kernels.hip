@@ -1,7 +1,7 @@
 // Per-patch kernels of the vertex-patch smoother with a nested p-multigrid
 // local solver (arXiv 2510.17785, Section 2.1 and Section 3.1), for CDNA4.
 //
-// One workgroup of kThreads threads owns one patch at a time.  Everything the
+// One workgroup (512 threads in FP32, 256 in FP64) owns one patch at a time.  Everything the
 // local solver touches lives in LDS: the 1D tables, the patch geometry (3^d
 // vertices relative to the patch centre and 2^d coefficients), the closure
 // input of the operator, its interior output, the sum-factorisation slab
@@ -74,6 +74,11 @@ __device__ __forceinline__ const T* ctab() {
   else
     return c_tab32;
 }
+
+// Threads per patch workgroup: 8 waves for FP32 (about 100 VGPRs, two
+// workgroups per CU), 4 waves for FP64 (about 230 VGPRs).
+template <typename T>
+constexpr int NT = sizeof(T) == 4 ? 512 : 256;
 
 template <int... Qs>
 struct Levels {
@@ -154,7 +159,11 @@ struct Layout {
   static constexpr int dense_total = dense_rel(L);
   // metric G at every Gauss point of every level, structure of arrays
   static constexpr int NG = DIM == 3 ? 6 : 3;
-  static constexpr int npts(int l) { return ipow(2 * (LV::q[l] + 1), DIM); }
+  // Gauss points of level l that need the metric (none for the stored dense
+  // levels and the coarsest level, which the V-cycle never applies)
+  static constexpr int npts(int l) {
+    return (l > 0 && (l == L - 1 || dense_level(l))) ? 0 : ipow(2 * (LV::q[l] + 1), DIM);
+  }
   static constexpr int G_rel(int l) {
     int o = 0;
     for (int i = 0; i < l; ++i) o += NG * npts(i);
@@ -293,7 +302,7 @@ template <typename T, int DIM>
 __device__ void jacobian_coefficients(const T* __restrict__ V, T* __restrict__ jc) {
   constexpr int ncell = ipow(2, DIM);
   constexpr int per = DIM * DIM * ipow(2, DIM - 1);
-  for (int i = threadIdx.x; i < ncell * DIM * DIM; i += kThreads) {
+  for (int i = threadIdx.x; i < ncell * DIM * DIM; i += NT<T>) {
     const int r = i % DIM, col = (i / DIM) % DIM, cell = i / (DIM * DIM);
     const int cx = cell & 1, cy = (cell >> 1) & 1, cz = (cell >> 2) & 1;
     T* out = jc + cell * per + (col * DIM + r) * ipow(2, DIM - 1);
@@ -402,7 +411,7 @@ __device__ __noinline__ void apply3(const T* __restrict__ X, T* __restrict__ Out
   for (int cz = 0; cz < 2; ++cz) {
     // x: A[zl][y][QX] = sum_a B[kx][a] X[cz Q + zl][y][cx Q + a]
 #pragma unroll 1
-    for (int idx = tid; idx < n * m * NQ; idx += kThreads) {
+    for (int idx = tid; idx < n * m * NQ; idx += NT<T>) {
       const int QX = idx % NQ, t = idx / NQ, y = t % m, zl = t / m;
       const int cx = QX >= n, kx = QX - cx * n;
       const T* xr = X + ((cz * Q + zl) * m + y) * m + cx * Q;
@@ -415,7 +424,7 @@ __device__ __noinline__ void apply3(const T* __restrict__ X, T* __restrict__ Out
     __syncthreads();
     // y: Bf[zl][QY][QX] = sum_a B[ky][a] A[zl][cy Q + a][QX]
 #pragma unroll 1
-    for (int idx = tid; idx < S; idx += kThreads) {
+    for (int idx = tid; idx < S; idx += NT<T>) {
       const int QX = idx % NQ, t = idx / NQ, QY = t % NQ, zl = t / NQ;
       const int cy = QY >= n, ky = QY - cy * n;
       const T* ar = A + (zl * m + cy * Q) * NQ + QX;
@@ -428,7 +437,7 @@ __device__ __noinline__ void apply3(const T* __restrict__ X, T* __restrict__ Out
     __syncthreads();
     // z: C[kz][QY][QX] = sum_zl B[kz][zl] Bf[zl][QY][QX]   (values at Gauss points)
 #pragma unroll 1
-    for (int idx = tid; idx < S; idx += kThreads) {
+    for (int idx = tid; idx < S; idx += NT<T>) {
       const int kz = idx / (NQ * NQ), rem = idx % (NQ * NQ);
       const T* br = Bt + kz * n;
       T acc = 0;
@@ -439,7 +448,7 @@ __device__ __noinline__ void apply3(const T* __restrict__ X, T* __restrict__ Out
     __syncthreads();
     // reference gradients by collocation, then the flux G grad
 #pragma unroll 1
-    for (int idx = tid; idx < S; idx += kThreads) {
+    for (int idx = tid; idx < S; idx += NT<T>) {
       const int QX = idx % NQ, t = idx / NQ, QY = t % NQ, kz = t / NQ;
       const int cx = QX >= n, kx = QX - cx * n, cy = QY >= n, ky = QY - cy * n;
       const T* dx = Dc + kx * n;
@@ -471,7 +480,7 @@ __device__ __noinline__ void apply3(const T* __restrict__ X, T* __restrict__ Out
     __syncthreads();
     // transposed collocation: C = Dc^T F
 #pragma unroll 1
-    for (int idx = tid; idx < S; idx += kThreads) {
+    for (int idx = tid; idx < S; idx += NT<T>) {
       const int QX = idx % NQ, t = idx / NQ, QY = t % NQ, kz = t / NQ;
       const int cx = QX >= n, kx = QX - cx * n, cy = QY >= n, ky = QY - cy * n;
       const T* fx = A + (kz * NQ + QY) * NQ + cx * n;
@@ -489,7 +498,7 @@ __device__ __noinline__ void apply3(const T* __restrict__ X, T* __restrict__ Out
     __syncthreads();
     // z^T: A[zl][QY][QX] = sum_kz B[kz][zl] C[kz][QY][QX]
 #pragma unroll 1
-    for (int idx = tid; idx < S; idx += kThreads) {
+    for (int idx = tid; idx < S; idx += NT<T>) {
       const int zl = idx / (NQ * NQ), rem = idx % (NQ * NQ);
       T acc = 0;
 #pragma unroll
@@ -499,7 +508,7 @@ __device__ __noinline__ void apply3(const T* __restrict__ X, T* __restrict__ Out
     __syncthreads();
     // y^T onto interior rows: Bf[zl][yi][QX], y = yi + 1
 #pragma unroll 1
-    for (int idx = tid; idx < n * mi * NQ; idx += kThreads) {
+    for (int idx = tid; idx < n * mi * NQ; idx += NT<T>) {
       const int QX = idx % NQ, t = idx / NQ, yi = t % mi, zl = t / mi;
       const int y = yi + 1;
       T acc = 0;
@@ -520,7 +529,7 @@ __device__ __noinline__ void apply3(const T* __restrict__ X, T* __restrict__ Out
     const int zl0 = cz == 0 ? 1 : 0;
     constexpr int nz = Q;  // interior planes per slab: z = 1..Q or Q..2Q-1
 #pragma unroll 1
-    for (int idx = tid; idx < nz * mi * mi; idx += kThreads) {
+    for (int idx = tid; idx < nz * mi * mi; idx += NT<T>) {
       const int xi = idx % mi, t = idx / mi, yi = t % mi, zl = zl0 + t / mi;
       const int x = xi + 1;
       const T* br = Bf + (zl * mi + yi) * NQ;
@@ -603,7 +612,8 @@ struct EpiChebStep {  // x += z, res -= A z, z = c1 z + c2 D^{-1} res
 
 template <typename T, int Q, bool CLOSURE_IN, bool CACHE, class Epi>
 __device__ __noinline__ void apply3seg(const LDSP T* __restrict__ in, Epi epi,
-                                       LDSP T* __restrict__ ab, const LDSP T* __restrict__ Dcl,
+                                       LDSP T* __restrict__ ab, const LDSP T* __restrict__ Bl,
+                                       const LDSP T* __restrict__ Dcl,
                                        const LDSP T* __restrict__ jc, const LDSP T* __restrict__ mu,
                                        const LDSP T* __restrict__ Gc) {
   using SG = Seg3<T, Q>;
@@ -623,7 +633,7 @@ __device__ __noinline__ void apply3seg(const LDSP T* __restrict__ in, Epi epi,
 
   // 1. x: A[zr][yr][QX] = sum_a B[k][a] in[zr][yr][cx q + a]
 #pragma unroll 1
-  for (int it = tid; it < 2 * NR * NR; it += kThreads) {
+  for (int it = tid; it < 2 * NR * NR; it += NT<T>) {
     const int line = it % (NR * NR), cx = it / (NR * NR);
     const LDSP T* src = in + line * NR;
     T v[n];
@@ -644,7 +654,7 @@ __device__ __noinline__ void apply3seg(const LDSP T* __restrict__ in, Epi epi,
   __syncthreads();
   // 2. y: Bb[zr][QY][QX] = sum_a B[k][a] A[zr][cy q + a][QX]
 #pragma unroll 1
-  for (int it = tid; it < 2 * NR * NQ; it += kThreads) {
+  for (int it = tid; it < 2 * NR * NQ; it += NT<T>) {
     const int QX = it % NQ, r = it / NQ, zr = r % NR, cy = r / NR;
     T v[n];
 #pragma unroll
@@ -664,7 +674,7 @@ __device__ __noinline__ void apply3seg(const LDSP T* __restrict__ in, Epi epi,
   __syncthreads();
   // 3. z: C[QZ][QY][QX] = sum_a B[k][a] Bb[cz q + a][QY][QX]   (values at Gauss points)
 #pragma unroll 1
-  for (int it = tid; it < 2 * NQ2; it += kThreads) {
+  for (int it = tid; it < 2 * NQ2; it += NT<T>) {
     const int col = it % NQ2, cz = it / NQ2;
     T v[n];
 #pragma unroll
@@ -686,7 +696,7 @@ __device__ __noinline__ void apply3seg(const LDSP T* __restrict__ in, Epi epi,
   //    one local Gauss point (kx, ky, kz) of the four cells of layer cz
   constexpr int n3 = n * n * n;
 #pragma unroll 1
-  for (int t = tid; t < 2 * n3; t += kThreads) {
+  for (int t = tid; t < 2 * n3; t += NT<T>) {
     const int k3 = t % n3, cz = t / n3;
     const int kx = k3 % n, ky = (k3 / n) % n, kz = k3 / (n * n);
     T dx[n], dy[n], dz[n];
@@ -726,99 +736,83 @@ __device__ __noinline__ void apply3seg(const LDSP T* __restrict__ in, Epi epi,
     }
   }
   __syncthreads();
-  // 5. transposed collocation W = Dc^T F along one full Gauss-point column
-  //    (both cells), then z^T onto the interior z nodes, summing the two
-  //    cells at the shared node: C[zi][QY][QX], zi = z - 1
+  // 5. transposed collocation W = Dc^T F along the z segment of one cell of
+  //    a Gauss-point column, then z^T of that cell: C[zc][QY][QX] in the
+  //    cell-local z layout (zc = cz n + a; the shared node appears twice)
 #pragma unroll 1
-  for (int col = tid; col < NQ2; col += kThreads) {
+  for (int it = tid; it < 2 * NQ2; it += NT<T>) {
+    const int col = it % NQ2, cz = it / NQ2;
     const int QX = col % NQ, QY = col / NQ;
     const int cx = QX >= n, kx = QX - cx * n, cy = QY >= n, ky = QY - cy * n;
-    T ex[n], ey[n];
+    T ex[n], ey[n], f2[n];
 #pragma unroll
     for (int a = 0; a < n; ++a) {
       ex[a] = Dcl[a * n + kx];
       ey[a] = Dcl[a * n + ky];
+      f2[a] = D[(cz * n + a) * NQ2 + col];
     }
-    T acc_z[mi];
+    T w[n];
 #pragma unroll
-    for (int zi = 0; zi < mi; ++zi) acc_z[zi] = 0;
+    for (int k = 0; k < n; ++k) {
+      const int QZ = cz * n + k;
+      const LDSP T* fx = A + (QZ * NQ + QY) * NQ + cx * n;
+      const LDSP T* fy = Bb + (QZ * NQ + cy * n) * NQ + QX;
+      T acc = 0;
 #pragma unroll
-    for (int cz = 0; cz < 2; ++cz) {
-      T f2[n];
+      for (int a = 0; a < n; ++a) acc += ex[a] * fx[a] + ey[a] * fy[a * NQ] + gDc[a * n + k] * f2[a];
+      w[k] = acc;
+    }
+    LDSP T* dst = C + cz * n * NQ2 + col;
 #pragma unroll
-      for (int a = 0; a < n; ++a) f2[a] = D[(cz * n + a) * NQ2 + col];
-      T w[n];
+    for (int a = 0; a < n; ++a) {
+      T acc = 0;
+#pragma unroll
+      for (int k = 0; k < n; ++k) acc += gB[k * n + a] * w[k];
+      dst[a * NQ2] = acc;
+    }
+  }
+  __syncthreads();
+  // 6. y^T, one interior (z, y) pair and one QX per item; the two cell-local
+  //    copies of the shared z node are summed on read: A[zi][yi][QX]
+#pragma unroll 1
+  for (int it = tid; it < mi * mi * NQ; it += NT<T>) {
+    const int QX = it % NQ, r = it / NQ, yi = r % mi, zi = r / mi;
+    const int z = zi + 1, y = yi + 1;
+    const int zc0 = z <= Q ? z : n + z - Q;          // cell-local z of node z
+    const int zc1 = z == Q ? n : zc0;                 // its second copy (z = q)
+    const bool two = z == Q;
+    T acc = 0;
+#pragma unroll
+    for (int cy = 0; cy < 2; ++cy) {
+      const int a = y - cy * Q;
+      if (a < 0 || a > Q) continue;
+      const LDSP T* s0 = C + zc0 * NQ2 + cy * n * NQ + QX;
+      const LDSP T* s1 = C + zc1 * NQ2 + cy * n * NQ + QX;
 #pragma unroll
       for (int k = 0; k < n; ++k) {
-        const int QZ = cz * n + k;
-        const LDSP T* fx = A + (QZ * NQ + QY) * NQ + cx * n;
-        const LDSP T* fy = Bb + (QZ * NQ + cy * n) * NQ + QX;
-        T acc = 0;
-#pragma unroll
-        for (int a = 0; a < n; ++a) acc += ex[a] * fx[a] + ey[a] * fy[a * NQ] + gDc[a * n + k] * f2[a];
-        w[k] = acc;
-      }
-      // z^T of this cell: node z = cz q + a, interior when 1 <= z <= m - 2
-#pragma unroll
-      for (int a = 0; a < n; ++a) {
-        const int zi = cz * Q + a - 1;
-        if (zi < 0 || zi >= mi) continue;
-        T acc = 0;
-#pragma unroll
-        for (int k = 0; k < n; ++k) acc += gB[k * n + a] * w[k];
-        acc_z[zi] += acc;
+        const T v = two ? s0[k * NQ] + s1[k * NQ] : s0[k * NQ];
+        acc += Bl[k * n + a] * v;
       }
     }
-#pragma unroll
-    for (int zi = 0; zi < mi; ++zi) C[zi * NQ2 + col] = acc_z[zi];
+    A[r * NQ + QX] = acc;
   }
   __syncthreads();
-  // 6. y^T onto interior y nodes (both cells of a line): A[zi][yi][QX]
+  // 7. x^T, one interior row per item, handed to the epilogue with its
+  //    interior index (the caller's vector update is fused here)
 #pragma unroll 1
-  for (int it = tid; it < mi * NQ; it += kThreads) {
-    const int QX = it % NQ, zi = it / NQ;
-    const LDSP T* src = C + zi * NQ2 + QX;
-    T v[NQ];
-#pragma unroll
-    for (int k = 0; k < NQ; ++k) v[k] = src[k * NQ];
-#pragma unroll
-    for (int yi = 0; yi < mi; ++yi) {
-      const int y = yi + 1;
-      T acc = 0;
-      if (y <= Q) {
-#pragma unroll
-        for (int k = 0; k < n; ++k) acc += gB[k * n + y] * v[k];
-      }
-      if (y >= Q) {
-#pragma unroll
-        for (int k = 0; k < n; ++k) acc += gB[k * n + (y - Q)] * v[n + k];
-      }
-      A[(zi * mi + yi) * NQ + QX] = acc;
-    }
-  }
-  __syncthreads();
-  // 7. x^T onto interior x nodes: the interior rows, handed to the epilogue
-  //    with their interior index (the caller's vector update is fused here)
-#pragma unroll 1
-  for (int line = tid; line < mi * mi; line += kThreads) {
+  for (int i = tid; i < mi * mi * mi; i += NT<T>) {
+    const int xi = i % mi, line = i / mi;
+    const int x = xi + 1;
     const LDSP T* src = A + line * NQ;
-    T v[NQ];
+    T acc = 0;
 #pragma unroll
-    for (int k = 0; k < NQ; ++k) v[k] = src[k];
+    for (int cx = 0; cx < 2; ++cx) {
+      const int a = x - cx * Q;
+      if (a < 0 || a > Q) continue;
 #pragma unroll
-    for (int xi = 0; xi < mi; ++xi) {
-      const int x = xi + 1;
-      T acc = 0;
-      if (x <= Q) {
-#pragma unroll
-        for (int k = 0; k < n; ++k) acc += gB[k * n + x] * v[k];
-      }
-      if (x >= Q) {
-#pragma unroll
-        for (int k = 0; k < n; ++k) acc += gB[k * n + (x - Q)] * v[n + k];
-      }
-      epi(line * mi + xi, acc);
+      for (int k = 0; k < n; ++k) acc += Bl[k * n + a] * src[cx * n + k];
     }
+    epi(i, acc);
   }
   __syncthreads();
 }
@@ -838,7 +832,7 @@ __device__ __noinline__ void apply2(const T* __restrict__ X, T* __restrict__ Out
   for (int cy = 0; cy < 2; ++cy) {
     // x: A[yl][QX] = sum_a B[kx][a] X[cy Q + yl][cx Q + a]
 #pragma unroll 1
-    for (int idx = tid; idx < n * NQ; idx += kThreads) {
+    for (int idx = tid; idx < n * NQ; idx += NT<T>) {
       const int QX = idx % NQ, yl = idx / NQ;
       const int cx = QX >= n, kx = QX - cx * n;
       const T* xr = X + (cy * Q + yl) * m + cx * Q;
@@ -850,7 +844,7 @@ __device__ __noinline__ void apply2(const T* __restrict__ X, T* __restrict__ Out
     __syncthreads();
     // y: C[ky][QX] = sum_yl B[ky][yl] A[yl][QX]
 #pragma unroll 1
-    for (int idx = tid; idx < n * NQ; idx += kThreads) {
+    for (int idx = tid; idx < n * NQ; idx += NT<T>) {
       const int QX = idx % NQ, ky = idx / NQ;
       T acc = 0;
 #pragma unroll
@@ -859,7 +853,7 @@ __device__ __noinline__ void apply2(const T* __restrict__ X, T* __restrict__ Out
     }
     __syncthreads();
 #pragma unroll 1
-    for (int idx = tid; idx < n * NQ; idx += kThreads) {
+    for (int idx = tid; idx < n * NQ; idx += NT<T>) {
       const int QX = idx % NQ, ky = idx / NQ;
       const int cx = QX >= n, kx = QX - cx * n;
       T gx = 0, gy = 0;
@@ -882,7 +876,7 @@ __device__ __noinline__ void apply2(const T* __restrict__ X, T* __restrict__ Out
     }
     __syncthreads();
 #pragma unroll 1
-    for (int idx = tid; idx < n * NQ; idx += kThreads) {
+    for (int idx = tid; idx < n * NQ; idx += NT<T>) {
       const int QX = idx % NQ, ky = idx / NQ;
       const int cx = QX >= n, kx = QX - cx * n;
       T acc = 0;
@@ -896,7 +890,7 @@ __device__ __noinline__ void apply2(const T* __restrict__ X, T* __restrict__ Out
     __syncthreads();
     // y^T: A[yl][QX] = sum_ky B[ky][yl] C[ky][QX]
 #pragma unroll 1
-    for (int idx = tid; idx < n * NQ; idx += kThreads) {
+    for (int idx = tid; idx < n * NQ; idx += NT<T>) {
       const int QX = idx % NQ, yl = idx / NQ;
       T acc = 0;
 #pragma unroll
@@ -906,7 +900,7 @@ __device__ __noinline__ void apply2(const T* __restrict__ X, T* __restrict__ Out
     __syncthreads();
     const int yl0 = cy == 0 ? 1 : 0;
 #pragma unroll 1
-    for (int idx = tid; idx < Q * mi; idx += kThreads) {
+    for (int idx = tid; idx < Q * mi; idx += NT<T>) {
       const int xi = idx % mi, yl = yl0 + idx / mi;
       const int x = xi + 1;
       const T* ar = A + yl * NQ;
@@ -933,10 +927,11 @@ __device__ __noinline__ void apply2(const T* __restrict__ X, T* __restrict__ Out
 template <typename T, int DIM, class LV, int L>
 __device__ __forceinline__ void apply_level(const Ctx<T, DIM, LV>& c) {
   constexpr int Q = LV::q[L];
-  constexpr bool CACHE = Layout<T, DIM, LV>::cache_G;
+  constexpr bool CACHE = Layout<T, DIM, LV>::cache_G && Layout<T, DIM, LV>::npts(L) > 0;
   if constexpr (Layout<T, DIM, LV>::use_seg(L))
     apply3seg<T, Q, true, CACHE>(lds_cast(c.X()), EpiStore<T, LDSP T*>{lds_cast(c.Out())},
-                                 lds_cast(c.abuf()), lds_cast(c.tabDc(L)), lds_cast(c.jc()),
+                                 lds_cast(c.abuf()), lds_cast(c.tabB(L)), lds_cast(c.tabDc(L)),
+                                 lds_cast(c.jc()),
                                  lds_cast(c.mu()), lds_cast(c.Gc(L)));
   else if constexpr (DIM == 3)
     apply3<T, Q, CACHE>(c.X(), c.Out(), c.abuf(), c.tabB(L), c.tabDc(L), c.tabXg(L), c.tabWg(L),
@@ -956,11 +951,11 @@ __device__ void prepare_geometry(const Ctx<T, DIM, LV>& c) {
   if constexpr (Lay::cache_G) {
     for (int l = 0; l < LV::count; ++l) {
       const int n = LV::q[l] + 1, NQ = 2 * n;
-      const int NP = ipow(NQ, DIM);
+      const int NP = Lay::npts(l);  // 0: this level is never applied matrix-free with the cache
       const T* xg = c.tabXg(l);
       const T* wg = c.tabWg(l);
       T* Gl = c.Gc(l);
-      for (int pt = threadIdx.x; pt < NP; pt += kThreads) {
+      for (int pt = threadIdx.x; pt < NP; pt += NT<T>) {
         const int QX = pt % NQ, QY = (pt / NQ) % NQ, QZ = DIM == 3 ? pt / (NQ * NQ) : 0;
         const int cx = QX >= n, cy = QY >= n, cz = QZ >= n;
         const int kx = QX - cx * n, ky = QY - cy * n, kz = QZ - cz * n;
@@ -988,7 +983,7 @@ __device__ __forceinline__ void load_closure(T* __restrict__ X, const T* __restr
   using SH = Sh<DIM, Q>;
   constexpr int m = SH::m, mi = SH::mi;
 #pragma unroll 1
-  for (int idx = threadIdx.x; idx < SH::closure; idx += kThreads) {
+  for (int idx = threadIdx.x; idx < SH::closure; idx += NT<T>) {
     const int x = idx % m, t = idx / m, y = t % m;
     const int zc = DIM == 3 ? t / m : 0;
     bool in = x > 0 && x < m - 1 && y > 0 && y < m - 1;
@@ -1018,7 +1013,7 @@ __device__ __forceinline__ void apply_vec_epi(const Ctx<T, DIM, LV>& c, const T*
     if (c.dense_ok) {
       constexpr int N = Lay::level_size(L);
       const T* M = c.dense(L);
-      for (int i = threadIdx.x; i < N; i += kThreads) {
+      for (int i = threadIdx.x; i < N; i += NT<T>) {
         T acc = 0;
 #pragma unroll
         for (int j = 0; j < N; ++j) acc += M[i * N + j] * v[j];
@@ -1029,14 +1024,15 @@ __device__ __forceinline__ void apply_vec_epi(const Ctx<T, DIM, LV>& c, const T*
     }
   }
   if constexpr (Lay::use_seg(L) && Lay::vec_in_lds) {
-    apply3seg<T, Q, false, Lay::cache_G>(lds_cast(v), epi, lds_cast(c.abuf()), lds_cast(c.tabDc(L)),
-                                         lds_cast(c.jc()), lds_cast(c.mu()), lds_cast(c.Gc(L)));
+    apply3seg<T, Q, false, (Lay::cache_G && Lay::npts(L) > 0)>(lds_cast(v), epi, lds_cast(c.abuf()), lds_cast(c.tabB(L)),
+                                         lds_cast(c.tabDc(L)), lds_cast(c.jc()), lds_cast(c.mu()),
+                                         lds_cast(c.Gc(L)));
   } else {
     load_closure<T, DIM, Q>(c.X(), v);
     apply_level<T, DIM, LV, L>(c);
     constexpr int N = Lay::level_size(L);
 #pragma unroll 1
-    for (int i = threadIdx.x; i < N; i += kThreads) epi(i, c.Out()[i]);
+    for (int i = threadIdx.x; i < N; i += NT<T>) epi(i, c.Out()[i]);
     __syncthreads();
   }
 }
@@ -1067,7 +1063,7 @@ __device__ __forceinline__ void chebyshev(const Ctx<T, DIM, LV>& c, int k, bool 
   if (x_zero) {
     // r_0 = f, z_0 = D^{-1} f / theta, x = 0
 #pragma unroll 1
-    for (int i = tid; i < N; i += kThreads) {
+    for (int i = tid; i < N; i += NT<T>) {
       res[i] = f[i];
       z[i] = dinv[i] * f[i] / theta;
       x[i] = 0;
@@ -1085,7 +1081,7 @@ __device__ __forceinline__ void chebyshev(const Ctx<T, DIM, LV>& c, int k, bool 
     rho = rho_new;
   }
 #pragma unroll 1
-  for (int i = tid; i < N; i += kThreads) x[i] += z[i];
+  for (int i = tid; i < N; i += NT<T>) x[i] += z[i];
   __syncthreads();
 }
 
@@ -1102,7 +1098,7 @@ __device__ __forceinline__ void restrict_vec(const T* __restrict__ rf, T* __rest
     T* t1 = ab;                       // [c][b][i]: mf*mf*mc
     T* t2 = ab + mf * mf * mc;        // [c][j][i]: mf*mc*mc
 #pragma unroll 1
-    for (int idx = tid; idx < mf * mf * mc; idx += kThreads) {
+    for (int idx = tid; idx < mf * mf * mc; idx += NT<T>) {
       const int i = idx % mc, cb = idx / mc;
       T acc = 0;
       for (int a = 0; a < mf; ++a) acc += P1[a * mc + i] * rf[cb * mf + a];
@@ -1110,7 +1106,7 @@ __device__ __forceinline__ void restrict_vec(const T* __restrict__ rf, T* __rest
     }
     __syncthreads();
 #pragma unroll 1
-    for (int idx = tid; idx < mf * mc * mc; idx += kThreads) {
+    for (int idx = tid; idx < mf * mc * mc; idx += NT<T>) {
       const int i = idx % mc, t = idx / mc, j = t % mc, cc = t / mc;
       T acc = 0;
       for (int b = 0; b < mf; ++b) acc += P1[b * mc + j] * t1[(cc * mf + b) * mc + i];
@@ -1118,7 +1114,7 @@ __device__ __forceinline__ void restrict_vec(const T* __restrict__ rf, T* __rest
     }
     __syncthreads();
 #pragma unroll 1
-    for (int idx = tid; idx < mc * mc * mc; idx += kThreads) {
+    for (int idx = tid; idx < mc * mc * mc; idx += NT<T>) {
       const int ji = idx % (mc * mc), k = idx / (mc * mc);
       T acc = 0;
       for (int cc = 0; cc < mf; ++cc) acc += P1[cc * mc + k] * t2[cc * mc * mc + ji];
@@ -1127,7 +1123,7 @@ __device__ __forceinline__ void restrict_vec(const T* __restrict__ rf, T* __rest
   } else {
     T* t1 = ab;  // [b][i]: mf*mc
 #pragma unroll 1
-    for (int idx = tid; idx < mf * mc; idx += kThreads) {
+    for (int idx = tid; idx < mf * mc; idx += NT<T>) {
       const int i = idx % mc, b = idx / mc;
       T acc = 0;
       for (int a = 0; a < mf; ++a) acc += P1[a * mc + i] * rf[b * mf + a];
@@ -1135,7 +1131,7 @@ __device__ __forceinline__ void restrict_vec(const T* __restrict__ rf, T* __rest
     }
     __syncthreads();
 #pragma unroll 1
-    for (int idx = tid; idx < mc * mc; idx += kThreads) {
+    for (int idx = tid; idx < mc * mc; idx += NT<T>) {
       const int i = idx % mc, j = idx / mc;
       T acc = 0;
       for (int b = 0; b < mf; ++b) acc += P1[b * mc + j] * t1[b * mc + i];
@@ -1155,7 +1151,7 @@ __device__ __forceinline__ void prolong_add(const T* __restrict__ dc, T* __restr
     T* t1 = ab;                  // [k][j][a]: mc*mc*mf
     T* t2 = ab + mc * mc * mf;   // [k][b][a]: mc*mf*mf
 #pragma unroll 1
-    for (int idx = tid; idx < mc * mc * mf; idx += kThreads) {
+    for (int idx = tid; idx < mc * mc * mf; idx += NT<T>) {
       const int a = idx % mf, kj = idx / mf;
       T acc = 0;
       for (int i = 0; i < mc; ++i) acc += P1[a * mc + i] * dc[kj * mc + i];
@@ -1163,7 +1159,7 @@ __device__ __forceinline__ void prolong_add(const T* __restrict__ dc, T* __restr
     }
     __syncthreads();
 #pragma unroll 1
-    for (int idx = tid; idx < mc * mf * mf; idx += kThreads) {
+    for (int idx = tid; idx < mc * mf * mf; idx += NT<T>) {
       const int a = idx % mf, t = idx / mf, b = t % mf, k = t / mf;
       T acc = 0;
       for (int j = 0; j < mc; ++j) acc += P1[b * mc + j] * t1[(k * mc + j) * mf + a];
@@ -1171,7 +1167,7 @@ __device__ __forceinline__ void prolong_add(const T* __restrict__ dc, T* __restr
     }
     __syncthreads();
 #pragma unroll 1
-    for (int idx = tid; idx < mf * mf * mf; idx += kThreads) {
+    for (int idx = tid; idx < mf * mf * mf; idx += NT<T>) {
       const int ba = idx % (mf * mf), cc = idx / (mf * mf);
       T acc = 0;
       for (int k = 0; k < mc; ++k) acc += P1[cc * mc + k] * t2[k * mf * mf + ba];
@@ -1180,7 +1176,7 @@ __device__ __forceinline__ void prolong_add(const T* __restrict__ dc, T* __restr
   } else {
     T* t1 = ab;  // [j][a]: mc*mf
 #pragma unroll 1
-    for (int idx = tid; idx < mc * mf; idx += kThreads) {
+    for (int idx = tid; idx < mc * mf; idx += NT<T>) {
       const int a = idx % mf, j = idx / mf;
       T acc = 0;
       for (int i = 0; i < mc; ++i) acc += P1[a * mc + i] * dc[j * mc + i];
@@ -1188,7 +1184,7 @@ __device__ __forceinline__ void prolong_add(const T* __restrict__ dc, T* __restr
     }
     __syncthreads();
 #pragma unroll 1
-    for (int idx = tid; idx < mf * mf; idx += kThreads) {
+    for (int idx = tid; idx < mf * mf; idx += NT<T>) {
       const int a = idx % mf, b = idx / mf;
       T acc = 0;
       for (int j = 0; j < mc; ++j) acc += P1[b * mc + j] * t1[j * mf + a];
@@ -1257,11 +1253,11 @@ __device__ void load_patch(const Ctx<T, DIM, LV>& c, const PatchArgs& a, int pat
   const T* tab = tptr<T>(a.tab);
   for (int l = 0; l < L; ++l) {
     const int sz = tab_size(LV::q[l]);
-    for (int i = tid; i < sz; i += kThreads) c.lds[Lay::tab_level_off(l) + i] = tab[l * kTabLevelStride + i];
+    for (int i = tid; i < sz; i += NT<T>) c.lds[Lay::tab_level_off(l) + i] = tab[l * kTabLevelStride + i];
   }
   for (int t = 0; t + 1 < L; ++t) {
     const int sz = (2 * LV::q[t] - 1) * (2 * LV::q[t + 1] - 1);
-    for (int i = tid; i < sz; i += kThreads)
+    for (int i = tid; i < sz; i += NT<T>)
       c.lds[Lay::tab_transfer_off(t) + i] =
           tab[kMaxLevels * kTabLevelStride + t * kTabTransferStride + i];
   }
@@ -1269,7 +1265,7 @@ __device__ void load_patch(const Ctx<T, DIM, LV>& c, const PatchArgs& a, int pat
   const int vlin = a.patch_vertex[patch];
   const int N1 = a.N + 1;
   const int vx = vlin % N1, vy = (vlin / N1) % N1, vz = DIM == 3 ? vlin / (N1 * N1) : 0;
-  for (int i = tid; i < Lay::nvert * DIM; i += kThreads) {
+  for (int i = tid; i < Lay::nvert * DIM; i += NT<T>) {
     const int r = i % DIM, t = i / DIM;
     const int tx = t % 3, ty = (t / 3) % 3, tz = DIM == 3 ? t / 9 : 0;
     int g = (vx - 1 + tx) + (vy - 1 + ty) * N1;
@@ -1277,32 +1273,32 @@ __device__ void load_patch(const Ctx<T, DIM, LV>& c, const PatchArgs& a, int pat
     const double centre = a.verts[vlin * DIM + r];
     c.geo()[i] = T(a.verts[g * DIM + r] - centre);
   }
-  for (int i = tid; i < ipow(2, DIM); i += kThreads) {
+  for (int i = tid; i < ipow(2, DIM); i += NT<T>) {
     const int cx = i & 1, cy = (i >> 1) & 1, cz = (i >> 2) & 1;
     int g = (vx - 1 + cx) + (vy - 1 + cy) * a.N;
     if (DIM == 3) g += (vz - 1 + cz) * a.N * a.N;
     c.mu()[i] = T(a.mu[g]);
   }
   const T* cheb = tptr<T>(a.cheb);
-  for (int i = tid; i < 2 * (L - 1); i += kThreads) c.cheb()[i] = cheb[(int64_t)patch * 2 * (L - 1) + i];
+  for (int i = tid; i < 2 * (L - 1); i += NT<T>) c.cheb()[i] = cheb[(int64_t)patch * 2 * (L - 1) + i];
   for (int l = 0; l < L; ++l) {
     const int sz = Lay::level_size(l);
     const T* src = tptr<T>(a.invdiag[l]) + (int64_t)patch * sz;
     T* dst = c.dinv(l);
-    for (int i = tid; i < sz; i += kThreads) dst[i] = src[i];
+    for (int i = tid; i < sz; i += NT<T>) dst[i] = src[i];
   }
   for (int l = 0; l < L; ++l) {
     if (!Lay::dense_level(l)) continue;
     const int sz = Lay::level_size(l) * Lay::level_size(l);
     const T* src = tptr<T>(a.dense[l]) + (int64_t)patch * sz;
     T* dst = c.dense(l);
-    for (int i = tid; i < sz; i += kThreads) dst[i] = src[i];
+    for (int i = tid; i < sz; i += NT<T>) dst[i] = src[i];
   }
   __syncthreads();
 }
 
 template <typename T, int DIM, class LV, int MODE>
-__global__ __launch_bounds__(kThreads) void patch_kernel(PatchArgs a) {
+__global__ __launch_bounds__(NT<T>) void patch_kernel(PatchArgs a) {
   using Lay = Layout<T, DIM, LV>;
   using S0 = Sh<DIM, LV::q[0]>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1326,11 +1322,11 @@ __global__ __launch_bounds__(kThreads) void patch_kernel(PatchArgs a) {
       constexpr int NL = Lay::level_size(L);
       T* v = c.z();
       const double* in = a.in + (int64_t)patch * NL;
-      for (int i = tid; i < NL; i += kThreads) v[i] = T(in[i]);
+      for (int i = tid; i < NL; i += NT<T>) v[i] = T(in[i]);
       __syncthreads();
       apply_vec<T, DIM, LV, L>(c, v);
       double* out = a.out + (int64_t)patch * NL;
-      for (int i = tid; i < NL; i += kThreads) out[i] = double(c.Out()[i]);
+      for (int i = tid; i < NL; i += NT<T>) out[i] = double(c.Out()[i]);
     };
     if (a.level == 0) run(std::integral_constant<int, 0>{});
     if constexpr (LV::count > 1)
@@ -1348,28 +1344,28 @@ __global__ __launch_bounds__(kThreads) void patch_kernel(PatchArgs a) {
       patch_base<DIM>(a.patch_vertex[patch], a.N, a.p, base, M);
       T* X = c.X();
   #pragma unroll 1
-    for (int idx = tid; idx < S0::closure; idx += kThreads) {
+    for (int idx = tid; idx < S0::closure; idx += NT<T>) {
         const int x = idx % m, t = idx / m, y = t % m, z = DIM == 3 ? t / m : 0;
         X[idx] = T(a.u[base + x + y * M + (int64_t)z * M * M]);
       }
   #pragma unroll 1
-    for (int idx = tid; idx < N0; idx += kThreads) {
+    for (int idx = tid; idx < N0; idx += NT<T>) {
         const int x = idx % mi + 1, t = idx / mi, y = t % mi + 1, z = DIM == 3 ? t / mi + 1 : 0;
         r0[idx] = T(a.b[base + x + y * M + (int64_t)z * M * M]);
       }
       __syncthreads();
       // evaluate: r_j = b_j - Pi_j A-bar_j u-bar_j (equation main:4)
       apply_level<T, DIM, LV, 0>(c);
-      for (int i = tid; i < N0; i += kThreads) r0[i] -= c.Out()[i];
+      for (int i = tid; i < N0; i += NT<T>) r0[i] -= c.Out()[i];
       __syncthreads();
       if constexpr (MODE == kModeResidual) {
         double* out = a.out + (int64_t)patch * N0;
-        for (int i = tid; i < N0; i += kThreads) out[i] = double(r0[i]);
+        for (int i = tid; i < N0; i += NT<T>) out[i] = double(r0[i]);
         return;
       }
     } else {
       const double* in = a.in + (int64_t)patch * N0;
-      for (int i = tid; i < N0; i += kThreads) r0[i] = T(in[i]);
+      for (int i = tid; i < N0; i += NT<T>) r0[i] = T(in[i]);
       __syncthreads();
     }
     // local solve: N_MG V-cycles from zero (equation main:5)
@@ -1378,13 +1374,13 @@ __global__ __launch_bounds__(kThreads) void patch_kernel(PatchArgs a) {
     if constexpr (MODE == kModeSmooth) {
       // scatter-add in FP64 (equation scatter); interiors of one colour are disjoint
   #pragma unroll 1
-    for (int idx = tid; idx < N0; idx += kThreads) {
+    for (int idx = tid; idx < N0; idx += NT<T>) {
         const int x = idx % mi + 1, t = idx / mi, y = t % mi + 1, z = DIM == 3 ? t / mi + 1 : 0;
         a.u[base + x + y * M + (int64_t)z * M * M] += double(d0[idx]);
       }
     } else {
       double* out = a.out + (int64_t)patch * N0;
-      for (int i = tid; i < N0; i += kThreads) out[i] = double(d0[i]);
+      for (int i = tid; i < N0; i += NT<T>) out[i] = double(d0[i]);
     }
   }
 }
@@ -1395,7 +1391,7 @@ __global__ __launch_bounds__(kThreads) void patch_kernel(PatchArgs a) {
 // ---------------------------------------------------------------------------
 
 template <int DIM, class LV>
-__global__ __launch_bounds__(kThreads) void diag_kernel(PatchArgs a) {
+__global__ __launch_bounds__(NT<double>) void diag_kernel(PatchArgs a) {
   using T = double;
   using Lay = Layout<T, DIM, LV>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1411,19 +1407,19 @@ __global__ __launch_bounds__(kThreads) void diag_kernel(PatchArgs a) {
     const T* tab = a.tab64;
     for (int l = 0; l < LV::count; ++l) {
       const int sz = tab_size(LV::q[l]);
-      for (int i = tid; i < sz; i += kThreads) c.lds[Lay::tab_level_off(l) + i] = tab[l * kTabLevelStride + i];
+      for (int i = tid; i < sz; i += NT<T>) c.lds[Lay::tab_level_off(l) + i] = tab[l * kTabLevelStride + i];
     }
     const int vlin = a.patch_vertex[patch];
     const int N1 = a.N + 1;
     const int vx = vlin % N1, vy = (vlin / N1) % N1, vz = DIM == 3 ? vlin / (N1 * N1) : 0;
-    for (int i = tid; i < Lay::nvert * DIM; i += kThreads) {
+    for (int i = tid; i < Lay::nvert * DIM; i += NT<T>) {
       const int r = i % DIM, t = i / DIM;
       const int tx = t % 3, ty = (t / 3) % 3, tz = DIM == 3 ? t / 9 : 0;
       int g = (vx - 1 + tx) + (vy - 1 + ty) * N1;
       if (DIM == 3) g += (vz - 1 + tz) * N1 * N1;
       c.geo()[i] = a.verts[g * DIM + r] - a.verts[vlin * DIM + r];
     }
-    for (int i = tid; i < ipow(2, DIM); i += kThreads) {
+    for (int i = tid; i < ipow(2, DIM); i += NT<T>) {
       const int cx = i & 1, cy = (i >> 1) & 1, cz = (i >> 2) & 1;
       int g = (vx - 1 + cx) + (vy - 1 + cy) * a.N;
       if (DIM == 3) g += (vz - 1 + cz) * a.N * a.N;
@@ -1443,11 +1439,11 @@ __global__ __launch_bounds__(kThreads) void diag_kernel(PatchArgs a) {
     const T* D = c.tabD(L);
     const T* xg = c.tabXg(L);
     const T* wg = c.tabWg(L);
-    for (int i = tid; i < ipow(m, DIM); i += kThreads) dg[i] = 0;
+    for (int i = tid; i < ipow(m, DIM); i += NT<T>) dg[i] = 0;
     __syncthreads();
     for (int cell = 0; cell < ncell; ++cell) {
       const int cx = cell & 1, cy = (cell >> 1) & 1, cz = (cell >> 2) & 1;
-      for (int k = tid; k < npt; k += kThreads) {
+      for (int k = tid; k < npt; k += NT<T>) {
         const int kx = k % n, ky = (k / n) % n, kz = DIM == 3 ? k / (n * n) : 0;
         if constexpr (DIM == 3)
           metric3<T>(c.geo(), cx, cy, cz, xg[kx], xg[ky], xg[kz],
@@ -1456,7 +1452,7 @@ __global__ __launch_bounds__(kThreads) void diag_kernel(PatchArgs a) {
           metric2<T>(c.geo(), cx, cy, xg[kx], xg[ky], c.mu()[cell] * wg[kx] * wg[ky], G + NG * k);
       }
       __syncthreads();
-      for (int aidx = tid; aidx < npt; aidx += kThreads) {
+      for (int aidx = tid; aidx < npt; aidx += NT<T>) {
         const int ax = aidx % n, ay = (aidx / n) % n, az = DIM == 3 ? aidx / (n * n) : 0;
         T acc = 0;
         for (int k = 0; k < npt; ++k) {
@@ -1482,7 +1478,7 @@ __global__ __launch_bounds__(kThreads) void diag_kernel(PatchArgs a) {
     }
     constexpr int NL = Lay::level_size(L);
     double* out = const_cast<double*>(a.invdiag64[L]) + (int64_t)patch * NL;
-    for (int i = tid; i < NL; i += kThreads) {
+    for (int i = tid; i < NL; i += NT<T>) {
       const int x = i % mi + 1, t = i / mi, y = t % mi + 1, z = DIM == 3 ? t / mi + 1 : 0;
       out[i] = 1.0 / dg[x + y * m + z * m * m];
     }
@@ -1508,6 +1504,7 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t n) {
 }
 
 __device__ double block_sum(double v, double* red) {
+  using T = double;
   // wavefront shuffle reduction, then across the waves of the block
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1515,7 +1512,7 @@ __device__ double block_sum(double v, double* red) {
   if (lane == 0) red[wave] = v;
   __syncthreads();
   double s = 0;
-  for (int w = 0; w < kThreads / 64; ++w) s += red[w];
+  for (int w = 0; w < NT<T> / 64; ++w) s += red[w];
   __syncthreads();
   return s;
 }
@@ -1562,49 +1559,49 @@ __device__ void lanczos_level(Ctx<double, DIM, LV>& c, const PatchArgs& a, int p
   double* Vb = a.lanczos_basis + (int64_t)blockIdx.x * (int64_t)a.lanczos_steps * NL;
   T* w = c.res();
   T* s = c.z();   // s = sqrt(dinv) * v, the operator input
-  __shared__ double red[kThreads / 64];
+  __shared__ double red[NT<double> / 64];
   __shared__ double al[64], be[64], coef[64];
   const T* dinv = c.dinv(L);
   // start vector: entry i of patch vertex v at smoothed level L
   const uint64_t vlin = (uint64_t)a.patch_vertex[patch];
   const uint64_t base = ((vlin * 16u + (uint64_t)L) << 24);
   double nrm = 0;
-  for (int i = tid; i < NL; i += kThreads) {
+  for (int i = tid; i < NL; i += NT<T>) {
     const double x = (double)(splitmix64(a.seed, base + (uint64_t)i) >> 11) * 0x1.0p-52 - 1.0;
     Vb[i] = x;
     nrm += x * x;
   }
   nrm = sqrt(block_sum(nrm, red));
-  for (int i = tid; i < NL; i += kThreads) Vb[i] /= nrm;
+  for (int i = tid; i < NL; i += NT<T>) Vb[i] /= nrm;
   __syncthreads();
   double b_prev = 0;
   int steps = 0;
   for (int j = 0; j < m; ++j) {
     const double* v = Vb + (int64_t)j * NL;
-    for (int i = tid; i < NL; i += kThreads) s[i] = sqrt(dinv[i]) * v[i];
+    for (int i = tid; i < NL; i += NT<T>) s[i] = sqrt(dinv[i]) * v[i];
     __syncthreads();
     apply_vec<T, DIM, LV, L>(c, s);
     double dot = 0;
-    for (int i = tid; i < NL; i += kThreads) {
+    for (int i = tid; i < NL; i += NT<T>) {
       double wi = sqrt(dinv[i]) * c.Out()[i];
       if (j > 0) wi -= b_prev * Vb[(int64_t)(j - 1) * NL + i];
       w[i] = wi;
       dot += wi * v[i];
     }
     const double alpha = block_sum(dot, red);
-    for (int i = tid; i < NL; i += kThreads) w[i] -= alpha * v[i];
+    for (int i = tid; i < NL; i += NT<T>) w[i] -= alpha * v[i];
     __syncthreads();
     // full reorthogonalisation (classical Gram-Schmidt, twice)
     for (int pass = 0; pass < 2; ++pass) {
       for (int q = 0; q <= j; ++q) {
         const double* vq = Vb + (int64_t)q * NL;
         double cq = 0;
-        for (int i = tid; i < NL; i += kThreads) cq += vq[i] * w[i];
+        for (int i = tid; i < NL; i += NT<T>) cq += vq[i] * w[i];
         cq = block_sum(cq, red);
         if (tid == 0) coef[q] = cq;
       }
       __syncthreads();
-      for (int i = tid; i < NL; i += kThreads) {
+      for (int i = tid; i < NL; i += NT<T>) {
         double wi = w[i];
         for (int q = 0; q <= j; ++q) wi -= coef[q] * Vb[(int64_t)q * NL + i];
         w[i] = wi;
@@ -1613,13 +1610,13 @@ __device__ void lanczos_level(Ctx<double, DIM, LV>& c, const PatchArgs& a, int p
     }
     if (tid == 0) al[j] = alpha;
     double bn = 0;
-    for (int i = tid; i < NL; i += kThreads) bn += w[i] * w[i];
+    for (int i = tid; i < NL; i += NT<T>) bn += w[i] * w[i];
     bn = sqrt(block_sum(bn, red));
     steps = j + 1;
     if (j == m - 1 || bn < 1e-12 * fabs(alpha)) break;
     if (tid == 0) be[j] = bn;
     double* vn = Vb + (int64_t)(j + 1) * NL;
-    for (int i = tid; i < NL; i += kThreads) vn[i] = w[i] / bn;
+    for (int i = tid; i < NL; i += NT<T>) vn[i] = w[i] / bn;
     b_prev = bn;
     __syncthreads();
   }
@@ -1640,7 +1637,7 @@ __device__ void lanczos_level(Ctx<double, DIM, LV>& c, const PatchArgs& a, int p
 }
 
 template <int DIM, class LV>
-__global__ __launch_bounds__(kThreads) void lanczos_kernel(PatchArgs a) {
+__global__ __launch_bounds__(NT<double>) void lanczos_kernel(PatchArgs a) {
   using T = double;
   using Lay = Layout<T, DIM, LV>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1656,19 +1653,19 @@ __global__ __launch_bounds__(kThreads) void lanczos_kernel(PatchArgs a) {
     const T* tab = a.tab64;
     for (int l = 0; l < LV::count; ++l) {
       const int sz = tab_size(LV::q[l]);
-      for (int i = tid; i < sz; i += kThreads) c.lds[Lay::tab_level_off(l) + i] = tab[l * kTabLevelStride + i];
+      for (int i = tid; i < sz; i += NT<T>) c.lds[Lay::tab_level_off(l) + i] = tab[l * kTabLevelStride + i];
     }
     const int vlin = a.patch_vertex[patch];
     const int N1 = a.N + 1;
     const int vx = vlin % N1, vy = (vlin / N1) % N1, vz = DIM == 3 ? vlin / (N1 * N1) : 0;
-    for (int i = tid; i < Lay::nvert * DIM; i += kThreads) {
+    for (int i = tid; i < Lay::nvert * DIM; i += NT<T>) {
       const int r = i % DIM, t = i / DIM;
       const int tx = t % 3, ty = (t / 3) % 3, tz = DIM == 3 ? t / 9 : 0;
       int g = (vx - 1 + tx) + (vy - 1 + ty) * N1;
       if (DIM == 3) g += (vz - 1 + tz) * N1 * N1;
       c.geo()[i] = a.verts[g * DIM + r] - a.verts[vlin * DIM + r];
     }
-    for (int i = tid; i < ipow(2, DIM); i += kThreads) {
+    for (int i = tid; i < ipow(2, DIM); i += NT<T>) {
       const int cx = i & 1, cy = (i >> 1) & 1, cz = (i >> 2) & 1;
       int g = (vx - 1 + cx) + (vy - 1 + cy) * a.N;
       if (DIM == 3) g += (vz - 1 + cz) * a.N * a.N;
@@ -1677,7 +1674,7 @@ __global__ __launch_bounds__(kThreads) void lanczos_kernel(PatchArgs a) {
     for (int l = 0; l < LV::count; ++l) {
       const int sz = Lay::level_size(l);
       const double* src = a.invdiag64[l] + (int64_t)patch * sz;
-      for (int i = tid; i < sz; i += kThreads) c.dinv(l)[i] = src[i];
+      for (int i = tid; i < sz; i += NT<T>) c.dinv(l)[i] = src[i];
     }
     __syncthreads();
   }
@@ -1695,7 +1692,7 @@ __global__ __launch_bounds__(kThreads) void lanczos_kernel(PatchArgs a) {
 // ---------------------------------------------------------------------------
 
 template <int DIM, class LV>
-__global__ __launch_bounds__(kThreads) void dense_kernel(PatchArgs a) {
+__global__ __launch_bounds__(NT<double>) void dense_kernel(PatchArgs a) {
   using T = double;
   using Lay = Layout<T, DIM, LV>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1710,19 +1707,19 @@ __global__ __launch_bounds__(kThreads) void dense_kernel(PatchArgs a) {
     const T* tab = a.tab64;
     for (int l = 0; l < LV::count; ++l) {
       const int sz = tab_size(LV::q[l]);
-      for (int i = tid; i < sz; i += kThreads) c.lds[Lay::tab_level_off(l) + i] = tab[l * kTabLevelStride + i];
+      for (int i = tid; i < sz; i += NT<T>) c.lds[Lay::tab_level_off(l) + i] = tab[l * kTabLevelStride + i];
     }
     const int vlin = a.patch_vertex[patch];
     const int N1 = a.N + 1;
     const int vx = vlin % N1, vy = (vlin / N1) % N1, vz = DIM == 3 ? vlin / (N1 * N1) : 0;
-    for (int i = tid; i < Lay::nvert * DIM; i += kThreads) {
+    for (int i = tid; i < Lay::nvert * DIM; i += NT<T>) {
       const int r = i % DIM, t = i / DIM;
       const int tx = t % 3, ty = (t / 3) % 3, tz = DIM == 3 ? t / 9 : 0;
       int g = (vx - 1 + tx) + (vy - 1 + ty) * N1;
       if (DIM == 3) g += (vz - 1 + tz) * N1 * N1;
       c.geo()[i] = a.verts[g * DIM + r] - a.verts[vlin * DIM + r];
     }
-    for (int i = tid; i < ipow(2, DIM); i += kThreads) {
+    for (int i = tid; i < ipow(2, DIM); i += NT<T>) {
       const int cx = i & 1, cy = (i >> 1) & 1, cz = (i >> 2) & 1;
       int g = (vx - 1 + cx) + (vy - 1 + cy) * a.N;
       if (DIM == 3) g += (vz - 1 + cz) * a.N * a.N;
@@ -1738,10 +1735,10 @@ __global__ __launch_bounds__(kThreads) void dense_kernel(PatchArgs a) {
       double* M = a.dense64[L] + (int64_t)patch * N * N;
       T* e = c.z();
       for (int j = 0; j < N; ++j) {
-        for (int i = tid; i < N; i += kThreads) e[i] = i == j ? 1.0 : 0.0;
+        for (int i = tid; i < N; i += NT<T>) e[i] = i == j ? 1.0 : 0.0;
         __syncthreads();
         apply_vec<T, DIM, LV, L>(c, e);
-        for (int i = tid; i < N; i += kThreads) M[i * N + j] = c.Out()[i];
+        for (int i = tid; i < N; i += NT<T>) M[i * N + j] = c.Out()[i];
         __syncthreads();
       }
     }
@@ -1775,7 +1772,7 @@ hipError_t allow_lds(K kernel, size_t bytes) {
 
 // On a failed launch, print what the runtime knows about the kernel.
 template <typename K>
-hipError_t report_launch(K kernel, const char* what, dim3 grid, size_t lds) {
+hipError_t report_launch(K kernel, const char* what, dim3 grid, size_t lds, int threads = 256) {
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) return e;
   hipFuncAttributes fa{};
@@ -1783,7 +1780,7 @@ hipError_t report_launch(K kernel, const char* what, dim3 grid, size_t lds) {
   fprintf(stderr,
           "libpmg: launch of %s failed: %s (grid %u, block %d, dynamic LDS %zu); attributes "
           "(%s): maxThreads %d, static LDS %zu, max dynamic LDS %d, regs %d, local %zu\n",
-          what, hipGetErrorString(e), grid.x, kThreads, lds, hipGetErrorString(e2),
+          what, hipGetErrorString(e), grid.x, threads, lds, hipGetErrorString(e2),
           fa.maxThreadsPerBlock, fa.sharedSizeBytes, fa.maxDynamicSharedSizeBytes, fa.numRegs,
           fa.localSizeBytes);
   return e;
@@ -1797,29 +1794,29 @@ struct Variant {
   static hipError_t launch(int mode, const PatchArgs& a, hipStream_t s) {
     if (a.n_patch <= 0) return hipSuccess;
     const size_t lds = lds_bytes(mode);
-    dim3 grid(a.n_patch), block(kThreads);
+    dim3 grid(a.n_patch), block(NT<T>);
     hipError_t e = hipSuccess;
     switch (mode) {
       case kModeSmooth:
         if ((e = allow_lds(patch_kernel<T, DIM, LV, kModeSmooth>, lds))) return e;
         (void)hipGetLastError();  // clear a stale error of an earlier call
         hipLaunchKernelGGL((patch_kernel<T, DIM, LV, kModeSmooth>), grid, block, lds, s, a);
-        return report_launch(patch_kernel<T, DIM, LV, kModeSmooth>, "patch", grid, lds);
+        return report_launch(patch_kernel<T, DIM, LV, kModeSmooth>, "patch", grid, lds, NT<T>);
       case kModeResidual:
         if ((e = allow_lds(patch_kernel<T, DIM, LV, kModeResidual>, lds))) return e;
         (void)hipGetLastError();  // clear a stale error of an earlier call
         hipLaunchKernelGGL((patch_kernel<T, DIM, LV, kModeResidual>), grid, block, lds, s, a);
-        return report_launch(patch_kernel<T, DIM, LV, kModeResidual>, "patch", grid, lds);
+        return report_launch(patch_kernel<T, DIM, LV, kModeResidual>, "patch", grid, lds, NT<T>);
       case kModeSolve:
         if ((e = allow_lds(patch_kernel<T, DIM, LV, kModeSolve>, lds))) return e;
         (void)hipGetLastError();  // clear a stale error of an earlier call
         hipLaunchKernelGGL((patch_kernel<T, DIM, LV, kModeSolve>), grid, block, lds, s, a);
-        return report_launch(patch_kernel<T, DIM, LV, kModeSolve>, "patch", grid, lds);
+        return report_launch(patch_kernel<T, DIM, LV, kModeSolve>, "patch", grid, lds, NT<T>);
       case kModeApply:
         if ((e = allow_lds(patch_kernel<T, DIM, LV, kModeApply>, lds))) return e;
         (void)hipGetLastError();  // clear a stale error of an earlier call
         hipLaunchKernelGGL((patch_kernel<T, DIM, LV, kModeApply>), grid, block, lds, s, a);
-        return report_launch(patch_kernel<T, DIM, LV, kModeApply>, "patch", grid, lds);
+        return report_launch(patch_kernel<T, DIM, LV, kModeApply>, "patch", grid, lds, NT<T>);
       default:
         return hipErrorInvalidValue;
     }
@@ -1832,7 +1829,7 @@ struct Variant {
     hipError_t e = allow_lds(diag_kernel<DIM, LV>, lds);
     if (e != hipSuccess) return e;
     (void)hipGetLastError();
-    hipLaunchKernelGGL((diag_kernel<DIM, LV>), dim3(a.n_patch), dim3(kThreads), lds, s, a);
+    hipLaunchKernelGGL((diag_kernel<DIM, LV>), dim3(a.n_patch), dim3(NT<double>), lds, s, a);
     return report_launch(diag_kernel<DIM, LV>, "diag", dim3(a.n_patch), lds);
   }
   static hipError_t launch_dense(const PatchArgs& a, hipStream_t s) {
@@ -1842,7 +1839,7 @@ struct Variant {
     hipError_t e = allow_lds(dense_kernel<DIM, LV>, lds);
     if (e != hipSuccess) return e;
     (void)hipGetLastError();
-    hipLaunchKernelGGL((dense_kernel<DIM, LV>), dim3(a.n_patch), dim3(kThreads), lds, s, a);
+    hipLaunchKernelGGL((dense_kernel<DIM, LV>), dim3(a.n_patch), dim3(NT<double>), lds, s, a);
     return report_launch(dense_kernel<DIM, LV>, "dense", dim3(a.n_patch), lds);
   }
   static hipError_t launch_lanczos(const PatchArgs& a, int level, hipStream_t s) {
@@ -1854,7 +1851,7 @@ struct Variant {
     hipError_t e = allow_lds(lanczos_kernel<DIM, LV>, lds);
     if (e != hipSuccess) return e;
     (void)hipGetLastError();
-    hipLaunchKernelGGL((lanczos_kernel<DIM, LV>), dim3(a.n_patch), dim3(kThreads), lds, s, b);
+    hipLaunchKernelGGL((lanczos_kernel<DIM, LV>), dim3(a.n_patch), dim3(NT<double>), lds, s, b);
     return report_launch(lanczos_kernel<DIM, LV>, "lanczos", dim3(a.n_patch), lds);
   }
 };
