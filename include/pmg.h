@@ -145,6 +145,24 @@ int pmg_get_bounds(const pmg_handle* h, double* lam);
  * Chebyshev intervals.  Requires 0 < lambda_min <= lambda_max. */
 int pmg_set_bounds(pmg_handle* h, const double* lam);
 
+/* A batch of n independent vertex patches (no mesh): every patch has its own
+ * 3^dim vertices (offsets t in {0,1,2}^dim, x fastest; the patch vertex is
+ * t = (1,...,1)) and 2^dim cell coefficients (cell c = sum c_i 2^i).
+ * verts: host, n x 3^dim x dim; coeff: host, n x 2^dim; both copied.  The
+ * handle supports the batched entry points (apply, local solve, inverse
+ * diagonals, bounds, features) but not pmg_patch_smooth / pmg_patch_residual
+ * (there is no global vector).  Lanczos start vectors use the patch number in
+ * place of the vertex index.  Same errors as pmg_patch_setup. */
+int pmg_patches_setup(int32_t dim, int64_t n, const double* verts, const double* coeff, int32_t p,
+                      const pmg_opts* opts, pmg_handle** out);
+
+/* Features of every patch for the bound-predicting network: for each cell c
+ * and each point g of the 2-point Gauss rule, det J / h^d, ||J||_F^2 / h^2 and
+ * ||cof J||_F^2 / h^(2(d-1)) at index (c 2^d + g) 3 + {0,1,2}, then
+ * log10 mu_c minus the patch mean at 3 4^d + c; h = (mean cell volume)^(1/d).
+ * out: device, n_patches x (3 4^d + 2^d) floats (200 in 3D, 52 in 2D). */
+int pmg_patch_features(pmg_handle* h, float* out);
+
 /* Linear vertex index sum_i v_i (N+1)^i of every patch, in patch order.
  * out: host, n_patches int32. */
 int pmg_get_patch_vertices(const pmg_handle* h, int32_t* out);
@@ -183,6 +201,45 @@ int gmg_query(const gmg_handle* g, int32_t what, int64_t* value);
 int gmg_level_smoother(gmg_handle* g, int32_t level, pmg_handle** h);
 
 int gmg_destroy(gmg_handle* g);
+
+/* Bound-predicting network: n_in -> 64 -> 64 -> 64 -> n_out, tanh hidden
+ * layers, linear output, inputs standardised by a stored mean and 1/std.
+ * Parameters (FP32) in the layout W1 (n_in x 64, row-major), b1, W2, b2, W3,
+ * b3, W4 (64 x n_out), b4.  Trained by mean squared error with Adam on the
+ * GPU.  All work on the given stream; max_batch bounds the rows processed at
+ * once (training batches, gradients). */
+typedef struct pmg_mlp pmg_mlp;
+int pmg_mlp_param_count(int32_t n_in, int32_t n_out, int64_t* count);
+/* params: host, param_count floats (the initial weights). */
+int pmg_mlp_create(int32_t n_in, int32_t n_out, const float* params, int64_t max_batch, void* stream,
+                   pmg_mlp** out);
+int pmg_mlp_get_params(const pmg_mlp* m, float* params);   /* host */
+int pmg_mlp_set_params(pmg_mlp* m, const float* params);   /* host; resets Adam */
+/* mean and 1/std of every input over the rows of X (device, n x n_in). */
+int pmg_mlp_fit_standardizer(pmg_mlp* m, const float* X, int64_t n);
+int pmg_mlp_get_standardizer(const pmg_mlp* m, float* mean, float* inv_std); /* host, n_in each */
+int pmg_mlp_set_standardizer(pmg_mlp* m, const float* mean, const float* inv_std);
+/* Y = net(X): X device n x n_in, Y device n x n_out. */
+int pmg_mlp_predict(pmg_mlp* m, const float* X, int64_t n, float* Y);
+/* gradient of the mean squared error over all rows (n <= max_batch):
+ * X, T device; grad host (param_count); loss host. */
+int pmg_mlp_gradient(pmg_mlp* m, const float* X, const float* T, int64_t n, float* grad, double* loss);
+/* Adam (beta 0.9, 0.999, eps 1e-8) over `epochs` passes; order (device,
+ * epochs x n int32) lists the sample of every position of every epoch;
+ * batches of `batch` consecutive positions.  epoch_loss: host, mean batch loss
+ * of every epoch (may be NULL).  Synchronous. */
+int pmg_mlp_train(pmg_mlp* m, const float* X, const float* T, int64_t n, const int32_t* order,
+                  int32_t epochs, int32_t batch, float lr, double* epoch_loss);
+int pmg_mlp_destroy(pmg_mlp* m);
+
+/* Chebyshev bounds from the network: features of every patch, prediction of
+ * (ln lambda_min, ln lambda_max) per smoothed level, lambda_max raised by the
+ * factor exp(margin).  Patches with a standardised feature beyond ood_z in
+ * magnitude (outside the training distribution) or a non-finite prediction
+ * fall back to per-patch Lanczos; n_fallback (host, may be NULL) returns their
+ * number.  The network must have 3 4^d + 2^d inputs and 2 (n_levels - 1)
+ * outputs.  Synchronous. */
+int pmg_set_bounds_mlp(pmg_handle* h, pmg_mlp* m, double margin, double ood_z, int64_t* n_fallback);
 
 const char* pmg_last_error(void);
 

@@ -8,7 +8,7 @@ The compute path is libpmg.so (HIP kernels, built in-tree by
 streams.  Importing this package does not load the library; constructing a
 solver does, and fails loudly when it is missing.
 """
-from .api import GMGSolver, PatchSmoother  # noqa: F401
+from .api import BoundNet, GMGSolver, PatchBatch, PatchSmoother, n_features  # noqa: F401
 from . import _lib  # noqa: F401
 
-__all__ = ["PatchSmoother", "GMGSolver"]
+__all__ = ["PatchSmoother", "PatchBatch", "BoundNet", "GMGSolver", "n_features"]

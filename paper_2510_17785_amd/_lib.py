@@ -37,7 +37,11 @@ EXPORTS = [
     "pmg_patch_residual", "pmg_patch_apply", "pmg_patch_local_solve", "pmg_get_inv_diag",
     "pmg_get_bounds", "pmg_set_bounds", "pmg_get_patch_vertices", "pmg_query",
     "pmg_patch_destroy", "gmg_setup", "gmg_apply", "gmg_vcycle", "gmg_cg_solve", "gmg_query",
-    "gmg_level_smoother", "gmg_destroy", "pmg_last_error",
+    "gmg_level_smoother", "gmg_destroy", "pmg_last_error", "pmg_patches_setup",
+    "pmg_patch_features", "pmg_mlp_param_count", "pmg_mlp_create", "pmg_mlp_get_params",
+    "pmg_mlp_set_params", "pmg_mlp_fit_standardizer", "pmg_mlp_get_standardizer",
+    "pmg_mlp_set_standardizer", "pmg_mlp_predict", "pmg_mlp_gradient", "pmg_mlp_train",
+    "pmg_mlp_destroy", "pmg_set_bounds_mlp",
 ]
 
 
@@ -75,6 +79,7 @@ def load() -> ctypes.CDLL:
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     D = ctypes.POINTER(ctypes.c_double)
+    F = ctypes.POINTER(ctypes.c_float)
     i32 = ctypes.c_int32
     sig = {
         "pmg_default_opts": [ctypes.POINTER(PmgOpts)],
@@ -100,6 +105,22 @@ def load() -> ctypes.CDLL:
         "gmg_level_smoother": [P, i32, ctypes.POINTER(P)],
         "gmg_destroy": [P],
         "pmg_last_error": [],
+        "pmg_patches_setup": [i32, ctypes.c_int64, D, D, i32, ctypes.POINTER(PmgOpts),
+                              ctypes.POINTER(P)],
+        "pmg_patch_features": [P, P],
+        "pmg_mlp_param_count": [i32, i32, ctypes.POINTER(ctypes.c_int64)],
+        "pmg_mlp_create": [i32, i32, F, ctypes.c_int64, P, ctypes.POINTER(P)],
+        "pmg_mlp_get_params": [P, F],
+        "pmg_mlp_set_params": [P, F],
+        "pmg_mlp_fit_standardizer": [P, P, ctypes.c_int64],
+        "pmg_mlp_get_standardizer": [P, F, F],
+        "pmg_mlp_set_standardizer": [P, F, F],
+        "pmg_mlp_predict": [P, P, ctypes.c_int64, P],
+        "pmg_mlp_gradient": [P, P, P, ctypes.c_int64, F, ctypes.POINTER(ctypes.c_double)],
+        "pmg_mlp_train": [P, P, P, ctypes.c_int64, P, i32, i32, ctypes.c_float, D],
+        "pmg_mlp_destroy": [P],
+        "pmg_set_bounds_mlp": [P, P, ctypes.c_double, ctypes.c_double,
+                               ctypes.POINTER(ctypes.c_int64)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)

@@ -48,6 +48,21 @@ def _opts(levels, precision, cheb_degree, n_vcycles, bounds, lanczos_steps, cheb
     return o
 
 
+def _fptr(t: torch.Tensor) -> int:
+    if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+        raise ValueError("expected a contiguous float32 device tensor")
+    return t.data_ptr()
+
+
+def _host_f(a):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def n_features(dim: int) -> int:
+    return 3 * 4 ** dim + 2 ** dim
+
+
 def _mesh(dim, n, vertices):
     v = np.ascontiguousarray(vertices, dtype=np.float64)
     if v.shape != ((n + 1) ** dim, dim):
@@ -139,6 +154,19 @@ class PatchSmoother:
         L.check(self._lib.pmg_get_inv_diag(self._h, int(level), _dptr(out)))
         return out
 
+    def features(self) -> torch.Tensor:
+        """pmg_patch_features: (n_patches, n_features) float32 on the device."""
+        out = torch.empty((self.n_patches, n_features(self.dim)), dtype=torch.float32, device="cuda")
+        L.check(self._lib.pmg_patch_features(self._h, _fptr(out)))
+        return out
+
+    def set_bounds_mlp(self, net: "BoundNet", margin: float, ood_z: float = 8.0) -> int:
+        """pmg_set_bounds_mlp; returns the number of patches that fell back to Lanczos."""
+        nf = ctypes.c_int64()
+        L.check(self._lib.pmg_set_bounds_mlp(self._h, net._h, float(margin), float(ood_z),
+                                             ctypes.byref(nf)))
+        return nf.value
+
     def bounds(self) -> np.ndarray:
         out = np.zeros((self.n_patches, self.n_levels - 1, 2))
         L.check(self._lib.pmg_get_bounds(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
@@ -153,6 +181,109 @@ class PatchSmoother:
     def close(self):
         if getattr(self, "_h", None) is not None and self._owner is None:
             L.check(self._lib.pmg_patch_destroy(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class PatchBatch(PatchSmoother):
+    """pmg_patches_setup: n independent vertex patches (vertices (n, 3^d, d),
+    coefficients (n, 2^d)); no global vector, so no smooth/residual."""
+
+    def __init__(self, dim: int, p: int, vertices, coeff, levels: Sequence[int] = None,
+                 precision: str = "fp64", cheb_degree: int = 3, n_vcycles: int = 1,
+                 bounds: str = "lanczos", lanczos_steps: int = 12, cheb_safety: float = 1.1,
+                 cheb_range: float = 15.0, seed: int = 0, stream=None):
+        lib = L.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("PatchBatch needs a GPU")
+        v = np.ascontiguousarray(vertices, dtype=np.float64)
+        mu = np.ascontiguousarray(coeff, dtype=np.float64)
+        n = v.shape[0]
+        if v.shape != (n, 3 ** dim, dim) or mu.shape != (n, 2 ** dim):
+            raise ValueError("vertices (n, 3^d, d) and coefficients (n, 2^d) expected")
+        o = _opts(levels, precision, cheb_degree, n_vcycles, bounds, lanczos_steps, cheb_safety,
+                  cheb_range, seed, stream)
+        h = ctypes.c_void_p()
+        L.check(lib.pmg_patches_setup(int(dim), int(n), v.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      mu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(p),
+                                      ctypes.byref(o), ctypes.byref(h)))
+        super().__init__(dim, 2, p, None, None, _handle=h)
+        self._owner = None
+
+
+class BoundNet:
+    """pmg_mlp_*: the bound-predicting network n_in -> 64 -> 64 -> 64 -> n_out."""
+
+    def __init__(self, n_in: int, n_out: int, params, max_batch: int = 4096, stream=None):
+        self._lib = L.load()
+        self.n_in, self.n_out = int(n_in), int(n_out)
+        cnt = ctypes.c_int64()
+        L.check(self._lib.pmg_mlp_param_count(self.n_in, self.n_out, ctypes.byref(cnt)))
+        self.n_params = cnt.value
+        arr, ptr = _host_f(params)
+        if arr.size != self.n_params:
+            raise ValueError(f"{self.n_params} parameters expected")
+        h = ctypes.c_void_p()
+        L.check(self._lib.pmg_mlp_create(self.n_in, self.n_out, ptr, int(max_batch),
+                                         _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(self.n_params, dtype=np.float32)
+        L.check(self._lib.pmg_mlp_get_params(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return out
+
+    def set_params(self, params):
+        arr, ptr = _host_f(params)
+        L.check(self._lib.pmg_mlp_set_params(self._h, ptr))
+
+    def fit_standardizer(self, X: torch.Tensor):
+        L.check(self._lib.pmg_mlp_fit_standardizer(self._h, _fptr(X), int(X.shape[0])))
+
+    def standardizer(self):
+        mean = np.zeros(self.n_in, dtype=np.float32)
+        inv = np.zeros(self.n_in, dtype=np.float32)
+        L.check(self._lib.pmg_mlp_get_standardizer(self._h, mean.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                                   inv.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return mean, inv
+
+    def set_standardizer(self, mean, inv_std):
+        m, pm = _host_f(mean)
+        s, ps = _host_f(inv_std)
+        L.check(self._lib.pmg_mlp_set_standardizer(self._h, pm, ps))
+
+    def predict(self, X: torch.Tensor) -> torch.Tensor:
+        Y = torch.empty((X.shape[0], self.n_out), dtype=torch.float32, device=X.device)
+        L.check(self._lib.pmg_mlp_predict(self._h, _fptr(X), int(X.shape[0]), _fptr(Y)))
+        return Y
+
+    def gradient(self, X: torch.Tensor, T: torch.Tensor):
+        g = np.zeros(self.n_params, dtype=np.float32)
+        loss = ctypes.c_double()
+        L.check(self._lib.pmg_mlp_gradient(self._h, _fptr(X), _fptr(T), int(X.shape[0]),
+                                           g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                           ctypes.byref(loss)))
+        return g, loss.value
+
+    def train(self, X: torch.Tensor, T: torch.Tensor, order: torch.Tensor, epochs: int, batch: int,
+              lr: float = 1e-3) -> np.ndarray:
+        """order: int32 device tensor (epochs, n) of sample indices."""
+        if order.dtype != torch.int32 or not order.is_cuda or tuple(order.shape) != (epochs, X.shape[0]):
+            raise ValueError("order must be an int32 device tensor of shape (epochs, n)")
+        hist = np.zeros(epochs)
+        L.check(self._lib.pmg_mlp_train(self._h, _fptr(X), _fptr(T), int(X.shape[0]),
+                                        order.data_ptr(), int(epochs), int(batch), float(lr),
+                                        hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return hist
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            L.check(self._lib.pmg_mlp_destroy(self._h))
         self._h = None
 
     def __del__(self):

@@ -125,6 +125,8 @@ struct pmg_handle {
   double* verts = nullptr;
   double* mu = nullptr;
   int32_t* patch_vertex = nullptr;
+  double* patch_geo = nullptr;  // independent patches: n x 3^d x d
+  double* patch_mu = nullptr;   // independent patches: n x 2^d
   double* tab64 = nullptr;
   void* tab = nullptr;
   double* invdiag64[kMaxLevels] = {nullptr};
@@ -143,6 +145,8 @@ struct pmg_handle {
     a.verts = verts;
     a.mu = mu;
     a.patch_vertex = patch_vertex;
+    a.patch_geo = patch_geo;
+    a.patch_mu = patch_mu;
     a.N = N;
     a.p = p;
     a.tab = tab;
@@ -168,7 +172,8 @@ namespace {
 
 void free_handle(pmg_handle* h) {
   if (!h) return;
-  void* ptrs[] = {h->verts, h->mu, h->patch_vertex, h->tab64, h->cheb, h->vec_scratch};
+  void* ptrs[] = {h->verts,    h->mu,  h->patch_vertex, h->patch_geo,
+                  h->patch_mu, h->tab64, h->cheb,        h->vec_scratch};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h->tab && h->tab != h->tab64) (void)hipFree(h->tab);  // FP64 handles share the tables
@@ -220,15 +225,8 @@ int set_cheb(pmg_handle* h) {
   return PMG_OK;
 }
 
-int patch_setup_impl(const pmg_mesh* mesh, const double* coeff, int p, const pmg_opts* o,
-                     pmg_handle** out) {
-  if (!mesh || !coeff || !o || !out || !mesh->vertices)
-    return fail(PMG_ERR_INVALID_ARG, "null argument");
-  *out = nullptr;
-  const int dim = mesh->dim, N = mesh->n_cells;
-  if (dim != 2 && dim != 3) return fail(PMG_ERR_INVALID_ARG, "dim must be 2 or 3, got %d", dim);
-  if (N < 2) return fail(PMG_ERR_INVALID_ARG, "need at least 2 cells per direction, got %d", N);
-  if (p < 1 || p > kMaxDegree) return fail(PMG_ERR_INVALID_ARG, "degree %d outside 1..15", p);
+// option checks shared by every setup; fills the level list and the kernel variant
+int check_opts(const pmg_opts* o, int dim, int p, int* levels, int& L, const PatchVariant*& var) {
   if (o->precision != PMG_FP64 && o->precision != PMG_FP32)
     return fail(PMG_ERR_INVALID_ARG, "unknown precision %d", o->precision);
   if (o->cheb_degree < 1 || o->cheb_degree > 8)
@@ -240,8 +238,7 @@ int patch_setup_impl(const pmg_mesh* mesh, const double* coeff, int p, const pmg
     return fail(PMG_ERR_INVALID_ARG, "lanczos_steps %d outside 2..64", o->lanczos_steps);
   if (!(o->cheb_safety >= 1.0) || !(o->cheb_range > 1.0))
     return fail(PMG_ERR_INVALID_ARG, "cheb_safety must be >= 1 and cheb_range > 1");
-  int levels[kMaxLevels] = {0};
-  int L = o->n_levels;
+  L = o->n_levels;
   if (L == 0) {
     int q = p;
     while (true) {
@@ -258,11 +255,14 @@ int patch_setup_impl(const pmg_mesh* mesh, const double* coeff, int p, const pmg
   if (levels[L - 1] != 1) return fail(PMG_ERR_INVALID_ARG, "last level must be degree 1");
   for (int l = 1; l < L; ++l)
     if (levels[l] >= levels[l - 1]) return fail(PMG_ERR_INVALID_ARG, "levels must strictly decrease");
-  const PatchVariant* var = find_variant(o->precision, dim, L, levels);
+  var = find_variant(o->precision, dim, L, levels);
   if (!var)
     return fail(PMG_ERR_UNSUPPORTED, "no kernel compiled for this level list (available: %s)",
                 list_variants().c_str());
-  PMG_TRY(check_mesh(dim, N, mesh->vertices, p));
+  return PMG_OK;
+}
+
+int init_tables_once() {
   {
     // the per-degree tables in constant memory, once per device
     static int initialised_device = -1;
@@ -274,62 +274,18 @@ int patch_setup_impl(const pmg_mesh* mesh, const double* coeff, int p, const pmg
     }
   }
 
-  pmg_handle* h = new pmg_handle();
-  h->dim = dim;
-  h->N = N;
-  h->p = p;
-  h->precision = o->precision;
-  h->L = L;
-  for (int l = 0; l < L; ++l) h->levels[l] = levels[l];
-  h->cheb_degree = o->cheb_degree;
-  h->n_vcycles = o->n_vcycles;
-  h->bounds_kind = o->bounds;
-  h->lanczos_steps = o->lanczos_steps;
-  h->safety = o->cheb_safety;
-  h->range = o->cheb_range;
-  h->seed = o->seed;
-  h->stream = reinterpret_cast<hipStream_t>(o->stream);
-  h->var = var;
-  auto cleanup = [&](int s) {
-    free_handle(h);
-    return s;
-  };
+  return PMG_OK;
+}
 
-  // patches in sweep order: colour sum_i 2^i (v_i mod 2), lexicographic within
-  const int N1 = N + 1;
-  std::vector<int32_t> order;
-  h->n_colors = 1 << dim;
-  h->color_off.assign(h->n_colors + 1, 0);
-  for (int col = 0; col < h->n_colors; ++col) {
-    h->color_off[col] = (int)order.size();
-    for (int vz = (dim == 3 ? 1 : 0); vz < (dim == 3 ? N : 1); ++vz)
-      for (int vy = 1; vy < N; ++vy)
-        for (int vx = 1; vx < N; ++vx) {
-          int c = (vx & 1) | ((vy & 1) << 1) | (dim == 3 ? ((vz & 1) << 2) : 0);
-          if (c != col) continue;
-          order.push_back(vx + vy * N1 + (dim == 3 ? vz * N1 * N1 : 0));
-        }
-    h->max_color = std::max(h->max_color, (int)order.size() - h->color_off[col]);
-  }
-  h->color_off[h->n_colors] = (int)order.size();
-  h->n_patches = (int)order.size();
-
-  const size_t nv = (size_t)ipow(N1, dim), nc = (size_t)ipow(N, dim);
-  int s;
-  if ((s = dev_alloc(&h->verts, nv * dim * sizeof(double), &h->device_bytes)) < 0) return cleanup(s);
-  if ((s = dev_alloc(&h->mu, nc * sizeof(double), &h->device_bytes)) < 0) return cleanup(s);
-  if ((s = dev_alloc(&h->patch_vertex, order.size() * sizeof(int32_t), &h->device_bytes)) < 0)
-    return cleanup(s);
+// everything after the geometry is on the device: tables, scratch, inverse
+// diagonals, dense small levels, Chebyshev bounds
+int setup_common(pmg_handle* h) {
+  const int L = h->L;
+  const int* levels = h->levels;
+  const PatchVariant* var = h->var;
   hipError_t e;
-  if ((e = hipMemcpy(h->verts, mesh->vertices, nv * dim * sizeof(double), hipMemcpyHostToDevice)) ||
-      (e = hipMemcpy(h->mu, coeff, nc * sizeof(double), hipMemcpyHostToDevice)) ||
-      (e = hipMemcpy(h->patch_vertex, order.data(), order.size() * sizeof(int32_t),
-                     hipMemcpyHostToDevice)))
-    return cleanup(fail(PMG_ERR_HIP, "upload: %s", hipGetErrorString(e)));
-  for (size_t i = 0; i < nc; ++i)
-    if (!(coeff[i] > 0.0) || !std::isfinite(coeff[i]))
-      return cleanup(fail(PMG_ERR_INVALID_ARG, "coefficient of cell %zu is %g", i, coeff[i]));
-
+  int s;
+  auto cleanup = [&](int st) { return st; };
   // 1D tables: per level B, Dc, D, xg, wg; per transfer the patch prolongation
   std::vector<double> tab(kTabSize, 0.0);
   for (int l = 0; l < L; ++l) {
@@ -479,11 +435,184 @@ int patch_setup_impl(const pmg_mesh* mesh, const double* coeff, int p, const pmg
     if ((e = hipStreamSynchronize(h->stream)))
       return cleanup(fail(PMG_ERR_HIP, "setup: %s", hipGetErrorString(e)));
   }
+  return PMG_OK;
+}
+
+pmg_handle* new_handle(const pmg_opts* o, int dim, int N, int p, int L, const int* levels,
+                       const PatchVariant* var) {
+  pmg_handle* h = new pmg_handle();
+  h->dim = dim;
+  h->N = N;
+  h->p = p;
+  h->precision = o->precision;
+  h->L = L;
+  for (int l = 0; l < L; ++l) h->levels[l] = levels[l];
+  h->cheb_degree = o->cheb_degree;
+  h->n_vcycles = o->n_vcycles;
+  h->bounds_kind = o->bounds;
+  h->lanczos_steps = o->lanczos_steps;
+  h->safety = o->cheb_safety;
+  h->range = o->cheb_range;
+  h->seed = o->seed;
+  h->stream = reinterpret_cast<hipStream_t>(o->stream);
+  h->var = var;
+
+  return h;
+}
+
+int patch_setup_impl(const pmg_mesh* mesh, const double* coeff, int p, const pmg_opts* o,
+                     pmg_handle** out) {
+  if (!mesh || !coeff || !o || !out || !mesh->vertices)
+    return fail(PMG_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  const int dim = mesh->dim, N = mesh->n_cells;
+  if (dim != 2 && dim != 3) return fail(PMG_ERR_INVALID_ARG, "dim must be 2 or 3, got %d", dim);
+  if (N < 2) return fail(PMG_ERR_INVALID_ARG, "need at least 2 cells per direction, got %d", N);
+  if (p < 1 || p > kMaxDegree) return fail(PMG_ERR_INVALID_ARG, "degree %d outside 1..15", p);
+  int levels[kMaxLevels] = {0};
+  int L = 0;
+  const PatchVariant* var = nullptr;
+  PMG_TRY(check_opts(o, dim, p, levels, L, var));
+  PMG_TRY(check_mesh(dim, N, mesh->vertices, p));
+  PMG_TRY(init_tables_once());
+  pmg_handle* h = new_handle(o, dim, N, p, L, levels, var);
+  auto cleanup = [&](int s) {
+    free_handle(h);
+    return s;
+  };
+  // patches in sweep order: colour sum_i 2^i (v_i mod 2), lexicographic within
+  const int N1 = N + 1;
+  std::vector<int32_t> order;
+  h->n_colors = 1 << dim;
+  h->color_off.assign(h->n_colors + 1, 0);
+  for (int col = 0; col < h->n_colors; ++col) {
+    h->color_off[col] = (int)order.size();
+    for (int vz = (dim == 3 ? 1 : 0); vz < (dim == 3 ? N : 1); ++vz)
+      for (int vy = 1; vy < N; ++vy)
+        for (int vx = 1; vx < N; ++vx) {
+          int c = (vx & 1) | ((vy & 1) << 1) | (dim == 3 ? ((vz & 1) << 2) : 0);
+          if (c != col) continue;
+          order.push_back(vx + vy * N1 + (dim == 3 ? vz * N1 * N1 : 0));
+        }
+    h->max_color = std::max(h->max_color, (int)order.size() - h->color_off[col]);
+  }
+  h->color_off[h->n_colors] = (int)order.size();
+  h->n_patches = (int)order.size();
+
+  const size_t nv = (size_t)ipow(N1, dim), nc = (size_t)ipow(N, dim);
+  int s;
+  if ((s = dev_alloc(&h->verts, nv * dim * sizeof(double), &h->device_bytes)) < 0) return cleanup(s);
+  if ((s = dev_alloc(&h->mu, nc * sizeof(double), &h->device_bytes)) < 0) return cleanup(s);
+  if ((s = dev_alloc(&h->patch_vertex, order.size() * sizeof(int32_t), &h->device_bytes)) < 0)
+    return cleanup(s);
+  hipError_t e;
+  if ((e = hipMemcpy(h->verts, mesh->vertices, nv * dim * sizeof(double), hipMemcpyHostToDevice)) ||
+      (e = hipMemcpy(h->mu, coeff, nc * sizeof(double), hipMemcpyHostToDevice)) ||
+      (e = hipMemcpy(h->patch_vertex, order.data(), order.size() * sizeof(int32_t),
+                     hipMemcpyHostToDevice)))
+    return cleanup(fail(PMG_ERR_HIP, "upload: %s", hipGetErrorString(e)));
+  for (size_t i = 0; i < nc; ++i)
+    if (!(coeff[i] > 0.0) || !std::isfinite(coeff[i]))
+      return cleanup(fail(PMG_ERR_INVALID_ARG, "coefficient of cell %zu is %g", i, coeff[i]));
+
+  if ((s = setup_common(h)) < 0) return cleanup(s);
   *out = h;
   return PMG_OK;
 }
 
 }  // namespace
+
+int patches_setup_impl(int dim, int64_t n, const double* verts, const double* coeff, int p,
+                       const pmg_opts* o, pmg_handle** out) {
+  if (!verts || !coeff || !o || !out) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  if (dim != 2 && dim != 3) return fail(PMG_ERR_INVALID_ARG, "dim must be 2 or 3, got %d", dim);
+  if (n < 1 || n > (1 << 26)) return fail(PMG_ERR_INVALID_ARG, "patch count %lld out of range", (long long)n);
+  if (p < 1 || p > kMaxDegree) return fail(PMG_ERR_INVALID_ARG, "degree %d outside 1..15", p);
+  int levels[kMaxLevels] = {0};
+  int L = 0;
+  const PatchVariant* var = nullptr;
+  PMG_TRY(check_opts(o, dim, p, levels, L, var));
+  const int nvert = ipow(3, dim), ncell = ipow(2, dim);
+  // every patch is a 2-cell-per-direction mesh: reuse the cell check
+  for (int64_t j = 0; j < n; ++j) {
+    int st = check_mesh(dim, 2, verts + j * nvert * dim, p);
+    if (st < 0) return fail(st, "patch %lld: %s", (long long)j, pmg_last_error());
+    for (int c = 0; c < ncell; ++c)
+      if (!(coeff[j * ncell + c] > 0.0) || !std::isfinite(coeff[j * ncell + c]))
+        return fail(PMG_ERR_INVALID_ARG, "patch %lld cell %d: coefficient %g", (long long)j, c,
+                    coeff[j * ncell + c]);
+  }
+  PMG_TRY(init_tables_once());
+  pmg_handle* h = new_handle(o, dim, 2, p, L, levels, var);
+  auto cleanup = [&](int st) {
+    free_handle(h);
+    return st;
+  };
+  h->n_patches = (int)n;
+  h->n_colors = 1;
+  h->color_off = {0, (int)n};
+  h->max_color = (int)n;
+  int s;
+  hipError_t e;
+  if ((s = dev_alloc(&h->patch_geo, (size_t)n * nvert * dim * sizeof(double), &h->device_bytes)) < 0)
+    return cleanup(s);
+  if ((s = dev_alloc(&h->patch_mu, (size_t)n * ncell * sizeof(double), &h->device_bytes)) < 0)
+    return cleanup(s);
+  if ((e = hipMemcpy(h->patch_geo, verts, (size_t)n * nvert * dim * sizeof(double), hipMemcpyHostToDevice)) ||
+      (e = hipMemcpy(h->patch_mu, coeff, (size_t)n * ncell * sizeof(double), hipMemcpyHostToDevice)))
+    return cleanup(fail(PMG_ERR_HIP, "upload: %s", hipGetErrorString(e)));
+  if ((s = setup_common(h)) < 0) return cleanup(s);
+  *out = h;
+  return PMG_OK;
+}
+
+int n_features(int dim) { return 3 * ipow(4, dim) + ipow(2, dim); }
+
+// Lanczos bounds for the listed patches (host indices) into h->bounds
+int lanczos_for(pmg_handle* h, const std::vector<int32_t>& list) {
+  if (list.empty()) return PMG_OK;
+  const int L = h->L;
+  const size_t nb = (size_t)h->n_patches * (L - 1) * 2;
+  double* dbounds = nullptr;
+  double* basis = nullptr;
+  int32_t* dlist = nullptr;
+  int st = PMG_OK;
+  const int cnt = (int)list.size();
+  int chunk = std::min(cnt, 4096);
+  if (h->vec_blocks > 0) chunk = std::min<int>(chunk, (int)h->vec_blocks);
+  if ((st = dev_alloc(&dbounds, nb * sizeof(double), nullptr)) < 0) return st;
+  if ((st = dev_alloc(&basis, (size_t)chunk * h->lanczos_steps * h->level_size(0) * sizeof(double), nullptr)) < 0 ||
+      (st = dev_alloc(&dlist, list.size() * sizeof(int32_t), nullptr)) < 0) {
+    (void)hipFree(dbounds);
+    if (basis) (void)hipFree(basis);
+    return st;
+  }
+  hipError_t e = hipMemcpy(dlist, list.data(), list.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  PatchArgs a = h->args();
+  a.vec_stride = h->vec_bytes / (int64_t)sizeof(double);
+  a.lanczos_basis = basis;
+  a.bounds_out = dbounds;
+  a.patch_list = dlist;
+  for (int l = 0; l + 1 < L && e == hipSuccess; ++l)
+    for (int b = 0; b < cnt && e == hipSuccess; b += chunk) {
+      a.patch_begin = b;
+      a.n_patch = std::min(chunk, cnt - b);
+      e = h->var->launch_lanczos(a, l, h->stream);
+    }
+  std::vector<double> hb(nb);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(hb.data(), dbounds, nb * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) st = fail(PMG_ERR_HIP, "lanczos fallback: %s", hipGetErrorString(e));
+  else
+    for (int32_t j : list)
+      for (int k = 0; k < (L - 1) * 2; ++k) h->bounds[(size_t)j * (L - 1) * 2 + k] = hb[(size_t)j * (L - 1) * 2 + k];
+  (void)hipFree(dbounds);
+  (void)hipFree(basis);
+  (void)hipFree(dlist);
+  return st;
+}
 
 // ---------------------------------------------------------------------------
 // GMG
@@ -838,6 +967,7 @@ int pmg_patch_setup(const pmg_mesh* mesh, const double* coeff, int32_t p, const 
 int pmg_patch_smooth_colors(pmg_handle* h, double* u, const double* b, int32_t c_begin,
                             int32_t c_end) {
   if (!h || !u || !b) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  if (h->patch_geo) return fail(PMG_ERR_UNSUPPORTED, "independent patches have no global vector to smooth");
   if (!h->bounds_valid) return fail(PMG_ERR_INVALID_ARG, "Chebyshev bounds not set");
   if (c_begin < 0 || c_end > h->n_colors || c_begin > c_end)
     return fail(PMG_ERR_INVALID_ARG, "colour range [%d, %d) outside [0, %d)", c_begin, c_end, h->n_colors);
@@ -858,6 +988,7 @@ int pmg_patch_smooth(pmg_handle* h, double* u, const double* b, int32_t directio
 
 int pmg_patch_residual(pmg_handle* h, const double* u, const double* b, double* r) {
   if (!h || !u || !b || !r) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  if (h->patch_geo) return fail(PMG_ERR_UNSUPPORTED, "independent patches have no global vector");
   PatchArgs a = h->args();
   a.u = const_cast<double*>(u);
   a.b = b;
@@ -912,6 +1043,10 @@ int pmg_set_bounds(pmg_handle* h, const double* lam) {
 
 int pmg_get_patch_vertices(const pmg_handle* h, int32_t* out) {
   if (!h || !out) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  if (h->patch_geo) {
+    for (int j = 0; j < h->n_patches; ++j) out[j] = j;
+    return PMG_OK;
+  }
   HIP_TRY(hipMemcpy(out, h->patch_vertex, (size_t)h->n_patches * sizeof(int32_t), hipMemcpyDeviceToHost));
   return PMG_OK;
 }
@@ -1055,6 +1190,216 @@ int gmg_destroy(gmg_handle* g) {
   if (g->stream) (void)hipStreamSynchronize(g->stream);
   else (void)hipDeviceSynchronize();
   free_gmg(g);
+  return PMG_OK;
+}
+
+
+int pmg_patches_setup(int32_t dim, int64_t n, const double* verts, const double* coeff, int32_t p,
+                      const pmg_opts* opts, pmg_handle** out) {
+  return patches_setup_impl(dim, n, verts, coeff, p, opts, out);
+}
+
+int pmg_patch_features(pmg_handle* h, float* out) {
+  if (!h || !out) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  PatchArgs a = h->args();
+  a.patch_begin = 0;
+  HIP_TRY(launch_features(h->dim, a, h->n_patches, out, h->stream));
+  return PMG_OK;
+}
+
+int pmg_mlp_param_count(int32_t n_in, int32_t n_out, int64_t* count) {
+  if (!count || n_in < 1 || n_out < 1) return fail(PMG_ERR_INVALID_ARG, "bad network size");
+  *count = mlp_param_count(n_in, n_out);
+  return PMG_OK;
+}
+
+int pmg_mlp_create(int32_t n_in, int32_t n_out, const float* params, int64_t max_batch, void* stream,
+                   pmg_mlp** out) {
+  if (!params || !out || n_in < 1 || n_out < 1 || max_batch < 1)
+    return fail(PMG_ERR_INVALID_ARG, "bad network arguments");
+  *out = nullptr;
+  MlpNet* m = new MlpNet();
+  m->n_in = n_in;
+  m->n_out = n_out;
+  m->stream = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = m->alloc(max_batch);
+  const size_t P = (size_t)mlp_param_count(n_in, n_out);
+  if (e == hipSuccess) e = hipMemcpy(m->theta, params, P * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(m->m, 0, P * 4);
+  if (e == hipSuccess) e = hipMemset(m->v, 0, P * 4);
+  if (e == hipSuccess) {
+    std::vector<float> zero(n_in, 0.0f), one(n_in, 1.0f);
+    e = hipMemcpy(m->mean, zero.data(), n_in * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->inv_std, one.data(), n_in * 4, hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) {
+    delete m;
+    return fail(e == hipErrorOutOfMemory ? PMG_ERR_OOM : PMG_ERR_HIP, "network allocation: %s",
+                hipGetErrorString(e));
+  }
+  *out = reinterpret_cast<pmg_mlp*>(m);
+  return PMG_OK;
+}
+
+int pmg_mlp_get_params(const pmg_mlp* mm, float* params) {
+  const MlpNet* m = reinterpret_cast<const MlpNet*>(mm);
+  if (!m || !params) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  HIP_TRY(hipStreamSynchronize(m->stream));
+  HIP_TRY(hipMemcpy(params, m->theta, (size_t)mlp_param_count(m->n_in, m->n_out) * 4, hipMemcpyDeviceToHost));
+  return PMG_OK;
+}
+
+int pmg_mlp_set_params(pmg_mlp* mm, const float* params) {
+  MlpNet* m = reinterpret_cast<MlpNet*>(mm);
+  if (!m || !params) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  const size_t P = (size_t)mlp_param_count(m->n_in, m->n_out);
+  HIP_TRY(hipStreamSynchronize(m->stream));
+  HIP_TRY(hipMemcpy(m->theta, params, P * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemset(m->m, 0, P * 4));
+  HIP_TRY(hipMemset(m->v, 0, P * 4));
+  m->t = 0;
+  return PMG_OK;
+}
+
+int pmg_mlp_fit_standardizer(pmg_mlp* mm, const float* X, int64_t n) {
+  MlpNet* m = reinterpret_cast<MlpNet*>(mm);
+  if (!m || !X || n < 1) return fail(PMG_ERR_INVALID_ARG, "bad arguments");
+  HIP_TRY(m->fit_standardizer(X, n));
+  return PMG_OK;
+}
+
+int pmg_mlp_get_standardizer(const pmg_mlp* mm, float* mean, float* inv_std) {
+  const MlpNet* m = reinterpret_cast<const MlpNet*>(mm);
+  if (!m || !mean || !inv_std) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  HIP_TRY(hipStreamSynchronize(m->stream));
+  HIP_TRY(hipMemcpy(mean, m->mean, m->n_in * 4, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(inv_std, m->inv_std, m->n_in * 4, hipMemcpyDeviceToHost));
+  return PMG_OK;
+}
+
+int pmg_mlp_set_standardizer(pmg_mlp* mm, const float* mean, const float* inv_std) {
+  MlpNet* m = reinterpret_cast<MlpNet*>(mm);
+  if (!m || !mean || !inv_std) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  HIP_TRY(hipStreamSynchronize(m->stream));
+  HIP_TRY(hipMemcpy(m->mean, mean, m->n_in * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(m->inv_std, inv_std, m->n_in * 4, hipMemcpyHostToDevice));
+  return PMG_OK;
+}
+
+int pmg_mlp_predict(pmg_mlp* mm, const float* X, int64_t n, float* Y) {
+  MlpNet* m = reinterpret_cast<MlpNet*>(mm);
+  if (!m || !X || !Y || n < 0) return fail(PMG_ERR_INVALID_ARG, "bad arguments");
+  for (int64_t s = 0; s < n; s += m->cap) {
+    const int B = (int)std::min<int64_t>(m->cap, n - s);
+    HIP_TRY(m->standardize(X + s * m->n_in, B, m->xs));
+    HIP_TRY(m->forward(m->xs, B));
+    HIP_TRY(hipMemcpyAsync(Y + s * m->n_out, m->y, (size_t)B * m->n_out * 4, hipMemcpyDeviceToDevice,
+                           m->stream));
+  }
+  return PMG_OK;
+}
+
+int pmg_mlp_gradient(pmg_mlp* mm, const float* X, const float* T, int64_t n, float* grad, double* loss) {
+  MlpNet* m = reinterpret_cast<MlpNet*>(mm);
+  if (!m || !X || !T || !grad || n < 1) return fail(PMG_ERR_INVALID_ARG, "bad arguments");
+  if (n > m->cap) return fail(PMG_ERR_INVALID_ARG, "%lld rows exceed max_batch %lld", (long long)n, (long long)m->cap);
+  HIP_TRY(hipMemsetAsync(m->loss, 0, sizeof(double), m->stream));
+  HIP_TRY(m->standardize(X, n, m->xs));
+  HIP_TRY(m->forward(m->xs, (int)n));
+  HIP_TRY(m->backward(m->xs, T, (int)n));
+  HIP_TRY(hipStreamSynchronize(m->stream));
+  HIP_TRY(hipMemcpy(grad, m->grad, (size_t)mlp_param_count(m->n_in, m->n_out) * 4, hipMemcpyDeviceToHost));
+  if (loss) HIP_TRY(hipMemcpy(loss, m->loss, sizeof(double), hipMemcpyDeviceToHost));
+  return PMG_OK;
+}
+
+int pmg_mlp_train(pmg_mlp* mm, const float* X, const float* T, int64_t n, const int32_t* order,
+                  int32_t epochs, int32_t batch, float lr, double* epoch_loss) {
+  MlpNet* m = reinterpret_cast<MlpNet*>(mm);
+  if (!m || !X || !T || !order || n < 1 || epochs < 1 || batch < 1 || !(lr > 0.0f))
+    return fail(PMG_ERR_INVALID_ARG, "bad training arguments");
+  if (batch > m->cap) return fail(PMG_ERR_INVALID_ARG, "batch %d exceeds max_batch %lld", batch, (long long)m->cap);
+  for (int ep = 0; ep < epochs; ++ep) {
+    HIP_TRY(hipMemsetAsync(m->loss, 0, sizeof(double), m->stream));
+    int nbatch = 0;
+    for (int64_t s = 0; s < n; s += batch, ++nbatch) {
+      const int B = (int)std::min<int64_t>(batch, n - s);
+      HIP_TRY(m->gather(X, T, order + (int64_t)ep * n + s, B));
+      HIP_TRY(m->standardize(m->xb, B, m->xs));
+      HIP_TRY(m->forward(m->xs, B));
+      HIP_TRY(m->backward(m->xs, m->tb, B));
+      HIP_TRY(m->adam_step(lr, 0.9f, 0.999f, 1e-8f));
+    }
+    if (epoch_loss) {
+      double l = 0;
+      HIP_TRY(hipMemcpyAsync(&l, m->loss, sizeof(double), hipMemcpyDeviceToHost, m->stream));
+      HIP_TRY(hipStreamSynchronize(m->stream));
+      epoch_loss[ep] = l / nbatch;
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(m->stream));
+  return PMG_OK;
+}
+
+int pmg_mlp_destroy(pmg_mlp* mm) {
+  MlpNet* m = reinterpret_cast<MlpNet*>(mm);
+  if (!m) return PMG_OK;
+  (void)hipStreamSynchronize(m->stream);
+  delete m;
+  return PMG_OK;
+}
+
+int pmg_set_bounds_mlp(pmg_handle* h, pmg_mlp* mm, double margin, double ood_z, int64_t* n_fallback) {
+  MlpNet* m = reinterpret_cast<MlpNet*>(mm);
+  if (!h || !m) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  const int nl = h->L - 1;
+  if (m->n_in != n_features(h->dim) || m->n_out != 2 * nl)
+    return fail(PMG_ERR_INVALID_ARG, "network has %d inputs and %d outputs, need %d and %d", m->n_in,
+                m->n_out, n_features(h->dim), 2 * nl);
+  if (!(margin >= 0.0) || !(ood_z > 0.0)) return fail(PMG_ERR_INVALID_ARG, "need margin >= 0 and ood_z > 0");
+  const int n = h->n_patches, nf = n_features(h->dim);
+  float *F = nullptr, *Y = nullptr, *Z = nullptr;
+  int st;
+  if ((st = dev_alloc(&F, (size_t)n * nf * 4, nullptr)) < 0) return st;
+  if ((st = dev_alloc(&Y, (size_t)n * 2 * nl * 4, nullptr)) < 0 || (st = dev_alloc(&Z, (size_t)n * 4, nullptr)) < 0) {
+    (void)hipFree(F);
+    if (Y) (void)hipFree(Y);
+    return st;
+  }
+  std::vector<float> hy((size_t)n * 2 * nl), hz(n);
+  PatchArgs a = h->args();
+  a.patch_begin = 0;
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess) e = launch_features(h->dim, a, n, F, m->stream);
+  if (e == hipSuccess) st = pmg_mlp_predict(mm, F, n, Y);
+  if (e == hipSuccess && st == PMG_OK) e = m->max_abs_z(F, n, Z);
+  if (e == hipSuccess && st == PMG_OK) e = hipMemcpyAsync(hy.data(), Y, hy.size() * 4, hipMemcpyDeviceToHost, m->stream);
+  if (e == hipSuccess && st == PMG_OK) e = hipMemcpyAsync(hz.data(), Z, hz.size() * 4, hipMemcpyDeviceToHost, m->stream);
+  if (e == hipSuccess && st == PMG_OK) e = hipStreamSynchronize(m->stream);
+  (void)hipFree(F);
+  (void)hipFree(Y);
+  (void)hipFree(Z);
+  if (st != PMG_OK) return st;
+  if (e != hipSuccess) return fail(PMG_ERR_HIP, "learned bounds: %s", hipGetErrorString(e));
+  std::vector<double> old = h->bounds;
+  std::vector<int32_t> fallback;
+  for (int j = 0; j < n; ++j) {
+    bool ok = hz[j] <= ood_z;
+    for (int l = 0; l < nl && ok; ++l) {
+      const double lo = std::exp((double)hy[(size_t)j * 2 * nl + 2 * l]);
+      double hi = std::exp((double)hy[(size_t)j * 2 * nl + 2 * l + 1] + margin);
+      ok = std::isfinite(lo) && std::isfinite(hi) && lo > 0.0;
+      if (!ok) break;
+      h->bounds[((size_t)j * nl + l) * 2] = std::min(lo, hi);
+      h->bounds[((size_t)j * nl + l) * 2 + 1] = hi;
+    }
+    if (!ok) fallback.push_back(j);
+  }
+  if ((st = lanczos_for(h, fallback)) < 0 || (st = set_cheb(h)) < 0) {
+    h->bounds = old;
+    return st;
+  }
+  if (n_fallback) *n_fallback = (int64_t)fallback.size();
   return PMG_OK;
 }
 

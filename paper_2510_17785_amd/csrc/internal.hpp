@@ -52,6 +52,11 @@ struct PatchArgs {
   uint64_t seed;
   double* lanczos_basis;     // per block: m x size_l doubles
   double* bounds_out;        // n_patches_total x (L-1) x 2
+  // independent patches (no mesh): 3^d vertices and 2^d coefficients each
+  const double* patch_geo;   // n_patches_total x 3^d x d, or null for a mesh
+  const double* patch_mu;    // n_patches_total x 2^d
+  // optional list of patch numbers: block b handles patch_list[patch_begin + b]
+  const int32_t* patch_list;
   // small levels held as dense matrices (see PatchVariant::dense_level)
   const void* dense[kMaxLevels];   // T, n_patches_total x size_l^2, row-major
   double* dense64[kMaxLevels];     // FP64 copies, written by the setup kernel
@@ -78,6 +83,8 @@ struct PatchVariant {
 };
 
 const PatchVariant* find_variant(int precision, int dim, int n_levels, const int* levels);
+// Features of every patch for the bound-predicting network (n x nf floats).
+hipError_t launch_features(int dim, const PatchArgs& a, int n_patch, float* out, hipStream_t s);
 // Fill the per-degree 1D tables in constant memory of the current device.
 hipError_t init_constant_tables();
 std::string list_variants();
@@ -109,5 +116,30 @@ hipError_t launch_scatter_interior(int dim, int M, const double* packed, double*
                                    hipStream_t s);
 hipError_t launch_convert_to_float(int64_t n, const double* in, float* out, hipStream_t s);
 constexpr int kDotBlocks = 512;
+
+// The bound-predicting MLP (mlp_kernels.hip).
+int64_t mlp_param_count(int n_in, int n_out);
+struct MlpNet {
+  int n_in = 0, n_out = 0;
+  int64_t cap = 0;  // largest batch the work buffers hold
+  int t = 0;        // Adam step counter
+  hipStream_t stream = nullptr;
+  float *theta = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
+  float *mean = nullptr, *inv_std = nullptr;
+  float *xb = nullptr, *tb = nullptr, *xs = nullptr, *h1 = nullptr, *h2 = nullptr, *h3 = nullptr;
+  float *y = nullptr, *d3 = nullptr, *d2 = nullptr, *d1 = nullptr, *dy = nullptr;
+  double *partial = nullptr, *loss = nullptr;
+  int32_t* idx = nullptr;
+  ~MlpNet();
+  int64_t offset(int layer) const;
+  hipError_t alloc(int64_t max_batch);
+  hipError_t forward(const float* in_std, int B);
+  hipError_t backward(const float* in_std, const float* targets, int B);
+  hipError_t standardize(const float* X, int64_t B, float* out);
+  hipError_t fit_standardizer(const float* X, int64_t n);
+  hipError_t adam_step(float lr, float b1, float b2, float eps);
+  hipError_t gather(const float* X, const float* T, const int32_t* order, int B);
+  hipError_t max_abs_z(const float* X, int64_t n, float* zmax);
+};
 
 }  // namespace pmgi

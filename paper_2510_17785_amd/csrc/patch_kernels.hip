@@ -1244,6 +1244,41 @@ __device__ __forceinline__ void patch_base(int vlin, int N, int p, int& base, in
   }
 }
 
+// Patch geometry: 3^d vertices relative to the patch centre and 2^d cell
+// coefficients, from the mesh or from the arrays of independent patches.
+template <typename T, int DIM>
+__device__ void load_geometry(const PatchArgs& a, int patch, T* geo, T* mu) {
+  constexpr int nvert = ipow(3, DIM), ncell = ipow(2, DIM);
+  const int tid = threadIdx.x;
+  if (a.patch_geo) {
+    const double* V = a.patch_geo + (int64_t)patch * nvert * DIM;
+    constexpr int centre = (nvert - 1) / 2;
+    for (int i = tid; i < nvert * DIM; i += blockDim.x) geo[i] = T(V[i] - V[centre * DIM + i % DIM]);
+    for (int i = tid; i < ncell; i += blockDim.x) mu[i] = T(a.patch_mu[(int64_t)patch * ncell + i]);
+    return;
+  }
+  const int vlin = a.patch_vertex[patch];
+  const int N1 = a.N + 1;
+  const int vx = vlin % N1, vy = (vlin / N1) % N1, vz = DIM == 3 ? vlin / (N1 * N1) : 0;
+  for (int i = tid; i < nvert * DIM; i += blockDim.x) {
+    const int r = i % DIM, t = i / DIM;
+    const int tx = t % 3, ty = (t / 3) % 3, tz = DIM == 3 ? t / 9 : 0;
+    int g = (vx - 1 + tx) + (vy - 1 + ty) * N1;
+    if (DIM == 3) g += (vz - 1 + tz) * N1 * N1;
+    geo[i] = T(a.verts[(int64_t)g * DIM + r] - a.verts[(int64_t)vlin * DIM + r]);
+  }
+  for (int i = tid; i < ncell; i += blockDim.x) {
+    const int cx = i & 1, cy = (i >> 1) & 1, cz = (i >> 2) & 1;
+    int g = (vx - 1 + cx) + (vy - 1 + cy) * a.N;
+    if (DIM == 3) g += (vz - 1 + cz) * a.N * a.N;
+    mu[i] = T(a.mu[g]);
+  }
+}
+
+__device__ __forceinline__ int patch_of_block(const PatchArgs& a) {
+  return a.patch_list ? a.patch_list[a.patch_begin + blockIdx.x] : a.patch_begin + blockIdx.x;
+}
+
 template <typename T, int DIM, class LV>
 __device__ void load_patch(const Ctx<T, DIM, LV>& c, const PatchArgs& a, int patch) {
   using Lay = Layout<T, DIM, LV>;
@@ -1261,24 +1296,7 @@ __device__ void load_patch(const Ctx<T, DIM, LV>& c, const PatchArgs& a, int pat
       c.lds[Lay::tab_transfer_off(t) + i] =
           tab[kMaxLevels * kTabLevelStride + t * kTabTransferStride + i];
   }
-  // geometry: 3^d vertices relative to the patch centre, 2^d coefficients
-  const int vlin = a.patch_vertex[patch];
-  const int N1 = a.N + 1;
-  const int vx = vlin % N1, vy = (vlin / N1) % N1, vz = DIM == 3 ? vlin / (N1 * N1) : 0;
-  for (int i = tid; i < Lay::nvert * DIM; i += NT<T>) {
-    const int r = i % DIM, t = i / DIM;
-    const int tx = t % 3, ty = (t / 3) % 3, tz = DIM == 3 ? t / 9 : 0;
-    int g = (vx - 1 + tx) + (vy - 1 + ty) * N1;
-    if (DIM == 3) g += (vz - 1 + tz) * N1 * N1;
-    const double centre = a.verts[vlin * DIM + r];
-    c.geo()[i] = T(a.verts[g * DIM + r] - centre);
-  }
-  for (int i = tid; i < ipow(2, DIM); i += NT<T>) {
-    const int cx = i & 1, cy = (i >> 1) & 1, cz = (i >> 2) & 1;
-    int g = (vx - 1 + cx) + (vy - 1 + cy) * a.N;
-    if (DIM == 3) g += (vz - 1 + cz) * a.N * a.N;
-    c.mu()[i] = T(a.mu[g]);
-  }
+  load_geometry<T, DIM>(a, patch, c.geo(), c.mu());
   const T* cheb = tptr<T>(a.cheb);
   for (int i = tid; i < 2 * (L - 1); i += NT<T>) c.cheb()[i] = cheb[(int64_t)patch * 2 * (L - 1) + i];
   for (int l = 0; l < L; ++l) {
@@ -1307,7 +1325,7 @@ __global__ __launch_bounds__(NT<T>) void patch_kernel(PatchArgs a) {
   c.vec = Lay::vec_in_lds ? c.lds + Lay::vec_off
                           : reinterpret_cast<T*>(a.vec_scratch) + (int64_t)blockIdx.x * a.vec_stride;
   c.gtab = tptr<T>(a.tab);
-  const int patch = a.patch_begin + blockIdx.x;
+  const int patch = patch_of_block(a);
   const int tid = threadIdx.x;
   load_patch<T, DIM, LV>(c, a, patch);
   c.dense_ok = true;
@@ -1400,7 +1418,7 @@ __global__ __launch_bounds__(NT<double>) void diag_kernel(PatchArgs a) {
   c.vec = Lay::vec_in_lds ? c.lds + Lay::vec_off
                           : reinterpret_cast<T*>(a.vec_scratch) + (int64_t)blockIdx.x * a.vec_stride;
   c.gtab = a.tab64;
-  const int patch = a.patch_begin + blockIdx.x;
+  const int patch = patch_of_block(a);
   const int tid = threadIdx.x;
   // load tables and geometry only (the inverse diagonals are the output)
   {
@@ -1409,22 +1427,7 @@ __global__ __launch_bounds__(NT<double>) void diag_kernel(PatchArgs a) {
       const int sz = tab_size(LV::q[l]);
       for (int i = tid; i < sz; i += NT<T>) c.lds[Lay::tab_level_off(l) + i] = tab[l * kTabLevelStride + i];
     }
-    const int vlin = a.patch_vertex[patch];
-    const int N1 = a.N + 1;
-    const int vx = vlin % N1, vy = (vlin / N1) % N1, vz = DIM == 3 ? vlin / (N1 * N1) : 0;
-    for (int i = tid; i < Lay::nvert * DIM; i += NT<T>) {
-      const int r = i % DIM, t = i / DIM;
-      const int tx = t % 3, ty = (t / 3) % 3, tz = DIM == 3 ? t / 9 : 0;
-      int g = (vx - 1 + tx) + (vy - 1 + ty) * N1;
-      if (DIM == 3) g += (vz - 1 + tz) * N1 * N1;
-      c.geo()[i] = a.verts[g * DIM + r] - a.verts[vlin * DIM + r];
-    }
-    for (int i = tid; i < ipow(2, DIM); i += NT<T>) {
-      const int cx = i & 1, cy = (i >> 1) & 1, cz = (i >> 2) & 1;
-      int g = (vx - 1 + cx) + (vy - 1 + cy) * a.N;
-      if (DIM == 3) g += (vz - 1 + cz) * a.N * a.N;
-      c.mu()[i] = a.mu[g];
-    }
+    load_geometry<T, DIM>(a, patch, c.geo(), c.mu());
     __syncthreads();
   }
   auto run = [&](auto Lc) {
@@ -1563,7 +1566,8 @@ __device__ void lanczos_level(Ctx<double, DIM, LV>& c, const PatchArgs& a, int p
   __shared__ double al[64], be[64], coef[64];
   const T* dinv = c.dinv(L);
   // start vector: entry i of patch vertex v at smoothed level L
-  const uint64_t vlin = (uint64_t)a.patch_vertex[patch];
+  // independent patches are numbered by their position in the batch
+  const uint64_t vlin = a.patch_geo ? (uint64_t)patch : (uint64_t)a.patch_vertex[patch];
   const uint64_t base = ((vlin * 16u + (uint64_t)L) << 24);
   double nrm = 0;
   for (int i = tid; i < NL; i += NT<T>) {
@@ -1646,7 +1650,7 @@ __global__ __launch_bounds__(NT<double>) void lanczos_kernel(PatchArgs a) {
   c.vec = Lay::vec_in_lds ? c.lds + Lay::vec_off
                           : reinterpret_cast<T*>(a.vec_scratch) + (int64_t)blockIdx.x * a.vec_stride;
   c.gtab = a.tab64;
-  const int patch = a.patch_begin + blockIdx.x;
+  const int patch = patch_of_block(a);
   {
     // load_patch without the Chebyshev parameters
     const int tid = threadIdx.x;
@@ -1655,22 +1659,7 @@ __global__ __launch_bounds__(NT<double>) void lanczos_kernel(PatchArgs a) {
       const int sz = tab_size(LV::q[l]);
       for (int i = tid; i < sz; i += NT<T>) c.lds[Lay::tab_level_off(l) + i] = tab[l * kTabLevelStride + i];
     }
-    const int vlin = a.patch_vertex[patch];
-    const int N1 = a.N + 1;
-    const int vx = vlin % N1, vy = (vlin / N1) % N1, vz = DIM == 3 ? vlin / (N1 * N1) : 0;
-    for (int i = tid; i < Lay::nvert * DIM; i += NT<T>) {
-      const int r = i % DIM, t = i / DIM;
-      const int tx = t % 3, ty = (t / 3) % 3, tz = DIM == 3 ? t / 9 : 0;
-      int g = (vx - 1 + tx) + (vy - 1 + ty) * N1;
-      if (DIM == 3) g += (vz - 1 + tz) * N1 * N1;
-      c.geo()[i] = a.verts[g * DIM + r] - a.verts[vlin * DIM + r];
-    }
-    for (int i = tid; i < ipow(2, DIM); i += NT<T>) {
-      const int cx = i & 1, cy = (i >> 1) & 1, cz = (i >> 2) & 1;
-      int g = (vx - 1 + cx) + (vy - 1 + cy) * a.N;
-      if (DIM == 3) g += (vz - 1 + cz) * a.N * a.N;
-      c.mu()[i] = a.mu[g];
-    }
+    load_geometry<T, DIM>(a, patch, c.geo(), c.mu());
     for (int l = 0; l < LV::count; ++l) {
       const int sz = Lay::level_size(l);
       const double* src = a.invdiag64[l] + (int64_t)patch * sz;
@@ -1701,7 +1690,7 @@ __global__ __launch_bounds__(NT<double>) void dense_kernel(PatchArgs a) {
   c.vec = Lay::vec_in_lds ? c.lds + Lay::vec_off
                           : reinterpret_cast<T*>(a.vec_scratch) + (int64_t)blockIdx.x * a.vec_stride;
   c.gtab = a.tab64;
-  const int patch = a.patch_begin + blockIdx.x;
+  const int patch = patch_of_block(a);
   const int tid = threadIdx.x;
   {
     const T* tab = a.tab64;
@@ -1709,22 +1698,7 @@ __global__ __launch_bounds__(NT<double>) void dense_kernel(PatchArgs a) {
       const int sz = tab_size(LV::q[l]);
       for (int i = tid; i < sz; i += NT<T>) c.lds[Lay::tab_level_off(l) + i] = tab[l * kTabLevelStride + i];
     }
-    const int vlin = a.patch_vertex[patch];
-    const int N1 = a.N + 1;
-    const int vx = vlin % N1, vy = (vlin / N1) % N1, vz = DIM == 3 ? vlin / (N1 * N1) : 0;
-    for (int i = tid; i < Lay::nvert * DIM; i += NT<T>) {
-      const int r = i % DIM, t = i / DIM;
-      const int tx = t % 3, ty = (t / 3) % 3, tz = DIM == 3 ? t / 9 : 0;
-      int g = (vx - 1 + tx) + (vy - 1 + ty) * N1;
-      if (DIM == 3) g += (vz - 1 + tz) * N1 * N1;
-      c.geo()[i] = a.verts[g * DIM + r] - a.verts[vlin * DIM + r];
-    }
-    for (int i = tid; i < ipow(2, DIM); i += NT<T>) {
-      const int cx = i & 1, cy = (i >> 1) & 1, cz = (i >> 2) & 1;
-      int g = (vx - 1 + cx) + (vy - 1 + cy) * a.N;
-      if (DIM == 3) g += (vz - 1 + cz) * a.N * a.N;
-      c.mu()[i] = a.mu[g];
-    }
+    load_geometry<T, DIM>(a, patch, c.geo(), c.mu());
     __syncthreads();
   }
   prepare_geometry<T, DIM, LV>(c);
@@ -1747,6 +1721,85 @@ __global__ __launch_bounds__(NT<double>) void dense_kernel(PatchArgs a) {
   if constexpr (LV::count > 1) run(std::integral_constant<int, 1>{});
   if constexpr (LV::count > 2) run(std::integral_constant<int, 2>{});
   if constexpr (LV::count > 3) run(std::integral_constant<int, 3>{});
+}
+
+// ---------------------------------------------------------------------------
+// features of the bound-predicting network, one 64-thread block per patch:
+// for every cell c and every point g of the 2-point Gauss rule,
+// det J / h^d, ||J||_F^2 / h^2 and ||cof J||_F^2 / h^(2(d-1)) at (c 2^d + g) 3,
+// then log10 mu_c minus its patch mean; h = (mean cell volume)^(1/d)
+// ---------------------------------------------------------------------------
+
+template <int DIM>
+__global__ __launch_bounds__(64) void feature_kernel(PatchArgs a, float* out) {
+  constexpr int ncell = ipow(2, DIM), npt = ipow(2, DIM), nvert = ipow(3, DIM);
+  constexpr int NF = 3 * ncell * npt + ncell;
+  __shared__ double geo[nvert * DIM], mu[ncell], red[64];
+  const int patch = a.patch_begin + blockIdx.x;
+  const int t = threadIdx.x;
+  load_geometry<double, DIM>(a, patch, geo, mu);
+  __syncthreads();
+  double det = 0, fro = 0, cfro = 0;
+  if (t < ncell * npt) {
+    const int c = t / npt, g = t % npt;
+    const double lo = 0.5 - 0.5 / sqrt(3.0), hi = 0.5 + 0.5 / sqrt(3.0);
+    const double xi[3] = {(g & 1) ? hi : lo, ((g >> 1) & 1) ? hi : lo, ((g >> 2) & 1) ? hi : lo};
+    const int cc[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
+    double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int k = 0; k < ncell; ++k) {
+      int b[3] = {k & 1, (k >> 1) & 1, (k >> 2) & 1};
+      int v = (cc[0] + b[0]) + 3 * (cc[1] + b[1]);
+      if (DIM == 3) v += 9 * (cc[2] + b[2]);
+      for (int s2 = 0; s2 < DIM; ++s2) {
+        double dphi = 1.0;
+        for (int i = 0; i < DIM; ++i)
+          dphi *= (i == s2) ? (b[i] ? 1.0 : -1.0) : (b[i] ? xi[i] : 1.0 - xi[i]);
+        for (int r = 0; r < DIM; ++r) J[r][s2] += geo[v * DIM + r] * dphi;
+      }
+    }
+    if (DIM == 3) {
+      double C[3][3];
+      C[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+      C[0][1] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+      C[0][2] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+      C[1][0] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+      C[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+      C[1][2] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+      C[2][0] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+      C[2][1] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+      C[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+      det = J[0][0] * C[0][0] + J[0][1] * C[0][1] + J[0][2] * C[0][2];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          fro += J[i][j] * J[i][j];
+          cfro += C[i][j] * C[i][j];
+        }
+    } else {
+      det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+      fro = J[0][0] * J[0][0] + J[0][1] * J[0][1] + J[1][0] * J[1][0] + J[1][1] * J[1][1];
+      cfro = fro;  // the 2D cofactor matrix is a signed permutation of J
+    }
+  }
+  red[t] = det;
+  __syncthreads();
+  if (t == 0) {
+    double sdet = 0;
+    for (int i = 0; i < ncell * npt; ++i) sdet += red[i];
+    red[0] = sdet / (ncell * npt);  // mean cell volume (Gauss weights 2^-d)
+  }
+  __syncthreads();
+  const double h = pow(red[0], 1.0 / DIM);
+  float* o = out + (int64_t)patch * NF;
+  if (t < ncell * npt) {
+    o[3 * t] = (float)(det / pow(h, (double)DIM));
+    o[3 * t + 1] = (float)(fro / (h * h));
+    o[3 * t + 2] = (float)(cfro / pow(h, 2.0 * (DIM - 1)));
+  }
+  if (t < ncell) {
+    double m = 0;
+    for (int i = 0; i < ncell; ++i) m += log10(mu[i]);
+    o[3 * ncell * npt + t] = (float)(log10(mu[t]) - m / ncell);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1892,6 +1945,16 @@ const PatchVariant* registry(size_t* count) {
 }
 
 }  // namespace
+
+hipError_t launch_features(int dim, const PatchArgs& a, int n_patch, float* out, hipStream_t s) {
+  if (n_patch <= 0) return hipSuccess;
+  (void)hipGetLastError();
+  if (dim == 3)
+    hipLaunchKernelGGL(feature_kernel<3>, dim3(n_patch), dim3(64), 0, s, a, out);
+  else
+    hipLaunchKernelGGL(feature_kernel<2>, dim3(n_patch), dim3(64), 0, s, a, out);
+  return hipGetLastError();
+}
 
 hipError_t init_constant_tables() {
   std::vector<double> t64(kConstTab, 0.0);

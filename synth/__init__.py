@@ -13,4 +13,5 @@ from .generators import (  # noqa: F401
     make_rhs,
     make_case,
     make_random_patch,
+    make_random_patches,
 )

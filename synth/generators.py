@@ -141,6 +141,39 @@ def _min_jacobian(X: np.ndarray, dim: int) -> np.ndarray:
     return best
 
 
+def _min_jacobian_batched(X: np.ndarray, dim: int, chunk: int = 4096) -> np.ndarray:
+    """Same sample points and result as _min_jacobian, computed with one
+    contraction per chunk of cells."""
+    g = 0.5 * np.sqrt(3.0 / 5.0)
+    pts1 = np.array([0.0, 0.5 - g, 0.5, 0.5 + g, 1.0])
+    P = np.array(np.meshgrid(*([pts1] * dim), indexing="ij")).reshape(dim, -1).T   # (npt, d)
+    dN = np.zeros((P.shape[0], 2 ** dim, dim))
+    for c in range(2 ** dim):
+        bits = [(c >> i) & 1 for i in range(dim)]
+        for k in range(dim):
+            v = np.ones(P.shape[0])
+            for i in range(dim):
+                if i == k:
+                    v = v * (1.0 if bits[i] else -1.0)
+                else:
+                    v = v * (P[:, i] if bits[i] else 1.0 - P[:, i])
+            dN[:, c, k] = v
+    out = np.empty(X.shape[0])
+    for s0 in range(0, X.shape[0], chunk):
+        Xc = X[s0:s0 + chunk]
+        dNm = dN.transpose(1, 0, 2).reshape(2 ** dim, -1)          # (corner, point*d)
+        J = np.stack([(Xc[:, :, r] @ dNm).reshape(Xc.shape[0], P.shape[0], dim)
+                      for r in range(dim)], axis=2)                 # (cell, point, r, s)
+        if dim == 3:
+            det = (J[..., 0, 0] * (J[..., 1, 1] * J[..., 2, 2] - J[..., 1, 2] * J[..., 2, 1])
+                   - J[..., 0, 1] * (J[..., 1, 0] * J[..., 2, 2] - J[..., 1, 2] * J[..., 2, 0])
+                   + J[..., 0, 2] * (J[..., 1, 0] * J[..., 2, 1] - J[..., 1, 1] * J[..., 2, 0]))
+        else:
+            det = J[..., 0, 0] * J[..., 1, 1] - J[..., 0, 1] * J[..., 1, 0]
+        out[s0:s0 + chunk] = det.min(axis=1)
+    return out
+
+
 def _all_cells(dim: int, n: int) -> np.ndarray:
     g = np.array(np.meshgrid(*([np.arange(n)] * dim), indexing="ij"))
     return np.stack([g[i].transpose(tuple(reversed(range(dim)))).reshape(-1)
@@ -239,4 +272,33 @@ def make_random_patch(dim: int, alpha: float, mu_log10, rng: np.random.Generator
         mu = np.ones(2 ** dim)
     else:
         mu = 10.0 ** rng.uniform(mu_log10[0], mu_log10[1], size=2 ** dim)
+    return X, mu
+
+
+def make_random_patches(dim: int, n: int, alpha: float, mu_log10, seed: int,
+                        det_floor: float = 0.05):
+    """n independent patches as make_random_patch draws them, vectorised:
+    all displacements are drawn first (patch-major, vertex, coordinate), then
+    patches with a tangled cell are redrawn in index order from the continuing
+    stream until none is left; the coefficients come last.  Returns
+    (vertices (n, 3^dim, dim), mu (n, 2^dim))."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    h = 0.5
+    coords = _all_cells(dim, 3).astype(np.float64) * h
+    corners = _corner_rows(dim, 3, _all_cells(dim, 2))      # (2^d cells, 2^d corners)
+    X = coords[None] + rng.uniform(-alpha * h, alpha * h, size=(n,) + coords.shape)
+    floor = det_floor * h ** dim
+    todo = np.arange(n)
+    for _ in range(10000):
+        dets = _min_jacobian_batched(X[todo][:, corners].reshape(-1, 2 ** dim, dim), dim).reshape(todo.size, -1)
+        todo = todo[dets.min(axis=1) <= floor]
+        if todo.size == 0:
+            break
+        X[todo] = coords[None] + rng.uniform(-alpha * h, alpha * h, size=(todo.size,) + coords.shape)
+    else:
+        raise RuntimeError("could not draw untangled patches")
+    if mu_log10 is None:
+        mu = np.ones((n, 2 ** dim))
+    else:
+        mu = 10.0 ** rng.uniform(mu_log10[0], mu_log10[1], size=(n, 2 ** dim))
     return X, mu
