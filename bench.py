@@ -6,10 +6,13 @@ A step is one forward multiplicative sweep (all 2^d colours; per patch:
 gather, evaluate, one local p-multigrid V-cycle, FP64 scatter-add) over the
 3D 16^3 Q4 mesh perturbed by 0.2 h (3,375 patches, local levels 4 -> 2 -> 1,
 Chebyshev degree 3) with inputs resident in HBM.  The headline value is the
-smoother throughput of the FP32 local solver in DoF/s (interior DoFs of the
-mesh x sweeps / time); the FP64 local solver is timed beside it, and the
-outer GMG-CG iteration counts of both are reported (FP32 counts must stay
-within one of FP64).  One JSON line is printed.
+smoother throughput in DoF/s (interior DoFs of the mesh x sweeps / time) of
+the FP32 local solver whose Chebyshev intervals come from the learned bound
+network (trained first, on the GPU, on Lanczos labels of random patches of
+the same distribution); the plain FP64 local solver with per-patch Lanczos
+bounds is timed beside it.  The comparison holds only if the outer GMG-CG
+iteration count of the FP32+learned solver stays within one of the FP64
+one; both counts are reported.  One JSON line is printed.
 """
 from __future__ import annotations
 
@@ -144,6 +147,9 @@ def main(argv=None):
     ap.add_argument("--workload", default="3d-n16-q4")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-cg", action="store_true", help="skip the outer CG iteration check")
+    ap.add_argument("--train-patches", type=int, default=6000,
+                    help="random patches whose Lanczos bounds train the bound network")
+    ap.add_argument("--train-epochs", type=int, default=30)
     ap.add_argument("--only", choices=["fp32", "fp64"], default=None,
                     help="time one precision only (for profiler runs; prints no JSON line)")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -179,31 +185,66 @@ def main(argv=None):
     dev = torch.device("cuda", 0)
     b = torch.tensor(bh, device=dev)
 
+    net = None
+    train = {}
+    if args.only != "fp64":
+        from paper_2510_17785_amd.learned import train_bound_network
+        Xt, mut = synth.make_random_patches(w.dim, args.train_patches, w.alpha, w.mu_log10, 4000 + w.cfg)
+        tr = train_bound_network(w.dim, w.p, w.levels, Xt, mut, epochs=args.train_epochs, batch=256,
+                                 lr=2e-3, seed=1)
+        net = tr
+        train = {"patches": args.train_patches, "epochs": args.train_epochs,
+                 "label_s": tr.label_seconds, "train_s": tr.train_seconds,
+                 "val_rmse_ln": [float(x) for x in tr.val_rmse], "margin_ln": tr.margin}
+        print(f"# bound network: labels {tr.label_seconds:.2f} s, training {tr.train_seconds:.2f} s, "
+              f"val rmse {tr.val_rmse}", file=sys.stderr, flush=True)
+
+    def learned(S):
+        return S.set_bounds_mlp(net.net, net.margin)
+
     res = {}
-    for prec in ((args.only,) if args.only else ("fp32", "fp64")):
+    variants = [("fp32", "learned"), ("fp64", "lanczos")]
+    if args.only:
+        variants = [v for v in variants if v[0] == args.only]
+    for prec, bsrc in variants:
         t0 = time.perf_counter()
-        S = PatchSmoother(w.dim, w.n, w.p, X, mu, levels=w.levels, precision=prec)
+        S = PatchSmoother(w.dim, w.n, w.p, X, mu, levels=w.levels, precision=prec,
+                          bounds="fixed" if bsrc == "learned" else "lanczos")
+        fallback = learned(S) if bsrc == "learned" else None
         torch.cuda.synchronize()
         setup_s = time.perf_counter() - t0
         u = torch.zeros_like(b)
         sweep_ms, per_launch, wall = time_sweeps(S, u, b, args.steps, args.warmup, torch)
         res[prec] = dict(S=S, setup_s=setup_s, sweep_ms=sweep_ms, per_launch=per_launch,
-                         dofs=S.n_interior_dofs, n_patches=S.n_patches)
-        print(f"# {prec}: sweep {sweep_ms:.4f} ms, setup {setup_s:.2f} s, "
+                         dofs=S.n_interior_dofs, n_patches=S.n_patches, fallback=fallback)
+        print(f"# {prec}+{bsrc}: sweep {sweep_ms:.4f} ms, setup {setup_s:.3f} s, "
               f"{S.n_interior_dofs * 1e3 / sweep_ms:.3e} DoF/s", file=sys.stderr, flush=True)
 
     if args.only:
         return 0
     cg = {}
     if not args.no_cg:
-        for prec in ("fp64", "fp32"):
-            G = GMGSolver(w.dim, w.n, w.p, X, mu, levels=w.levels, precision=prec)
+        for key, prec, bsrc in (("fp64_lanczos", "fp64", "lanczos"), ("fp32_learned", "fp32", "learned"),
+                                ("fp32_lanczos", "fp32", "lanczos")):
             t0 = time.perf_counter()
+            G = GMGSolver(w.dim, w.n, w.p, X, mu, levels=w.levels, precision=prec,
+                          bounds="fixed" if bsrc == "learned" else "lanczos")
+            nfb = 0
+            if bsrc == "learned":
+                for l in range(1, G.n_mesh_levels):
+                    nfb += learned(G.smoother(l))
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
             x, it, rel = G.cg(b, rtol=w.rtol)
             torch.cuda.synchronize()
-            cg[prec] = {"iterations": it, "relres": rel, "seconds": time.perf_counter() - t0}
+            cg[key] = {"iterations": it, "relres": rel, "setup_s": t1 - t0,
+                       "solve_s": time.perf_counter() - t1}
+            if bsrc == "learned":
+                cg[key]["lanczos_fallback_patches"] = nfb
             G.close()
-            print(f"# cg {prec}: {it} iterations, relres {rel:.2e}", file=sys.stderr, flush=True)
+            print(f"# cg {key}: {it} iterations, relres {rel:.2e}", file=sys.stderr, flush=True)
+        cg["fp32_learned_within_one_of_fp64"] = (cg["fp32_learned"]["iterations"]
+                                                 <= cg["fp64_lanczos"]["iterations"] + 1)
 
     r32 = res["fp32"]
     F, B = algorithmic_per_patch(w.dim, w.levels, 3, 4)
@@ -215,7 +256,7 @@ def main(argv=None):
     value = r32["dofs"] / (r32["sweep_ms"] / 1e3)
     value64 = res["fp64"]["dofs"] / (res["fp64"]["sweep_ms"] / 1e3)
     out = {
-        "metric": "patch-smoother DoF/s (FP32 local p-MG) vs FP64 local p-MG, same outer CG iters",
+        "metric": "patch-smoother DoF/s: FP32-MFMA+learned vs FP64 plain, same outer CG iters",
         "value": value,
         "unit": "DoF/s",
         "n_gpus": 1,
@@ -231,14 +272,16 @@ def main(argv=None):
             "workload": f"{w.name}: 3D {w.n}^3 hexes perturbed by {w.alpha} h, Q{w.p}, mu=1, "
                         f"{r32['n_patches']} vertex patches, local levels "
                         f"{'->'.join(map(str, w.levels))}, Chebyshev degree 3, N_MG=1, "
-                        f"Lanczos bounds (12 steps)",
+                        f"FP32 local solver with learned Chebyshev bounds vs FP64 local "
+                        f"solver with Lanczos bounds (12 steps)",
             "interior_dofs": r32["dofs"],
             "sweep": "forward, 8 colours",
         },
         "fp64": {"value": value64, "unit": "DoF/s", "ms_per_step": res["fp64"]["sweep_ms"],
                  "speedup_fp32_over_fp64": value / value64},
         "vcycles_per_s": r32["n_patches"] / (r32["sweep_ms"] / 1e3),
-        "setup_s": {p: res[p]["setup_s"] for p in res},
+        "setup_s": {"fp32_learned": res["fp32"]["setup_s"], "fp64_lanczos": res["fp64"]["setup_s"]},
+        "learned_bounds": dict(train, lanczos_fallback_patches=res["fp32"]["fallback"]),
         "outer_cg": cg,
         "roofline": {
             "bound": "alu",
