@@ -128,9 +128,17 @@ struct Layout {
   // buffers fit 40 KB at the top degree (else the two-slab form)
   static constexpr int P0 = ipow(2 * (LV::q[0] + 1), DIM);
   static constexpr bool seg_top = DIM == 3 && 4 * P0 * (int)sizeof(T) <= 40 * 1024;
-  static constexpr int abuf_elems = seg_top ? 4 * P0 : 4 * S0::S;
+  // where four full slabs would take more than 64 KB, the top level works in
+  // quarter-slabs (n x n x NQ buffers)
+  static constexpr bool quarter_top =
+      DIM == 3 && !seg_top && 4 * S0::S * (int)sizeof(T) > 64 * 1024;
+  static constexpr int abuf_elems =
+      seg_top ? 4 * P0 : (quarter_top ? 4 * S0::n * S0::n * S0::NQ : 4 * S0::S);
   static constexpr bool use_seg(int l) {
     return DIM == 3 && 4 * ipow(2 * (LV::q[l] + 1), DIM) <= abuf_elems;
+  }
+  static constexpr bool use_quarter(int l) {
+    return DIM == 3 && !use_seg(l) && 4 * ipow(2 * (LV::q[l] + 1), 3) / 2 > abuf_elems;
   }
   static constexpr int base_total = round_up(abuf_off + abuf_elems, 4);
   static constexpr int level_size(int l) { return ipow(2 * LV::q[l] - 1, DIM); }
@@ -554,6 +562,160 @@ __device__ __noinline__ void apply3(const T* __restrict__ X, T* __restrict__ Out
 }
 
 
+// The same operator in quarter-slabs: cell layer cz and cell row cy at a
+// time, so the four work buffers hold n x n x NQ values instead of
+// n x NQ x NQ (for degrees whose full slabs do not fit LDS next to the rest
+// of the patch).  Out is cleared first and every quarter adds its part.
+template <typename T, int Q, bool CACHE>
+__device__ __noinline__ void apply3q(const LDSP T* __restrict__ X, LDSP T* __restrict__ Out,
+                                     LDSP T* __restrict__ ab, const LDSP T* __restrict__ Bt,
+                                     const LDSP T* __restrict__ Dc, const LDSP T* __restrict__ xg,
+                                     const LDSP T* __restrict__ wg, const LDSP T* __restrict__ jc,
+                                     const LDSP T* __restrict__ mu, const LDSP T* __restrict__ Gc) {
+  using SH = Sh<3, Q>;
+  constexpr int n = SH::n, m = SH::m, mi = SH::mi, NQ = SH::NQ;
+  constexpr int H = n * n * NQ;  // one quarter-slab buffer: [z or kz][y or ky][QX]
+  LDSP T* A = ab;
+  LDSP T* Bf = ab + H;
+  LDSP T* C = ab + 2 * H;
+  LDSP T* Dd = ab + 3 * H;
+  const int tid = threadIdx.x;
+#pragma unroll 1
+  for (int i = tid; i < SH::interior; i += NT<T>) Out[i] = T(0);
+#pragma unroll 1
+  for (int qs = 0; qs < 4; ++qs) {
+    const int cz = qs >> 1, cy = qs & 1;
+    // x: A[zl][ya][QX] = sum_a B[kx][a] X[cz Q + zl][cy Q + ya][cx Q + a]
+#pragma unroll 1
+    for (int idx = tid; idx < H; idx += NT<T>) {
+      const int QX = idx % NQ, t = idx / NQ, ya = t % n, zl = t / n;
+      const int cx = QX >= n, kx = QX - cx * n;
+      const LDSP T* xr = X + ((cz * Q + zl) * m + cy * Q + ya) * m + cx * Q;
+      const LDSP T* br = Bt + kx * n;
+      T acc = 0;
+#pragma unroll
+      for (int a = 0; a < n; ++a) acc += br[a] * xr[a];
+      A[idx] = acc;
+    }
+    __syncthreads();
+    // y: Bf[zl][ky][QX] = sum_a B[ky][a] A[zl][a][QX]
+#pragma unroll 1
+    for (int idx = tid; idx < H; idx += NT<T>) {
+      const int QX = idx % NQ, t = idx / NQ, ky = t % n, zl = t / n;
+      const LDSP T* ar = A + zl * n * NQ + QX;
+      const LDSP T* br = Bt + ky * n;
+      T acc = 0;
+#pragma unroll
+      for (int a = 0; a < n; ++a) acc += br[a] * ar[a * NQ];
+      Bf[idx] = acc;
+    }
+    __syncthreads();
+    // z: C[kz][ky][QX] = sum_zl B[kz][zl] Bf[zl][ky][QX]   (values at Gauss points)
+#pragma unroll 1
+    for (int idx = tid; idx < H; idx += NT<T>) {
+      const int kz = idx / (n * NQ), rem = idx % (n * NQ);
+      const LDSP T* br = Bt + kz * n;
+      T acc = 0;
+#pragma unroll
+      for (int a = 0; a < n; ++a) acc += br[a] * Bf[a * n * NQ + rem];
+      C[idx] = acc;
+    }
+    __syncthreads();
+    // reference gradients by collocation, then the flux G grad
+#pragma unroll 1
+    for (int idx = tid; idx < H; idx += NT<T>) {
+      const int QX = idx % NQ, t = idx / NQ, ky = t % n, kz = t / n;
+      const int cx = QX >= n, kx = QX - cx * n;
+      const LDSP T* dx = Dc + kx * n;
+      const LDSP T* dy = Dc + ky * n;
+      const LDSP T* dz = Dc + kz * n;
+      const LDSP T* cxr = C + (kz * n + ky) * NQ + cx * n;
+      const LDSP T* cyr = C + kz * n * NQ + QX;
+      const LDSP T* czr = C + ky * NQ + QX;
+      T gx = 0, gy = 0, gz = 0;
+#pragma unroll
+      for (int a = 0; a < n; ++a) {
+        gx += dx[a] * cxr[a];
+        gy += dy[a] * cyr[a * NQ];
+        gz += dz[a] * czr[a * n * NQ];
+      }
+      T G[6];
+      if constexpr (CACHE) {
+        const int gp = ((cz * n + kz) * NQ + cy * n + ky) * NQ + QX;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) G[c] = Gc[c * NQ * NQ * NQ + gp];
+      } else {
+        const int cell = cz * 4 + cy * 2 + cx;
+        metric3c<T>(jc + cell * 36, xg[kx], xg[ky], xg[kz], mu[cell] * wg[kx] * wg[ky] * wg[kz], G);
+      }
+      A[idx] = G[0] * gx + G[1] * gy + G[2] * gz;
+      Bf[idx] = G[1] * gx + G[3] * gy + G[4] * gz;
+      Dd[idx] = G[2] * gx + G[4] * gy + G[5] * gz;
+    }
+    __syncthreads();
+    // transposed collocation: C = Dc^T F
+#pragma unroll 1
+    for (int idx = tid; idx < H; idx += NT<T>) {
+      const int QX = idx % NQ, t = idx / NQ, ky = t % n, kz = t / n;
+      const int cx = QX >= n, kx = QX - cx * n;
+      const LDSP T* fx = A + (kz * n + ky) * NQ + cx * n;
+      const LDSP T* fy = Bf + kz * n * NQ + QX;
+      const LDSP T* fz = Dd + ky * NQ + QX;
+      T acc = 0;
+#pragma unroll
+      for (int a = 0; a < n; ++a) {
+        acc += Dc[a * n + kx] * fx[a];
+        acc += Dc[a * n + ky] * fy[a * NQ];
+        acc += Dc[a * n + kz] * fz[a * n * NQ];
+      }
+      C[idx] = acc;
+    }
+    __syncthreads();
+    // z^T: A[zl][ky][QX] = sum_kz B[kz][zl] C[kz][ky][QX]
+#pragma unroll 1
+    for (int idx = tid; idx < H; idx += NT<T>) {
+      const int zl = idx / (n * NQ), rem = idx % (n * NQ);
+      T acc = 0;
+#pragma unroll
+      for (int k = 0; k < n; ++k) acc += Bt[k * n + zl] * C[k * n * NQ + rem];
+      A[idx] = acc;
+    }
+    __syncthreads();
+    // y^T: Bf[zl][ya][QX] = sum_ky B[ky][ya] A[zl][ky][QX]
+#pragma unroll 1
+    for (int idx = tid; idx < H; idx += NT<T>) {
+      const int QX = idx % NQ, t = idx / NQ, ya = t % n, zl = t / n;
+      const LDSP T* ar = A + zl * n * NQ + QX;
+      T acc = 0;
+#pragma unroll
+      for (int k = 0; k < n; ++k) acc += Bt[k * n + ya] * ar[k * NQ];
+      Bf[idx] = acc;
+    }
+    __syncthreads();
+    // x^T onto the interior nodes of this quarter: z = cz Q + zl and
+    // y = cy Q + ya in 1 .. 2Q-1, Q planes and Q rows per quarter
+    const int zl0 = cz == 0 ? 1 : 0, ya0 = cy == 0 ? 1 : 0;
+#pragma unroll 1
+    for (int idx = tid; idx < Q * Q * mi; idx += NT<T>) {
+      const int xi = idx % mi, t = idx / mi, ya = ya0 + t % Q, zl = zl0 + t / Q;
+      const int x = xi + 1;
+      const LDSP T* br = Bf + (zl * n + ya) * NQ;
+      T acc = 0;
+      if (x <= Q) {
+#pragma unroll
+        for (int k = 0; k < n; ++k) acc += Bt[k * n + x] * br[k];
+      }
+      if (x >= Q) {
+#pragma unroll
+        for (int k = 0; k < n; ++k) acc += Bt[k * n + (x - Q)] * br[n + k];
+      }
+      const int zz = cz * Q + zl - 1, yy = cy * Q + ya - 1;
+      Out[(zz * mi + yy) * mi + xi] += acc;
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // 3D level operator in segment form
 //
@@ -933,9 +1095,19 @@ __device__ __forceinline__ void apply_level(const Ctx<T, DIM, LV>& c) {
                                  lds_cast(c.abuf()), lds_cast(c.tabB(L)), lds_cast(c.tabDc(L)),
                                  lds_cast(c.jc()),
                                  lds_cast(c.mu()), lds_cast(c.Gc(L)));
-  else if constexpr (DIM == 3)
+  else if constexpr (Layout<T, DIM, LV>::use_quarter(L)) {
+    static_assert(4 * (Q + 1) * (Q + 1) * 2 * (Q + 1) <= Layout<T, DIM, LV>::abuf_elems,
+                  "quarter-slab buffers exceed the work area");
+    apply3q<T, Q, CACHE>(lds_cast(c.X()), lds_cast(c.Out()), lds_cast(c.abuf()),
+                         lds_cast(c.tabB(L)), lds_cast(c.tabDc(L)), lds_cast(c.tabXg(L)),
+                         lds_cast(c.tabWg(L)), lds_cast(c.jc()), lds_cast(c.mu()),
+                         lds_cast(c.Gc(L)));
+  } else if constexpr (DIM == 3) {
+    static_assert(4 * Sh<3, Q>::S <= Layout<T, DIM, LV>::abuf_elems,
+                  "slab buffers exceed the work area");
     apply3<T, Q, CACHE>(c.X(), c.Out(), c.abuf(), c.tabB(L), c.tabDc(L), c.tabXg(L), c.tabWg(L),
                         c.jc(), c.mu(), c.Gc(L));
+  }
   else
     apply2<T, Q, CACHE>(c.X(), c.Out(), c.abuf(), c.tabB(L), c.tabDc(L), c.tabXg(L), c.tabWg(L),
                         c.jc(), c.mu(), c.Gc(L));
@@ -1210,6 +1382,9 @@ __device__ void vcycle(const Ctx<T, DIM, LV>& c, int k, bool d_zero) {
     __syncthreads();
   } else {
     constexpr int QF = LV::q[L], QC = LV::q[L + 1];
+    constexpr int mf = 2 * QF - 1, mc = 2 * QC - 1;
+    static_assert(DIM != 3 || mf * mf * mc + mf * mc * mc <= Layout<T, DIM, LV>::abuf_elems,
+                  "transfer temporaries exceed the work area");
     using PT = VecPtr<T, DIM, LV>;
     chebyshev<T, DIM, LV, L>(c, k, d_zero);          // pre-smoothing
     T* res = c.res();
@@ -1438,6 +1613,7 @@ __global__ __launch_bounds__(NT<double>) void diag_kernel(PatchArgs a) {
     T* dg = c.X();      // closure diagonal
     T* G = c.abuf();    // metric at the Gauss points of one cell
     constexpr int NG = DIM == 3 ? 6 : 3;
+    static_assert(NG * npt <= Lay::abuf_elems, "one cell's metric exceeds the work area");
     const T* B = c.tabB(L);
     const T* D = c.tabD(L);
     const T* xg = c.tabXg(L);

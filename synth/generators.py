@@ -204,17 +204,30 @@ def make_vertices(dim: int, n: int, alpha: float, seed: int,
     delta[~interior] = 0.0
     if alpha == 0.0:
         return base.copy()
-    corners = _corner_rows(dim, n1, _all_cells(dim, n))
+    cells = _all_cells(dim, n)
+    corners = _corner_rows(dim, n1, cells)
     floor = det_floor * h ** dim
+    check = np.arange(cells.shape[0])
     for _ in range(max_redraws):
         verts = base + delta
-        bad = np.nonzero(_min_jacobian(verts[corners], dim) <= floor)[0]
+        # only cells touching a redrawn vertex can change; the others passed
+        bad = check[_min_jacobian(verts[corners[check]], dim) <= floor]
         if bad.size == 0:
             return verts
+        moved = []
         for c in bad:
             for vi in corners[c]:
                 if interior[vi]:
                     delta[vi] = rng.uniform(-alpha * h, alpha * h, size=dim)
+                    moved.append(vi)
+        touched = set()
+        for vi in set(moved):
+            v = coords[vi]
+            for k in range(2 ** dim):
+                c = v - np.array([(k >> i) & 1 for i in range(dim)])
+                if np.all((c >= 0) & (c < n)):
+                    touched.add(int(sum(int(c[i]) * n ** i for i in range(dim))))
+        check = np.array(sorted(touched), dtype=np.int64)
     raise RuntimeError("could not draw a mesh without degenerate cells")
 
 

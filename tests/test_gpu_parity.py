@@ -26,6 +26,7 @@ CASES = [
     ("3d-n16-q4", 4, 4, (4, 2, 1)),
     ("3d-n32-q7-jump", 3, 7, (7, 3, 1)),
     ("3d-n32-q6-learned", 3, 6, (6, 3, 1)),
+    ("3d-n24-q8-batch", 2, 8, (8, 4, 2, 1)),
 ]
 TOL = {"fp64": 1e-11, "fp32": 2e-5}
 
