@@ -56,6 +56,17 @@ extern "C" {
 /* precision of the local p-multigrid (global vectors stay FP64) */
 #define PMG_FP64 0
 #define PMG_FP32 1
+/* FP32 local p-multigrid whose top-level interpolation contractions take
+ * BF16-rounded inputs on the matrix cores and accumulate in FP32; the
+ * collocation derivatives, the metric, Chebyshev updates, diagonals and all
+ * lower levels stay FP32.  3D top-level degrees 6 and 7 only (others return
+ * PMG_ERR_UNSUPPORTED). */
+#define PMG_BF16_FP32ACC 2
+/* As PMG_BF16_FP32ACC with every operand split into two BF16 numbers
+ * (x = hi + lo, hi = bf16(x), lo = bf16(x - hi)) and three products per
+ * tile (hi hi + hi lo + lo hi), accumulated in FP32: about 16 significant
+ * bits per operand instead of 8. */
+#define PMG_BF16X3_FP32ACC 3
 
 /* source of the Chebyshev eigenvalue bounds */
 #define PMG_BOUNDS_LANCZOS 0  /* per-patch Lanczos at setup */
@@ -83,7 +94,7 @@ typedef struct pmg_mesh {
 } pmg_mesh;
 
 typedef struct pmg_opts {
-  int32_t precision;     /* PMG_FP64 or PMG_FP32 */
+  int32_t precision;     /* PMG_FP64, PMG_FP32, PMG_BF16_FP32ACC or PMG_BF16X3_FP32ACC */
   int32_t n_levels;      /* number of local p-levels, 2..4 */
   int32_t levels[8];     /* degrees, strictly descending, levels[0] = p, last = 1 */
   int32_t cheb_degree;   /* Chebyshev steps per smoothing pass, 1..8 (default 3) */

@@ -19,6 +19,8 @@ PMG_WARN_NOT_CONVERGED = 1
 
 PMG_FP64 = 0
 PMG_FP32 = 1
+PMG_BF16_FP32ACC = 2
+PMG_BF16X3_FP32ACC = 3
 PMG_BOUNDS_LANCZOS = 0
 PMG_BOUNDS_FIXED = 1
 

@@ -32,7 +32,8 @@ def _opts(levels, precision, cheb_degree, n_vcycles, bounds, lanczos_steps, cheb
     lib = L.load()
     o = L.PmgOpts()
     L.check(lib.pmg_default_opts(ctypes.byref(o)))
-    o.precision = {"fp64": L.PMG_FP64, "fp32": L.PMG_FP32}[precision]
+    o.precision = {"fp64": L.PMG_FP64, "fp32": L.PMG_FP32, "bf16": L.PMG_BF16_FP32ACC,
+                    "bf16x3": L.PMG_BF16X3_FP32ACC}[precision]
     lv = list(levels) if levels is not None else []
     o.n_levels = len(lv)
     for i, q in enumerate(lv):

@@ -227,7 +227,7 @@ int set_cheb(pmg_handle* h) {
 
 // option checks shared by every setup; fills the level list and the kernel variant
 int check_opts(const pmg_opts* o, int dim, int p, int* levels, int& L, const PatchVariant*& var) {
-  if (o->precision != PMG_FP64 && o->precision != PMG_FP32)
+  if (o->precision < PMG_FP64 || o->precision > PMG_BF16X3_FP32ACC)
     return fail(PMG_ERR_INVALID_ARG, "unknown precision %d", o->precision);
   if (o->cheb_degree < 1 || o->cheb_degree > 8)
     return fail(PMG_ERR_INVALID_ARG, "Chebyshev degree %d outside 1..8", o->cheb_degree);
@@ -349,7 +349,7 @@ int setup_common(pmg_handle* h) {
         return cleanup(fail(PMG_ERR_HIP, "diagonal kernel (%d patches, LDS %zu bytes of FP64 layout): %s",
                             a.n_patch, var->lds_bytes(-1), hipGetErrorString(e)));
     }
-    if (h->precision == PMG_FP32)
+    if (h->precision != PMG_FP64)
       for (int l = 0; l < L; ++l)
         if ((e = launch_convert_to_float((int64_t)h->n_patches * h->level_size(l), h->invdiag64[l],
                                          reinterpret_cast<float*>(h->invdiag[l]), h->stream)))
@@ -379,7 +379,7 @@ int setup_common(pmg_handle* h) {
         if ((e = var->launch_dense(a, h->stream)))
           return cleanup(fail(PMG_ERR_HIP, "dense level kernel: %s", hipGetErrorString(e)));
       }
-      if (h->precision == PMG_FP32)
+      if (h->precision != PMG_FP64)
         for (int l = 0; l < L; ++l)
           if (var->dense_level[l] &&
               (e = launch_convert_to_float((int64_t)h->n_patches * h->level_size(l) * h->level_size(l),

@@ -84,6 +84,16 @@ template <int... Qs>
 struct Levels {
   static constexpr int count = sizeof...(Qs);
   static constexpr int q[kMaxLevels] = {Qs...};
+  static constexpr bool bf16 = false;
+  static constexpr bool split = false;
+};
+// The same level list with the BF16-input / FP32-accumulate top-level
+// operator (interpolation contractions on the matrix cores); SPLIT: every
+// operand as a sum of two BF16 numbers, three products per tile.
+template <bool SPLIT, int... Qs>
+struct LevelsBF16 : Levels<Qs...> {
+  static constexpr bool bf16 = true;
+  static constexpr bool split = SPLIT;
 };
 
 template <int DIM, int Q>
@@ -717,6 +727,207 @@ __device__ __noinline__ void apply3q(const LDSP T* __restrict__ X, LDSP T* __res
 }
 
 // ---------------------------------------------------------------------------
+// Contractions on the matrix cores (BF16 inputs, FP32 accumulation)
+//
+// One contraction phase is a product D = M In with a 1D (patch-level) matrix
+// M of at most 16 x 16 and an input of at most 16 rows and ncols columns.
+// Every wavefront takes 16-column tiles; one v_mfma_f32_16x16x16_bf16 per
+// tile.  Lane l supplies M[l % 16][4 (l / 16) + s] and In[4 (l / 16) + s][j]
+// for its column j = 16 tile + l % 16 (s = 0..3), and receives
+// D[4 (l / 16) + r][j] (r = 0..3).  Inputs are rounded to BF16 (nearest
+// even) when they are packed into the operands; the products are exact in
+// FP32 and accumulated in FP32; results are stored in FP32.
+// ---------------------------------------------------------------------------
+
+typedef short mm_s4 __attribute__((ext_vector_type(4)));
+typedef float mm_f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short to_bf16(float x) { return __builtin_bit_cast(short, (__bf16)x); }
+
+__device__ __forceinline__ float from_bf16(short h) {
+  return (float)__builtin_bit_cast(__bf16, h);
+}
+
+// SPLIT: x = hi + lo with hi = bf16(x), lo = bf16(x - hi); the product
+// M In is taken as Mhi Inhi + Mhi Inlo + Mlo Inhi (the dropped lo lo term
+// is below 2^-16 relative), all accumulated in FP32.
+template <bool SPLIT, class MatF, class InF, class OutF>
+__device__ __forceinline__ void mm_phase(int ncols, MatF mat, InF in, OutF out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int NW = NT<float> / 64;
+  const int i = lane & 15, g = lane >> 4;
+  mm_s4 av, al;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const float x = mat(i, 4 * g + s);
+    av[s] = to_bf16(x);
+    if constexpr (SPLIT) al[s] = to_bf16(x - from_bf16(av[s]));
+  }
+#pragma unroll 1
+  for (int tile = wave; tile * 16 < ncols; tile += NW) {
+    const int j = tile * 16 + i;
+    const bool live = j < ncols;
+    mm_s4 bv, bl;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const float x = live ? in(4 * g + s, j) : 0.0f;
+      bv[s] = to_bf16(x);
+      if constexpr (SPLIT) bl[s] = to_bf16(x - from_bf16(bv[s]));
+    }
+    mm_f4 c = {0.0f, 0.0f, 0.0f, 0.0f};
+    if constexpr (SPLIT) {
+      c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bv, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bl, c, 0, 0, 0);
+    }
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, c, 0, 0, 0);
+    if (live) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) out(4 * g + r, j, c[r]);
+    }
+  }
+}
+
+// The slab-form operator (apply3) with its six interpolation contractions
+// (x, y, z and their transposes) on the matrix cores; the collocation
+// derivatives and the flux G grad stay in FP32 on the vector ALUs.
+template <int Q, bool CACHE, bool SPLIT>
+__device__ __noinline__ void apply3mm(const LDSP float* __restrict__ X, LDSP float* __restrict__ Out,
+                                      LDSP float* __restrict__ ab, const LDSP float* __restrict__ Bt,
+                                      const LDSP float* __restrict__ Dc,
+                                      const LDSP float* __restrict__ xg,
+                                      const LDSP float* __restrict__ wg,
+                                      const LDSP float* __restrict__ jc,
+                                      const LDSP float* __restrict__ mu,
+                                      const LDSP float* __restrict__ Gc) {
+  using T = float;
+  using SH = Sh<3, Q>;
+  constexpr int n = SH::n, m = SH::m, mi = SH::mi, NQ = SH::NQ, S = SH::S, NQ2 = NQ * NQ;
+  static_assert(NQ <= 16 && m <= 16, "one matrix-core tile per contraction");
+  LDSP T* A = ab;
+  LDSP T* Bf = ab + S;
+  LDSP T* C = ab + 2 * S;
+  LDSP T* Dd = ab + 3 * S;
+  const int tid = threadIdx.x;
+  // patch-level 1D interpolation matrix: row = Gauss point QA = c n + k of
+  // cell c, column = closure node x; B[k][x - c q] inside cell c, else 0
+  auto Bp = [&](int QA, int x) -> T {
+    const int c = QA >= n ? 1 : 0, k = QA - c * n, a = x - c * Q;
+    return (QA < NQ && x < m && a >= 0 && a <= Q) ? Bt[k * n + a] : T(0);
+  };
+  auto Bc = [&](int k, int a) -> T { return (k < n && a < n) ? Bt[k * n + a] : T(0); };
+#pragma unroll 1
+  for (int cz = 0; cz < 2; ++cz) {
+    // x: A[zl][y][QX] = sum_x Bp[QX][x] X[cz Q + zl][y][x]
+    mm_phase<SPLIT>(
+        n * m, Bp,
+        [&](int x, int j) -> T { return x < m ? X[(cz * Q + j / m) * m * m + (j % m) * m + x] : T(0); },
+        [&](int QX, int j, T v) {
+          if (QX < NQ) A[j * NQ + QX] = v;
+        });
+    __syncthreads();
+    // y: Bf[zl][QY][QX] = sum_y Bp[QY][y] A[zl][y][QX]
+    mm_phase<SPLIT>(
+        n * NQ, Bp,
+        [&](int y, int j) -> T { return y < m ? A[((j / NQ) * m + y) * NQ + j % NQ] : T(0); },
+        [&](int QY, int j, T v) {
+          if (QY < NQ) Bf[((j / NQ) * NQ + QY) * NQ + j % NQ] = v;
+        });
+    __syncthreads();
+    // z: C[kz][QY][QX] = sum_zl B[kz][zl] Bf[zl][QY][QX]
+    mm_phase<SPLIT>(
+        NQ2, Bc, [&](int zl, int j) -> T { return zl < n ? Bf[zl * NQ2 + j] : T(0); },
+        [&](int kz, int j, T v) {
+          if (kz < n) C[kz * NQ2 + j] = v;
+        });
+    __syncthreads();
+    // reference gradients by collocation, then the flux G grad (FP32)
+#pragma unroll 1
+    for (int idx = tid; idx < S; idx += NT<T>) {
+      const int QX = idx % NQ, t = idx / NQ, QY = t % NQ, kz = t / NQ;
+      const int cx = QX >= n, kx = QX - cx * n, cy = QY >= n, ky = QY - cy * n;
+      const LDSP T* dx = Dc + kx * n;
+      const LDSP T* dy = Dc + ky * n;
+      const LDSP T* dz = Dc + kz * n;
+      const LDSP T* cxr = C + (kz * NQ + QY) * NQ + cx * n;
+      const LDSP T* cyr = C + (kz * NQ + cy * n) * NQ + QX;
+      const LDSP T* czr = C + QY * NQ + QX;
+      T gx = 0, gy = 0, gz = 0;
+#pragma unroll
+      for (int a = 0; a < n; ++a) {
+        gx += dx[a] * cxr[a];
+        gy += dy[a] * cyr[a * NQ];
+        gz += dz[a] * czr[a * NQ2];
+      }
+      T G[6];
+      if constexpr (CACHE) {
+        const int gp = cz * S + idx;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) G[c] = Gc[c * 2 * S + gp];
+      } else {
+        const int cell = cz * 4 + cy * 2 + cx;
+        metric3c<T>(jc + cell * 36, xg[kx], xg[ky], xg[kz], mu[cell] * wg[kx] * wg[ky] * wg[kz], G);
+      }
+      A[idx] = G[0] * gx + G[1] * gy + G[2] * gz;
+      Bf[idx] = G[1] * gx + G[3] * gy + G[4] * gz;
+      Dd[idx] = G[2] * gx + G[4] * gy + G[5] * gz;
+    }
+    __syncthreads();
+    // transposed collocation: C = Dc^T F (FP32)
+#pragma unroll 1
+    for (int idx = tid; idx < S; idx += NT<T>) {
+      const int QX = idx % NQ, t = idx / NQ, QY = t % NQ, kz = t / NQ;
+      const int cx = QX >= n, kx = QX - cx * n, cy = QY >= n, ky = QY - cy * n;
+      const LDSP T* fx = A + (kz * NQ + QY) * NQ + cx * n;
+      const LDSP T* fy = Bf + (kz * NQ + cy * n) * NQ + QX;
+      const LDSP T* fz = Dd + QY * NQ + QX;
+      T acc = 0;
+#pragma unroll
+      for (int a = 0; a < n; ++a) {
+        acc += Dc[a * n + kx] * fx[a];
+        acc += Dc[a * n + ky] * fy[a * NQ];
+        acc += Dc[a * n + kz] * fz[a * NQ2];
+      }
+      C[idx] = acc;
+    }
+    __syncthreads();
+    // z^T: A[zl][QY][QX] = sum_kz B[kz][zl] C[kz][QY][QX]
+    mm_phase<SPLIT>(
+        NQ2, [&](int zl, int kz) -> T { return Bc(kz, zl); },
+        [&](int kz, int j) -> T { return kz < n ? C[kz * NQ2 + j] : T(0); },
+        [&](int zl, int j, T v) {
+          if (zl < n) A[zl * NQ2 + j] = v;
+        });
+    __syncthreads();
+    // y^T onto interior rows: Bf[zl][yi][QX] = sum_QY Bp[QY][yi + 1] A[zl][QY][QX]
+    mm_phase<SPLIT>(
+        n * NQ, [&](int yi, int QY) -> T { return yi < mi ? Bp(QY, yi + 1) : T(0); },
+        [&](int QY, int j) -> T { return QY < NQ ? A[((j / NQ) * NQ + QY) * NQ + j % NQ] : T(0); },
+        [&](int yi, int j, T v) {
+          if (yi < mi) Bf[((j / NQ) * mi + yi) * NQ + j % NQ] = v;
+        });
+    __syncthreads();
+    // x^T onto interior columns and the interior z-planes of this slab
+    const int zl0 = cz == 0 ? 1 : 0;
+    mm_phase<SPLIT>(
+        Q * mi, [&](int xi, int QX) -> T { return xi < mi ? Bp(QX, xi + 1) : T(0); },
+        [&](int QX, int j) -> T {
+          return QX < NQ ? Bf[((zl0 + j / mi) * mi + j % mi) * NQ + QX] : T(0);
+        },
+        [&](int xi, int j, T v) {
+          if (xi < mi) {
+            const int zl = zl0 + j / mi, yi = j % mi;
+            LDSP T* o = Out + ((cz * Q + zl - 1) * mi + yi) * mi + xi;
+            if (cz == 1 && zl == 0)
+              *o += v;
+            else
+              *o = v;
+          }
+        });
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // 3D level operator in segment form
 //
 // Every contraction phase works on line segments: a work item reads the n =
@@ -1102,6 +1313,12 @@ __device__ __forceinline__ void apply_level(const Ctx<T, DIM, LV>& c) {
                          lds_cast(c.tabB(L)), lds_cast(c.tabDc(L)), lds_cast(c.tabXg(L)),
                          lds_cast(c.tabWg(L)), lds_cast(c.jc()), lds_cast(c.mu()),
                          lds_cast(c.Gc(L)));
+  } else if constexpr (DIM == 3 && LV::bf16 && std::is_same<T, float>::value && L == 0) {
+    static_assert(4 * Sh<3, Q>::S <= Layout<T, DIM, LV>::abuf_elems,
+                  "slab buffers exceed the work area");
+    apply3mm<Q, CACHE, LV::split>(lds_cast(c.X()), lds_cast(c.Out()), lds_cast(c.abuf()), lds_cast(c.tabB(L)),
+                       lds_cast(c.tabDc(L)), lds_cast(c.tabXg(L)), lds_cast(c.tabWg(L)),
+                       lds_cast(c.jc()), lds_cast(c.mu()), lds_cast(c.Gc(L)));
   } else if constexpr (DIM == 3) {
     static_assert(4 * Sh<3, Q>::S <= Layout<T, DIM, LV>::abuf_elems,
                   "slab buffers exceed the work area");
@@ -2108,6 +2325,25 @@ PatchVariant make_variant() {
   return v;
 }
 
+// BF16-input / FP32-accumulate variants: FP32 layout and vectors, the top
+// level's interpolation contractions on the matrix cores (slab-form tops of
+// degree 6 and 7); setup kernels as for the plain level list.
+template <bool SPLIT, int DIM, int... Qs>
+PatchVariant make_variant_bf16() {
+  using LV = LevelsBF16<SPLIT, Qs...>;
+  using LP = Levels<Qs...>;
+  using V = Variant<float, DIM, LV>;
+  static_assert(!Layout<float, DIM, LV>::seg_top && !Layout<float, DIM, LV>::quarter_top,
+                "the matrix-core operator is the slab form");
+  PatchVariant v = make_variant<float, DIM, Qs...>();
+  v.precision = SPLIT ? PMG_BF16X3_FP32ACC : PMG_BF16_FP32ACC;
+  v.launch = &V::launch;
+  v.lds_bytes = &V::lds_bytes;
+  v.vec_scratch_elems = &V::vec_elems;
+  v.vec_scratch_elems64 = &Variant<double, DIM, LP>::vec_elems;
+  return v;
+}
+
 #define PMG_VARIANTS(T)                                                                        \
   make_variant<T, 2, 2, 1>(), make_variant<T, 2, 3, 1>(), make_variant<T, 2, 3, 2, 1>(),       \
       make_variant<T, 2, 4, 2, 1>(), make_variant<T, 2, 7, 3, 1>(), make_variant<T, 3, 2, 1>(), \
@@ -2115,7 +2351,11 @@ PatchVariant make_variant() {
       make_variant<T, 3, 6, 3, 1>(), make_variant<T, 3, 7, 3, 1>(), make_variant<T, 3, 8, 4, 2, 1>()
 
 const PatchVariant* registry(size_t* count) {
-  static const PatchVariant table[] = {PMG_VARIANTS(double), PMG_VARIANTS(float)};
+  static const PatchVariant table[] = {PMG_VARIANTS(double), PMG_VARIANTS(float),
+                                       make_variant_bf16<false, 3, 6, 3, 1>(),
+                                       make_variant_bf16<false, 3, 7, 3, 1>(),
+                                       make_variant_bf16<true, 3, 6, 3, 1>(),
+                                       make_variant_bf16<true, 3, 7, 3, 1>()};
   *count = sizeof(table) / sizeof(table[0]);
   return table;
 }
@@ -2167,7 +2407,9 @@ std::string list_variants() {
   const PatchVariant* t = registry(&n);
   std::string s;
   for (size_t i = 0; i < n; ++i) {
-    if (t[i].precision != PMG_FP64) continue;
+    if (t[i].precision == PMG_FP32) continue;  // same level lists as FP64
+    if (t[i].precision == PMG_BF16X3_FP32ACC) continue;  // same level lists as BF16
+    s += t[i].precision == PMG_BF16_FP32ACC ? "bf16 " : "";
     s += std::to_string(t[i].dim) + "D:";
     for (int l = 0; l < t[i].n_levels; ++l) s += (l ? "," : "") + std::to_string(t[i].levels[l]);
     s += " ";

@@ -6,8 +6,9 @@ that colour are recomputed one by one by the oracle from the same u and b
 (same-colour patches are independent, so each update depends only on the
 starting vector), and every node outside the colour's patch interiors must
 keep its value bit for bit.  At the 32^3 Q7 jump size the outer GMG-CG of the
-FP32 local solver must converge within one iteration of the FP64 one (the
-FP64 path itself is pinned to the oracle on down-scaled meshes).
+FP32 and split-BF16 local solvers must converge within one iteration of the
+FP64 one, plain BF16 is reported (the FP64 path itself is pinned to the
+oracle on down-scaled meshes).
 """
 import numpy as np
 import pytest
@@ -22,10 +23,12 @@ from oracle.smoother import patch_indices, patch_order, vertex_color  # noqa: E4
 pytestmark = pytest.mark.gpu
 
 # relative to the largest entry of the local correction
-TOL = {"fp64": 1e-11, "fp32": 1e-4}
+TOL = {"fp64": 1e-11, "fp32": 1e-4, "bf16": 5e-2, "bf16x3": 4e-4}
 
 FULL = [("3d-n16-q4", "fp64"), ("3d-n16-q4", "fp32"), ("3d-n32-q7-jump", "fp64"),
-        ("3d-n32-q7-jump", "fp32"), ("3d-n32-q6-learned", "fp32"), ("3d-n24-q8-batch", "fp32")]
+        ("3d-n32-q7-jump", "fp32"), ("3d-n32-q7-jump", "bf16"), ("3d-n32-q7-jump", "bf16x3"),
+        ("3d-n32-q6-learned", "fp32"),
+        ("3d-n24-q8-batch", "fp32")]
 
 _inputs = {}
 
@@ -87,17 +90,19 @@ def test_full_size_colour_sweep(name, precision):
     S.close()
 
 
-def test_full_size_gmg_cg_fp32_within_one():
+def test_full_size_gmg_cg_within_one():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2510_17785_amd import GMGSolver
     w, X, mu, b, _ = _case("3d-n32-q7-jump")
     bd = torch.tensor(b, device="cuda")
     its = {}
-    for prec in ("fp64", "fp32"):
+    for prec in ("fp64", "fp32", "bf16", "bf16x3"):
         G = GMGSolver(w.dim, w.n, w.p, X, mu, levels=w.levels, precision=prec)
         _, its[prec], rel = G.cg(bd, rtol=w.rtol)
         G.close()
-        assert rel <= w.rtol, (prec, rel)
-    print(f"\n32^3 Q7 jump GMG-CG iterations: {its}")
+        # plain BF16 operands may stall above the tolerance at this size: reported only
+        assert prec == "bf16" or rel <= w.rtol, (prec, rel)
+    print(f"\n32^3 Q7 jump GMG-CG iterations (101 = not converged in 100): {its}")
     assert its["fp32"] <= its["fp64"] + 1
+    assert its["bf16x3"] <= its["fp64"] + 1
