@@ -80,6 +80,11 @@ def measured_traffic(workload):
     return None
 
 
+def has_bf16(w):
+    """The BF16-input variants exist for 3D top degrees 6 and 7."""
+    return w.dim == 3 and w.levels[0] in (6, 7)
+
+
 def time_sweeps(S, u, b, steps, warmup, torch):
     """Per-colour launch times (ms) over `steps` forward sweeps, recorded with
     events on the stream the kernels run on."""
@@ -112,7 +117,8 @@ def cpu_baseline(w, X, mu, b, budget_s=12.0):
 
     order = patch_order(w.dim, w.n)
     rng = np.random.default_rng(0)
-    sample_n = min(96, len(order))
+    # the oracle assembles dense patch matrices: fewer sample patches at high degree
+    sample_n = min(96 if w.p <= 4 else 8, len(order))
     pick = sorted(rng.choice(len(order), sample_n, replace=False))
     sample = [order[i] for i in pick]
     mesh = fem.Mesh(w.dim, w.n, X, mu)
@@ -204,6 +210,8 @@ def main(argv=None):
 
     res = {}
     variants = [("fp32", "learned"), ("fp64", "lanczos")]
+    if has_bf16(w):
+        variants += [("bf16", "learned"), ("bf16x3", "learned")]
     if args.only:
         variants = [v for v in variants if v[0] == args.only]
     for prec, bsrc in variants:
@@ -224,8 +232,11 @@ def main(argv=None):
         return 0
     cg = {}
     if not args.no_cg:
-        for key, prec, bsrc in (("fp64_lanczos", "fp64", "lanczos"), ("fp32_learned", "fp32", "learned"),
-                                ("fp32_lanczos", "fp32", "lanczos")):
+        cg_variants = [("fp64_lanczos", "fp64", "lanczos"), ("fp32_learned", "fp32", "learned"),
+                       ("fp32_lanczos", "fp32", "lanczos")]
+        if has_bf16(w):
+            cg_variants += [("bf16_learned", "bf16", "learned"), ("bf16x3_learned", "bf16x3", "learned")]
+        for key, prec, bsrc in cg_variants:
             t0 = time.perf_counter()
             G = GMGSolver(w.dim, w.n, w.p, X, mu, levels=w.levels, precision=prec,
                           bounds="fixed" if bsrc == "learned" else "lanczos")
@@ -269,18 +280,23 @@ def main(argv=None):
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"{w.name}: 3D {w.n}^3 hexes perturbed by {w.alpha} h, Q{w.p}, mu=1, "
+            "workload": f"{w.name}: {w.dim}D {w.n}^{w.dim} cells perturbed by {w.alpha} h, Q{w.p}, "
+                        f"mu={'1' if w.mu_log10 is None else '10^U' + str(tuple(w.mu_log10))}, "
                         f"{r32['n_patches']} vertex patches, local levels "
                         f"{'->'.join(map(str, w.levels))}, Chebyshev degree 3, N_MG=1, "
                         f"FP32 local solver with learned Chebyshev bounds vs FP64 local "
                         f"solver with Lanczos bounds (12 steps)",
             "interior_dofs": r32["dofs"],
-            "sweep": "forward, 8 colours",
+            "sweep": f"forward, {2 ** w.dim} colours",
         },
         "fp64": {"value": value64, "unit": "DoF/s", "ms_per_step": res["fp64"]["sweep_ms"],
                  "speedup_fp32_over_fp64": value / value64},
+        **{prec: {"value": res[prec]["dofs"] / (res[prec]["sweep_ms"] / 1e3), "unit": "DoF/s",
+                  "ms_per_step": res[prec]["sweep_ms"],
+                  "speedup_over_fp64": res["fp64"]["sweep_ms"] / res[prec]["sweep_ms"]}
+           for prec in ("bf16", "bf16x3") if prec in res},
         "vcycles_per_s": r32["n_patches"] / (r32["sweep_ms"] / 1e3),
-        "setup_s": {"fp32_learned": res["fp32"]["setup_s"], "fp64_lanczos": res["fp64"]["setup_s"]},
+        "setup_s": {f"{p}_{'lanczos' if p == 'fp64' else 'learned'}": res[p]["setup_s"] for p in res},
         "learned_bounds": dict(train, lanczos_fallback_patches=res["fp32"]["fallback"]),
         "outer_cg": cg,
         "roofline": {
@@ -290,7 +306,7 @@ def main(argv=None):
             "unit": "TFLOP/s",
             "frac": achieved / VALU_PEAK_TFLOPS,
             "traffic": measured_traffic(w.name),
-            "kernel": "patch_kernel<float,3,Levels<4,2,1>,smooth>",
+            "kernel": f"patch_kernel<float,{w.dim},Levels<{','.join(map(str, w.levels))}>,smooth>",
             "algorithmic_flops_per_patch": F,
             "algorithmic_bytes_per_patch": B,
             "patches_per_launch": patches_per_launch,

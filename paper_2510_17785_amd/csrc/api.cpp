@@ -8,6 +8,8 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "fe_tables.hpp"
@@ -65,44 +67,72 @@ int dev_alloc(P** ptr, size_t bytes, size_t* counter) {
 // det J > 0 at the corners and Gauss points of every cell (the paper excludes
 // degenerate patches, Section 3.2)
 int check_mesh(int dim, int N, const double* X, int p) {
+  // det J at the cell corners and at the Gauss points of degree p, every
+  // cell; shape-function derivatives tabulated once, cells split over threads
   std::vector<double> xg, wg;
   gauss_rule(p + 1, xg, wg);
   std::vector<double> pts = {0.0, 1.0};
   pts.insert(pts.end(), xg.begin(), xg.end());
   const int N1 = N + 1;
   const int ncell = ipow(N, dim);
-  for (int e = 0; e < ncell; ++e) {
-    const int ex = e % N, ey = (e / N) % N, ez = dim == 3 ? e / (N * N) : 0;
-    double C[8][3];
-    for (int c = 0; c < (1 << dim); ++c) {
-      int g = (ex + (c & 1)) + (ey + ((c >> 1) & 1)) * N1;
-      if (dim == 3) g += (ez + ((c >> 2) & 1)) * N1 * N1;
-      for (int r = 0; r < dim; ++r) C[c][r] = X[g * dim + r];
-    }
-    const int np = (int)pts.size();
-    for (int kz = 0; kz < (dim == 3 ? np : 1); ++kz)
-      for (int ky = 0; ky < np; ++ky)
-        for (int kx = 0; kx < np; ++kx) {
-          double xi[3] = {pts[kx], pts[ky], dim == 3 ? pts[kz] : 0.0};
-          double J[3][3] = {{0}};
-          for (int c = 0; c < (1 << dim); ++c)
-            for (int s = 0; s < dim; ++s) {
-              double d = 1.0;
-              for (int i = 0; i < dim; ++i) {
-                const int b = (c >> i) & 1;
-                d *= (i == s) ? (b ? 1.0 : -1.0) : (b ? xi[i] : 1.0 - xi[i]);
-              }
-              for (int r = 0; r < dim; ++r) J[r][s] += C[c][r] * d;
-            }
-          double det = dim == 2 ? J[0][0] * J[1][1] - J[0][1] * J[1][0]
-                                : J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
-                                      J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
-                                      J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
-          if (!(det > 0.0))
-            return fail(PMG_ERR_DEGENERATE, "cell %d (%d,%d,%d) has det J = %g at a quadrature point",
-                        e, ex, ey, ez, det);
+  const int np = (int)pts.size(), nc = 1 << dim;
+  const int npt = dim == 3 ? np * np * np : np * np;
+  std::vector<double> dN((size_t)npt * nc * dim);
+  for (int k = 0; k < npt; ++k) {
+    const double xi[3] = {pts[k % np], pts[(k / np) % np], dim == 3 ? pts[k / (np * np)] : 0.0};
+    for (int c = 0; c < nc; ++c)
+      for (int s = 0; s < dim; ++s) {
+        double d = 1.0;
+        for (int i = 0; i < dim; ++i) {
+          const int b = (c >> i) & 1;
+          d *= (i == s) ? (b ? 1.0 : -1.0) : (b ? xi[i] : 1.0 - xi[i]);
         }
+        dN[((size_t)k * nc + c) * dim + s] = d;
+      }
   }
+  auto bad_cell = [&](auto dim_tag, int e) {
+    constexpr int D = decltype(dim_tag)::value, NC = 1 << D;
+    const int ex = e % N, ey = (e / N) % N, ez = D == 3 ? e / (N * N) : 0;
+    double C[NC][D];
+    for (int c = 0; c < NC; ++c) {
+      int g = (ex + (c & 1)) + (ey + ((c >> 1) & 1)) * N1;
+      if (D == 3) g += (ez + ((c >> 2) & 1)) * N1 * N1;
+      for (int r = 0; r < D; ++r) C[c][r] = X[g * D + r];
+    }
+    for (int k = 0; k < npt; ++k) {
+      double J[D][D] = {};
+      const double* d = dN.data() + (size_t)k * NC * D;
+      for (int c = 0; c < NC; ++c)
+        for (int s2 = 0; s2 < D; ++s2)
+          for (int r = 0; r < D; ++r) J[r][s2] += C[c][r] * d[c * D + s2];
+      double det;
+      if constexpr (D == 2)
+        det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+      else
+        det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+              J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+              J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+      if (!(det > 0.0)) return true;
+    }
+    return false;
+  };
+  const int nthreads = std::max(1, std::min<int>(16, (int)std::thread::hardware_concurrency()));
+  std::vector<int> first_bad(nthreads, ncell);
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nthreads; ++t)
+    pool.emplace_back([&, t]() {
+      for (int e = t; e < ncell; e += nthreads)
+        if (dim == 3 ? bad_cell(std::integral_constant<int, 3>{}, e)
+                     : bad_cell(std::integral_constant<int, 2>{}, e)) {
+          first_bad[t] = e;
+          return;
+        }
+    });
+  for (auto& th : pool) th.join();
+  const int e = *std::min_element(first_bad.begin(), first_bad.end());
+  if (e < ncell)
+    return fail(PMG_ERR_DEGENERATE, "cell %d (%d,%d,%d) has det J <= 0 at a quadrature point", e,
+                e % N, (e / N) % N, dim == 3 ? e / (N * N) : 0);
   return PMG_OK;
 }
 

@@ -1,0 +1,68 @@
+"""Argument checks of pmg_patch_setup that run on the host before any device
+work (no GPU needed): each invalid request returns its documented status and
+a message that names the problem."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import synth
+
+
+def _setup(dim, n, p, verts, levels=None, prec="fp64", **kw):
+    from paper_2510_17785_amd import _lib as L
+    from paper_2510_17785_amd.api import _mesh
+    lib = L.load()
+    m, keep = _mesh(dim, n, verts)
+    mu = np.ones(n ** dim)
+    o = L.PmgOpts()
+    L.check(lib.pmg_default_opts(ctypes.byref(o)))      # host only: stream stays NULL
+    o.precision = {"fp64": L.PMG_FP64, "bf16": L.PMG_BF16_FP32ACC}[prec]
+    lv = list(levels or [])
+    o.n_levels = len(lv)
+    for i, q in enumerate(lv):
+        o.levels[i] = q
+    for k, v in kw.items():
+        setattr(o, k, v)
+    h = ctypes.c_void_p()
+    st = lib.pmg_patch_setup(ctypes.byref(m), mu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                             int(p), ctypes.byref(o), ctypes.byref(h))
+    return st, lib.pmg_last_error().decode(), h.value
+
+
+def test_tangled_cell_is_reported():
+    from paper_2510_17785_amd import _lib as L
+    X = synth.make_vertices(3, 4, 0.0, 1).copy()
+    v = 2 + 2 * 5 + 2 * 25             # interior vertex (2,2,2)
+    X[v, 0] += 0.6                     # pushed past its neighbours in x
+    st, msg, h = _setup(3, 4, 2, X, (2, 1))
+    assert st == L.PMG_ERR_DEGENERATE and h is None
+    assert "det J" in msg and "cell" in msg
+
+
+@pytest.mark.parametrize("levels,fragment", [((5, 2, 1), "no kernel compiled"),
+                                             ((5, 5, 1), "strictly decrease"),
+                                             ((5, 2), "last level")])
+def test_level_lists(levels, fragment):
+    from paper_2510_17785_amd import _lib as L
+    X = synth.make_vertices(3, 4, 0.0, 1)
+    st, msg, _ = _setup(3, 4, 5, X, levels)
+    want = L.PMG_ERR_UNSUPPORTED if fragment == "no kernel compiled" else L.PMG_ERR_INVALID_ARG
+    assert st == want and fragment in msg
+
+
+def test_bf16_only_where_compiled():
+    from paper_2510_17785_amd import _lib as L
+    X = synth.make_vertices(3, 4, 0.0, 1)
+    st, msg, _ = _setup(3, 4, 4, X, (4, 2, 1), prec="bf16")
+    assert st == L.PMG_ERR_UNSUPPORTED and "bf16 3D:7,3,1" in msg
+
+
+def test_bad_scalars():
+    from paper_2510_17785_amd import _lib as L
+    X = synth.make_vertices(3, 4, 0.0, 1)
+    assert _setup(3, 4, 16, X, None)[0] == L.PMG_ERR_INVALID_ARG          # p > 15
+    assert _setup(3, 4, 4, X, (4, 2, 1), precision=7)[0] == L.PMG_ERR_INVALID_ARG
+    assert _setup(3, 4, 4, X, (4, 2, 1), cheb_degree=0)[0] == L.PMG_ERR_INVALID_ARG
+    assert _setup(3, 4, 4, X, (4, 2, 1), lanczos_steps=1)[0] == L.PMG_ERR_INVALID_ARG
+    assert _setup(3, 4, 4, X, (4, 2, 1), n_vcycles=0)[0] == L.PMG_ERR_INVALID_ARG
