@@ -223,13 +223,31 @@ class Mesh:
     def cells(self):
         return _multi(self.n, self.dim)
 
+    def patch_start(self, v):
+        """First cell index of the patch of vertex v per direction: the cells
+        of the patch are {v_i - 1, v_i} intersected with the mesh (Section
+        2.1), one cell in a direction where v lies on the boundary."""
+        return [max(v[i] - 1, 0) for i in range(self.dim)]
+
+    def patch_ncell(self, v):
+        return tuple(2 if 0 < v[i] < self.n else 1 for i in range(self.dim))
+
     def patch(self, v) -> PatchGeometry:
-        """The vertex patch around interior vertex v (all 2^dim cells)."""
-        verts = np.array([self.vertex([v[i] - 1 + t[i] for i in range(self.dim)])
-                          for t in _multi(3, self.dim)])
-        mu = np.array([self.cell_mu([v[i] - 1 + c[i] for i in range(self.dim)])
-                       for c in _multi(2, self.dim)])
-        return PatchGeometry(verts, mu)
+        """The vertex patch around vertex v: all 2^dim cells for an interior
+        vertex, the cells inside the mesh for a boundary vertex (entries of
+        unused offsets are left at zero and never read)."""
+        st, nc = self.patch_start(v), self.patch_ncell(v)
+        verts = np.zeros((3 ** self.dim, self.dim))
+        for t in _multi(3, self.dim):
+            if all(t[i] <= nc[i] for i in range(self.dim)):
+                verts[sum(t[i] * 3 ** i for i in range(self.dim))] = \
+                    self.vertex([st[i] + t[i] for i in range(self.dim)])
+        mu = np.zeros(2 ** self.dim)
+        for c in _multi(2, self.dim):
+            if all(c[i] < nc[i] for i in range(self.dim)):
+                mu[sum(c[i] * 2 ** i for i in range(self.dim))] = \
+                    self.cell_mu([st[i] + c[i] for i in range(self.dim)])
+        return PatchGeometry(verts, mu, nc)
 
     def coarsen(self) -> "Mesh":
         """Parent mesh with n/2 cells: vertices are the fine vertices with even

@@ -70,7 +70,7 @@ def prolongation_h(dim: int, nc: int, p: int) -> sp.csr_matrix:
 
 class GMG:
     def __init__(self, mesh: Mesh, p: int, levels, cheb_degree=3, n_vcycles=1,
-                 lanczos_steps=12, seed=0, bounds=None):
+                 lanczos_steps=12, seed=0, bounds=None, with_boundary=False):
         self.dim, self.p = mesh.dim, p
         sizes = hierarchy_sizes(mesh.n)
         meshes = [mesh]
@@ -83,7 +83,8 @@ class GMG:
         for li, m in enumerate(self.meshes[1:], start=1):
             bl = "lanczos" if bounds is None else bounds[li]
             self.smoothers.append(PatchSmoother(m, p, levels, cheb_degree, n_vcycles, bl,
-                                                lanczos_steps, seed, global_matrix=self.A[li]))
+                                                lanczos_steps, seed, global_matrix=self.A[li],
+                                                with_boundary=with_boundary))
         mask = dirichlet_mask(self.dim, self.meshes[0].n, p)
         self.coarse_mask = mask
         Ac = self.A[0].toarray()[np.ix_(mask, mask)]

@@ -101,6 +101,10 @@ def chebyshev(A, dinv, f, x, a, b, k, x_is_zero=False):
     return x
 
 
+def _level_size(patch: PatchGeometry, q: int) -> int:
+    return int(np.prod([patch.ncell[i] * q - 1 for i in range(patch.dim)]))
+
+
 class LocalSolver:
     """p-multigrid V-cycle for A_{j,p} d = r on one patch.
 
@@ -112,7 +116,10 @@ class LocalSolver:
     def __init__(self, patch: PatchGeometry, levels, bounds=None, cheb_degree=3,
                  n_vcycles=1, safety=CHEB_SAFETY, rng=CHEB_RANGE):
         self.patch = patch
-        self.levels = tuple(levels)
+        # a patch cut by the boundary has no interior node at low degrees
+        # (q - 1 = 0 nodes along a one-cell direction at q = 1): the coarsest
+        # level is the lowest one with a node, solved by Cholesky there
+        self.levels = tuple(q for q in levels if _level_size(patch, q) > 0)
         self.k = cheb_degree
         self.n_vcycles = n_vcycles
         self.safety, self.rng = safety, rng

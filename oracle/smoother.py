@@ -19,6 +19,8 @@ the same result.
 """
 from __future__ import annotations
 
+import itertools
+
 import numpy as np
 
 from .fem import Mesh, PatchGeometry, _multi, global_node, patch_closure_matrix
@@ -35,22 +37,33 @@ def interior_vertices(dim: int, n: int):
     return [tuple(t + 1 for t in v) for v in _multi(n - 1, dim)]
 
 
-def patch_order(dim: int, n: int):
-    """Forward sweep order: colours ascending, lexicographic within a colour."""
-    verts = interior_vertices(dim, n)
+def all_vertices(dim: int, n: int):
+    """Every vertex, boundary included, in x-fastest order."""
+    return [tuple(v) for v in _multi(n + 1, dim)]
+
+
+def patch_order(dim: int, n: int, with_boundary: bool = False):
+    """Forward sweep order: colours ascending, lexicographic within a colour;
+    with_boundary adds the patches of the boundary vertices (cut to the cells
+    inside the mesh)."""
+    verts = all_vertices(dim, n) if with_boundary else interior_vertices(dim, n)
     return [v for c in range(2 ** dim) for v in verts if vertex_color(v) == c]
 
 
 def patch_indices(v, p: int, n: int, dim: int):
     """(closure global indices, interior global indices) of the patch around
-    interior vertex v at degree p: node offsets s in [0, 2p]^dim from
-    (v - 1) p, interior s in [1, 2p-1]^dim, both x-fastest."""
+    vertex v at degree p: node offsets s in [0, k_i p] from start_i p per
+    direction (k_i cells, start_i = max(v_i - 1, 0)), interior s in
+    [1, k_i p - 1], both x-fastest."""
     m = n * p + 1
+    st = [max(v[i] - 1, 0) for i in range(dim)]
+    nc = [2 if 0 < v[i] < n else 1 for i in range(dim)]
     clo, inn = [], []
-    for s in _multi(2 * p + 1, dim):
-        g = global_node([(v[i] - 1) * p + s[i] for i in range(dim)], m, dim)
+    for s in itertools.product(*[range(nc[i] * p + 1) for i in reversed(range(dim))]):
+        s = tuple(reversed(s))
+        g = global_node([st[i] * p + s[i] for i in range(dim)], m, dim)
         clo.append(g)
-        if all(0 < s[i] < 2 * p for i in range(dim)):
+        if all(0 < s[i] < nc[i] * p for i in range(dim)):
             inn.append(g)
     return np.array(clo), np.array(inn)
 
@@ -69,10 +82,10 @@ class PatchSmoother:
 
     def __init__(self, mesh: Mesh, p: int, levels, cheb_degree=3, n_vcycles=1,
                  bounds="lanczos", lanczos_steps=12, seed=0, global_matrix=None,
-                 keep_closure=False, vertices=None):
+                 keep_closure=False, vertices=None, with_boundary=False):
         self.mesh, self.p, self.levels = mesh, p, tuple(levels)
         self.dim, self.n = mesh.dim, mesh.n
-        self.order = patch_order(self.dim, self.n)
+        self.order = patch_order(self.dim, self.n, with_boundary)
         if vertices is not None:
             keep = set(tuple(v) for v in vertices)
             self.order = [v for v in self.order if v in keep]
@@ -86,7 +99,7 @@ class PatchSmoother:
             if bounds == "lanczos":
                 vlin = sum(v[i] * (self.n + 1) ** i for i in range(self.dim))
                 b = [lanczos.bounds(s.A[l], s.dinv[l], lanczos_steps, seed, vlin, l)
-                     for l in range(len(self.levels) - 1)]
+                     for l in range(len(s.levels) - 1)]
             else:
                 b = bounds[v]
             s.set_bounds(b)

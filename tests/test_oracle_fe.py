@@ -206,3 +206,27 @@ def test_table1_dof_counts():
         val = float(printed.rstrip("kM")) * scale
         digits = len(printed.rstrip("kM").replace(".", "").lstrip("0"))
         assert abs(total - val) <= 0.5 * 10 ** (math.floor(math.log10(val)) - digits + 1), (line, total)
+
+
+def test_boundary_patch_matrix_equals_global_block():
+    # patches of boundary vertices keep only the cells inside the mesh
+    # (Section 2.1): their interior block and evaluate rows still equal the
+    # globally assembled matrix; face / edge / corner patches in 3D and edge /
+    # corner patches in 2D
+    from oracle.smoother import patch_indices
+    for dim, n, verts in [(3, 3, [(0, 1, 2), (3, 0, 1), (0, 3, 0), (3, 3, 3), (1, 0, 2)]),
+                          (2, 4, [(0, 2), (4, 0), (0, 0), (2, 4)])]:
+        X = synth.make_vertices(dim, n, 0.2, 5)
+        mu = 10.0 ** np.random.default_rng(2).uniform(-1, 1, n ** dim)
+        mesh = fem.Mesh(dim, n, X, mu)
+        A = fem.assemble_global(mesh, 2)
+        for v in verts:
+            clo, inn = patch_indices(v, 2, n, dim)
+            P = mesh.patch(v)
+            k = [2 if 0 < v[i] < n else 1 for i in range(dim)]
+            assert len(inn) == np.prod([k[i] * 2 - 1 for i in range(dim)])
+            Pj = fem.patch_matrix(P, 2)
+            assert np.allclose(A[np.ix_(inn, inn)].toarray(), Pj, atol=1e-13, rtol=0), v
+            Abar = fem.patch_closure_matrix(P, 2)
+            m = P.interior_mask(2)
+            assert np.allclose(A[np.ix_(inn, clo)].toarray(), Abar[m], atol=1e-13, rtol=0), v

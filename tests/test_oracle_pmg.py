@@ -379,3 +379,55 @@ def test_gmg_cg_2d_converges_to_direct_solution():
     rng = np.random.default_rng(0)
     r1, r2 = rng.standard_normal(b.shape) * m, rng.standard_normal(b.shape) * m
     assert abs(r2 @ G.precondition(r1) - r1 @ G.precondition(r2)) <= 1e-11 * abs(r1 @ G.precondition(r1))
+
+
+def test_boundary_patches_cover_and_colour():
+    # with boundary vertices there are (n+1)^d patches; same-colour interiors
+    # avoid each other's closures; every interior DoF lies in some patch
+    # interior, and nodes near the boundary lie in more patches than without
+    from oracle.smoother import patch_indices
+    dim, n, p = 3, 4, 2
+    order = patch_order(dim, n, with_boundary=True)
+    assert len(order) == (n + 1) ** dim
+    cover = np.zeros((n * p + 1) ** dim, dtype=int)
+    for c in range(8):
+        vs = [v for v in order if vertex_color(v) == c]
+        idx = [patch_indices(v, p, n, dim) for v in vs]
+        for i in range(len(vs)):
+            cover[idx[i][1]] += 1
+            for j in range(i + 1, len(vs)):
+                assert not set(idx[i][1]) & set(idx[j][0])
+                assert not set(idx[j][1]) & set(idx[i][0])
+    mask = fem.dirichlet_mask(dim, n, p)
+    assert np.all(cover[mask] >= 1) and np.all(cover[~mask] == 0)
+
+
+def test_truncated_patch_levels_and_coarse_solve():
+    # a corner patch has (q-1)^d interior nodes: empty at q = 1, so the
+    # coarsest level is the lowest non-empty one, solved by Cholesky
+    X = synth.make_vertices(3, 4, 0.2, 3)
+    mesh = fem.Mesh(3, 4, X, np.ones(64))
+    corner, edge, face = mesh.patch((0, 0, 0)), mesh.patch((4, 0, 2)), mesh.patch((2, 2, 4))
+    s = pmg.LocalSolver(corner, (4, 2, 1))
+    assert s.levels == (4, 2) and s.A[1].shape == (1, 1)
+    s = pmg.LocalSolver(edge, (4, 2, 1))
+    assert s.levels == (4, 2) and s.A[1].shape == (3, 3) and s.A[0].shape == (7 * 9, 7 * 9)
+    s = pmg.LocalSolver(face, (2, 1))
+    assert s.levels == (2,)
+    r = np.random.default_rng(0).standard_normal(s.A[0].shape[0])
+    assert np.allclose(s.solve(r), np.linalg.solve(s.A[0], r), rtol=1e-12, atol=1e-12)
+
+
+def test_gmg_cg_with_boundary_patches():
+    # the smoother with boundary patches is still symmetric in the V-cycle
+    # and the outer CG converges
+    from oracle.gmg import GMG
+    X = synth.make_vertices(2, 8, 0.2, 9)
+    mesh = fem.Mesh(2, 8, X, np.ones(64))
+    b = synth.make_rhs(2, 8, 2, 3)
+    G = GMG(mesh, 2, (2, 1), with_boundary=True)
+    r1 = np.random.default_rng(1).standard_normal(b.shape) * fem.dirichlet_mask(2, 8, 2)
+    r2 = np.random.default_rng(2).standard_normal(b.shape) * fem.dirichlet_mask(2, 8, 2)
+    assert abs(r2 @ G.precondition(r1) - r1 @ G.precondition(r2)) <= 1e-10 * abs(r1 @ G.precondition(r1))
+    x, it, hist = G.cg(b, rtol=1e-10)
+    assert it <= 30
