@@ -72,6 +72,16 @@ extern "C" {
 #define PMG_BOUNDS_LANCZOS 0  /* per-patch Lanczos at setup */
 #define PMG_BOUNDS_FIXED 1    /* caller sets them with pmg_set_bounds */
 
+/* which vertices get a patch (Section 2.1: the patch of a vertex is the
+ * set of cells sharing it).  PMG_PATCH_WITH_BOUNDARY adds the patches of
+ * boundary vertices, cut to the cells inside the mesh (4, 2 or 1 cells in
+ * 3D); their interior excludes the Dirichlet boundary, their coarsest p-level
+ * is the lowest one with an interior node, solved exactly (FP64 Cholesky
+ * inverse formed at setup), and learned Chebyshev bounds fall back to
+ * Lanczos for them. */
+#define PMG_PATCH_INTERIOR 0
+#define PMG_PATCH_WITH_BOUNDARY 1
+
 /* pmg_query keys */
 #define PMG_Q_N_PATCHES 0
 #define PMG_Q_N_COLORS 1
@@ -105,6 +115,7 @@ typedef struct pmg_opts {
   double cheb_range;     /* rho: a = max(lambda_min, b / rho) (default 15) */
   uint64_t seed;         /* seed of the Lanczos start vectors (default 0) */
   void* stream;          /* hipStream_t, NULL = null stream */
+  int32_t patch_set;     /* PMG_PATCH_INTERIOR (default) or PMG_PATCH_WITH_BOUNDARY */
 } pmg_opts;
 
 /* Fill *o with the defaults listed above (levels: p, floor halvings, 1 is

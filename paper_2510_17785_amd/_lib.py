@@ -21,6 +21,8 @@ PMG_FP64 = 0
 PMG_FP32 = 1
 PMG_BF16_FP32ACC = 2
 PMG_BF16X3_FP32ACC = 3
+PMG_PATCH_INTERIOR = 0
+PMG_PATCH_WITH_BOUNDARY = 1
 PMG_BOUNDS_LANCZOS = 0
 PMG_BOUNDS_FIXED = 1
 
@@ -58,7 +60,7 @@ class PmgOpts(ctypes.Structure):
                 ("n_vcycles", ctypes.c_int32), ("bounds", ctypes.c_int32),
                 ("lanczos_steps", ctypes.c_int32), ("cheb_safety", ctypes.c_double),
                 ("cheb_range", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("patch_set", ctypes.c_int32)]
 
 
 class PmgError(RuntimeError):

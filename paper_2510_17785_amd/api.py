@@ -28,7 +28,7 @@ def _stream_handle(stream) -> Optional[int]:
 
 
 def _opts(levels, precision, cheb_degree, n_vcycles, bounds, lanczos_steps, cheb_safety,
-          cheb_range, seed, stream) -> L.PmgOpts:
+          cheb_range, seed, stream, with_boundary=False) -> L.PmgOpts:
     lib = L.load()
     o = L.PmgOpts()
     L.check(lib.pmg_default_opts(ctypes.byref(o)))
@@ -46,6 +46,7 @@ def _opts(levels, precision, cheb_degree, n_vcycles, bounds, lanczos_steps, cheb
     o.cheb_range = float(cheb_range)
     o.seed = int(seed)
     o.stream = _stream_handle(stream)
+    o.patch_set = L.PMG_PATCH_WITH_BOUNDARY if with_boundary else L.PMG_PATCH_INTERIOR
     return o
 
 
@@ -78,7 +79,8 @@ class PatchSmoother:
     def __init__(self, dim: int, n: int, p: int, vertices, coeff, levels: Sequence[int] = None,
                  precision: str = "fp64", cheb_degree: int = 3, n_vcycles: int = 1,
                  bounds: str = "lanczos", lanczos_steps: int = 12, cheb_safety: float = 1.1,
-                 cheb_range: float = 15.0, seed: int = 0, stream=None, _handle=None, _owner=None):
+                 cheb_range: float = 15.0, seed: int = 0, stream=None, with_boundary: bool = False,
+                 _handle=None, _owner=None):
         self._lib = L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("PatchSmoother needs a GPU")
@@ -91,7 +93,7 @@ class PatchSmoother:
             if mu.shape != (n ** dim,):
                 raise ValueError("one coefficient per cell expected")
             o = _opts(levels, precision, cheb_degree, n_vcycles, bounds, lanczos_steps, cheb_safety,
-                      cheb_range, seed, stream)
+                      cheb_range, seed, stream, with_boundary)
             h = ctypes.c_void_p()
             L.check(self._lib.pmg_patch_setup(ctypes.byref(m), mu.ctypes.data_as(
                 ctypes.POINTER(ctypes.c_double)), int(p), ctypes.byref(o), ctypes.byref(h)))
@@ -301,14 +303,14 @@ class GMGSolver:
     def __init__(self, dim: int, n: int, p: int, vertices, coeff, levels: Sequence[int] = None,
                  precision: str = "fp64", cheb_degree: int = 3, n_vcycles: int = 1,
                  bounds: str = "lanczos", lanczos_steps: int = 12, cheb_safety: float = 1.1,
-                 cheb_range: float = 15.0, seed: int = 0, stream=None):
+                 cheb_range: float = 15.0, seed: int = 0, stream=None, with_boundary: bool = False):
         self._lib = L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("GMGSolver needs a GPU")
         m, keep = _mesh(dim, n, vertices)
         mu = np.ascontiguousarray(coeff, dtype=np.float64)
         o = _opts(levels, precision, cheb_degree, n_vcycles, bounds, lanczos_steps, cheb_safety,
-                  cheb_range, seed, stream)
+                  cheb_range, seed, stream, with_boundary)
         h = ctypes.c_void_p()
         L.check(self._lib.gmg_setup(ctypes.byref(m), mu.ctypes.data_as(
             ctypes.POINTER(ctypes.c_double)), int(p), ctypes.byref(o), ctypes.byref(h)))

@@ -168,6 +168,13 @@ struct pmg_handle {
   int64_t vec_bytes = 0;  // bytes per block slot of vec_scratch
   int64_t vec_blocks = 0;
   std::vector<double> bounds;  // host copy, n_patches x (L-1) x 2
+  // patches of boundary vertices (PMG_PATCH_WITH_BOUNDARY)
+  bool with_boundary = false;
+  std::vector<int32_t> vertex_host;  // patch vertex per patch (mesh handles)
+  std::vector<int32_t> trunc_host;   // per patch: slot of its coarse inverse or -1
+  int32_t* trunc_index = nullptr;
+  double* trunc_inv = nullptr;
+  int n_trunc = 0;
   int level_size(int l) const { return ipow(2 * levels[l] - 1, dim); }
   size_t tsize() const { return precision == PMG_FP64 ? sizeof(double) : sizeof(float); }
   PatchArgs args() const {
@@ -194,6 +201,9 @@ struct pmg_handle {
     a.vec_stride = vec_bytes / (int64_t)tsize();
     a.lanczos_steps = lanczos_steps;
     a.seed = seed;
+    a.with_boundary = with_boundary ? 1 : 0;
+    a.trunc_index = trunc_index;
+    a.trunc_inv = trunc_inv;
     return a;
   }
 };
@@ -202,8 +212,8 @@ namespace {
 
 void free_handle(pmg_handle* h) {
   if (!h) return;
-  void* ptrs[] = {h->verts,    h->mu,  h->patch_vertex, h->patch_geo,
-                  h->patch_mu, h->tab64, h->cheb,        h->vec_scratch};
+  void* ptrs[] = {h->verts, h->mu,          h->patch_vertex, h->patch_geo, h->patch_mu,
+                  h->tab64, h->cheb,        h->vec_scratch,  h->trunc_index, h->trunc_inv};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h->tab && h->tab != h->tab64) (void)hipFree(h->tab);  // FP64 handles share the tables
@@ -264,6 +274,8 @@ int check_opts(const pmg_opts* o, int dim, int p, int* levels, int& L, const Pat
   if (o->n_vcycles < 1) return fail(PMG_ERR_INVALID_ARG, "n_vcycles must be >= 1");
   if (o->bounds != PMG_BOUNDS_LANCZOS && o->bounds != PMG_BOUNDS_FIXED)
     return fail(PMG_ERR_INVALID_ARG, "unknown bounds source %d", o->bounds);
+  if (o->patch_set != PMG_PATCH_INTERIOR && o->patch_set != PMG_PATCH_WITH_BOUNDARY)
+    return fail(PMG_ERR_INVALID_ARG, "unknown patch set %d", o->patch_set);
   if (o->lanczos_steps < 2 || o->lanczos_steps > 64)
     return fail(PMG_ERR_INVALID_ARG, "lanczos_steps %d outside 2..64", o->lanczos_steps);
   if (!(o->cheb_safety >= 1.0) || !(o->cheb_range > 1.0))
@@ -304,6 +316,138 @@ int init_tables_once() {
     }
   }
 
+  return PMG_OK;
+}
+
+// Boundary-vertex patches: per direction the first unmasked interior offset
+// and the number of unmasked offsets at degree q (flags as in the kernels:
+// bit 2i low boundary, bit 2i+1 high boundary of direction i).
+int vertex_flags(const pmg_handle* h, int vlin) {
+  const int N1 = h->N + 1;
+  const int v[3] = {vlin % N1, (vlin / N1) % N1, h->dim == 3 ? vlin / (N1 * N1) : 1};
+  int f = 0;
+  for (int i = 0; i < h->dim; ++i) {
+    if (v[i] == 0) f |= 1 << (2 * i);
+    if (v[i] == h->N) f |= 2 << (2 * i);
+  }
+  return f;
+}
+void unmasked_box(int f, int dim, int q, int* lo, int* n) {
+  for (int i = 0; i < 3; ++i) {
+    const int fl = i < dim ? (f >> (2 * i)) & 3 : 0;
+    lo[i] = (fl & 1) ? q + 1 : 1;
+    n[i] = i < dim ? (fl ? q - 1 : 2 * q - 1) : 1;
+  }
+}
+
+// Exact coarse solves of the boundary-vertex patches: the matrix of level
+// L-2 (the lowest with nodes) formed on the device in FP64, its unmasked
+// block inverted on the host by Cholesky, stored per patch in the cut
+// patch's own node numbering.
+int setup_truncated(pmg_handle* h) {
+  const int L = h->L, Lc = L - 2, q = h->levels[Lc], n = h->level_size(Lc);
+  std::vector<int32_t> list;
+  h->trunc_host.assign(h->n_patches, -1);
+  for (int j = 0; j < h->n_patches; ++j)
+    if (vertex_flags(h, h->vertex_host[j])) {
+      h->trunc_host[j] = (int32_t)list.size();
+      list.push_back(j);
+    }
+  h->n_trunc = (int)list.size();
+  if (list.empty()) return PMG_OK;
+  int lo[3], nn[3];
+  unmasked_box(1, h->dim, q, lo, nn);  // a face patch has the largest unmasked box
+  const int64_t slot = (int64_t)nn[0] * nn[1] * nn[2] * nn[0] * nn[1] * nn[2];
+  int s;
+  hipError_t e;
+  int32_t* dlist = nullptr;
+  double* dmat = nullptr;
+  const int chunk_max = 1024;
+  if ((s = dev_alloc(&dlist, list.size() * sizeof(int32_t), nullptr)) < 0) return s;
+  if ((s = dev_alloc(&dmat, (size_t)chunk_max * n * n * sizeof(double), nullptr)) < 0) {
+    (void)hipFree(dlist);
+    return s;
+  }
+  std::vector<double> inv((size_t)list.size() * slot, 0.0), A((size_t)chunk_max * n * n);
+  int st = PMG_OK;
+  if ((e = hipMemcpy(dlist, list.data(), list.size() * sizeof(int32_t), hipMemcpyHostToDevice)))
+    st = fail(PMG_ERR_HIP, "upload: %s", hipGetErrorString(e));
+  PatchArgs a = h->args();
+  a.vec_stride = h->vec_bytes / (int64_t)sizeof(double);  // FP64 setup kernels
+  a.level = Lc;
+  a.out = dmat;
+  for (int b = 0; b < (int)list.size() && st == PMG_OK; b += chunk_max) {
+    const int cnt = std::min(chunk_max, (int)list.size() - b);
+    const int c2 = h->vec_blocks > 0 ? std::min<int>(cnt, (int)h->vec_blocks) : cnt;
+    a.patch_list = dlist + b;  // the kernel writes list position patch_begin + block
+    for (int b2 = b; b2 < b + cnt && st == PMG_OK; b2 += c2) {
+      a.patch_begin = b2 - b;
+      a.n_patch = std::min(c2, b + cnt - b2);
+      if ((e = h->var->launch_level_matrix(a, h->stream)))
+        st = fail(PMG_ERR_HIP, "level matrix kernel: %s", hipGetErrorString(e));
+    }
+    if (st == PMG_OK &&
+        ((e = hipMemcpyAsync(A.data(), dmat, (size_t)cnt * n * n * sizeof(double), hipMemcpyDeviceToHost,
+                             h->stream)) ||
+         (e = hipStreamSynchronize(h->stream))))
+      st = fail(PMG_ERR_HIP, "level matrices: %s", hipGetErrorString(e));
+    for (int k = 0; k < cnt && st == PMG_OK; ++k) {
+      const int j = list[b + k];
+      unmasked_box(vertex_flags(h, h->vertex_host[j]), h->dim, q, lo, nn);
+      const int nu = nn[0] * nn[1] * nn[2], mi = 2 * q - 1;
+      std::vector<int> full(nu);
+      for (int u = 0; u < nu; ++u) {
+        const int ox = u % nn[0], oy = (u / nn[0]) % nn[1], oz = u / (nn[0] * nn[1]);
+        full[u] = (lo[0] + ox - 1) + mi * ((lo[1] + oy - 1) + (h->dim == 3 ? mi * (lo[2] + oz - 1) : 0));
+      }
+      // Cholesky A = R^T R of the unmasked block, then the inverse column by column
+      std::vector<double> R((size_t)nu * nu);
+      const double* Ak = A.data() + (size_t)k * n * n;
+      for (int r = 0; r < nu; ++r)
+        for (int c = 0; c < nu; ++c) R[(size_t)r * nu + c] = Ak[(size_t)full[r] * n + full[c]];
+      for (int c = 0; c < nu && st == PMG_OK; ++c) {
+        double d = R[(size_t)c * nu + c];
+        for (int t = 0; t < c; ++t) d -= R[(size_t)t * nu + c] * R[(size_t)t * nu + c];
+        if (!(d > 0.0)) {
+          st = fail(PMG_ERR_DEGENERATE, "patch %d: coarse level matrix not positive definite", j);
+          break;
+        }
+        d = std::sqrt(d);
+        R[(size_t)c * nu + c] = d;
+        for (int r = c + 1; r < nu; ++r) {
+          double v = R[(size_t)c * nu + r];
+          for (int t = 0; t < c; ++t) v -= R[(size_t)t * nu + c] * R[(size_t)t * nu + r];
+          R[(size_t)c * nu + r] = v / d;
+        }
+      }
+      if (st != PMG_OK) break;
+      double* out = inv.data() + (size_t)(b + k) * slot;
+      std::vector<double> y(nu);
+      for (int c = 0; c < nu; ++c) {
+        // R^T y = e_c, then R x = y
+        for (int r = 0; r < nu; ++r) {
+          double v = r == c ? 1.0 : 0.0;
+          for (int t = 0; t < r; ++t) v -= R[(size_t)t * nu + r] * y[t];
+          y[r] = v / R[(size_t)r * nu + r];
+        }
+        for (int r = nu - 1; r >= 0; --r) {
+          double v = y[r];
+          for (int t = r + 1; t < nu; ++t) v -= R[(size_t)r * nu + t] * out[(size_t)t * nu + c];
+          out[(size_t)r * nu + c] = v / R[(size_t)r * nu + r];
+        }
+      }
+    }
+  }
+  (void)hipFree(dlist);
+  (void)hipFree(dmat);
+  if (st != PMG_OK) return st;
+  if ((s = dev_alloc(&h->trunc_inv, inv.size() * sizeof(double), &h->device_bytes)) < 0) return s;
+  if ((s = dev_alloc(&h->trunc_index, (size_t)h->n_patches * sizeof(int32_t), &h->device_bytes)) < 0)
+    return s;
+  if ((e = hipMemcpy(h->trunc_inv, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice)) ||
+      (e = hipMemcpy(h->trunc_index, h->trunc_host.data(), h->trunc_host.size() * sizeof(int32_t),
+                     hipMemcpyHostToDevice)))
+    return fail(PMG_ERR_HIP, "upload: %s", hipGetErrorString(e));
   return PMG_OK;
 }
 
@@ -418,6 +562,7 @@ int setup_common(pmg_handle* h) {
             return cleanup(fail(PMG_ERR_HIP, "convert: %s", hipGetErrorString(e)));
     }
   }
+  if (h->with_boundary && !h->patch_geo && (s = setup_truncated(h)) < 0) return cleanup(s);
   const size_t ncheb = (size_t)h->n_patches * (L - 1) * 2;
   if ((s = dev_alloc(&h->cheb, ncheb * h->tsize(), &h->device_bytes)) < 0) return cleanup(s);
   h->bounds.assign(ncheb, 0.0);
@@ -486,6 +631,7 @@ pmg_handle* new_handle(const pmg_opts* o, int dim, int N, int p, int L, const in
   h->seed = o->seed;
   h->stream = reinterpret_cast<hipStream_t>(o->stream);
   h->var = var;
+  h->with_boundary = o->patch_set == PMG_PATCH_WITH_BOUNDARY;
 
   return h;
 }
@@ -515,11 +661,12 @@ int patch_setup_impl(const pmg_mesh* mesh, const double* coeff, int p, const pmg
   std::vector<int32_t> order;
   h->n_colors = 1 << dim;
   h->color_off.assign(h->n_colors + 1, 0);
+  const int v_lo = h->with_boundary ? 0 : 1, v_hi = h->with_boundary ? N : N - 1;
   for (int col = 0; col < h->n_colors; ++col) {
     h->color_off[col] = (int)order.size();
-    for (int vz = (dim == 3 ? 1 : 0); vz < (dim == 3 ? N : 1); ++vz)
-      for (int vy = 1; vy < N; ++vy)
-        for (int vx = 1; vx < N; ++vx) {
+    for (int vz = (dim == 3 ? v_lo : 0); vz <= (dim == 3 ? v_hi : 0); ++vz)
+      for (int vy = v_lo; vy <= v_hi; ++vy)
+        for (int vx = v_lo; vx <= v_hi; ++vx) {
           int c = (vx & 1) | ((vy & 1) << 1) | (dim == 3 ? ((vz & 1) << 2) : 0);
           if (c != col) continue;
           order.push_back(vx + vy * N1 + (dim == 3 ? vz * N1 * N1 : 0));
@@ -528,6 +675,7 @@ int patch_setup_impl(const pmg_mesh* mesh, const double* coeff, int p, const pmg
   }
   h->color_off[h->n_colors] = (int)order.size();
   h->n_patches = (int)order.size();
+  h->vertex_host = order;
 
   const size_t nv = (size_t)ipow(N1, dim), nc = (size_t)ipow(N, dim);
   int s;
@@ -575,6 +723,7 @@ int patches_setup_impl(int dim, int64_t n, const double* verts, const double* co
   }
   PMG_TRY(init_tables_once());
   pmg_handle* h = new_handle(o, dim, 2, p, L, levels, var);
+  h->with_boundary = false;  // independent patches have no mesh boundary
   auto cleanup = [&](int st) {
     free_handle(h);
     return st;
@@ -986,6 +1135,7 @@ int pmg_default_opts(pmg_opts* o) {
   o->cheb_range = 15.0;
   o->seed = 0;
   o->stream = nullptr;
+  o->patch_set = PMG_PATCH_INTERIOR;
   return PMG_OK;
 }
 
@@ -1414,7 +1564,8 @@ int pmg_set_bounds_mlp(pmg_handle* h, pmg_mlp* mm, double margin, double ood_z, 
   std::vector<double> old = h->bounds;
   std::vector<int32_t> fallback;
   for (int j = 0; j < n; ++j) {
-    bool ok = hz[j] <= ood_z;
+    // boundary-vertex patches are outside the training distribution: Lanczos
+    bool ok = hz[j] <= ood_z && (h->trunc_host.empty() || h->trunc_host[j] < 0);
     for (int l = 0; l < nl && ok; ++l) {
       const double lo = std::exp((double)hy[(size_t)j * 2 * nl + 2 * l]);
       double hi = std::exp((double)hy[(size_t)j * 2 * nl + 2 * l + 1] + margin);

@@ -60,6 +60,13 @@ struct PatchArgs {
   // small levels held as dense matrices (see PatchVariant::dense_level)
   const void* dense[kMaxLevels];   // T, n_patches_total x size_l^2, row-major
   double* dense64[kMaxLevels];     // FP64 copies, written by the setup kernel
+  // patches of boundary vertices (mesh handles only): cells outside the mesh
+  // are ghosts with mu = 0, nodes on or beyond the boundary are masked
+  int32_t with_boundary;
+  // per patch: row of trunc_inv holding the FP64 inverse of its lowest
+  // non-empty level (level count - 2, masked rows and columns zero), or -1
+  const int32_t* trunc_index;
+  const double* trunc_inv;   // rows x size_{L-2}^2
 };
 
 // One compiled (precision, dim, levels) variant of the patch kernels.
@@ -73,6 +80,9 @@ struct PatchVariant {
   size_t (*lds_bytes)(int mode);
   int64_t (*vec_scratch_elems)();
   int64_t (*vec_scratch_elems64)();  // same for the FP64 layout of the setup kernels
+  // FP64 matrix of level args.level for the patches args.patch_list[patch_begin + b],
+  // written to args.out + (patch_begin + b) * size^2 (row-major)
+  hipError_t (*launch_level_matrix)(const PatchArgs& a, hipStream_t s);
   // FP64 setup kernels (inverse diagonals of every level; Lanczos bounds)
   hipError_t (*launch_diag)(const PatchArgs& a, hipStream_t s);
   hipError_t (*launch_lanczos)(const PatchArgs& a, int level, hipStream_t s);

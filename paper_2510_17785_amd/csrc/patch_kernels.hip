@@ -367,6 +367,10 @@ struct Ctx {
   T* lds;
   T* vec;          // vector storage (LDS or global scratch)
   const T* gtab;   // the same 1D tables in global memory (read with scalar loads)
+  // patch of a boundary vertex: FP64 inverse of its lowest non-empty level
+  // (level count - 2), which the V-cycle solves exactly; null otherwise
+  const double* trunc = nullptr;
+  int pf = 0;  // boundary flags of the patch (see patch_flags)
   __device__ const T* gB(int l) const { return gtab + l * kTabLevelStride; }
   __device__ const T* gDc(int l) const {
     const int n = LV::q[l] + 1;
@@ -1598,6 +1602,38 @@ __device__ void vcycle(const Ctx<T, DIM, LV>& c, int k, bool d_zero) {
     if (tid == 0) d[0] = dinv[0] * r[0];
     __syncthreads();
   } else {
+    if constexpr (L + 2 == LV::count) {
+      // a boundary-vertex patch has no node at degree 1: its lowest level
+      // with nodes is solved exactly (FP64 Cholesky inverse from the setup)
+      if (c.trunc) {
+        // the inverse is stored over the unmasked nodes only, in the cut
+        // patch's numbering (x fastest over the unmasked box)
+        constexpr int q = LV::q[L], mi = 2 * q - 1;
+        int lo[3], nb[3];
+        for (int i = 0; i < 3; ++i) {
+          const int fl = i < DIM ? (c.pf >> (2 * i)) & 3 : 0;
+          lo[i] = (fl & 1) ? q + 1 : 1;
+          nb[i] = i < DIM ? (fl ? q - 1 : mi) : 1;
+        }
+        const int nu = nb[0] * nb[1] * nb[2];
+        auto full = [&](int u) {
+          const int ox = u % nb[0], oy = (u / nb[0]) % nb[1], oz = u / (nb[0] * nb[1]);
+          return (lo[0] + ox - 1) + mi * ((lo[1] + oy - 1) + (DIM == 3 ? mi * (lo[2] + oz - 1) : 0));
+        };
+        T* d = c.d(L);
+        const T* r = c.r(L);
+        for (int i = tid; i < N; i += NT<T>) d[i] = T(0);
+        __syncthreads();
+        for (int u = tid; u < nu; u += NT<T>) {
+          const double* row = c.trunc + (int64_t)u * nu;
+          double acc = 0;
+          for (int w = 0; w < nu; ++w) acc += row[w] * double(r[full(w)]);
+          d[full(u)] = T(acc);
+        }
+        __syncthreads();
+        return;
+      }
+    }
     constexpr int QF = LV::q[L], QC = LV::q[L + 1];
     constexpr int mf = 2 * QF - 1, mc = 2 * QC - 1;
     static_assert(DIM != 3 || mf * mf * mc + mf * mc * mc <= Layout<T, DIM, LV>::abuf_elems,
@@ -1636,6 +1672,83 @@ __device__ __forceinline__ void patch_base(int vlin, int N, int p, int& base, in
   }
 }
 
+// Patches of boundary vertices keep the two-cell shape per direction: the
+// cells outside the mesh are ghosts with coefficient zero, and the interior
+// nodes on or beyond the boundary are masked (zero inverse diagonal, never
+// gathered or scattered), so the unmasked rows and columns of every level
+// operator are those of the cut patch.  Bit 2i of the flags: vertex on the
+// low boundary of direction i (v_i = 0); bit 2i+1: on the high one (v_i = N).
+template <int DIM>
+__device__ __forceinline__ int patch_flags(const PatchArgs& a, int patch) {
+  if (!a.with_boundary || a.patch_geo) return 0;
+  const int N1 = a.N + 1, vlin = a.patch_vertex[patch];
+  const int v[3] = {vlin % N1, (vlin / N1) % N1, DIM == 3 ? vlin / (N1 * N1) : 1};
+  int f = 0;
+  for (int i = 0; i < DIM; ++i) {
+    if (v[i] == 0) f |= 1 << (2 * i);
+    if (v[i] == a.N) f |= 2 << (2 * i);
+  }
+  return f;
+}
+
+// Interior node idx (x fastest over (2q-1)^DIM) at degree q lies inside the
+// mesh; *ci gets its number among the unmasked nodes (x fastest), i.e. in
+// the cut patch's own interior numbering.
+template <int DIM>
+__device__ __forceinline__ bool interior_node(int f, int q, int idx, int* ci) {
+  const int mi = 2 * q - 1;
+  const int s[3] = {idx % mi + 1, (idx / mi) % mi + 1, DIM == 3 ? idx / (mi * mi) + 1 : 1};
+  int c = 0, stride = 1;
+  for (int i = 0; i < DIM; ++i) {
+    const int fl = (f >> (2 * i)) & 3;
+    const int lo = (fl & 1) ? q + 1 : 1, n = fl ? q - 1 : 2 * q - 1;
+    const int o = s[i] - lo;
+    if (o < 0 || o >= n) return false;
+    c += o * stride;
+    stride *= n;
+  }
+  if (ci) *ci = c;
+  return true;
+}
+
+// Mesh vertex at indices ii (each in -1 .. N+1), continued linearly across
+// the boundary for -1 and N+1 (ghost vertices: only a finite metric is
+// needed there, the ghost coefficient is zero).
+template <int DIM>
+__device__ double mesh_vertex(const PatchArgs& a, const int* ii, int r) {
+  const int N = a.N, N1 = N + 1;
+  double acc = 0;
+  for (int combo = 0; combo < (1 << DIM); ++combo) {
+    double w = 1;
+    int64_t g = 0, stride = 1;
+    bool used = true;
+    for (int d = 0; d < DIM; ++d) {
+      const int v = ii[d], bit = (combo >> d) & 1;
+      int idx;
+      double cf;
+      if (v < 0) {
+        idx = bit ? 1 : 0;
+        cf = bit ? -1.0 : 2.0;
+      } else if (v > N) {
+        idx = bit ? N - 1 : N;
+        cf = bit ? -1.0 : 2.0;
+      } else {
+        if (bit) {
+          used = false;
+          break;
+        }
+        idx = v;
+        cf = 1.0;
+      }
+      w *= cf;
+      g += idx * stride;
+      stride *= N1;
+    }
+    if (used) acc += w * a.verts[g * DIM + r];
+  }
+  return acc;
+}
+
 // Patch geometry: 3^d vertices relative to the patch centre and 2^d cell
 // coefficients, from the mesh or from the arrays of independent patches.
 template <typename T, int DIM>
@@ -1654,16 +1767,21 @@ __device__ void load_geometry(const PatchArgs& a, int patch, T* geo, T* mu) {
   const int vx = vlin % N1, vy = (vlin / N1) % N1, vz = DIM == 3 ? vlin / (N1 * N1) : 0;
   for (int i = tid; i < nvert * DIM; i += blockDim.x) {
     const int r = i % DIM, t = i / DIM;
-    const int tx = t % 3, ty = (t / 3) % 3, tz = DIM == 3 ? t / 9 : 0;
-    int g = (vx - 1 + tx) + (vy - 1 + ty) * N1;
-    if (DIM == 3) g += (vz - 1 + tz) * N1 * N1;
-    geo[i] = T(a.verts[(int64_t)g * DIM + r] - a.verts[(int64_t)vlin * DIM + r]);
+    const int ii[3] = {vx - 1 + t % 3, vy - 1 + (t / 3) % 3, DIM == 3 ? vz - 1 + t / 9 : 0};
+    bool inside = true;
+    for (int d = 0; d < DIM; ++d) inside = inside && ii[d] >= 0 && ii[d] <= a.N;
+    int64_t g = ii[0] + (int64_t)ii[1] * N1;
+    if (DIM == 3) g += (int64_t)ii[2] * N1 * N1;
+    const double x = inside ? a.verts[g * DIM + r] : mesh_vertex<DIM>(a, ii, r);
+    geo[i] = T(x - a.verts[(int64_t)vlin * DIM + r]);
   }
   for (int i = tid; i < ncell; i += blockDim.x) {
-    const int cx = i & 1, cy = (i >> 1) & 1, cz = (i >> 2) & 1;
-    int g = (vx - 1 + cx) + (vy - 1 + cy) * a.N;
-    if (DIM == 3) g += (vz - 1 + cz) * a.N * a.N;
-    mu[i] = T(a.mu[g]);
+    const int ci[3] = {vx - 1 + (i & 1), vy - 1 + ((i >> 1) & 1), DIM == 3 ? vz - 1 + ((i >> 2) & 1) : 0};
+    bool inside = true;
+    for (int d = 0; d < DIM; ++d) inside = inside && ci[d] >= 0 && ci[d] < a.N;
+    int64_t g = ci[0] + (int64_t)ci[1] * a.N;
+    if (DIM == 3) g += (int64_t)ci[2] * a.N * a.N;
+    mu[i] = inside ? T(a.mu[g]) : T(0);   // ghost cells of a boundary-vertex patch
   }
 }
 
@@ -1719,6 +1837,15 @@ __global__ __launch_bounds__(NT<T>) void patch_kernel(PatchArgs a) {
   c.gtab = tptr<T>(a.tab);
   const int patch = patch_of_block(a);
   const int tid = threadIdx.x;
+  const int pf = patch_flags<DIM>(a, patch);
+  c.pf = pf;
+  if (pf && a.trunc_index) {
+    const int k = a.trunc_index[patch];
+    // one slot holds the largest unmasked box, a face patch's
+    constexpr int qc = LV::q[LV::count - 2];
+    constexpr int nbox = ipow(2 * qc - 1, DIM - 1) * (qc - 1);
+    if (k >= 0) c.trunc = a.trunc_inv + (int64_t)k * nbox * nbox;
+  }
   load_patch<T, DIM, LV>(c, a, patch);
   c.dense_ok = true;
   prepare_geometry<T, DIM, LV>(c);
@@ -1753,20 +1880,43 @@ __global__ __launch_bounds__(NT<T>) void patch_kernel(PatchArgs a) {
       // gather u-bar_j (closure) and b_j (interior): equation gather
       patch_base<DIM>(a.patch_vertex[patch], a.N, a.p, base, M);
       T* X = c.X();
+      if (pf == 0) {
   #pragma unroll 1
-    for (int idx = tid; idx < S0::closure; idx += NT<T>) {
-        const int x = idx % m, t = idx / m, y = t % m, z = DIM == 3 ? t / m : 0;
-        X[idx] = T(a.u[base + x + y * M + (int64_t)z * M * M]);
-      }
+        for (int idx = tid; idx < S0::closure; idx += NT<T>) {
+          const int x = idx % m, t = idx / m, y = t % m, z = DIM == 3 ? t / m : 0;
+          X[idx] = T(a.u[base + x + y * M + (int64_t)z * M * M]);
+        }
   #pragma unroll 1
-    for (int idx = tid; idx < N0; idx += NT<T>) {
-        const int x = idx % mi + 1, t = idx / mi, y = t % mi + 1, z = DIM == 3 ? t / mi + 1 : 0;
-        r0[idx] = T(a.b[base + x + y * M + (int64_t)z * M * M]);
+        for (int idx = tid; idx < N0; idx += NT<T>) {
+          const int x = idx % mi + 1, t = idx / mi, y = t % mi + 1, z = DIM == 3 ? t / mi + 1 : 0;
+          r0[idx] = T(a.b[base + x + y * M + (int64_t)z * M * M]);
+        }
+      } else {
+        // boundary-vertex patch: closure nodes outside the mesh read as zero
+        const int N1 = a.N + 1, vlin = a.patch_vertex[patch];
+        const int g0[3] = {(vlin % N1 - 1) * a.p, ((vlin / N1) % N1 - 1) * a.p,
+                           DIM == 3 ? (vlin / (N1 * N1) - 1) * a.p : 0};
+  #pragma unroll 1
+        for (int idx = tid; idx < S0::closure; idx += NT<T>) {
+          const int x = idx % m, t = idx / m, y = t % m, z = DIM == 3 ? t / m : 0;
+          const bool in = g0[0] + x >= 0 && g0[0] + x < M && g0[1] + y >= 0 && g0[1] + y < M &&
+                          (DIM == 2 || (g0[2] + z >= 0 && g0[2] + z < M));
+          X[idx] = in ? T(a.u[base + x + y * M + (int64_t)z * M * M]) : T(0);
+        }
+  #pragma unroll 1
+        for (int idx = tid; idx < N0; idx += NT<T>) {
+          const int x = idx % mi + 1, t = idx / mi, y = t % mi + 1, z = DIM == 3 ? t / mi + 1 : 0;
+          r0[idx] = interior_node<DIM>(pf, a.p, idx, nullptr)
+                        ? T(a.b[base + x + y * M + (int64_t)z * M * M])
+                        : T(0);
+        }
       }
       __syncthreads();
-      // evaluate: r_j = b_j - Pi_j A-bar_j u-bar_j (equation main:4)
+      // evaluate: r_j = b_j - Pi_j A-bar_j u-bar_j (equation main:4); masked
+      // rows (boundary-vertex patches) are set to zero
       apply_level<T, DIM, LV, 0>(c);
-      for (int i = tid; i < N0; i += NT<T>) r0[i] -= c.Out()[i];
+      for (int i = tid; i < N0; i += NT<T>)
+        r0[i] = (pf == 0 || interior_node<DIM>(pf, a.p, i, nullptr)) ? r0[i] - c.Out()[i] : T(0);
       __syncthreads();
       if constexpr (MODE == kModeResidual) {
         double* out = a.out + (int64_t)patch * N0;
@@ -1786,7 +1936,8 @@ __global__ __launch_bounds__(NT<T>) void patch_kernel(PatchArgs a) {
   #pragma unroll 1
     for (int idx = tid; idx < N0; idx += NT<T>) {
         const int x = idx % mi + 1, t = idx / mi, y = t % mi + 1, z = DIM == 3 ? t / mi + 1 : 0;
-        a.u[base + x + y * M + (int64_t)z * M * M] += double(d0[idx]);
+        if (pf == 0 || interior_node<DIM>(pf, a.p, idx, nullptr))
+          a.u[base + x + y * M + (int64_t)z * M * M] += double(d0[idx]);
       }
     } else {
       double* out = a.out + (int64_t)patch * N0;
@@ -1874,9 +2025,11 @@ __global__ __launch_bounds__(NT<double>) void diag_kernel(PatchArgs a) {
     }
     constexpr int NL = Lay::level_size(L);
     double* out = const_cast<double*>(a.invdiag64[L]) + (int64_t)patch * NL;
+    const int pf = patch_flags<DIM>(a, patch);
     for (int i = tid; i < NL; i += NT<T>) {
       const int x = i % mi + 1, t = i / mi, y = t % mi + 1, z = DIM == 3 ? t / mi + 1 : 0;
-      out[i] = 1.0 / dg[x + y * m + z * m * m];
+      // masked nodes of a boundary-vertex patch: zero, so no update reaches them
+      out[i] = (pf && !interior_node<DIM>(pf, Q, i, nullptr)) ? 0.0 : 1.0 / dg[x + y * m + z * m * m];
     }
     __syncthreads();
   };
@@ -1962,9 +2115,14 @@ __device__ void lanczos_level(Ctx<double, DIM, LV>& c, const PatchArgs& a, int p
   // independent patches are numbered by their position in the batch
   const uint64_t vlin = a.patch_geo ? (uint64_t)patch : (uint64_t)a.patch_vertex[patch];
   const uint64_t base = ((vlin * 16u + (uint64_t)L) << 24);
+  // a boundary-vertex patch numbers its unmasked nodes as the cut patch does
+  const int pf = patch_flags<DIM>(a, patch);
   double nrm = 0;
   for (int i = tid; i < NL; i += NT<T>) {
-    const double x = (double)(splitmix64(a.seed, base + (uint64_t)i) >> 11) * 0x1.0p-52 - 1.0;
+    int ci = i;
+    const bool live = pf == 0 || interior_node<DIM>(pf, LV::q[L], i, &ci);
+    const double x =
+        live ? (double)(splitmix64(a.seed, base + (uint64_t)ci) >> 11) * 0x1.0p-52 - 1.0 : 0.0;
     Vb[i] = x;
     nrm += x * x;
   }
@@ -2114,6 +2272,53 @@ __global__ __launch_bounds__(NT<double>) void dense_kernel(PatchArgs a) {
   if constexpr (LV::count > 1) run(std::integral_constant<int, 1>{});
   if constexpr (LV::count > 2) run(std::integral_constant<int, 2>{});
   if constexpr (LV::count > 3) run(std::integral_constant<int, 3>{});
+}
+
+// setup: FP64 matrix of one level (args.level) for a list of patches, by the
+// matrix-free operator applied to unit vectors; row-major, one matrix per
+// list position
+template <int DIM, class LV>
+__global__ __launch_bounds__(NT<double>) void level_matrix_kernel(PatchArgs a) {
+  using T = double;
+  using Lay = Layout<T, DIM, LV>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  Ctx<T, DIM, LV> c;
+  c.lds = reinterpret_cast<T*>(smem_raw);
+  c.vec = Lay::vec_in_lds ? c.lds + Lay::vec_off
+                          : reinterpret_cast<T*>(a.vec_scratch) + (int64_t)blockIdx.x * a.vec_stride;
+  c.gtab = a.tab64;
+  const int patch = patch_of_block(a);
+  const int tid = threadIdx.x;
+  {
+    const T* tab = a.tab64;
+    for (int l = 0; l < LV::count; ++l) {
+      const int sz = tab_size(LV::q[l]);
+      for (int i = tid; i < sz; i += NT<T>) c.lds[Lay::tab_level_off(l) + i] = tab[l * kTabLevelStride + i];
+    }
+    load_geometry<T, DIM>(a, patch, c.geo(), c.mu());
+    __syncthreads();
+  }
+  prepare_geometry<T, DIM, LV>(c);
+  auto run = [&](auto Lc) {
+    constexpr int L = decltype(Lc)::value;
+    constexpr int N = Lay::level_size(L);
+    double* M = a.out + (int64_t)(a.patch_begin + blockIdx.x) * N * N;
+    T* e = c.z();
+    for (int j = 0; j < N; ++j) {
+      for (int i = tid; i < N; i += NT<T>) e[i] = i == j ? 1.0 : 0.0;
+      __syncthreads();
+      apply_vec<T, DIM, LV, L>(c, e);
+      for (int i = tid; i < N; i += NT<T>) M[(int64_t)i * N + j] = c.Out()[i];
+      __syncthreads();
+    }
+  };
+  if (a.level == 0) run(std::integral_constant<int, 0>{});
+  if constexpr (LV::count > 1)
+    if (a.level == 1) run(std::integral_constant<int, 1>{});
+  if constexpr (LV::count > 2)
+    if (a.level == 2) run(std::integral_constant<int, 2>{});
+  if constexpr (LV::count > 3)
+    if (a.level == 3) run(std::integral_constant<int, 3>{});
 }
 
 // ---------------------------------------------------------------------------
@@ -2288,6 +2493,16 @@ struct Variant {
     hipLaunchKernelGGL((dense_kernel<DIM, LV>), dim3(a.n_patch), dim3(NT<double>), lds, s, a);
     return report_launch(dense_kernel<DIM, LV>, "dense", dim3(a.n_patch), lds);
   }
+  static hipError_t launch_level_matrix(const PatchArgs& a, hipStream_t s) {
+    using L64 = Layout<double, DIM, LV>;
+    if (a.n_patch <= 0) return hipSuccess;
+    const size_t lds = (size_t)L64::lds_elems * sizeof(double);
+    hipError_t e = allow_lds(level_matrix_kernel<DIM, LV>, lds);
+    if (e != hipSuccess) return e;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL((level_matrix_kernel<DIM, LV>), dim3(a.n_patch), dim3(NT<double>), lds, s, a);
+    return report_launch(level_matrix_kernel<DIM, LV>, "level matrix", dim3(a.n_patch), lds);
+  }
   static hipError_t launch_lanczos(const PatchArgs& a, int level, hipStream_t s) {
     using L64 = Layout<double, DIM, LV>;
     if (a.n_patch <= 0) return hipSuccess;
@@ -2320,6 +2535,7 @@ PatchVariant make_variant() {
   v.launch_diag = &Variant<double, DIM, LV>::launch_diag;
   v.launch_lanczos = &Variant<double, DIM, LV>::launch_lanczos;
   v.launch_dense = &Variant<double, DIM, LV>::launch_dense;
+  v.launch_level_matrix = &Variant<double, DIM, LV>::launch_level_matrix;
   for (int l = 0; l < kMaxLevels; ++l)
     v.dense_level[l] = l < LV::count && Layout<T, DIM, LV>::dense_level(l) ? 1 : 0;
   return v;
