@@ -89,12 +89,17 @@ extern "C" {
 #define PMG_Q_N_DOFS 3           /* (N p + 1)^dim */
 #define PMG_Q_N_INTERIOR_DOFS 4  /* (N p - 1)^dim */
 #define PMG_Q_DEVICE_BYTES 5
+#define PMG_Q_N_BOUNDARY_PATCHES 6  /* patches of boundary vertices */
+#define PMG_Q_LOCAL_DOFS 7          /* sum over patches of local interior nodes (top level) */
+#define PMG_Q_TUNED_GRID 8          /* smoothing launch: workgroups (0 = one per patch) */
+#define PMG_Q_TUNED_MAP 9           /* smoothing launch: 0 linear, 1 XCD-aware mapping */
 #define PMG_Q_COLOR_OFFSET 16    /* + c: first patch of colour c, c <= n_colors */
 #define PMG_Q_LEVEL_DEGREE 32    /* + l: degree of local level l */
 #define PMG_Q_LEVEL_SIZE 48      /* + l: interior nodes per patch at level l */
 
 typedef struct pmg_handle pmg_handle; /* opaque; owns the device memory it allocates */
 typedef struct gmg_handle gmg_handle;
+typedef struct pmg_batch pmg_batch;   /* opaque; owns its instance handles */
 
 /* Structured mesh of [0,1]^dim with n_cells cells per direction. */
 typedef struct pmg_mesh {
@@ -193,6 +198,50 @@ int pmg_get_patch_vertices(const pmg_handle* h, int32_t* out);
 int pmg_query(const pmg_handle* h, int32_t what, int64_t* value);
 
 int pmg_patch_destroy(pmg_handle* h);
+
+/* Launch shape of the smoothing kernel (no change to the arithmetic: every
+ * patch update is the same).  grid = 0: one workgroup per patch of a colour;
+ * grid > 0: at most `grid` workgroups, each updating several patches in
+ * turn.  map_mode 0: patch i of a colour goes to workgroup i mod grid;
+ * map_mode 1: the colour's patches are split into 8 contiguous ranges, one
+ * per XCD (workgroups are dealt to the XCDs round-robin), so neighbouring
+ * patches share an L2. */
+int pmg_set_launch(pmg_handle* h, int32_t grid, int32_t map_mode);
+
+/* Autotuner: times the largest colour of a sweep (on a device copy of u,
+ * which is left unchanged) for the launch shapes (one workgroup per patch,
+ * linear or XCD-aware; 1, 2 or 4 workgroups per compute unit, XCD-aware; 2
+ * per compute unit, linear) and keeps the fastest.  u, b: device, as for
+ * pmg_patch_smooth.  best_ms (host, may be NULL): its time per colour
+ * launch.  Synchronises the handle's stream. */
+int pmg_autotune(pmg_handle* h, const double* u, const double* b, float* best_ms);
+
+/* Batches of independent problems (meshes of their own, degrees may differ),
+ * smoothed together: a sweep takes the colours in order and, per colour,
+ * launches every instance's patches concurrently on a stream of its own,
+ * joined before the next colour.  meshes[i], coeffs[i] (host), p[i]: instance
+ * i, set up as by pmg_patch_setup with opts (opts->n_levels must be 0:
+ * default level lists p, p/2, ..., 1).  Synchronises opts->stream. */
+int pmg_batch_setup(const pmg_mesh* meshes, const double* const* coeffs, const int32_t* p,
+                    int32_t n, const pmg_opts* opts, pmg_batch** out);
+/* The handle of instance i (owned by the batch: do not destroy it). */
+int pmg_batch_instance(pmg_batch* b, int32_t i, pmg_handle** h);
+/* One sweep of every instance (direction +1 or -1); u[i], rhs[i]: device
+ * vectors of instance i.  The first call per direction captures the sweep
+ * into a HIP graph bound to these addresses; later calls with the same
+ * addresses replay it, other addresses capture again (counted by
+ * pmg_batch_query).  Asynchronous on opts->stream. */
+int pmg_batch_smooth(pmg_batch* b, double* const* u, const double* const* rhs, int32_t direction);
+/* The same sweep enqueued directly, without a graph. */
+int pmg_batch_smooth_eager(pmg_batch* b, double* const* u, const double* const* rhs,
+                           int32_t direction);
+/* pmg_autotune for every instance; drops captured graphs. */
+int pmg_batch_autotune(pmg_batch* b, double* const* u, const double* const* rhs);
+#define PMG_BQ_N_INSTANCES 0
+#define PMG_BQ_CAPTURES 1
+#define PMG_BQ_REPLAYS 2
+int pmg_batch_query(const pmg_batch* b, int32_t what, int64_t* value);
+int pmg_batch_destroy(pmg_batch* b);
 
 /* Geometric multigrid over meshes with N, N/2, ... cells (halving while N
  * stays even and the halved mesh has an interior vertex), degree p on every

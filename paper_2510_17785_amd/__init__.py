@@ -8,7 +8,8 @@ The compute path is libpmg.so (HIP kernels, built in-tree by
 streams.  Importing this package does not load the library; constructing a
 solver does, and fails loudly when it is missing.
 """
-from .api import BoundNet, GMGSolver, PatchBatch, PatchSmoother, n_features  # noqa: F401
+from .api import (BoundNet, GMGSolver, PatchBatch, PatchSmoother, SmootherBatch,  # noqa: F401
+                  n_features)
 from . import _lib  # noqa: F401
 
-__all__ = ["PatchSmoother", "PatchBatch", "BoundNet", "GMGSolver", "n_features"]
+__all__ = ["PatchSmoother", "PatchBatch", "SmootherBatch", "BoundNet", "GMGSolver", "n_features"]

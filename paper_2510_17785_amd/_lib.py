@@ -32,6 +32,13 @@ PMG_Q_N_LEVELS = 2
 PMG_Q_N_DOFS = 3
 PMG_Q_N_INTERIOR_DOFS = 4
 PMG_Q_DEVICE_BYTES = 5
+PMG_Q_N_BOUNDARY_PATCHES = 6
+PMG_Q_LOCAL_DOFS = 7
+PMG_Q_TUNED_GRID = 8
+PMG_Q_TUNED_MAP = 9
+PMG_BQ_N_INSTANCES = 0
+PMG_BQ_CAPTURES = 1
+PMG_BQ_REPLAYS = 2
 PMG_Q_COLOR_OFFSET = 16
 PMG_Q_LEVEL_DEGREE = 32
 PMG_Q_LEVEL_SIZE = 48
@@ -45,7 +52,9 @@ EXPORTS = [
     "pmg_patch_features", "pmg_mlp_param_count", "pmg_mlp_create", "pmg_mlp_get_params",
     "pmg_mlp_set_params", "pmg_mlp_fit_standardizer", "pmg_mlp_get_standardizer",
     "pmg_mlp_set_standardizer", "pmg_mlp_predict", "pmg_mlp_gradient", "pmg_mlp_train",
-    "pmg_mlp_destroy", "pmg_set_bounds_mlp",
+    "pmg_mlp_destroy", "pmg_set_bounds_mlp", "pmg_set_launch", "pmg_autotune",
+    "pmg_batch_setup", "pmg_batch_instance", "pmg_batch_smooth", "pmg_batch_smooth_eager",
+    "pmg_batch_autotune", "pmg_batch_query", "pmg_batch_destroy",
 ]
 
 
@@ -125,6 +134,16 @@ def load() -> ctypes.CDLL:
         "pmg_mlp_destroy": [P],
         "pmg_set_bounds_mlp": [P, P, ctypes.c_double, ctypes.c_double,
                                ctypes.POINTER(ctypes.c_int64)],
+        "pmg_set_launch": [P, i32, i32],
+        "pmg_autotune": [P, P, P, F],
+        "pmg_batch_setup": [ctypes.POINTER(PmgMesh), ctypes.POINTER(D), ctypes.POINTER(i32), i32,
+                            ctypes.POINTER(PmgOpts), ctypes.POINTER(P)],
+        "pmg_batch_instance": [P, i32, ctypes.POINTER(P)],
+        "pmg_batch_smooth": [P, ctypes.POINTER(P), ctypes.POINTER(P), i32],
+        "pmg_batch_smooth_eager": [P, ctypes.POINTER(P), ctypes.POINTER(P), i32],
+        "pmg_batch_autotune": [P, ctypes.POINTER(P), ctypes.POINTER(P)],
+        "pmg_batch_query": [P, i32, ctypes.POINTER(ctypes.c_int64)],
+        "pmg_batch_destroy": [P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)

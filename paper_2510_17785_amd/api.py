@@ -109,6 +109,8 @@ class PatchSmoother:
         self.color_offsets = [q(L.PMG_Q_COLOR_OFFSET + c) for c in range(self.n_colors + 1)]
         self.n_dofs = q(L.PMG_Q_N_DOFS)
         self.n_interior_dofs = q(L.PMG_Q_N_INTERIOR_DOFS)
+        self.n_boundary_patches = q(L.PMG_Q_N_BOUNDARY_PATCHES)
+        self.local_dofs = q(L.PMG_Q_LOCAL_DOFS)
 
     def query(self, what: int) -> int:
         v = ctypes.c_int64()
@@ -169,6 +171,21 @@ class PatchSmoother:
         L.check(self._lib.pmg_set_bounds_mlp(self._h, net._h, float(margin), float(ood_z),
                                              ctypes.byref(nf)))
         return nf.value
+
+    def set_launch(self, grid: int, map_mode: int) -> None:
+        """pmg_set_launch: smoothing-kernel launch shape (grid 0 = one
+        workgroup per patch; map_mode 1 = XCD-aware ranges)."""
+        L.check(self._lib.pmg_set_launch(self._h, int(grid), int(map_mode)))
+
+    def autotune(self, u: torch.Tensor, b: torch.Tensor) -> float:
+        """pmg_autotune; returns the best time per colour launch in ms."""
+        ms = ctypes.c_float()
+        L.check(self._lib.pmg_autotune(self._h, _dptr(u), _dptr(b), ctypes.byref(ms)))
+        return ms.value
+
+    @property
+    def launch(self):
+        return self.query(L.PMG_Q_TUNED_GRID), self.query(L.PMG_Q_TUNED_MAP)
 
     def bounds(self) -> np.ndarray:
         out = np.zeros((self.n_patches, self.n_levels - 1, 2))
@@ -354,6 +371,76 @@ class GMGSolver:
         if getattr(self, "_h", None) is not None:
             L.check(self._lib.gmg_destroy(self._h))
         self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SmootherBatch:
+    """pmg_batch_*: independent meshes of mixed degree smoothed together, a
+    sweep captured once into a HIP graph and replayed."""
+
+    def __init__(self, dim: int, ns, ps, vertices, coeffs, precision: str = "fp32",
+                 bounds: str = "lanczos", with_boundary: bool = True, cheb_degree: int = 3,
+                 lanczos_steps: int = 12, seed: int = 0, stream=None):
+        self._lib = L.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("SmootherBatch needs a GPU")
+        k = len(ps)
+        meshes = (L.PmgMesh * k)()
+        self._keep = []
+        for i in range(k):
+            m, v = _mesh(dim, ns[i], vertices[i])
+            meshes[i] = m
+            mu = np.ascontiguousarray(coeffs[i], dtype=np.float64)
+            if mu.shape != (ns[i] ** dim,):
+                raise ValueError("one coefficient per cell expected")
+            self._keep += [v, mu]
+        cptr = (ctypes.POINTER(ctypes.c_double) * k)(
+            *[self._keep[2 * i + 1].ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for i in range(k)])
+        pp = (ctypes.c_int32 * k)(*[int(x) for x in ps])
+        o = _opts(None, precision, cheb_degree, 1, bounds, lanczos_steps, 1.1, 15.0, seed, stream,
+                  with_boundary)
+        h = ctypes.c_void_p()
+        L.check(self._lib.pmg_batch_setup(meshes, cptr, pp, k, ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self.instances = []
+        for i in range(k):
+            hi = ctypes.c_void_p()
+            L.check(self._lib.pmg_batch_instance(self._h, i, ctypes.byref(hi)))
+            self.instances.append(PatchSmoother(dim, ns[i], ps[i], None, None, _handle=hi, _owner=self))
+
+    @staticmethod
+    def _ptrs(ts):
+        return (ctypes.c_void_p * len(ts))(*[_dptr(t) for t in ts])
+
+    def smooth(self, us, bs, direction: int = 1, graph: bool = True):
+        f = self._lib.pmg_batch_smooth if graph else self._lib.pmg_batch_smooth_eager
+        L.check(f(self._h, self._ptrs(us), self._ptrs(bs), int(direction)))
+
+    def autotune(self, us, bs):
+        L.check(self._lib.pmg_batch_autotune(self._h, self._ptrs(us), self._ptrs(bs)))
+
+    def query(self, what: int) -> int:
+        v = ctypes.c_int64()
+        L.check(self._lib.pmg_batch_query(self._h, int(what), ctypes.byref(v)))
+        return v.value
+
+    @property
+    def captures(self) -> int:
+        return self.query(L.PMG_BQ_CAPTURES)
+
+    @property
+    def replays(self) -> int:
+        return self.query(L.PMG_BQ_REPLAYS)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            self._lib.pmg_batch_destroy(self._h)
+            self._h = None
 
     def __del__(self):
         try:

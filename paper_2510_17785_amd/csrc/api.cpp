@@ -175,6 +175,9 @@ struct pmg_handle {
   int32_t* trunc_index = nullptr;
   double* trunc_inv = nullptr;
   int n_trunc = 0;
+  // launch shape of the smoothing kernel (set by pmg_autotune)
+  int tune_grid = 0, tune_map = 0;
+  int64_t local_dofs = 0;  // sum over patches of unmasked interior nodes (top level)
   int level_size(int l) const { return ipow(2 * levels[l] - 1, dim); }
   size_t tsize() const { return precision == PMG_FP64 ? sizeof(double) : sizeof(float); }
   PatchArgs args() const {
@@ -204,6 +207,8 @@ struct pmg_handle {
     a.with_boundary = with_boundary ? 1 : 0;
     a.trunc_index = trunc_index;
     a.trunc_inv = trunc_inv;
+    a.grid = tune_grid;
+    a.map_mode = tune_map;
     return a;
   }
 };
@@ -228,12 +233,29 @@ void free_handle(pmg_handle* h) {
 
 // launch a per-patch kernel over patches [begin, end) in chunks that fit the
 // vector scratch
-int launch_chunks(pmg_handle* h, int mode, PatchArgs a, int begin, int end) {
+int launch_chunks(pmg_handle* h, int mode, PatchArgs a, int begin, int end,
+                  hipStream_t stream) {
   const int chunk = h->vec_blocks > 0 ? (int)h->vec_blocks : (end - begin);
   for (int s = begin; s < end; s += std::max(chunk, 1)) {
     a.patch_begin = s;
     a.n_patch = std::min(chunk, end - s);
-    HIP_TRY(h->var->launch(mode, a, h->stream));
+    HIP_TRY(h->var->launch(mode, a, stream));
+  }
+  return PMG_OK;
+}
+int launch_chunks(pmg_handle* h, int mode, PatchArgs a, int begin, int end) {
+  return launch_chunks(h, mode, a, begin, end, h->stream);
+}
+
+// colours [c_begin, c_end) of a sweep (reversed for direction -1) on `stream`
+int smooth_on(pmg_handle* h, double* u, const double* b, int c_begin, int c_end, int direction,
+              hipStream_t stream) {
+  PatchArgs a = h->args();
+  a.u = u;
+  a.b = b;
+  for (int k = c_begin; k < c_end; ++k) {
+    const int c = direction > 0 ? k : c_end - 1 - (k - c_begin);
+    PMG_TRY(launch_chunks(h, kModeSmooth, a, h->color_off[c], h->color_off[c + 1], stream));
   }
   return PMG_OK;
 }
@@ -495,7 +517,8 @@ int setup_common(pmg_handle* h) {
     const int64_t e2 = var->vec_scratch_elems64() * (int64_t)sizeof(double);
     const int64_t bytes_per_block = std::max(e1, e2);
     if (bytes_per_block > 0) {
-      h->vec_blocks = h->max_color;
+      // a multiple of 8 slots: the XCD-aware launch rounds its grid up to one
+      h->vec_blocks = (h->max_color + 7) / 8 * 8;
       h->vec_bytes = bytes_per_block;
       if ((s = dev_alloc(&h->vec_scratch, (size_t)bytes_per_block * h->vec_blocks, &h->device_bytes)) < 0)
         return cleanup(s);
@@ -676,6 +699,14 @@ int patch_setup_impl(const pmg_mesh* mesh, const double* coeff, int p, const pmg
   h->color_off[h->n_colors] = (int)order.size();
   h->n_patches = (int)order.size();
   h->vertex_host = order;
+  for (int32_t v : order) {  // local interior nodes: 2p-1 per direction, p-1 where cut
+    int64_t cnt = 1;
+    for (int i = 0; i < dim; ++i) {
+      const int vi = i == 0 ? v % N1 : i == 1 ? (v / N1) % N1 : v / (N1 * N1);
+      cnt *= (vi == 0 || vi == N) ? p - 1 : 2 * p - 1;
+    }
+    h->local_dofs += cnt;
+  }
 
   const size_t nv = (size_t)ipow(N1, dim), nc = (size_t)ipow(N, dim);
   int s;
@@ -1151,11 +1182,7 @@ int pmg_patch_smooth_colors(pmg_handle* h, double* u, const double* b, int32_t c
   if (!h->bounds_valid) return fail(PMG_ERR_INVALID_ARG, "Chebyshev bounds not set");
   if (c_begin < 0 || c_end > h->n_colors || c_begin > c_end)
     return fail(PMG_ERR_INVALID_ARG, "colour range [%d, %d) outside [0, %d)", c_begin, c_end, h->n_colors);
-  PatchArgs a = h->args();
-  a.u = u;
-  a.b = b;
-  for (int c = c_begin; c < c_end; ++c) PMG_TRY(launch_chunks(h, kModeSmooth, a, h->color_off[c], h->color_off[c + 1]));
-  return PMG_OK;
+  return smooth_on(h, u, b, c_begin, c_end, 1, h->stream);
 }
 
 int pmg_patch_smooth(pmg_handle* h, double* u, const double* b, int32_t direction) {
@@ -1241,6 +1268,10 @@ int pmg_query(const pmg_handle* h, int32_t what, int64_t* value) {
     case PMG_Q_N_DOFS: *value = h->dim == 3 ? M * M * M : M * M; return PMG_OK;
     case PMG_Q_N_INTERIOR_DOFS: *value = h->dim == 3 ? (M - 2) * (M - 2) * (M - 2) : (M - 2) * (M - 2); return PMG_OK;
     case PMG_Q_DEVICE_BYTES: *value = (int64_t)h->device_bytes; return PMG_OK;
+    case PMG_Q_N_BOUNDARY_PATCHES: *value = h->n_trunc; return PMG_OK;
+    case PMG_Q_LOCAL_DOFS: *value = h->local_dofs; return PMG_OK;
+    case PMG_Q_TUNED_GRID: *value = h->tune_grid; return PMG_OK;
+    case PMG_Q_TUNED_MAP: *value = h->tune_map; return PMG_OK;
     default: break;
   }
   if (what >= PMG_Q_COLOR_OFFSET && what <= PMG_Q_COLOR_OFFSET + h->n_colors) {
@@ -1581,6 +1612,271 @@ int pmg_set_bounds_mlp(pmg_handle* h, pmg_mlp* mm, double margin, double ood_z, 
     return st;
   }
   if (n_fallback) *n_fallback = (int64_t)fallback.size();
+  return PMG_OK;
+}
+
+int pmg_autotune(pmg_handle* h, const double* u, const double* b, float* best_ms) {
+  if (!h || !u || !b) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  if (h->patch_geo) return fail(PMG_ERR_UNSUPPORTED, "independent patches have no sweep to tune");
+  if (!h->bounds_valid) return fail(PMG_ERR_INVALID_ARG, "Chebyshev bounds not set");
+  int dev = 0, cus = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  // the largest colour, smoothed on a copy of u
+  int cbig = 0;
+  for (int c = 1; c < h->n_colors; ++c)
+    if (h->color_off[c + 1] - h->color_off[c] > h->color_off[cbig + 1] - h->color_off[cbig]) cbig = c;
+  const int64_t M = (int64_t)h->N * h->p + 1;
+  const size_t n = (size_t)(h->dim == 3 ? M * M * M : M * M);
+  double* w = nullptr;
+  int st;
+  if ((st = dev_alloc(&w, n * sizeof(double), nullptr)) < 0) return st;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = hipMemcpyAsync(w, u, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream);
+  const int cand[][2] = {{0, 0}, {0, 1}, {cus, 1}, {2 * cus, 1}, {4 * cus, 1}, {2 * cus, 0}};
+  float best = 1e30f;
+  int bg = 0, bm = 0;
+  st = PMG_OK;
+  for (const auto& cd : cand) {
+    if (e != hipSuccess || st != PMG_OK) break;
+    h->tune_grid = cd[0];
+    h->tune_map = cd[1];
+    if ((st = smooth_on(h, w, b, cbig, cbig + 1, 1, h->stream)) < 0) break;  // warm-up
+    e = hipEventRecord(e0, h->stream);
+    for (int r = 0; r < 5 && e == hipSuccess && st == PMG_OK; ++r) st = smooth_on(h, w, b, cbig, cbig + 1, 1, h->stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess && st == PMG_OK && ms / 5 < best) {
+      best = ms / 5;
+      bg = cd[0];
+      bm = cd[1];
+    }
+  }
+  h->tune_grid = bg;
+  h->tune_map = bm;
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(w);
+  if (st != PMG_OK) return st;
+  if (e != hipSuccess) return fail(PMG_ERR_HIP, "autotune: %s", hipGetErrorString(e));
+  if (best_ms) *best_ms = best;
+  return PMG_OK;
+}
+
+int pmg_set_launch(pmg_handle* h, int32_t grid, int32_t map_mode) {
+  if (!h) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  if (grid < 0 || (map_mode != 0 && map_mode != 1))
+    return fail(PMG_ERR_INVALID_ARG, "grid must be >= 0 and map_mode 0 or 1");
+  h->tune_grid = grid;
+  h->tune_map = map_mode;
+  return PMG_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batches of independent instances (meshes of their own, mixed degrees):
+// a sweep runs colour by colour, the instances of one colour concurrently on
+// one stream each, and is captured once into a HIP graph that later calls
+// replay
+// ---------------------------------------------------------------------------
+
+struct pmg_batch {
+  std::vector<pmg_handle*> inst;
+  hipStream_t stream = nullptr;  // the caller's stream (opts.stream)
+  hipStream_t cap = nullptr;     // capture stream (the null stream cannot capture)
+  std::vector<hipStream_t> side;
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  std::vector<const void*> bound[2];  // (u, b) per instance of each captured graph
+  int64_t captures = 0, replays = 0;
+  int max_colors = 0;
+};
+
+namespace {
+
+void drop_graphs(pmg_batch* b) {
+  for (int d = 0; d < 2; ++d) {
+    if (b->exec[d]) (void)hipGraphExecDestroy(b->exec[d]);
+    if (b->graph[d]) (void)hipGraphDestroy(b->graph[d]);
+    b->exec[d] = nullptr;
+    b->graph[d] = nullptr;
+    b->bound[d].clear();
+  }
+}
+
+void free_batch(pmg_batch* b) {
+  if (!b) return;
+  drop_graphs(b);
+  for (hipStream_t s : b->side)
+    if (s) (void)hipStreamDestroy(s);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  for (hipEvent_t e : b->join)
+    if (e) (void)hipEventDestroy(e);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  for (pmg_handle* h : b->inst) free_handle(h);
+  delete b;
+}
+
+// enqueue one sweep of every instance: colour by colour, instances forked
+// onto their side streams and joined back before the next colour
+int enqueue_sweep(pmg_batch* b, double* const* u, const double* const* rhs, int direction,
+                  hipStream_t main) {
+  hipError_t e;
+  for (int k = 0; k < b->max_colors; ++k) {
+    if ((e = hipEventRecord(b->fork, main))) return fail(PMG_ERR_HIP, "batch fork: %s", hipGetErrorString(e));
+    for (size_t i = 0; i < b->inst.size(); ++i) {
+      pmg_handle* h = b->inst[i];
+      const int c = direction > 0 ? k : h->n_colors - 1 - k;
+      if (c < 0 || c >= h->n_colors) continue;
+      if ((e = hipStreamWaitEvent(b->side[i], b->fork, 0)))
+        return fail(PMG_ERR_HIP, "batch wait: %s", hipGetErrorString(e));
+      PMG_TRY(smooth_on(h, u[i], rhs[i], c, c + 1, 1, b->side[i]));
+      if ((e = hipEventRecord(b->join[i], b->side[i])) || (e = hipStreamWaitEvent(main, b->join[i], 0)))
+        return fail(PMG_ERR_HIP, "batch join: %s", hipGetErrorString(e));
+    }
+  }
+  return PMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pmg_batch_setup(const pmg_mesh* meshes, const double* const* coeffs, const int32_t* p, int32_t n,
+                    const pmg_opts* o, pmg_batch** out) {
+  if (!meshes || !coeffs || !p || !o || !out || n < 1) return fail(PMG_ERR_INVALID_ARG, "null argument or n < 1");
+  if (o->n_levels != 0)
+    return fail(PMG_ERR_INVALID_ARG, "a batch of mixed degrees uses the default level lists (n_levels = 0)");
+  *out = nullptr;
+  pmg_batch* b = new pmg_batch();
+  b->stream = reinterpret_cast<hipStream_t>(o->stream);
+  hipError_t e;
+  auto bail = [&](int st) {
+    free_batch(b);
+    return st;
+  };
+  for (int i = 0; i < n; ++i) {
+    pmg_handle* h = nullptr;
+    int st = patch_setup_impl(&meshes[i], coeffs[i], p[i], o, &h);
+    if (st < 0) return bail(st);
+    b->inst.push_back(h);
+    b->max_colors = std::max(b->max_colors, h->n_colors);
+    hipStream_t s = nullptr;
+    hipEvent_t ev = nullptr;
+    if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) ||
+        (e = hipEventCreateWithFlags(&ev, hipEventDisableTiming))) {
+      if (s) (void)hipStreamDestroy(s);
+      return bail(fail(PMG_ERR_HIP, "batch streams: %s", hipGetErrorString(e)));
+    }
+    b->side.push_back(s);
+    b->join.push_back(ev);
+  }
+  if ((e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming)) ||
+      (e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking)))
+    return bail(fail(PMG_ERR_HIP, "batch events: %s", hipGetErrorString(e)));
+  // set the launch attributes of every kernel before any capture: smooth
+  // each instance's first colour once on zero vectors
+  for (pmg_handle* h : b->inst) {
+    const int64_t M = (int64_t)h->N * h->p + 1;
+    const size_t nd = (size_t)(h->dim == 3 ? M * M * M : M * M);
+    double* z = nullptr;
+    int st = dev_alloc(&z, 2 * nd * sizeof(double), nullptr);
+    if (st < 0) return bail(st);
+    if (!(e = hipMemsetAsync(z, 0, 2 * nd * sizeof(double), h->stream)) && h->bounds_valid)
+      st = smooth_on(h, z, z + nd, 0, 1, 1, h->stream);
+    if (!e) e = hipStreamSynchronize(h->stream);
+    (void)hipFree(z);
+    if (st < 0) return bail(st);
+    if (e) return bail(fail(PMG_ERR_HIP, "batch warm-up: %s", hipGetErrorString(e)));
+  }
+  *out = b;
+  return PMG_OK;
+}
+
+int pmg_batch_instance(pmg_batch* b, int32_t i, pmg_handle** h) {
+  if (!b || !h || i < 0 || i >= (int)b->inst.size()) return fail(PMG_ERR_INVALID_ARG, "no instance %d", i);
+  *h = b->inst[i];
+  return PMG_OK;
+}
+
+int pmg_batch_smooth_eager(pmg_batch* b, double* const* u, const double* const* rhs, int32_t direction) {
+  if (!b || !u || !rhs) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  if (direction != 1 && direction != -1) return fail(PMG_ERR_INVALID_ARG, "direction must be +1 or -1");
+  for (size_t i = 0; i < b->inst.size(); ++i)
+    if (!u[i] || !rhs[i] || !b->inst[i]->bounds_valid)
+      return fail(PMG_ERR_INVALID_ARG, "instance %zu: null vector or bounds not set", i);
+  return enqueue_sweep(b, u, rhs, direction, b->stream);
+}
+
+int pmg_batch_smooth(pmg_batch* b, double* const* u, const double* const* rhs, int32_t direction) {
+  if (!b || !u || !rhs) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  if (direction != 1 && direction != -1) return fail(PMG_ERR_INVALID_ARG, "direction must be +1 or -1");
+  const int d = direction > 0 ? 0 : 1;
+  std::vector<const void*> ptrs;
+  for (size_t i = 0; i < b->inst.size(); ++i) {
+    if (!u[i] || !rhs[i] || !b->inst[i]->bounds_valid)
+      return fail(PMG_ERR_INVALID_ARG, "instance %zu: null vector or bounds not set", i);
+    ptrs.push_back(u[i]);
+    ptrs.push_back(rhs[i]);
+  }
+  hipError_t e;
+  if (!b->exec[d] || b->bound[d] != ptrs) {
+    // (re)capture: the graph is bound to these vector addresses
+    if (b->exec[d]) (void)hipGraphExecDestroy(b->exec[d]);
+    if (b->graph[d]) (void)hipGraphDestroy(b->graph[d]);
+    b->exec[d] = nullptr;
+    b->graph[d] = nullptr;
+    if ((e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal)))
+      return fail(PMG_ERR_HIP, "batch capture: %s", hipGetErrorString(e));
+    const int st = enqueue_sweep(b, u, rhs, direction, b->cap);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(b->cap, &g);
+    if (st < 0) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e) return fail(PMG_ERR_HIP, "batch capture: %s", hipGetErrorString(e));
+    b->graph[d] = g;
+    if ((e = hipGraphInstantiate(&b->exec[d], g, nullptr, nullptr, 0)))
+      return fail(PMG_ERR_HIP, "batch graph: %s", hipGetErrorString(e));
+    b->bound[d] = ptrs;
+    ++b->captures;
+  } else {
+    ++b->replays;
+  }
+  if ((e = hipGraphLaunch(b->exec[d], b->stream))) return fail(PMG_ERR_HIP, "batch launch: %s", hipGetErrorString(e));
+  return PMG_OK;
+}
+
+int pmg_batch_autotune(pmg_batch* b, double* const* u, const double* const* rhs) {
+  if (!b || !u || !rhs) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  for (size_t i = 0; i < b->inst.size(); ++i) PMG_TRY(pmg_autotune(b->inst[i], u[i], rhs[i], nullptr));
+  drop_graphs(b);  // launch shapes are baked into captured graphs
+  return PMG_OK;
+}
+
+int pmg_batch_query(const pmg_batch* b, int32_t what, int64_t* value) {
+  if (!b || !value) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  switch (what) {
+    case PMG_BQ_N_INSTANCES: *value = (int64_t)b->inst.size(); return PMG_OK;
+    case PMG_BQ_CAPTURES: *value = b->captures; return PMG_OK;
+    case PMG_BQ_REPLAYS: *value = b->replays; return PMG_OK;
+    default: return fail(PMG_ERR_INVALID_ARG, "unknown batch query %d", what);
+  }
+}
+
+int pmg_batch_destroy(pmg_batch* b) {
+  if (!b) return PMG_OK;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  else (void)hipDeviceSynchronize();
+  free_batch(b);
   return PMG_OK;
 }
 

@@ -67,6 +67,10 @@ struct PatchArgs {
   // non-empty level (level count - 2, masked rows and columns zero), or -1
   const int32_t* trunc_index;
   const double* trunc_inv;   // rows x size_{L-2}^2
+  // patch kernel launch shape: grid (0 = one workgroup per patch, else at
+  // most this many workgroups, each taking several patches) and the
+  // patch-to-workgroup mapping (0 linear, 1 XCD-aware ranges)
+  int32_t grid, map_mode;
 };
 
 // One compiled (precision, dim, levels) variant of the patch kernels.

@@ -25,7 +25,10 @@
 
 #include <cstdio>
 #include <cstring>
+#include <mutex>
+#include <set>
 #include <string>
+#include <tuple>
 #include <type_traits>
 #include <vector>
 #include <algorithm>
@@ -1825,20 +1828,15 @@ __device__ void load_patch(const Ctx<T, DIM, LV>& c, const PatchArgs& a, int pat
   __syncthreads();
 }
 
+// One patch update (mode: smooth, residual, local solve or level apply).
 template <typename T, int DIM, class LV, int MODE>
-__global__ __launch_bounds__(NT<T>) void patch_kernel(PatchArgs a) {
+__device__ __forceinline__ void patch_update(const PatchArgs& a, Ctx<T, DIM, LV>& c, int patch) {
   using Lay = Layout<T, DIM, LV>;
   using S0 = Sh<DIM, LV::q[0]>;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  Ctx<T, DIM, LV> c;
-  c.lds = reinterpret_cast<T*>(smem_raw);
-  c.vec = Lay::vec_in_lds ? c.lds + Lay::vec_off
-                          : reinterpret_cast<T*>(a.vec_scratch) + (int64_t)blockIdx.x * a.vec_stride;
-  c.gtab = tptr<T>(a.tab);
-  const int patch = patch_of_block(a);
   const int tid = threadIdx.x;
   const int pf = patch_flags<DIM>(a, patch);
   c.pf = pf;
+  c.trunc = nullptr;
   if (pf && a.trunc_index) {
     const int k = a.trunc_index[patch];
     // one slot holds the largest unmasked box, a face patch's
@@ -1943,6 +1941,44 @@ __global__ __launch_bounds__(NT<T>) void patch_kernel(PatchArgs a) {
       double* out = a.out + (int64_t)patch * N0;
       for (int i = tid; i < N0; i += NT<T>) out[i] = double(d0[i]);
     }
+  }
+}
+
+// Work item k of workgroup b in a grid of G workgroups over n patches, or -1
+// when the workgroup is done.  map_mode 0: item b + k G.  map_mode 1
+// (XCD-aware; workgroups are dealt to the 8 XCDs round-robin): the patches
+// are split into 8 contiguous ranges, workgroup b works in range b mod 8, so
+// neighbouring patches, which share closure nodes, meet in one L2.
+__device__ __forceinline__ int work_item(const PatchArgs& a, int b, int k, int G) {
+  const int n = a.n_patch;
+  if (a.map_mode == 1 && (G & 7) == 0) {
+    const int per = G >> 3, chunk = (n + 7) >> 3;
+    const int o = (b >> 3) + k * per;
+    const int i = (b & 7) * chunk + o;
+    return (o < chunk && i < n) ? i : -1;
+  }
+  const int i = b + k * G;
+  return i < n ? i : -1;
+}
+
+// Patch kernel: one workgroup per patch, or fewer workgroups that each take
+// several patches in turn (the grid and the mapping are launch parameters).
+template <typename T, int DIM, class LV, int MODE>
+__global__ __launch_bounds__(NT<T>) void patch_kernel(PatchArgs a) {
+  using Lay = Layout<T, DIM, LV>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  Ctx<T, DIM, LV> c;
+  c.lds = reinterpret_cast<T*>(smem_raw);
+  c.vec = Lay::vec_in_lds ? c.lds + Lay::vec_off
+                          : reinterpret_cast<T*>(a.vec_scratch) + (int64_t)blockIdx.x * a.vec_stride;
+  c.gtab = tptr<T>(a.tab);
+#pragma unroll 1
+  for (int k = 0;; ++k) {
+    const int i = work_item(a, blockIdx.x, k, gridDim.x);
+    if (i < 0) break;
+    if (k > 0) __syncthreads();  // the previous patch is done with the LDS
+    const int patch = a.patch_list ? a.patch_list[a.patch_begin + i] : a.patch_begin + i;
+    patch_update<T, DIM, LV, MODE>(a, c, patch);
   }
 }
 
@@ -2409,9 +2445,23 @@ __global__ __launch_bounds__(64) void feature_kernel(PatchArgs a, float* out) {
 template <typename K>
 hipError_t allow_lds(K kernel, size_t bytes) {
   if (bytes == 0) return hipSuccess;
+  // set once per kernel and device: the attribute persists, and launches
+  // recorded into a graph must not be preceded by other runtime calls
+  static std::mutex mu;
+  static std::set<std::tuple<const void*, int, size_t>> done;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const auto key = std::make_tuple(reinterpret_cast<const void*>(kernel), dev, bytes);
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    if (done.count(key)) return hipSuccess;
+  }
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (e != hipSuccess) {
+  if (e == hipSuccess) {
+    std::lock_guard<std::mutex> lock(mu);
+    done.insert(key);
+  } else {
     int dev = 0, lim = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
@@ -2445,7 +2495,10 @@ struct Variant {
   static hipError_t launch(int mode, const PatchArgs& a, hipStream_t s) {
     if (a.n_patch <= 0) return hipSuccess;
     const size_t lds = lds_bytes(mode);
-    dim3 grid(a.n_patch), block(NT<T>);
+    int g = a.n_patch;
+    if (a.grid > 0 && a.grid < g) g = a.grid;
+    if (a.map_mode == 1) g = (g + 7) / 8 * 8;  // whole rounds over the 8 XCDs
+    dim3 grid(g), block(NT<T>);
     hipError_t e = hipSuccess;
     switch (mode) {
       case kModeSmooth:
