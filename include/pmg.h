@@ -211,9 +211,9 @@ int pmg_set_launch(pmg_handle* h, int32_t grid, int32_t map_mode);
 /* Autotuner: times the largest colour of a sweep (on a device copy of u,
  * which is left unchanged) for the launch shapes (one workgroup per patch,
  * linear or XCD-aware; 1, 2 or 4 workgroups per compute unit, XCD-aware; 2
- * per compute unit, linear) and keeps the fastest.  u, b: device, as for
- * pmg_patch_smooth.  best_ms (host, may be NULL): its time per colour
- * launch.  Synchronises the handle's stream. */
+ * per compute unit, linear), after a warm-up, in two rounds, and keeps the
+ * fastest.  u, b: device, as for pmg_patch_smooth.  best_ms (host, may be
+ * NULL): its time per colour launch.  Synchronises the handle's stream. */
 int pmg_autotune(pmg_handle* h, const double* u, const double* b, float* best_ms);
 
 /* Batches of independent problems (meshes of their own, degrees may differ),
@@ -235,7 +235,10 @@ int pmg_batch_smooth(pmg_batch* b, double* const* u, const double* const* rhs, i
 /* The same sweep enqueued directly, without a graph. */
 int pmg_batch_smooth_eager(pmg_batch* b, double* const* u, const double* const* rhs,
                            int32_t direction);
-/* pmg_autotune for every instance; drops captured graphs. */
+/* Launch shapes for every instance, chosen with the instances running
+ * together: whole-batch graph sweeps (captured per candidate) on copies of u
+ * (left unchanged), one instance's shape at a time, highest degree first,
+ * over the candidates of pmg_autotune.  Drops captured graphs. */
 int pmg_batch_autotune(pmg_batch* b, double* const* u, const double* const* rhs);
 #define PMG_BQ_N_INSTANCES 0
 #define PMG_BQ_CAPTURES 1

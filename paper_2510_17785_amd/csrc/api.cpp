@@ -247,6 +247,45 @@ int launch_chunks(pmg_handle* h, int mode, PatchArgs a, int begin, int end) {
   return launch_chunks(h, mode, a, begin, end, h->stream);
 }
 
+size_t n_dofs(const pmg_handle* h) {
+  const int64_t M = (int64_t)h->N * h->p + 1;
+  return (size_t)(h->dim == 3 ? M * M * M : M * M);
+}
+
+// launch shapes the autotuners try: (workgroups, mapping); 0 workgroups =
+// one per patch
+constexpr int kLaunchCandidates = 6;
+int launch_candidates(int (*c)[2]) {
+  int dev = 0, cus = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int t[kLaunchCandidates][2] = {{0, 0}, {0, 1}, {cus, 1}, {2 * cus, 1}, {4 * cus, 1}, {2 * cus, 0}};
+  for (int k = 0; k < kLaunchCandidates; ++k) {
+    c[k][0] = t[k][0];
+    c[k][1] = t[k][1];
+  }
+  return PMG_OK;
+}
+
+// reps calls of fn on `stream`, timed with events (ms for all of them)
+template <class F>
+int time_launches(hipStream_t stream, int reps, F fn, float* ms) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (!e) e = hipEventCreate(&e1);
+  if (!e) e = hipEventRecord(e0, stream);
+  int st = PMG_OK;
+  for (int r = 0; r < reps && !e && st == PMG_OK; ++r) st = fn();
+  if (!e) e = hipEventRecord(e1, stream);
+  if (!e) e = hipEventSynchronize(e1);
+  if (!e && ms) e = hipEventElapsedTime(ms, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (st != PMG_OK) return st;
+  if (e) return fail(PMG_ERR_HIP, "timing: %s", hipGetErrorString(e));
+  return PMG_OK;
+}
+
 // colours [c_begin, c_end) of a sweep (reversed for direction -1) on `stream`
 int smooth_on(pmg_handle* h, double* u, const double* b, int c_begin, int c_end, int direction,
               hipStream_t stream) {
@@ -1619,51 +1658,45 @@ int pmg_autotune(pmg_handle* h, const double* u, const double* b, float* best_ms
   if (!h || !u || !b) return fail(PMG_ERR_INVALID_ARG, "null argument");
   if (h->patch_geo) return fail(PMG_ERR_UNSUPPORTED, "independent patches have no sweep to tune");
   if (!h->bounds_valid) return fail(PMG_ERR_INVALID_ARG, "Chebyshev bounds not set");
-  int dev = 0, cus = 0;
-  HIP_TRY(hipGetDevice(&dev));
-  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  int cands[kLaunchCandidates][2];
+  PMG_TRY(launch_candidates(cands));
   // the largest colour, smoothed on a copy of u
   int cbig = 0;
   for (int c = 1; c < h->n_colors; ++c)
     if (h->color_off[c + 1] - h->color_off[c] > h->color_off[cbig + 1] - h->color_off[cbig]) cbig = c;
-  const int64_t M = (int64_t)h->N * h->p + 1;
-  const size_t n = (size_t)(h->dim == 3 ? M * M * M : M * M);
+  const size_t n = n_dofs(h);
   double* w = nullptr;
   int st;
   if ((st = dev_alloc(&w, n * sizeof(double), nullptr)) < 0) return st;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  hipError_t e = hipEventCreate(&e0);
-  if (e == hipSuccess) e = hipEventCreate(&e1);
-  if (e == hipSuccess) e = hipMemcpyAsync(w, u, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream);
-  const int cand[][2] = {{0, 0}, {0, 1}, {cus, 1}, {2 * cus, 1}, {4 * cus, 1}, {2 * cus, 0}};
-  float best = 1e30f;
-  int bg = 0, bm = 0;
-  st = PMG_OK;
-  for (const auto& cd : cand) {
-    if (e != hipSuccess || st != PMG_OK) break;
-    h->tune_grid = cd[0];
-    h->tune_map = cd[1];
-    if ((st = smooth_on(h, w, b, cbig, cbig + 1, 1, h->stream)) < 0) break;  // warm-up
-    e = hipEventRecord(e0, h->stream);
-    for (int r = 0; r < 5 && e == hipSuccess && st == PMG_OK; ++r) st = smooth_on(h, w, b, cbig, cbig + 1, 1, h->stream);
-    if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
-    if (e == hipSuccess) e = hipEventSynchronize(e1);
-    float ms = 0;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    if (e == hipSuccess && st == PMG_OK && ms / 5 < best) {
-      best = ms / 5;
-      bg = cd[0];
-      bm = cd[1];
-    }
+  hipError_t e = hipMemcpyAsync(w, u, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream);
+  if (e) {
+    (void)hipFree(w);
+    return fail(PMG_ERR_HIP, "autotune: %s", hipGetErrorString(e));
   }
-  h->tune_grid = bg;
-  h->tune_map = bm;
-  if (e0) (void)hipEventDestroy(e0);
-  if (e1) (void)hipEventDestroy(e1);
+  float best_t[kLaunchCandidates];
+  for (float& t : best_t) t = 1e30f;
+  auto run = [&]() { return smooth_on(h, w, b, cbig, cbig + 1, 1, h->stream); };
+  // warm-up at the default shape (clocks and caches), then two rounds over
+  // the candidates, keeping each one's best time
+  h->tune_grid = h->tune_map = 0;
+  st = time_launches(h->stream, 20, run, nullptr);
+  for (int round = 0; round < 2 && st == PMG_OK; ++round)
+    for (int k = 0; k < kLaunchCandidates && st == PMG_OK; ++k) {
+      h->tune_grid = cands[k][0];
+      h->tune_map = cands[k][1];
+      float ms = 0;
+      if ((st = time_launches(h->stream, 1, run, nullptr)) == PMG_OK &&
+          (st = time_launches(h->stream, 10, run, &ms)) == PMG_OK)
+        best_t[k] = std::min(best_t[k], ms / 10);
+    }
   (void)hipFree(w);
   if (st != PMG_OK) return st;
-  if (e != hipSuccess) return fail(PMG_ERR_HIP, "autotune: %s", hipGetErrorString(e));
-  if (best_ms) *best_ms = best;
+  int kb = 0;
+  for (int k = 1; k < kLaunchCandidates; ++k)
+    if (best_t[k] < best_t[kb]) kb = k;
+  h->tune_grid = cands[kb][0];
+  h->tune_map = cands[kb][1];
+  if (best_ms) *best_ms = best_t[kb];
   return PMG_OK;
 }
 
@@ -1857,8 +1890,52 @@ int pmg_batch_smooth(pmg_batch* b, double* const* u, const double* const* rhs, i
 
 int pmg_batch_autotune(pmg_batch* b, double* const* u, const double* const* rhs) {
   if (!b || !u || !rhs) return fail(PMG_ERR_INVALID_ARG, "null argument");
-  for (size_t i = 0; i < b->inst.size(); ++i) PMG_TRY(pmg_autotune(b->inst[i], u[i], rhs[i], nullptr));
   drop_graphs(b);  // launch shapes are baked into captured graphs
+  int cands[kLaunchCandidates][2];
+  PMG_TRY(launch_candidates(cands));
+  // whole-batch sweeps on copies of the vectors: the instances run
+  // concurrently, so each one's shape is chosen with the others running
+  const size_t k = b->inst.size();
+  std::vector<double*> w(k, nullptr);
+  int st = PMG_OK;
+  hipError_t e = hipSuccess;
+  for (size_t i = 0; i < k && st == PMG_OK && !e; ++i) {
+    const size_t n = n_dofs(b->inst[i]);
+    if ((st = dev_alloc(&w[i], n * sizeof(double), nullptr)) == PMG_OK)
+      e = hipMemcpyAsync(w[i], u[i], n * sizeof(double), hipMemcpyDeviceToDevice, b->stream);
+  }
+  // timed as used: graph replays (a fresh capture per candidate)
+  auto sweep = [&]() { return pmg_batch_smooth(b, w.data(), rhs, 1); };
+  for (pmg_handle* h : b->inst) h->tune_grid = h->tune_map = 0;
+  if (st == PMG_OK && !e) st = time_launches(b->stream, 3, sweep, nullptr);
+  // instances in order of decreasing work (degree), one coordinate at a time
+  std::vector<size_t> order(k);
+  for (size_t i = 0; i < k; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](size_t x, size_t y) { return b->inst[x]->p > b->inst[y]->p; });
+  for (size_t oi = 0; oi < k && st == PMG_OK && !e; ++oi) {
+    pmg_handle* h = b->inst[order[oi]];
+    float best = 1e30f;
+    int kb = 0;
+    for (int c = 0; c < kLaunchCandidates && st == PMG_OK; ++c) {
+      h->tune_grid = cands[c][0];
+      h->tune_map = cands[c][1];
+      drop_graphs(b);
+      float ms = 0;
+      if ((st = time_launches(b->stream, 1, sweep, nullptr)) == PMG_OK &&
+          (st = time_launches(b->stream, 4, sweep, &ms)) == PMG_OK && ms < best) {
+        best = ms;
+        kb = c;
+      }
+    }
+    h->tune_grid = cands[kb][0];
+    h->tune_map = cands[kb][1];
+  }
+  drop_graphs(b);  // bound to the copies
+  (void)hipStreamSynchronize(b->stream);
+  for (double* p : w)
+    if (p) (void)hipFree(p);
+  if (st != PMG_OK) return st;
+  if (e) return fail(PMG_ERR_HIP, "batch autotune: %s", hipGetErrorString(e));
   return PMG_OK;
 }
 

@@ -1961,9 +1961,11 @@ __device__ __forceinline__ int work_item(const PatchArgs& a, int b, int k, int G
   return i < n ? i : -1;
 }
 
-// Patch kernel: one workgroup per patch, or fewer workgroups that each take
-// several patches in turn (the grid and the mapping are launch parameters).
-template <typename T, int DIM, class LV, int MODE>
+// Patch kernel: one workgroup per patch (PERSIST false), or fewer workgroups
+// that each take several patches in turn (PERSIST true: a separate
+// instantiation, since the loop raises register use); the mapping is a
+// launch parameter.
+template <typename T, int DIM, class LV, int MODE, bool PERSIST>
 __global__ __launch_bounds__(NT<T>) void patch_kernel(PatchArgs a) {
   using Lay = Layout<T, DIM, LV>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1972,13 +1974,19 @@ __global__ __launch_bounds__(NT<T>) void patch_kernel(PatchArgs a) {
   c.vec = Lay::vec_in_lds ? c.lds + Lay::vec_off
                           : reinterpret_cast<T*>(a.vec_scratch) + (int64_t)blockIdx.x * a.vec_stride;
   c.gtab = tptr<T>(a.tab);
+  if constexpr (!PERSIST) {
+    const int i = work_item(a, blockIdx.x, 0, gridDim.x);
+    if (i < 0) return;
+    patch_update<T, DIM, LV, MODE>(a, c, a.patch_list ? a.patch_list[a.patch_begin + i] : a.patch_begin + i);
+  } else {
 #pragma unroll 1
-  for (int k = 0;; ++k) {
-    const int i = work_item(a, blockIdx.x, k, gridDim.x);
-    if (i < 0) break;
-    if (k > 0) __syncthreads();  // the previous patch is done with the LDS
-    const int patch = a.patch_list ? a.patch_list[a.patch_begin + i] : a.patch_begin + i;
-    patch_update<T, DIM, LV, MODE>(a, c, patch);
+    for (int k = 0;; ++k) {
+      const int i = work_item(a, blockIdx.x, k, gridDim.x);
+      if (i < 0) break;
+      if (k > 0) __syncthreads();  // the previous patch is done with the LDS
+      const int patch = a.patch_list ? a.patch_list[a.patch_begin + i] : a.patch_begin + i;
+      patch_update<T, DIM, LV, MODE>(a, c, patch);
+    }
   }
 }
 
@@ -2492,39 +2500,29 @@ struct Variant {
   using Lay = Layout<T, DIM, LV>;
   static size_t lds_bytes(int) { return (size_t)Lay::lds_elems * sizeof(T); }
   static int64_t vec_elems() { return Lay::vec_in_lds ? 0 : (int64_t)Lay::vec_total; }
+  template <int MODE, bool PERSIST>
+  static hipError_t go(const PatchArgs& a, int g, size_t lds, hipStream_t s) {
+    hipError_t e = allow_lds(patch_kernel<T, DIM, LV, MODE, PERSIST>, lds);
+    if (e) return e;
+    (void)hipGetLastError();  // clear a stale error of an earlier call
+    hipLaunchKernelGGL((patch_kernel<T, DIM, LV, MODE, PERSIST>), dim3(g), dim3(NT<T>), lds, s, a);
+    return report_launch(patch_kernel<T, DIM, LV, MODE, PERSIST>, "patch", dim3(g), lds, NT<T>);
+  }
   static hipError_t launch(int mode, const PatchArgs& a, hipStream_t s) {
     if (a.n_patch <= 0) return hipSuccess;
     const size_t lds = lds_bytes(mode);
-    int g = a.n_patch;
-    if (a.grid > 0 && a.grid < g) g = a.grid;
+    // persistent grids for smoothing only; other modes: one workgroup per patch
+    const bool persist = mode == kModeSmooth && a.grid > 0 && a.grid < a.n_patch;
+    int g = persist ? a.grid : a.n_patch;
     if (a.map_mode == 1) g = (g + 7) / 8 * 8;  // whole rounds over the 8 XCDs
-    dim3 grid(g), block(NT<T>);
-    hipError_t e = hipSuccess;
     switch (mode) {
       case kModeSmooth:
-        if ((e = allow_lds(patch_kernel<T, DIM, LV, kModeSmooth>, lds))) return e;
-        (void)hipGetLastError();  // clear a stale error of an earlier call
-        hipLaunchKernelGGL((patch_kernel<T, DIM, LV, kModeSmooth>), grid, block, lds, s, a);
-        return report_launch(patch_kernel<T, DIM, LV, kModeSmooth>, "patch", grid, lds, NT<T>);
-      case kModeResidual:
-        if ((e = allow_lds(patch_kernel<T, DIM, LV, kModeResidual>, lds))) return e;
-        (void)hipGetLastError();  // clear a stale error of an earlier call
-        hipLaunchKernelGGL((patch_kernel<T, DIM, LV, kModeResidual>), grid, block, lds, s, a);
-        return report_launch(patch_kernel<T, DIM, LV, kModeResidual>, "patch", grid, lds, NT<T>);
-      case kModeSolve:
-        if ((e = allow_lds(patch_kernel<T, DIM, LV, kModeSolve>, lds))) return e;
-        (void)hipGetLastError();  // clear a stale error of an earlier call
-        hipLaunchKernelGGL((patch_kernel<T, DIM, LV, kModeSolve>), grid, block, lds, s, a);
-        return report_launch(patch_kernel<T, DIM, LV, kModeSolve>, "patch", grid, lds, NT<T>);
-      case kModeApply:
-        if ((e = allow_lds(patch_kernel<T, DIM, LV, kModeApply>, lds))) return e;
-        (void)hipGetLastError();  // clear a stale error of an earlier call
-        hipLaunchKernelGGL((patch_kernel<T, DIM, LV, kModeApply>), grid, block, lds, s, a);
-        return report_launch(patch_kernel<T, DIM, LV, kModeApply>, "patch", grid, lds, NT<T>);
-      default:
-        return hipErrorInvalidValue;
+        return persist ? go<kModeSmooth, true>(a, g, lds, s) : go<kModeSmooth, false>(a, g, lds, s);
+      case kModeResidual: return go<kModeResidual, false>(a, g, lds, s);
+      case kModeSolve: return go<kModeSolve, false>(a, g, lds, s);
+      case kModeApply: return go<kModeApply, false>(a, g, lds, s);
+      default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
   }
   static hipError_t launch_diag(const PatchArgs& a, hipStream_t s) {
     using L64 = Layout<double, DIM, LV>;
