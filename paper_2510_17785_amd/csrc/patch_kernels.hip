@@ -185,19 +185,38 @@ struct Layout {
   static constexpr int npts(int l) {
     return (l > 0 && (l == L - 1 || dense_level(l))) ? 0 : ipow(2 * (LV::q[l] + 1), DIM);
   }
+  static constexpr int G_all = [] {
+    int o = 0;
+    for (int i = 0; i < L; ++i) o += NG * npts(i);
+    return o;
+  }();
+  // LDS budgets: 80 KB keeps two workgroups per CU; the slab-form degrees
+  // (6 and up in 3D) hold one workgroup per CU by their registers anyway, so
+  // they may use nearly all of the 160 KB for the top level's metric
+  static constexpr int kBudget = 80 * 1024, kBudgetOne = 159 * 1024;
+  static constexpr int sz = (int)sizeof(T);
+  static constexpr bool all_fit = (base_total + G_all + vec_total) * sz <= kBudget;
+  static constexpr bool one_wg = DIM == 3 && !seg_top;
+  static constexpr int G_top = NG * ipow(2 * (LV::q[0] + 1), DIM);
+  static constexpr bool top_vec_fit = !all_fit && one_wg && (base_total + G_top + vec_total) * sz <= kBudgetOne;
+  static constexpr bool top_fit = !all_fit && one_wg && (base_total + G_top) * sz <= kBudgetOne;
+  // the metric of level l is kept in LDS (else recomputed at every Gauss point)
+  static constexpr bool cache_level(int l) {
+    return npts(l) > 0 && (all_fit || ((top_vec_fit || top_fit) && l == 0));
+  }
   static constexpr int G_rel(int l) {
     int o = 0;
-    for (int i = 0; i < l; ++i) o += NG * npts(i);
+    for (int i = 0; i < l; ++i) o += cache_level(i) ? NG * npts(i) : 0;
     return o;
   }
   static constexpr int G_total = G_rel(L);
-  static constexpr int kBudget = 80 * 1024;
-  // keep the metric in LDS when everything fits the budget; else keep the
-  // vectors in LDS if they fit; else vectors go to global scratch
-  static constexpr bool cache_G = (base_total + G_total + vec_total) * (int)sizeof(T) <= kBudget;
-  static constexpr bool vec_in_lds = cache_G || (base_total + vec_total) * (int)sizeof(T) <= kBudget;
+  static constexpr bool cache_G = G_total > 0;
+  // level vectors in LDS when they fit next to the cached metric, or, with
+  // no metric cached, within the two-workgroup budget; else global scratch
+  static constexpr bool vec_in_lds =
+      all_fit || top_vec_fit || (!cache_G && (base_total + vec_total) * sz <= kBudget);
   static constexpr int G_off = base_total;
-  static constexpr int vec_off = base_total + (cache_G ? G_total : 0);
+  static constexpr int vec_off = base_total + G_total;
   static constexpr int dense_off = round_up(vec_off + (vec_in_lds ? vec_total : 0), 4);
   static constexpr int lds_elems = dense_off + dense_total;
 };
@@ -421,16 +440,17 @@ struct Ctx {
 // ---------------------------------------------------------------------------
 
 template <typename T, int Q, bool CACHE>
-__device__ __noinline__ void apply3(const T* __restrict__ X, T* __restrict__ Out, T* __restrict__ ab,
-                       const T* __restrict__ Bt, const T* __restrict__ Dc, const T* __restrict__ xg,
-                       const T* __restrict__ wg, const T* __restrict__ jc, const T* __restrict__ mu,
-                       const T* __restrict__ Gc) {
+__device__ __noinline__ void apply3(const LDSP T* __restrict__ X, LDSP T* __restrict__ Out,
+                                    LDSP T* __restrict__ ab, const LDSP T* __restrict__ Bt,
+                                    const LDSP T* __restrict__ Dc, const LDSP T* __restrict__ xg,
+                                    const LDSP T* __restrict__ wg, const LDSP T* __restrict__ jc,
+                                    const LDSP T* __restrict__ mu, const LDSP T* __restrict__ Gc) {
   using SH = Sh<3, Q>;
   constexpr int n = SH::n, m = SH::m, mi = SH::mi, NQ = SH::NQ, S = SH::S;
-  T* A = ab;
-  T* Bf = ab + S;
-  T* C = ab + 2 * S;
-  T* Dd = ab + 3 * S;
+  LDSP T* A = ab;
+  LDSP T* Bf = ab + S;
+  LDSP T* C = ab + 2 * S;
+  LDSP T* Dd = ab + 3 * S;
   const int tid = threadIdx.x;
 #pragma unroll 1
   for (int cz = 0; cz < 2; ++cz) {
@@ -439,8 +459,8 @@ __device__ __noinline__ void apply3(const T* __restrict__ X, T* __restrict__ Out
     for (int idx = tid; idx < n * m * NQ; idx += NT<T>) {
       const int QX = idx % NQ, t = idx / NQ, y = t % m, zl = t / m;
       const int cx = QX >= n, kx = QX - cx * n;
-      const T* xr = X + ((cz * Q + zl) * m + y) * m + cx * Q;
-      const T* br = Bt + kx * n;
+      const LDSP T* xr = X + ((cz * Q + zl) * m + y) * m + cx * Q;
+      const LDSP T* br = Bt + kx * n;
       T acc = 0;
 #pragma unroll
       for (int a = 0; a < n; ++a) acc += br[a] * xr[a];
@@ -452,8 +472,8 @@ __device__ __noinline__ void apply3(const T* __restrict__ X, T* __restrict__ Out
     for (int idx = tid; idx < S; idx += NT<T>) {
       const int QX = idx % NQ, t = idx / NQ, QY = t % NQ, zl = t / NQ;
       const int cy = QY >= n, ky = QY - cy * n;
-      const T* ar = A + (zl * m + cy * Q) * NQ + QX;
-      const T* br = Bt + ky * n;
+      const LDSP T* ar = A + (zl * m + cy * Q) * NQ + QX;
+      const LDSP T* br = Bt + ky * n;
       T acc = 0;
 #pragma unroll
       for (int a = 0; a < n; ++a) acc += br[a] * ar[a * NQ];
@@ -464,7 +484,7 @@ __device__ __noinline__ void apply3(const T* __restrict__ X, T* __restrict__ Out
 #pragma unroll 1
     for (int idx = tid; idx < S; idx += NT<T>) {
       const int kz = idx / (NQ * NQ), rem = idx % (NQ * NQ);
-      const T* br = Bt + kz * n;
+      const LDSP T* br = Bt + kz * n;
       T acc = 0;
 #pragma unroll
       for (int a = 0; a < n; ++a) acc += br[a] * Bf[a * NQ * NQ + rem];
@@ -476,12 +496,12 @@ __device__ __noinline__ void apply3(const T* __restrict__ X, T* __restrict__ Out
     for (int idx = tid; idx < S; idx += NT<T>) {
       const int QX = idx % NQ, t = idx / NQ, QY = t % NQ, kz = t / NQ;
       const int cx = QX >= n, kx = QX - cx * n, cy = QY >= n, ky = QY - cy * n;
-      const T* dx = Dc + kx * n;
-      const T* dy = Dc + ky * n;
-      const T* dz = Dc + kz * n;
-      const T* cxr = C + (kz * NQ + QY) * NQ + cx * n;
-      const T* cyr = C + (kz * NQ + cy * n) * NQ + QX;
-      const T* czr = C + QY * NQ + QX;
+      const LDSP T* dx = Dc + kx * n;
+      const LDSP T* dy = Dc + ky * n;
+      const LDSP T* dz = Dc + kz * n;
+      const LDSP T* cxr = C + (kz * NQ + QY) * NQ + cx * n;
+      const LDSP T* cyr = C + (kz * NQ + cy * n) * NQ + QX;
+      const LDSP T* czr = C + QY * NQ + QX;
       T gx = 0, gy = 0, gz = 0;
 #pragma unroll
       for (int a = 0; a < n; ++a) {
@@ -508,9 +528,9 @@ __device__ __noinline__ void apply3(const T* __restrict__ X, T* __restrict__ Out
     for (int idx = tid; idx < S; idx += NT<T>) {
       const int QX = idx % NQ, t = idx / NQ, QY = t % NQ, kz = t / NQ;
       const int cx = QX >= n, kx = QX - cx * n, cy = QY >= n, ky = QY - cy * n;
-      const T* fx = A + (kz * NQ + QY) * NQ + cx * n;
-      const T* fy = Bf + (kz * NQ + cy * n) * NQ + QX;
-      const T* fz = Dd + QY * NQ + QX;
+      const LDSP T* fx = A + (kz * NQ + QY) * NQ + cx * n;
+      const LDSP T* fy = Bf + (kz * NQ + cy * n) * NQ + QX;
+      const LDSP T* fz = Dd + QY * NQ + QX;
       T acc = 0;
 #pragma unroll
       for (int a = 0; a < n; ++a) {
@@ -538,12 +558,12 @@ __device__ __noinline__ void apply3(const T* __restrict__ X, T* __restrict__ Out
       const int y = yi + 1;
       T acc = 0;
       if (y <= Q) {
-        const T* ar = A + (zl * NQ) * NQ + QX;
+        const LDSP T* ar = A + (zl * NQ) * NQ + QX;
 #pragma unroll
         for (int k = 0; k < n; ++k) acc += Bt[k * n + y] * ar[k * NQ];
       }
       if (y >= Q) {
-        const T* ar = A + (zl * NQ + n) * NQ + QX;
+        const LDSP T* ar = A + (zl * NQ + n) * NQ + QX;
 #pragma unroll
         for (int k = 0; k < n; ++k) acc += Bt[k * n + (y - Q)] * ar[k * NQ];
       }
@@ -557,7 +577,7 @@ __device__ __noinline__ void apply3(const T* __restrict__ X, T* __restrict__ Out
     for (int idx = tid; idx < nz * mi * mi; idx += NT<T>) {
       const int xi = idx % mi, t = idx / mi, yi = t % mi, zl = zl0 + t / mi;
       const int x = xi + 1;
-      const T* br = Bf + (zl * mi + yi) * NQ;
+      const LDSP T* br = Bf + (zl * mi + yi) * NQ;
       T acc = 0;
       if (x <= Q) {
 #pragma unroll
@@ -568,7 +588,7 @@ __device__ __noinline__ void apply3(const T* __restrict__ X, T* __restrict__ Out
         for (int k = 0; k < n; ++k) acc += Bt[k * n + (x - Q)] * br[n + k];
       }
       const int zz = cz * Q + zl - 1;
-      T* o = Out + (zz * mi + yi) * mi + xi;
+      LDSP T* o = Out + (zz * mi + yi) * mi + xi;
       if (cz == 1 && zl == 0)
         *o += acc;
       else
@@ -1307,7 +1327,7 @@ __device__ __noinline__ void apply2(const T* __restrict__ X, T* __restrict__ Out
 template <typename T, int DIM, class LV, int L>
 __device__ __forceinline__ void apply_level(const Ctx<T, DIM, LV>& c) {
   constexpr int Q = LV::q[L];
-  constexpr bool CACHE = Layout<T, DIM, LV>::cache_G && Layout<T, DIM, LV>::npts(L) > 0;
+  constexpr bool CACHE = Layout<T, DIM, LV>::cache_level(L);
   if constexpr (Layout<T, DIM, LV>::use_seg(L))
     apply3seg<T, Q, true, CACHE>(lds_cast(c.X()), EpiStore<T, LDSP T*>{lds_cast(c.Out())},
                                  lds_cast(c.abuf()), lds_cast(c.tabB(L)), lds_cast(c.tabDc(L)),
@@ -1329,8 +1349,9 @@ __device__ __forceinline__ void apply_level(const Ctx<T, DIM, LV>& c) {
   } else if constexpr (DIM == 3) {
     static_assert(4 * Sh<3, Q>::S <= Layout<T, DIM, LV>::abuf_elems,
                   "slab buffers exceed the work area");
-    apply3<T, Q, CACHE>(c.X(), c.Out(), c.abuf(), c.tabB(L), c.tabDc(L), c.tabXg(L), c.tabWg(L),
-                        c.jc(), c.mu(), c.Gc(L));
+    apply3<T, Q, CACHE>(lds_cast(c.X()), lds_cast(c.Out()), lds_cast(c.abuf()), lds_cast(c.tabB(L)),
+                        lds_cast(c.tabDc(L)), lds_cast(c.tabXg(L)), lds_cast(c.tabWg(L)),
+                        lds_cast(c.jc()), lds_cast(c.mu()), lds_cast(c.Gc(L)));
   }
   else
     apply2<T, Q, CACHE>(c.X(), c.Out(), c.abuf(), c.tabB(L), c.tabDc(L), c.tabXg(L), c.tabWg(L),
@@ -1347,7 +1368,7 @@ __device__ void prepare_geometry(const Ctx<T, DIM, LV>& c) {
   if constexpr (Lay::cache_G) {
     for (int l = 0; l < LV::count; ++l) {
       const int n = LV::q[l] + 1, NQ = 2 * n;
-      const int NP = Lay::npts(l);  // 0: this level is never applied matrix-free with the cache
+      const int NP = Lay::cache_level(l) ? Lay::npts(l) : 0;  // 0: not cached
       const T* xg = c.tabXg(l);
       const T* wg = c.tabWg(l);
       T* Gl = c.Gc(l);
@@ -1420,7 +1441,7 @@ __device__ __forceinline__ void apply_vec_epi(const Ctx<T, DIM, LV>& c, const T*
     }
   }
   if constexpr (Lay::use_seg(L) && Lay::vec_in_lds) {
-    apply3seg<T, Q, false, (Lay::cache_G && Lay::npts(L) > 0)>(lds_cast(v), epi, lds_cast(c.abuf()), lds_cast(c.tabB(L)),
+    apply3seg<T, Q, false, Lay::cache_level(L)>(lds_cast(v), epi, lds_cast(c.abuf()), lds_cast(c.tabB(L)),
                                          lds_cast(c.tabDc(L)), lds_cast(c.jc()), lds_cast(c.mu()),
                                          lds_cast(c.Gc(L)));
   } else {
