@@ -286,8 +286,12 @@ def main(argv=None):
     ap.add_argument("--no-cg", action="store_true", help="skip the outer CG iteration check")
     ap.add_argument("--no-tune", action="store_true",
                     help="time the default launch shape (one workgroup per patch)")
-    ap.add_argument("--train-patches", type=int, default=6000,
-                    help="random patches whose Lanczos bounds train the bound network")
+    ap.add_argument("--launch", action="append", default=[],
+                    help="PREC:GRID:MAP, a fixed launch shape instead of the autotuner's "
+                         "(for profiler runs that must launch what a tuned run timed)")
+    ap.add_argument("--train-patches", type=int, default=None,
+                    help="random patches whose Lanczos bounds train the bound network "
+                         "(default 100000 for the 32^3 Q6 learned-bounds workload, else 6000)")
     ap.add_argument("--train-epochs", type=int, default=30)
     ap.add_argument("--only", choices=["fp32", "fp64"], default=None,
                     help="time one precision only (for profiler runs; prints no JSON line)")
@@ -320,6 +324,8 @@ def main(argv=None):
     w = synth.workload(args.workload)
     if w.name == "3d-n24-q8-batch":
         return bench_batch(args, w)
+    if args.train_patches is None:
+        args.train_patches = 100000 if w.name == "3d-n32-q6-learned" else 6000
     X = synth.make_vertices(w.dim, w.n, w.alpha, w.mesh_seed)
     mu = synth.make_coefficients(w.dim, w.n, w.mu_log10, w.coef_seed)
     bh = synth.make_rhs(w.dim, w.n, w.p, w.rhs_seed)
@@ -357,7 +363,10 @@ def main(argv=None):
         torch.cuda.synchronize()
         setup_s = time.perf_counter() - t0
         u = torch.zeros_like(b)
-        if not args.no_tune:
+        fixed = [x.split(":") for x in args.launch if x.split(":")[0] == prec]
+        if fixed:
+            S.set_launch(int(fixed[0][1]), int(fixed[0][2]))
+        elif not args.no_tune:
             S.autotune(u, b)
         sweep_ms, per_launch, wall = time_sweeps(S, u, b, args.steps, args.warmup, torch)
         res[prec] = dict(S=S, setup_s=setup_s, sweep_ms=sweep_ms, per_launch=per_launch,
@@ -374,14 +383,22 @@ def main(argv=None):
                        ("fp32_lanczos", "fp32", "lanczos")]
         if has_bf16(w):
             cg_variants += [("bf16_learned", "bf16", "learned"), ("bf16x3_learned", "bf16x3", "learned")]
+        # one interval for every patch and level: the envelope of the Lanczos bounds
+        cg_variants += [("fp32_fixed", "fp32", "fixed")]
         for key, prec, bsrc in cg_variants:
             t0 = time.perf_counter()
             G = GMGSolver(w.dim, w.n, w.p, X, mu, levels=w.levels, precision=prec,
-                          bounds="fixed" if bsrc == "learned" else "lanczos")
+                          bounds="lanczos" if bsrc in ("lanczos", "fixed") else "fixed")
             nfb = 0
             if bsrc == "learned":
                 for l in range(1, G.n_mesh_levels):
                     nfb += learned(G.smoother(l))
+            elif bsrc == "fixed":
+                for l in range(1, G.n_mesh_levels):
+                    S_l = G.smoother(l)
+                    lam = S_l.bounds()
+                    env = np.array([lam[..., 0].min(), lam[..., 1].max()])
+                    S_l.set_bounds(np.broadcast_to(env, lam.shape).copy())
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             x, it, rel = G.cg(b, rtol=w.rtol)
@@ -445,7 +462,9 @@ def main(argv=None):
             "unit": "TFLOP/s",
             "frac": achieved / VALU_PEAK_TFLOPS,
             "traffic": measured_traffic(w.name),
-            "kernel": f"patch_kernel<float,{w.dim},Levels<{','.join(map(str, w.levels))}>,smooth>",
+            "kernel": f"patch_kernel<float,{w.dim},Levels<{','.join(map(str, w.levels))}>,smooth,"
+                      f"{'persistent' if 0 < r32['launch'][0] < max(r32['S'].color_offsets[c + 1] - r32['S'].color_offsets[c] for c in range(r32['S'].n_colors)) else 'one workgroup per patch'}>",
+            "launch_shape": r32["launch"],
             "algorithmic_flops_per_patch": F,
             "algorithmic_bytes_per_patch": B,
             "patches_per_launch": patches_per_launch,
