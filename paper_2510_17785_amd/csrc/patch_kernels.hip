@@ -1865,11 +1865,50 @@ __device__ __forceinline__ void patch_update(const PatchArgs& a, Ctx<T, DIM, LV>
     constexpr int nbox = ipow(2 * qc - 1, DIM - 1) * (qc - 1);
     if (k >= 0) c.trunc = a.trunc_inv + (int64_t)k * nbox * nbox;
   }
-  load_patch<T, DIM, LV>(c, a, patch);
-  c.dense_ok = true;
-  prepare_geometry<T, DIM, LV>(c);
   constexpr int N0 = S0::interior;
   constexpr int m = S0::m, mi = S0::mi;
+  T* r0 = c.r(0);
+  int base = 0, M = 0;
+  if constexpr (MODE == kModeSmooth || MODE == kModeResidual) {
+    // gather u-bar_j (closure) and b_j (interior), equation gather; issued
+    // first so that its global loads overlap those of the patch data
+    patch_base<DIM>(a.patch_vertex[patch], a.N, a.p, base, M);
+    T* X = c.X();
+    if (pf == 0) {
+#pragma unroll 1
+      for (int idx = tid; idx < S0::closure; idx += NT<T>) {
+        const int x = idx % m, t = idx / m, y = t % m, z = DIM == 3 ? t / m : 0;
+        X[idx] = T(a.u[base + x + y * M + (int64_t)z * M * M]);
+      }
+#pragma unroll 1
+      for (int idx = tid; idx < N0; idx += NT<T>) {
+        const int x = idx % mi + 1, t = idx / mi, y = t % mi + 1, z = DIM == 3 ? t / mi + 1 : 0;
+        r0[idx] = T(a.b[base + x + y * M + (int64_t)z * M * M]);
+      }
+    } else {
+      // boundary-vertex patch: closure nodes outside the mesh read as zero
+      const int N1 = a.N + 1, vlin = a.patch_vertex[patch];
+      const int g0[3] = {(vlin % N1 - 1) * a.p, ((vlin / N1) % N1 - 1) * a.p,
+                         DIM == 3 ? (vlin / (N1 * N1) - 1) * a.p : 0};
+#pragma unroll 1
+      for (int idx = tid; idx < S0::closure; idx += NT<T>) {
+        const int x = idx % m, t = idx / m, y = t % m, z = DIM == 3 ? t / m : 0;
+        const bool in = g0[0] + x >= 0 && g0[0] + x < M && g0[1] + y >= 0 && g0[1] + y < M &&
+                        (DIM == 2 || (g0[2] + z >= 0 && g0[2] + z < M));
+        X[idx] = in ? T(a.u[base + x + y * M + (int64_t)z * M * M]) : T(0);
+      }
+#pragma unroll 1
+      for (int idx = tid; idx < N0; idx += NT<T>) {
+        const int x = idx % mi + 1, t = idx / mi, y = t % mi + 1, z = DIM == 3 ? t / mi + 1 : 0;
+        r0[idx] = interior_node<DIM>(pf, a.p, idx, nullptr)
+                      ? T(a.b[base + x + y * M + (int64_t)z * M * M])
+                      : T(0);
+      }
+    }
+  }
+  load_patch<T, DIM, LV>(c, a, patch);  // ends with a barrier: the gather is in place too
+  c.dense_ok = true;
+  prepare_geometry<T, DIM, LV>(c);
 
   if constexpr (MODE == kModeApply) {
     // y = A_{j,q} x for the requested level
@@ -1893,44 +1932,7 @@ __device__ __forceinline__ void patch_update(const PatchArgs& a, Ctx<T, DIM, LV>
       if (a.level == 3) run(std::integral_constant<int, 3>{});
     return;
   } else {
-    T* r0 = c.r(0);
-    int base = 0, M = 0;
     if constexpr (MODE == kModeSmooth || MODE == kModeResidual) {
-      // gather u-bar_j (closure) and b_j (interior): equation gather
-      patch_base<DIM>(a.patch_vertex[patch], a.N, a.p, base, M);
-      T* X = c.X();
-      if (pf == 0) {
-  #pragma unroll 1
-        for (int idx = tid; idx < S0::closure; idx += NT<T>) {
-          const int x = idx % m, t = idx / m, y = t % m, z = DIM == 3 ? t / m : 0;
-          X[idx] = T(a.u[base + x + y * M + (int64_t)z * M * M]);
-        }
-  #pragma unroll 1
-        for (int idx = tid; idx < N0; idx += NT<T>) {
-          const int x = idx % mi + 1, t = idx / mi, y = t % mi + 1, z = DIM == 3 ? t / mi + 1 : 0;
-          r0[idx] = T(a.b[base + x + y * M + (int64_t)z * M * M]);
-        }
-      } else {
-        // boundary-vertex patch: closure nodes outside the mesh read as zero
-        const int N1 = a.N + 1, vlin = a.patch_vertex[patch];
-        const int g0[3] = {(vlin % N1 - 1) * a.p, ((vlin / N1) % N1 - 1) * a.p,
-                           DIM == 3 ? (vlin / (N1 * N1) - 1) * a.p : 0};
-  #pragma unroll 1
-        for (int idx = tid; idx < S0::closure; idx += NT<T>) {
-          const int x = idx % m, t = idx / m, y = t % m, z = DIM == 3 ? t / m : 0;
-          const bool in = g0[0] + x >= 0 && g0[0] + x < M && g0[1] + y >= 0 && g0[1] + y < M &&
-                          (DIM == 2 || (g0[2] + z >= 0 && g0[2] + z < M));
-          X[idx] = in ? T(a.u[base + x + y * M + (int64_t)z * M * M]) : T(0);
-        }
-  #pragma unroll 1
-        for (int idx = tid; idx < N0; idx += NT<T>) {
-          const int x = idx % mi + 1, t = idx / mi, y = t % mi + 1, z = DIM == 3 ? t / mi + 1 : 0;
-          r0[idx] = interior_node<DIM>(pf, a.p, idx, nullptr)
-                        ? T(a.b[base + x + y * M + (int64_t)z * M * M])
-                        : T(0);
-        }
-      }
-      __syncthreads();
       // evaluate: r_j = b_j - Pi_j A-bar_j u-bar_j (equation main:4); masked
       // rows (boundary-vertex patches) are set to zero
       apply_level<T, DIM, LV, 0>(c);
