@@ -305,6 +305,16 @@ int pmg_mlp_gradient(pmg_mlp* m, const float* X, const float* T, int64_t n, floa
 int pmg_mlp_train(pmg_mlp* m, const float* X, const float* T, int64_t n, const int32_t* order,
                   int32_t epochs, int32_t batch, float lr, double* epoch_loss);
 int pmg_mlp_destroy(pmg_mlp* m);
+/* Save a network to a file: the 8 bytes "PMGMLP1" and a zero, int32 n_in,
+ * int32 n_out, double margin (the caller's lambda_max margin, stored for
+ * pmg_set_bounds_mlp), the parameters (param_count floats), the input mean
+ * and 1/std (n_in floats each); little-endian.  Synchronises the network's
+ * stream. */
+int pmg_mlp_save(const pmg_mlp* m, double margin, const char* path);
+/* Load a saved network (checked: magic, sizes, file length) on `stream`;
+ * margin (host, may be NULL) receives the stored margin.  A malformed file
+ * returns PMG_ERR_INVALID_ARG before any device work. */
+int pmg_mlp_load(const char* path, int64_t max_batch, void* stream, pmg_mlp** out, double* margin);
 
 /* Chebyshev bounds from the network: features of every patch, prediction of
  * (ln lambda_min, ln lambda_max) per smoothed level, lambda_max raised by the

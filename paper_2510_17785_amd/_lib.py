@@ -54,7 +54,7 @@ EXPORTS = [
     "pmg_mlp_set_standardizer", "pmg_mlp_predict", "pmg_mlp_gradient", "pmg_mlp_train",
     "pmg_mlp_destroy", "pmg_set_bounds_mlp", "pmg_set_launch", "pmg_autotune",
     "pmg_batch_setup", "pmg_batch_instance", "pmg_batch_smooth", "pmg_batch_smooth_eager",
-    "pmg_batch_autotune", "pmg_batch_query", "pmg_batch_destroy",
+    "pmg_batch_autotune", "pmg_batch_query", "pmg_batch_destroy", "pmg_mlp_save", "pmg_mlp_load",
 ]
 
 
@@ -144,6 +144,9 @@ def load() -> ctypes.CDLL:
         "pmg_batch_autotune": [P, ctypes.POINTER(P), ctypes.POINTER(P)],
         "pmg_batch_query": [P, i32, ctypes.POINTER(ctypes.c_int64)],
         "pmg_batch_destroy": [P],
+        "pmg_mlp_save": [P, ctypes.c_double, ctypes.c_char_p],
+        "pmg_mlp_load": [ctypes.c_char_p, ctypes.c_int64, P, ctypes.POINTER(P),
+                         ctypes.POINTER(ctypes.c_double)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)

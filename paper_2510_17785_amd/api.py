@@ -253,6 +253,30 @@ class BoundNet:
                                          _stream_handle(stream), ctypes.byref(h)))
         self._h = h
 
+    def save(self, path: str, margin: float = 0.0) -> None:
+        """pmg_mlp_save: parameters, standardiser and the lambda_max margin."""
+        L.check(self._lib.pmg_mlp_save(self._h, float(margin), str(path).encode()))
+
+    @classmethod
+    def load(cls, path: str, max_batch: int = 4096, stream=None):
+        """pmg_mlp_load; returns (network, margin)."""
+        lib = L.load()
+        h = ctypes.c_void_p()
+        margin = ctypes.c_double()
+        L.check(lib.pmg_mlp_load(str(path).encode(), int(max_batch), _stream_handle(stream),
+                                 ctypes.byref(h), ctypes.byref(margin)))
+        net = cls.__new__(cls)
+        net._lib = lib
+        net._h = h
+        # sizes from the file header
+        with open(path, "rb") as f:
+            f.read(8)
+            net.n_in, net.n_out = (int(x) for x in np.frombuffer(f.read(8), dtype="<i4"))
+        cnt = ctypes.c_int64()
+        L.check(lib.pmg_mlp_param_count(net.n_in, net.n_out, ctypes.byref(cnt)))
+        net.n_params = cnt.value
+        return net, margin.value
+
     def params(self) -> np.ndarray:
         out = np.zeros(self.n_params, dtype=np.float32)
         L.check(self._lib.pmg_mlp_get_params(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))

@@ -1599,6 +1599,60 @@ int pmg_mlp_destroy(pmg_mlp* mm) {
   return PMG_OK;
 }
 
+int pmg_mlp_save(const pmg_mlp* mm, double margin, const char* path) {
+  const MlpNet* m = reinterpret_cast<const MlpNet*>(mm);
+  if (!m || !path) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  const size_t P = (size_t)mlp_param_count(m->n_in, m->n_out);
+  std::vector<float> theta(P), mean(m->n_in), inv(m->n_in);
+  PMG_TRY(pmg_mlp_get_params(mm, theta.data()));
+  PMG_TRY(pmg_mlp_get_standardizer(mm, mean.data(), inv.data()));
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(PMG_ERR_INVALID_ARG, "cannot open %s for writing", path);
+  const char magic[8] = {'P', 'M', 'G', 'M', 'L', 'P', '1', 0};
+  const int32_t dims[2] = {m->n_in, m->n_out};
+  bool ok = std::fwrite(magic, 1, 8, f) == 8 && std::fwrite(dims, 4, 2, f) == 2 &&
+            std::fwrite(&margin, 8, 1, f) == 1 && std::fwrite(theta.data(), 4, P, f) == P &&
+            std::fwrite(mean.data(), 4, m->n_in, f) == (size_t)m->n_in &&
+            std::fwrite(inv.data(), 4, m->n_in, f) == (size_t)m->n_in;
+  ok = (std::fclose(f) == 0) && ok;
+  return ok ? PMG_OK : fail(PMG_ERR_INVALID_ARG, "write to %s failed", path);
+}
+
+int pmg_mlp_load(const char* path, int64_t max_batch, void* stream, pmg_mlp** out, double* margin) {
+  if (!path || !out) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(PMG_ERR_INVALID_ARG, "cannot open %s", path);
+  char magic[8] = {0};
+  int32_t dims[2] = {0, 0};
+  double mg = 0;
+  bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "PMGMLP1", 8) == 0 &&
+            std::fread(dims, 4, 2, f) == 2 && dims[0] >= 1 && dims[0] <= 4096 && dims[1] >= 1 &&
+            dims[1] <= 64 && std::fread(&mg, 8, 1, f) == 1;
+  std::vector<float> theta, mean, inv;
+  if (ok) {
+    const size_t P = (size_t)mlp_param_count(dims[0], dims[1]);
+    theta.resize(P);
+    mean.resize(dims[0]);
+    inv.resize(dims[0]);
+    char extra;
+    ok = std::fread(theta.data(), 4, P, f) == P && std::fread(mean.data(), 4, dims[0], f) == (size_t)dims[0] &&
+         std::fread(inv.data(), 4, dims[0], f) == (size_t)dims[0] && std::fread(&extra, 1, 1, f) == 0;
+  }
+  std::fclose(f);
+  if (!ok) return fail(PMG_ERR_INVALID_ARG, "%s is not a saved network (magic, sizes or length)", path);
+  pmg_mlp* m = nullptr;
+  PMG_TRY(pmg_mlp_create(dims[0], dims[1], theta.data(), max_batch, stream, &m));
+  const int st = pmg_mlp_set_standardizer(m, mean.data(), inv.data());
+  if (st < 0) {
+    pmg_mlp_destroy(m);
+    return st;
+  }
+  if (margin) *margin = mg;
+  *out = m;
+  return PMG_OK;
+}
+
 int pmg_set_bounds_mlp(pmg_handle* h, pmg_mlp* mm, double margin, double ood_z, int64_t* n_fallback) {
   MlpNet* m = reinterpret_cast<MlpNet*>(mm);
   if (!h || !m) return fail(PMG_ERR_INVALID_ARG, "null argument");

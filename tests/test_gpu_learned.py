@@ -170,3 +170,17 @@ def test_learned_bounds_gain(dev):
           f"CG iterations: Lanczos {it_l}, learned {it_m}, fixed {it_f}")
     assert it_m <= it_l + 1
     assert it_m <= it_f
+
+
+def test_network_save_load_round_trip(dev, tmp_path):
+    from paper_2510_17785_amd import BoundNet
+    theta, X, T = _net_case(n=64, n_in=52, n_out=4, seed=9)
+    net = BoundNet(52, 4, theta.astype(np.float32), max_batch=128)
+    Xd = torch.tensor(X, dtype=torch.float32, device=dev)
+    net.fit_standardizer(Xd)
+    path = tmp_path / "net.bin"
+    net.save(path, margin=0.125)
+    net2, margin = BoundNet.load(path, max_batch=128)
+    assert margin == 0.125 and net2.n_in == 52 and net2.n_out == 4
+    assert np.array_equal(net2.params(), net.params())
+    assert torch.equal(net2.predict(Xd), net.predict(Xd))

@@ -66,3 +66,19 @@ def test_bad_scalars():
     assert _setup(3, 4, 4, X, (4, 2, 1), cheb_degree=0)[0] == L.PMG_ERR_INVALID_ARG
     assert _setup(3, 4, 4, X, (4, 2, 1), lanczos_steps=1)[0] == L.PMG_ERR_INVALID_ARG
     assert _setup(3, 4, 4, X, (4, 2, 1), n_vcycles=0)[0] == L.PMG_ERR_INVALID_ARG
+
+
+def test_network_file_rejected_before_device_work(tmp_path):
+    # a malformed network file is refused while parsing, with no GPU needed
+    from paper_2510_17785_amd import _lib as L
+    lib = L.load()
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(b"PMGMLP1\x00" + np.array([200, 4], dtype="<i4").tobytes() + b"\x00" * 20)
+    h = ctypes.c_void_p()
+    mg = ctypes.c_double()
+    for path in (bad, tmp_path / "missing.bin"):
+        st = lib.pmg_mlp_load(str(path).encode(), 64, None, ctypes.byref(h), ctypes.byref(mg))
+        assert st == L.PMG_ERR_INVALID_ARG and h.value is None
+    wrong = tmp_path / "wrong.bin"
+    wrong.write_bytes(b"NOTANET\x00" + b"\x00" * 64)
+    assert lib.pmg_mlp_load(str(wrong).encode(), 64, None, ctypes.byref(h), ctypes.byref(mg)) == L.PMG_ERR_INVALID_ARG
