@@ -29,7 +29,7 @@ if ROOT not in sys.path:
 # Peak figures of MI355X used for the roofline fraction.
 HBM_PEAK_GBS = 8000.0
 # FP32 / FP64 FMA on the vector ALUs without packed FP32 (packed FP32 is
-# disabled in this build): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz.
+# disabled in these kernels): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz.
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 
@@ -311,7 +311,7 @@ def main(argv=None):
         return 0
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the smoother is measured on one MI355X "
-              "(a multi-GPU run would need a halo exchange per colour, which this build "
+              "(a multi-GPU run would need a halo exchange per colour, which this library "
               "does not have)", file=sys.stderr)
         return 2
 

@@ -46,7 +46,7 @@ extern "C" {
 /* status codes */
 #define PMG_OK 0
 #define PMG_ERR_INVALID_ARG (-1)  /* null pointer, bad size, bad level list */
-#define PMG_ERR_UNSUPPORTED (-2)  /* valid request this build has no kernel for */
+#define PMG_ERR_UNSUPPORTED (-2)  /* valid request the library has no kernel for */
 #define PMG_ERR_DEGENERATE (-3)   /* a cell with det J <= 0 at a quadrature point */
 #define PMG_ERR_HIP (-4)          /* a HIP runtime call failed */
 #define PMG_ERR_OOM (-5)          /* device allocation failed */

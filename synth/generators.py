@@ -186,7 +186,7 @@ def make_vertices(dim: int, n: int, alpha: float, seed: int,
 
     Every interior vertex is moved by an independent U(-alpha h, alpha h) draw
     per coordinate (the paper moves each interior vertex randomly, Section 3.2
-    and Section 4; the per-coordinate law is this build's workload recipe).
+    and Section 4; the per-coordinate law is the workload recipe of this package).
     Draws happen for all vertices in lexicographic order, coordinates innermost;
     boundary draws are discarded.  Cells whose sampled Jacobian determinant
     falls to det_floor * h^dim or below get the displacements of their interior
