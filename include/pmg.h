@@ -82,6 +82,11 @@ extern "C" {
 #define PMG_PATCH_INTERIOR 0
 #define PMG_PATCH_WITH_BOUNDARY 1
 
+/* coarse-cell coefficients of the geometric multigrid hierarchy */
+#define PMG_COARSE_ARITHMETIC 0
+#define PMG_COARSE_GEOMETRIC 1
+#define PMG_COARSE_HARMONIC 2
+
 /* pmg_query keys */
 #define PMG_Q_N_PATCHES 0
 #define PMG_Q_N_COLORS 1
@@ -121,6 +126,8 @@ typedef struct pmg_opts {
   uint64_t seed;         /* seed of the Lanczos start vectors (default 0) */
   void* stream;          /* hipStream_t, NULL = null stream */
   int32_t patch_set;     /* PMG_PATCH_INTERIOR (default) or PMG_PATCH_WITH_BOUNDARY */
+  int32_t coarse_mean;   /* gmg_setup: coefficient of a coarse cell from its 2^d children,
+                            PMG_COARSE_ARITHMETIC (default), _GEOMETRIC or _HARMONIC mean */
 } pmg_opts;
 
 /* Fill *o with the defaults listed above (levels: p, floor halvings, 1 is
@@ -249,7 +256,8 @@ int pmg_batch_destroy(pmg_batch* b);
 /* Geometric multigrid over meshes with N, N/2, ... cells (halving while N
  * stays even and the halved mesh has an interior vertex), degree p on every
  * level.  Coarse vertices are the shared fine vertices; a coarse cell's
- * coefficient is the mean of its children.  Smoothers on every level but the
+ * coefficient is the arithmetic, geometric or harmonic mean of its children
+ * (opts->coarse_mean).  Smoothers on every level but the
  * coarsest use opts; the coarsest level is solved exactly (dense Cholesky,
  * FP64).  mesh, coeff: host.  Synchronises opts->stream. */
 int gmg_setup(const pmg_mesh* mesh, const double* coeff, int32_t p, const pmg_opts* opts,

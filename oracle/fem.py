@@ -249,17 +249,20 @@ class Mesh:
                     self.cell_mu([st[i] + c[i] for i in range(self.dim)])
         return PatchGeometry(verts, mu, nc)
 
-    def coarsen(self) -> "Mesh":
+    def coarsen(self, rule: str = "arithmetic") -> "Mesh":
         """Parent mesh with n/2 cells: vertices are the fine vertices with even
         indices (topological nesting, Section 2); a parent cell's coefficient
-        is the arithmetic mean of its 2^dim children."""
+        is the arithmetic, geometric or harmonic mean of its 2^dim children."""
         if self.n % 2:
             raise ValueError("odd mesh cannot be coarsened")
         nc = self.n // 2
         verts = np.array([self.vertex([2 * v[i] for i in range(self.dim)])
                           for v in _multi(nc + 1, self.dim)])
-        mu = np.array([np.mean([self.cell_mu([2 * e[i] + c[i] for i in range(self.dim)])
-                                for c in _multi(2, self.dim)])
+        means = {"arithmetic": lambda x: np.mean(x),
+                 "geometric": lambda x: np.exp(np.mean(np.log(x))),
+                 "harmonic": lambda x: 1.0 / np.mean(1.0 / np.asarray(x))}
+        mu = np.array([means[rule]([self.cell_mu([2 * e[i] + c[i] for i in range(self.dim)])
+                                    for c in _multi(2, self.dim)])
                        for e in _multi(nc, self.dim)])
         return Mesh(self.dim, nc, verts, mu)
 

@@ -70,12 +70,13 @@ def prolongation_h(dim: int, nc: int, p: int) -> sp.csr_matrix:
 
 class GMG:
     def __init__(self, mesh: Mesh, p: int, levels, cheb_degree=3, n_vcycles=1,
-                 lanczos_steps=12, seed=0, bounds=None, with_boundary=False):
+                 lanczos_steps=12, seed=0, bounds=None, with_boundary=False,
+                 coarse_mean="arithmetic"):
         self.dim, self.p = mesh.dim, p
         sizes = hierarchy_sizes(mesh.n)
         meshes = [mesh]
         while meshes[-1].n != sizes[0]:
-            meshes.append(meshes[-1].coarsen())
+            meshes.append(meshes[-1].coarsen(coarse_mean))
         self.meshes = list(reversed(meshes))            # coarsest first
         self.A = [dirichlet_operator(m, p) for m in self.meshes]
         self.P = [prolongation_h(self.dim, m.n, p) for m in self.meshes[:-1]]

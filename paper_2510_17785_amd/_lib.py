@@ -23,6 +23,9 @@ PMG_BF16_FP32ACC = 2
 PMG_BF16X3_FP32ACC = 3
 PMG_PATCH_INTERIOR = 0
 PMG_PATCH_WITH_BOUNDARY = 1
+PMG_COARSE_ARITHMETIC = 0
+PMG_COARSE_GEOMETRIC = 1
+PMG_COARSE_HARMONIC = 2
 PMG_BOUNDS_LANCZOS = 0
 PMG_BOUNDS_FIXED = 1
 
@@ -69,7 +72,8 @@ class PmgOpts(ctypes.Structure):
                 ("n_vcycles", ctypes.c_int32), ("bounds", ctypes.c_int32),
                 ("lanczos_steps", ctypes.c_int32), ("cheb_safety", ctypes.c_double),
                 ("cheb_range", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("stream", ctypes.c_void_p), ("patch_set", ctypes.c_int32)]
+                ("stream", ctypes.c_void_p), ("patch_set", ctypes.c_int32),
+                ("coarse_mean", ctypes.c_int32)]
 
 
 class PmgError(RuntimeError):

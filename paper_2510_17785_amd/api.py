@@ -344,7 +344,8 @@ class GMGSolver:
     def __init__(self, dim: int, n: int, p: int, vertices, coeff, levels: Sequence[int] = None,
                  precision: str = "fp64", cheb_degree: int = 3, n_vcycles: int = 1,
                  bounds: str = "lanczos", lanczos_steps: int = 12, cheb_safety: float = 1.1,
-                 cheb_range: float = 15.0, seed: int = 0, stream=None, with_boundary: bool = False):
+                 cheb_range: float = 15.0, seed: int = 0, stream=None, with_boundary: bool = False,
+                 coarse_mean: str = "arithmetic"):
         self._lib = L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("GMGSolver needs a GPU")
@@ -352,6 +353,8 @@ class GMGSolver:
         mu = np.ascontiguousarray(coeff, dtype=np.float64)
         o = _opts(levels, precision, cheb_degree, n_vcycles, bounds, lanczos_steps, cheb_safety,
                   cheb_range, seed, stream, with_boundary)
+        o.coarse_mean = {"arithmetic": L.PMG_COARSE_ARITHMETIC, "geometric": L.PMG_COARSE_GEOMETRIC,
+                         "harmonic": L.PMG_COARSE_HARMONIC}[coarse_mean]
         h = ctypes.c_void_p()
         L.check(self._lib.gmg_setup(ctypes.byref(m), mu.ctypes.data_as(
             ctypes.POINTER(ctypes.c_double)), int(p), ctypes.byref(o), ctypes.byref(h)))

@@ -337,6 +337,8 @@ int check_opts(const pmg_opts* o, int dim, int p, int* levels, int& L, const Pat
     return fail(PMG_ERR_INVALID_ARG, "unknown bounds source %d", o->bounds);
   if (o->patch_set != PMG_PATCH_INTERIOR && o->patch_set != PMG_PATCH_WITH_BOUNDARY)
     return fail(PMG_ERR_INVALID_ARG, "unknown patch set %d", o->patch_set);
+  if (o->coarse_mean < PMG_COARSE_ARITHMETIC || o->coarse_mean > PMG_COARSE_HARMONIC)
+    return fail(PMG_ERR_INVALID_ARG, "unknown coarse coefficient rule %d", o->coarse_mean);
   if (o->lanczos_steps < 2 || o->lanczos_steps > 64)
     return fail(PMG_ERR_INVALID_ARG, "lanczos_steps %d outside 2..64", o->lanczos_steps);
   if (!(o->cheb_safety >= 1.0) || !(o->cheb_range > 1.0))
@@ -1066,9 +1068,15 @@ int gmg_setup_impl(const pmg_mesh* mesh, const double* coeff, int p, const pmg_o
       for (int c = 0; c < (1 << dim); ++c) {
         int f = (2 * ex + (c & 1)) + (2 * ey + ((c >> 1) & 1)) * Nf;
         if (dim == 3) f += (2 * ez + ((c >> 2) & 1)) * Nf * Nf;
-        s += Mu[l + 1][f];
+        const double mu = Mu[l + 1][f];
+        s += o->coarse_mean == PMG_COARSE_GEOMETRIC ? std::log(mu)
+             : o->coarse_mean == PMG_COARSE_HARMONIC ? 1.0 / mu
+                                                     : mu;
       }
-      Mu[l][e] = s / (1 << dim);
+      s /= (1 << dim);
+      Mu[l][e] = o->coarse_mean == PMG_COARSE_GEOMETRIC ? std::exp(s)
+                 : o->coarse_mean == PMG_COARSE_HARMONIC ? 1.0 / s
+                                                         : s;
     }
   }
   g->smoother.assign(L, nullptr);
@@ -1206,6 +1214,7 @@ int pmg_default_opts(pmg_opts* o) {
   o->seed = 0;
   o->stream = nullptr;
   o->patch_set = PMG_PATCH_INTERIOR;
+  o->coarse_mean = PMG_COARSE_ARITHMETIC;
   return PMG_OK;
 }
 

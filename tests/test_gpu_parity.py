@@ -146,3 +146,16 @@ def test_gmg_cg(dev, name, n):
     assert it == ito
     assert rel <= w.rtol
     assert rel_err(x.cpu().numpy(), xo) <= 1e-10
+
+
+@pytest.mark.parametrize("rule", ["geometric", "harmonic"])
+def test_gmg_coarse_rules(dev, rule):
+    # the coarse-coefficient rules of the hierarchy against the oracle's
+    from oracle.gmg import GMG
+    from paper_2510_17785_amd import GMGSolver
+    w, p, levels, X, mu, b = case("3d-n32-q7-jump", 4, 3, (3, 1))
+    G = GMGSolver(w.dim, w.n, p, X, mu, levels=levels, coarse_mean=rule)
+    r = np.random.default_rng(2).standard_normal(b.shape) * fem.dirichlet_mask(w.dim, w.n, p)
+    z = G.vcycle(torch.tensor(r, device=dev)).cpu().numpy()
+    ref = GMG(fem.Mesh(w.dim, w.n, X, mu), p, levels, coarse_mean=rule).precondition(r)
+    assert rel_err(z, ref) <= 1e-10

@@ -431,3 +431,14 @@ def test_gmg_cg_with_boundary_patches():
     assert abs(r2 @ G.precondition(r1) - r1 @ G.precondition(r2)) <= 1e-10 * abs(r1 @ G.precondition(r1))
     x, it, hist = G.cg(b, rtol=1e-10)
     assert it <= 30
+
+
+@pytest.mark.parametrize("rule,expect", [("arithmetic", 21.25), ("geometric", 8.0),
+                                         ("harmonic", 1.0 / 0.33203125)])
+def test_coarse_coefficient_means(rule, expect):
+    # one parent cell of 2x2x2 children with mu = 1, 4, 16, 64 (twice): the
+    # three means in closed form
+    X = synth.make_vertices(3, 2, 0.0, 1)
+    mu = np.array([1.0, 4.0, 16.0, 64.0, 1.0, 4.0, 16.0, 64.0])
+    c = fem.Mesh(3, 2, X, mu).coarsen(rule)
+    assert c.n == 1 and np.isclose(c.mu[0], expect, rtol=1e-14)
