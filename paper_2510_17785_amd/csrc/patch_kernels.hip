@@ -178,12 +178,20 @@ struct Layout {
     return o;
   }
   static constexpr int dense_total = dense_rel(L);
+  // Intermediate levels of up to 125 interior nodes (degree 3 in 3D) that do
+  // not fit LDS as dense matrices are applied as dense matrices read from
+  // global memory: one matrix-vector phase instead of seven latency-bound
+  // sum-factorisation phases on a tiny tensor.
+  static constexpr bool dense_global(int l) {
+    return l > 0 && l < L - 1 && !dense_level(l) && level_size(l) <= 125;
+  }
   // metric G at every Gauss point of every level, structure of arrays
   static constexpr int NG = DIM == 3 ? 6 : 3;
   // Gauss points of level l that need the metric (none for the stored dense
   // levels and the coarsest level, which the V-cycle never applies)
   static constexpr int npts(int l) {
-    return (l > 0 && (l == L - 1 || dense_level(l))) ? 0 : ipow(2 * (LV::q[l] + 1), DIM);
+    return (l > 0 && (l == L - 1 || dense_level(l) || dense_global(l))) ? 0
+                                                                        : ipow(2 * (LV::q[l] + 1), DIM);
   }
   static constexpr int G_all = [] {
     int o = 0;
@@ -393,6 +401,7 @@ struct Ctx {
   // (level count - 2), which the V-cycle solves exactly; null otherwise
   const double* trunc = nullptr;
   int pf = 0;  // boundary flags of the patch (see patch_flags)
+  const T* dglob[kMaxLevels] = {nullptr};  // this patch's dense matrices in global memory
   __device__ const T* gB(int l) const { return gtab + l * kTabLevelStride; }
   __device__ const T* gDc(int l) const {
     const int n = LV::q[l] + 1;
@@ -1426,6 +1435,45 @@ template <typename T, int DIM, class LV, int L, class Epi>
 __device__ __forceinline__ void apply_vec_epi(const Ctx<T, DIM, LV>& c, const T* v, Epi epi) {
   constexpr int Q = LV::q[L];
   using Lay = Layout<T, DIM, LV>;
+  if constexpr (Lay::dense_global(L)) {
+    if (c.dense_ok) {
+      // symmetric: column j is row j, so threads of consecutive rows read
+      // consecutive addresses; four partial sums per row, added in LDS
+      constexpr int N = Lay::level_size(L);
+      constexpr int NP = NT<T> / N >= 4 ? 4 : NT<T> / N;
+      constexpr int CH = (N + NP - 1) / NP;
+      static_assert(NP >= 1 && NP * N <= Lay::abuf_elems, "dense global apply layout");
+      const T* M = c.dglob[L];
+      T* part = c.abuf();
+      const int t = threadIdx.x;
+      if (t < NP * N) {
+        const int i = t % N, ch = t / N;
+        // all CH loads of the chunk issued before the sums
+        T mv[CH];
+#pragma unroll
+        for (int jj = 0; jj < CH; ++jj) {
+          const int j = ch * CH + jj;
+          mv[jj] = j < N ? M[(int64_t)j * N + i] : T(0);
+        }
+        T acc = 0;
+#pragma unroll
+        for (int jj = 0; jj < CH; ++jj) {
+          const int j = ch * CH + jj;
+          acc += j < N ? mv[jj] * v[j] : T(0);
+        }
+        part[ch * N + i] = acc;
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < N; i += NT<T>) {
+        T acc = 0;
+#pragma unroll
+        for (int ch = 0; ch < NP; ++ch) acc += part[ch * N + i];
+        epi(i, acc);
+      }
+      __syncthreads();
+      return;
+    }
+  }
   if constexpr (Lay::dense_level(L)) {
     if (c.dense_ok) {
       constexpr int N = Lay::level_size(L);
@@ -1507,18 +1555,23 @@ __device__ __forceinline__ void chebyshev(const Ctx<T, DIM, LV>& c, int k, bool 
 
 // restriction: rc = (P1^T (x) ... (x) P1^T) rf
 template <typename T, int DIM, int QF, int QC>
-__device__ __forceinline__ void restrict_vec(const T* __restrict__ rf, T* __restrict__ rc, const T* __restrict__ P1,
-                             T* __restrict__ ab) {
+__device__ __forceinline__ void restrict_vec(const T* __restrict__ rf, T* __restrict__ rc,
+                                             const LDSP T* __restrict__ P1, LDSP T* __restrict__ ab) {
   constexpr int mf = 2 * QF - 1, mc = 2 * QC - 1;
   const int tid = threadIdx.x;
   if constexpr (DIM == 3) {
-    T* t1 = ab;                       // [c][b][i]: mf*mf*mc
-    T* t2 = ab + mf * mf * mc;        // [c][j][i]: mf*mc*mc
+    LDSP T* t1 = ab;                  // [c][b][i]: mf*mf*mc
+    LDSP T* t2 = t1 + mf * mf * mc;   // [c][j][i]: mf*mc*mc
+    LDSP T* sf = t2 + mf * mc * mc;   // the fine vector, staged in LDS
+#pragma unroll 1
+    for (int idx = tid; idx < mf * mf * mf; idx += NT<T>) sf[idx] = rf[idx];
+    __syncthreads();
 #pragma unroll 1
     for (int idx = tid; idx < mf * mf * mc; idx += NT<T>) {
       const int i = idx % mc, cb = idx / mc;
       T acc = 0;
-      for (int a = 0; a < mf; ++a) acc += P1[a * mc + i] * rf[cb * mf + a];
+#pragma unroll
+      for (int a = 0; a < mf; ++a) acc += P1[a * mc + i] * sf[cb * mf + a];
       t1[idx] = acc;
     }
     __syncthreads();
@@ -1526,6 +1579,7 @@ __device__ __forceinline__ void restrict_vec(const T* __restrict__ rf, T* __rest
     for (int idx = tid; idx < mf * mc * mc; idx += NT<T>) {
       const int i = idx % mc, t = idx / mc, j = t % mc, cc = t / mc;
       T acc = 0;
+#pragma unroll
       for (int b = 0; b < mf; ++b) acc += P1[b * mc + j] * t1[(cc * mf + b) * mc + i];
       t2[idx] = acc;
     }
@@ -1534,16 +1588,22 @@ __device__ __forceinline__ void restrict_vec(const T* __restrict__ rf, T* __rest
     for (int idx = tid; idx < mc * mc * mc; idx += NT<T>) {
       const int ji = idx % (mc * mc), k = idx / (mc * mc);
       T acc = 0;
+#pragma unroll
       for (int cc = 0; cc < mf; ++cc) acc += P1[cc * mc + k] * t2[cc * mc * mc + ji];
       rc[idx] = acc;
     }
   } else {
-    T* t1 = ab;  // [b][i]: mf*mc
+    LDSP T* t1 = ab;            // [b][i]: mf*mc
+    LDSP T* sf = t1 + mf * mc;  // the fine vector, staged in LDS
+#pragma unroll 1
+    for (int idx = tid; idx < mf * mf; idx += NT<T>) sf[idx] = rf[idx];
+    __syncthreads();
 #pragma unroll 1
     for (int idx = tid; idx < mf * mc; idx += NT<T>) {
       const int i = idx % mc, b = idx / mc;
       T acc = 0;
-      for (int a = 0; a < mf; ++a) acc += P1[a * mc + i] * rf[b * mf + a];
+#pragma unroll
+      for (int a = 0; a < mf; ++a) acc += P1[a * mc + i] * sf[b * mf + a];
       t1[idx] = acc;
     }
     __syncthreads();
@@ -1551,6 +1611,7 @@ __device__ __forceinline__ void restrict_vec(const T* __restrict__ rf, T* __rest
     for (int idx = tid; idx < mc * mc; idx += NT<T>) {
       const int i = idx % mc, j = idx / mc;
       T acc = 0;
+#pragma unroll
       for (int b = 0; b < mf; ++b) acc += P1[b * mc + j] * t1[b * mc + i];
       rc[idx] = acc;
     }
@@ -1560,18 +1621,23 @@ __device__ __forceinline__ void restrict_vec(const T* __restrict__ rf, T* __rest
 
 // prolongation and correction: df += (P1 (x) ... (x) P1) dc
 template <typename T, int DIM, int QF, int QC>
-__device__ __forceinline__ void prolong_add(const T* __restrict__ dc, T* __restrict__ df, const T* __restrict__ P1,
-                            T* __restrict__ ab) {
+__device__ __forceinline__ void prolong_add(const T* __restrict__ dc, T* __restrict__ df,
+                                            const LDSP T* __restrict__ P1, LDSP T* __restrict__ ab) {
   constexpr int mf = 2 * QF - 1, mc = 2 * QC - 1;
   const int tid = threadIdx.x;
   if constexpr (DIM == 3) {
-    T* t1 = ab;                  // [k][j][a]: mc*mc*mf
-    T* t2 = ab + mc * mc * mf;   // [k][b][a]: mc*mf*mf
+    LDSP T* t1 = ab;                  // [k][j][a]: mc*mc*mf
+    LDSP T* t2 = t1 + mc * mc * mf;   // [k][b][a]: mc*mf*mf
+    LDSP T* sc = t2 + mc * mf * mf;   // the coarse vector, staged in LDS
+#pragma unroll 1
+    for (int idx = tid; idx < mc * mc * mc; idx += NT<T>) sc[idx] = dc[idx];
+    __syncthreads();
 #pragma unroll 1
     for (int idx = tid; idx < mc * mc * mf; idx += NT<T>) {
       const int a = idx % mf, kj = idx / mf;
       T acc = 0;
-      for (int i = 0; i < mc; ++i) acc += P1[a * mc + i] * dc[kj * mc + i];
+#pragma unroll
+      for (int i = 0; i < mc; ++i) acc += P1[a * mc + i] * sc[kj * mc + i];
       t1[idx] = acc;
     }
     __syncthreads();
@@ -1579,6 +1645,7 @@ __device__ __forceinline__ void prolong_add(const T* __restrict__ dc, T* __restr
     for (int idx = tid; idx < mc * mf * mf; idx += NT<T>) {
       const int a = idx % mf, t = idx / mf, b = t % mf, k = t / mf;
       T acc = 0;
+#pragma unroll
       for (int j = 0; j < mc; ++j) acc += P1[b * mc + j] * t1[(k * mc + j) * mf + a];
       t2[idx] = acc;
     }
@@ -1587,16 +1654,22 @@ __device__ __forceinline__ void prolong_add(const T* __restrict__ dc, T* __restr
     for (int idx = tid; idx < mf * mf * mf; idx += NT<T>) {
       const int ba = idx % (mf * mf), cc = idx / (mf * mf);
       T acc = 0;
+#pragma unroll
       for (int k = 0; k < mc; ++k) acc += P1[cc * mc + k] * t2[k * mf * mf + ba];
       df[idx] += acc;
     }
   } else {
-    T* t1 = ab;  // [j][a]: mc*mf
+    LDSP T* t1 = ab;            // [j][a]: mc*mf
+    LDSP T* sc = t1 + mc * mf;  // the coarse vector, staged in LDS
+#pragma unroll 1
+    for (int idx = tid; idx < mc * mc; idx += NT<T>) sc[idx] = dc[idx];
+    __syncthreads();
 #pragma unroll 1
     for (int idx = tid; idx < mc * mf; idx += NT<T>) {
       const int a = idx % mf, j = idx / mf;
       T acc = 0;
-      for (int i = 0; i < mc; ++i) acc += P1[a * mc + i] * dc[j * mc + i];
+#pragma unroll
+      for (int i = 0; i < mc; ++i) acc += P1[a * mc + i] * sc[j * mc + i];
       t1[idx] = acc;
     }
     __syncthreads();
@@ -1604,6 +1677,7 @@ __device__ __forceinline__ void prolong_add(const T* __restrict__ dc, T* __restr
     for (int idx = tid; idx < mf * mf; idx += NT<T>) {
       const int a = idx % mf, b = idx / mf;
       T acc = 0;
+#pragma unroll
       for (int j = 0; j < mc; ++j) acc += P1[b * mc + j] * t1[j * mf + a];
       df[idx] += acc;
     }
@@ -1660,16 +1734,17 @@ __device__ void vcycle(const Ctx<T, DIM, LV>& c, int k, bool d_zero) {
     }
     constexpr int QF = LV::q[L], QC = LV::q[L + 1];
     constexpr int mf = 2 * QF - 1, mc = 2 * QC - 1;
-    static_assert(DIM != 3 || mf * mf * mc + mf * mc * mc <= Layout<T, DIM, LV>::abuf_elems,
+    static_assert((DIM == 3 ? mf * mf * mc + mf * mc * mc + mf * mf * mf
+                            : mf * mc + mf * mf) <= Layout<T, DIM, LV>::abuf_elems,
                   "transfer temporaries exceed the work area");
     using PT = VecPtr<T, DIM, LV>;
     chebyshev<T, DIM, LV, L>(c, k, d_zero);          // pre-smoothing
     T* res = c.res();
     apply_vec_epi<T, DIM, LV, L>(c, c.d(L),           // residual
                                  EpiResidual<T, PT>{vp<T, DIM, LV>(c.r(L)), vp<T, DIM, LV>(res)});
-    restrict_vec<T, DIM, QF, QC>(res, c.r(L + 1), c.tabP(L), c.abuf());  // restriction
+    restrict_vec<T, DIM, QF, QC>(res, c.r(L + 1), lds_cast(c.tabP(L)), lds_cast(c.abuf()));  // restriction
     vcycle<T, DIM, LV, L + 1>(c, k, true);                               // recursion
-    prolong_add<T, DIM, QF, QC>(c.d(L + 1), c.d(L), c.tabP(L), c.abuf());  // correction
+    prolong_add<T, DIM, QF, QC>(c.d(L + 1), c.d(L), lds_cast(c.tabP(L)), lds_cast(c.abuf()));  // correction
     chebyshev<T, DIM, LV, L>(c, k, false);           // post-smoothing
   }
 }
@@ -1908,6 +1983,10 @@ __device__ __forceinline__ void patch_update(const PatchArgs& a, Ctx<T, DIM, LV>
   }
   load_patch<T, DIM, LV>(c, a, patch);  // ends with a barrier: the gather is in place too
   c.dense_ok = true;
+#pragma unroll
+  for (int l = 0; l < kMaxLevels; ++l)
+    if (l < LV::count && Lay::dense_global(l))
+      c.dglob[l] = tptr<T>(a.dense[l]) + (int64_t)patch * Lay::level_size(l) * Lay::level_size(l);
   prepare_geometry<T, DIM, LV>(c);
 
   if constexpr (MODE == kModeApply) {
@@ -2322,7 +2401,7 @@ __global__ __launch_bounds__(NT<double>) void dense_kernel(PatchArgs a) {
   prepare_geometry<T, DIM, LV>(c);
   auto run = [&](auto Lc) {
     constexpr int L = decltype(Lc)::value;
-    if constexpr (Lay::dense_level(L)) {
+    if constexpr (Lay::dense_level(L) || Lay::dense_global(L)) {
       constexpr int N = Lay::level_size(L);
       double* M = a.dense64[L] + (int64_t)patch * N * N;
       T* e = c.z();
@@ -2611,7 +2690,8 @@ PatchVariant make_variant() {
   v.launch_dense = &Variant<double, DIM, LV>::launch_dense;
   v.launch_level_matrix = &Variant<double, DIM, LV>::launch_level_matrix;
   for (int l = 0; l < kMaxLevels; ++l)
-    v.dense_level[l] = l < LV::count && Layout<T, DIM, LV>::dense_level(l) ? 1 : 0;
+    v.dense_level[l] = l < LV::count && (Layout<T, DIM, LV>::dense_level(l) ||
+                                         Layout<T, DIM, LV>::dense_global(l)) ? 1 : 0;
   return v;
 }
 
