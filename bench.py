@@ -31,6 +31,26 @@ HBM_PEAK_GBS = 8000.0
 # FP32 / FP64 FMA on the vector ALUs without packed FP32 (packed FP32 is
 # disabled in these kernels): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz.
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# Dense FP32 matrix-core peak (v_mfma_f32_16x16x4_f32).
+MFMA_FP32_PEAK_TFLOPS = 157.3
+
+
+def mfma_flops_per_patch(dim, levels, k):
+    """Algorithmic flops of one patch update that the FP32 kernels run on the
+    matrix cores: the top level's 1D interpolation contractions (the
+    2^d 8 d n^{d+1} part of f(q), counted 1 + 2k times) when the top degree
+    is 6 or 7 in 3D (slab-form top level); everything else is vector ALU."""
+    if dim != 3 or levels[0] not in (6, 7):
+        return 0
+    n = levels[0] + 1
+    return 2 ** dim * 8 * dim * n ** (dim + 1) * (1 + 2 * k)
+
+
+def mixed_peak(share):
+    """Peak of a kernel whose flops run a fraction `share` on the FP32 matrix
+    cores and the rest on the vector ALUs, each at its own peak: the time
+    the ideal kernel needs, inverted."""
+    return 1.0 / (share / MFMA_FP32_PEAK_TFLOPS + (1.0 - share) / VALU_PEAK_TFLOPS)
 
 
 def algorithmic_per_patch(dim, levels, k, tsize):
@@ -419,6 +439,8 @@ def main(argv=None):
     avg_launch_s = total_launch_ms / n_launch / 1e3
     patches_per_launch = r32["n_patches"] / n_launch
     achieved = F * patches_per_launch / avg_launch_s / 1e12
+    mshare = mfma_flops_per_patch(w.dim, w.levels, 3) / F
+    peak = mixed_peak(mshare)
     value = r32["dofs"] / (r32["sweep_ms"] / 1e3)
     value64 = res["fp64"]["dofs"] / (res["fp64"]["sweep_ms"] / 1e3)
     out = {
@@ -456,12 +478,14 @@ def main(argv=None):
         "learned_bounds": dict(train, lanczos_fallback_patches=res["fp32"]["fallback"]),
         "outer_cg": cg,
         "roofline": {
-            "bound": "alu",
+            "bound": "mfma" if mshare > 0.5 else "alu",
             "achieved": achieved,
-            "peak": VALU_PEAK_TFLOPS,
+            "peak": peak,
             "unit": "TFLOP/s",
-            "frac": achieved / VALU_PEAK_TFLOPS,
+            "frac": achieved / peak,
             "traffic": measured_traffic(w.name),
+            "peak_parts": {"valu_fp32": VALU_PEAK_TFLOPS, "mfma_fp32": MFMA_FP32_PEAK_TFLOPS,
+                           "mfma_flop_share": mshare},
             "kernel": f"patch_kernel<float,{w.dim},Levels<{','.join(map(str, w.levels))}>,smooth,"
                       f"{'persistent' if 0 < r32['launch'][0] < max(r32['S'].color_offsets[c + 1] - r32['S'].color_offsets[c] for c in range(r32['S'].n_colors)) else 'one workgroup per patch'}>",
             "launch_shape": r32["launch"],

@@ -784,38 +784,51 @@ __device__ __forceinline__ float from_bf16(short h) {
   return (float)__builtin_bit_cast(__bf16, h);
 }
 
-// SPLIT: x = hi + lo with hi = bf16(x), lo = bf16(x - hi); the product
-// M In is taken as Mhi Inhi + Mhi Inlo + Mlo Inhi (the dropped lo lo term
-// is below 2^-16 relative), all accumulated in FP32.
-template <bool SPLIT, class MatF, class InF, class OutF>
+// Operand modes: kMmBf16 rounds both operands to BF16 (one product per
+// tile); kMmBf16x3 splits x = hi + lo with hi = bf16(x), lo = bf16(x - hi)
+// and takes M In as Mhi Inhi + Mhi Inlo + Mlo Inhi (the dropped lo lo term is
+// below 2^-16 relative); kMmF32 keeps FP32 operands (v_mfma_f32_16x16x4_f32,
+// four products over K = 16: step s takes k = 4 (l / 16) + s from lane l).
+// All accumulate in FP32.
+constexpr int kMmBf16 = 0, kMmBf16x3 = 1, kMmF32 = 2;
+template <int MODE, class MatF, class InF, class OutF>
 __device__ __forceinline__ void mm_phase(int ncols, MatF mat, InF in, OutF out) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   constexpr int NW = NT<float> / 64;
   const int i = lane & 15, g = lane >> 4;
   mm_s4 av, al;
+  float af[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     const float x = mat(i, 4 * g + s);
-    av[s] = to_bf16(x);
-    if constexpr (SPLIT) al[s] = to_bf16(x - from_bf16(av[s]));
+    af[s] = x;
+    if constexpr (MODE != kMmF32) av[s] = to_bf16(x);
+    if constexpr (MODE == kMmBf16x3) al[s] = to_bf16(x - from_bf16(av[s]));
   }
 #pragma unroll 1
   for (int tile = wave; tile * 16 < ncols; tile += NW) {
     const int j = tile * 16 + i;
     const bool live = j < ncols;
     mm_s4 bv, bl;
+    float bf[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const float x = live ? in(4 * g + s, j) : 0.0f;
-      bv[s] = to_bf16(x);
-      if constexpr (SPLIT) bl[s] = to_bf16(x - from_bf16(bv[s]));
+      bf[s] = x;
+      if constexpr (MODE != kMmF32) bv[s] = to_bf16(x);
+      if constexpr (MODE == kMmBf16x3) bl[s] = to_bf16(x - from_bf16(bv[s]));
     }
     mm_f4 c = {0.0f, 0.0f, 0.0f, 0.0f};
-    if constexpr (SPLIT) {
-      c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bv, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bl, c, 0, 0, 0);
+    if constexpr (MODE == kMmF32) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) c = __builtin_amdgcn_mfma_f32_16x16x4f32(af[s], bf[s], c, 0, 0, 0);
+    } else {
+      if constexpr (MODE == kMmBf16x3) {
+        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bv, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bl, c, 0, 0, 0);
+      }
+      c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, c, 0, 0, 0);
     }
-    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, c, 0, 0, 0);
     if (live) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) out(4 * g + r, j, c[r]);
@@ -826,7 +839,7 @@ __device__ __forceinline__ void mm_phase(int ncols, MatF mat, InF in, OutF out) 
 // The slab-form operator (apply3) with its six interpolation contractions
 // (x, y, z and their transposes) on the matrix cores; the collocation
 // derivatives and the flux G grad stay in FP32 on the vector ALUs.
-template <int Q, bool CACHE, bool SPLIT>
+template <int Q, bool CACHE, int MODE>
 __device__ __noinline__ void apply3mm(const LDSP float* __restrict__ X, LDSP float* __restrict__ Out,
                                       LDSP float* __restrict__ ab, const LDSP float* __restrict__ Bt,
                                       const LDSP float* __restrict__ Dc,
@@ -854,7 +867,7 @@ __device__ __noinline__ void apply3mm(const LDSP float* __restrict__ X, LDSP flo
 #pragma unroll 1
   for (int cz = 0; cz < 2; ++cz) {
     // x: A[zl][y][QX] = sum_x Bp[QX][x] X[cz Q + zl][y][x]
-    mm_phase<SPLIT>(
+    mm_phase<MODE>(
         n * m, Bp,
         [&](int x, int j) -> T { return x < m ? X[(cz * Q + j / m) * m * m + (j % m) * m + x] : T(0); },
         [&](int QX, int j, T v) {
@@ -862,7 +875,7 @@ __device__ __noinline__ void apply3mm(const LDSP float* __restrict__ X, LDSP flo
         });
     __syncthreads();
     // y: Bf[zl][QY][QX] = sum_y Bp[QY][y] A[zl][y][QX]
-    mm_phase<SPLIT>(
+    mm_phase<MODE>(
         n * NQ, Bp,
         [&](int y, int j) -> T { return y < m ? A[((j / NQ) * m + y) * NQ + j % NQ] : T(0); },
         [&](int QY, int j, T v) {
@@ -870,7 +883,7 @@ __device__ __noinline__ void apply3mm(const LDSP float* __restrict__ X, LDSP flo
         });
     __syncthreads();
     // z: C[kz][QY][QX] = sum_zl B[kz][zl] Bf[zl][QY][QX]
-    mm_phase<SPLIT>(
+    mm_phase<MODE>(
         NQ2, Bc, [&](int zl, int j) -> T { return zl < n ? Bf[zl * NQ2 + j] : T(0); },
         [&](int kz, int j, T v) {
           if (kz < n) C[kz * NQ2 + j] = v;
@@ -927,7 +940,7 @@ __device__ __noinline__ void apply3mm(const LDSP float* __restrict__ X, LDSP flo
     }
     __syncthreads();
     // z^T: A[zl][QY][QX] = sum_kz B[kz][zl] C[kz][QY][QX]
-    mm_phase<SPLIT>(
+    mm_phase<MODE>(
         NQ2, [&](int zl, int kz) -> T { return Bc(kz, zl); },
         [&](int kz, int j) -> T { return kz < n ? C[kz * NQ2 + j] : T(0); },
         [&](int zl, int j, T v) {
@@ -935,7 +948,7 @@ __device__ __noinline__ void apply3mm(const LDSP float* __restrict__ X, LDSP flo
         });
     __syncthreads();
     // y^T onto interior rows: Bf[zl][yi][QX] = sum_QY Bp[QY][yi + 1] A[zl][QY][QX]
-    mm_phase<SPLIT>(
+    mm_phase<MODE>(
         n * NQ, [&](int yi, int QY) -> T { return yi < mi ? Bp(QY, yi + 1) : T(0); },
         [&](int QY, int j) -> T { return QY < NQ ? A[((j / NQ) * NQ + QY) * NQ + j % NQ] : T(0); },
         [&](int yi, int j, T v) {
@@ -944,7 +957,7 @@ __device__ __noinline__ void apply3mm(const LDSP float* __restrict__ X, LDSP flo
     __syncthreads();
     // x^T onto interior columns and the interior z-planes of this slab
     const int zl0 = cz == 0 ? 1 : 0;
-    mm_phase<SPLIT>(
+    mm_phase<MODE>(
         Q * mi, [&](int xi, int QX) -> T { return xi < mi ? Bp(QX, xi + 1) : T(0); },
         [&](int QX, int j) -> T {
           return QX < NQ ? Bf[((zl0 + j / mi) * mi + j % mi) * NQ + QX] : T(0);
@@ -1349,10 +1362,13 @@ __device__ __forceinline__ void apply_level(const Ctx<T, DIM, LV>& c) {
                          lds_cast(c.tabB(L)), lds_cast(c.tabDc(L)), lds_cast(c.tabXg(L)),
                          lds_cast(c.tabWg(L)), lds_cast(c.jc()), lds_cast(c.mu()),
                          lds_cast(c.Gc(L)));
-  } else if constexpr (DIM == 3 && LV::bf16 && std::is_same<T, float>::value && L == 0) {
+  } else if constexpr (DIM == 3 && std::is_same<T, float>::value && L == 0 && Q <= 7) {
+    // slab-form top level in FP32 storage: contractions on the matrix cores
+    // (BF16 or split-BF16 operands for those variants, FP32 operands else)
     static_assert(4 * Sh<3, Q>::S <= Layout<T, DIM, LV>::abuf_elems,
                   "slab buffers exceed the work area");
-    apply3mm<Q, CACHE, LV::split>(lds_cast(c.X()), lds_cast(c.Out()), lds_cast(c.abuf()), lds_cast(c.tabB(L)),
+    constexpr int MODE = !LV::bf16 ? kMmF32 : (LV::split ? kMmBf16x3 : kMmBf16);
+    apply3mm<Q, CACHE, MODE>(lds_cast(c.X()), lds_cast(c.Out()), lds_cast(c.abuf()), lds_cast(c.tabB(L)),
                        lds_cast(c.tabDc(L)), lds_cast(c.tabXg(L)), lds_cast(c.tabWg(L)),
                        lds_cast(c.jc()), lds_cast(c.mu()), lds_cast(c.Gc(L)));
   } else if constexpr (DIM == 3) {
@@ -1448,18 +1464,25 @@ __device__ __forceinline__ void apply_vec_epi(const Ctx<T, DIM, LV>& c, const T*
       const int t = threadIdx.x;
       if (t < NP * N) {
         const int i = t % N, ch = t / N;
-        // all CH loads of the chunk issued before the sums
-        T mv[CH];
-#pragma unroll
-        for (int jj = 0; jj < CH; ++jj) {
-          const int j = ch * CH + jj;
-          mv[jj] = j < N ? M[(int64_t)j * N + i] : T(0);
-        }
+        // the chunk's loads issued in batches before their sums: all at once
+        // in FP32 (these levels occur under slab-form tops, which hold one
+        // workgroup per CU by their LDS, so registers are free), eight at a
+        // time in FP64, where more in flight would cost workgroups per CU
+        constexpr int BT = sizeof(T) == 4 ? CH : 8;
         T acc = 0;
+#pragma unroll 1
+        for (int j0 = 0; j0 < CH; j0 += BT) {
+          T mv[BT];
 #pragma unroll
-        for (int jj = 0; jj < CH; ++jj) {
-          const int j = ch * CH + jj;
-          acc += j < N ? mv[jj] * v[j] : T(0);
+          for (int jj = 0; jj < BT; ++jj) {
+            const int j = ch * CH + j0 + jj;
+            mv[jj] = (j0 + jj < CH && j < N) ? M[(int64_t)j * N + i] : T(0);
+          }
+#pragma unroll
+          for (int jj = 0; jj < BT; ++jj) {
+            const int j = ch * CH + j0 + jj;
+            acc += (j0 + jj < CH && j < N) ? mv[jj] * v[j] : T(0);
+          }
         }
         part[ch * N + i] = acc;
       }
