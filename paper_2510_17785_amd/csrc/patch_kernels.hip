@@ -763,16 +763,17 @@ __device__ __noinline__ void apply3q(const LDSP T* __restrict__ X, LDSP T* __res
 }
 
 // ---------------------------------------------------------------------------
-// Contractions on the matrix cores (BF16 inputs, FP32 accumulation)
+// Contractions on the matrix cores (FP32 accumulation)
 //
 // One contraction phase is a product D = M In with a 1D (patch-level) matrix
 // M of at most 16 x 16 and an input of at most 16 rows and ncols columns.
-// Every wavefront takes 16-column tiles; one v_mfma_f32_16x16x16_bf16 per
-// tile.  Lane l supplies M[l % 16][4 (l / 16) + s] and In[4 (l / 16) + s][j]
-// for its column j = 16 tile + l % 16 (s = 0..3), and receives
-// D[4 (l / 16) + r][j] (r = 0..3).  Inputs are rounded to BF16 (nearest
-// even) when they are packed into the operands; the products are exact in
-// FP32 and accumulated in FP32; results are stored in FP32.
+// Every wavefront takes 16-column tiles.  Lane l supplies M[l % 16][4 (l / 16)
+// + s] and In[4 (l / 16) + s][j] for its column j = 16 tile + l % 16
+// (s = 0..3), and receives D[4 (l / 16) + r][j] (r = 0..3).  With BF16
+// operands the inputs are rounded (nearest even) when they are packed, the
+// products are exact in FP32 and accumulated in FP32; with FP32 operands the
+// four values of a lane go to four 16x16x4 products.  Results are stored in
+// FP32.
 // ---------------------------------------------------------------------------
 
 typedef short mm_s4 __attribute__((ext_vector_type(4)));
@@ -1174,14 +1175,21 @@ __device__ __noinline__ void apply3seg(const LDSP T* __restrict__ in, Epi epi,
       f2[a] = D[(cz * n + a) * NQ2 + col];
     }
     T w[n];
+    // plane k of this cell layer is a constant offset k NQ^2 from these
+    const LDSP T* fx0 = A + (cz * n * NQ + QY) * NQ + cx * n;
+    const LDSP T* fy0 = Bb + (cz * n * NQ + cy * n) * NQ + QX;
 #pragma unroll
     for (int k = 0; k < n; ++k) {
-      const int QZ = cz * n + k;
-      const LDSP T* fx = A + (QZ * NQ + QY) * NQ + cx * n;
-      const LDSP T* fy = Bb + (QZ * NQ + cy * n) * NQ + QX;
-      T acc = 0;
+      const LDSP T* fx = fx0 + k * NQ2;
+      const LDSP T* fy = fy0 + k * NQ2;
+      // one multiply-add per term (a single fused chain, no zero start)
+      T acc = gDc[k] * f2[0];
 #pragma unroll
-      for (int a = 0; a < n; ++a) acc += ex[a] * fx[a] + ey[a] * fy[a * NQ] + gDc[a * n + k] * f2[a];
+      for (int a = 0; a < n; ++a) {
+        if (a > 0) acc = fma(gDc[a * n + k], f2[a], acc);
+        acc = fma(ex[a], fx[a], acc);
+        acc = fma(ey[a], fy[a * NQ], acc);
+      }
       w[k] = acc;
     }
     LDSP T* dst = C + cz * n * NQ2 + col;
@@ -1195,46 +1203,52 @@ __device__ __noinline__ void apply3seg(const LDSP T* __restrict__ in, Epi epi,
   }
   __syncthreads();
   // 6. y^T, one interior (z, y) pair and one QX per item; the two cell-local
-  //    copies of the shared z node are summed on read: A[zi][yi][QX]
+  //    copies of the shared z node are summed on read: A[zi][yi][QX].
+  //    Branch-free: both copies and both y cells are read for every item
+  //    (the second copy with weight 0 off the shared node, a cell the node
+  //    is not in with a clamped row, its sum discarded), so all loads are
+  //    issued together.
 #pragma unroll 1
   for (int it = tid; it < mi * mi * NQ; it += NT<T>) {
     const int QX = it % NQ, r = it / NQ, yi = r % mi, zi = r / mi;
     const int z = zi + 1, y = yi + 1;
     const int zc0 = z <= Q ? z : n + z - Q;          // cell-local z of node z
     const int zc1 = z == Q ? n : zc0;                 // its second copy (z = q)
-    const bool two = z == Q;
-    T acc = 0;
+    const T t1 = z == Q ? T(1) : T(0);
+    const int a0 = y <= Q ? y : Q, a1 = y >= Q ? y - Q : 0;
+    const LDSP T* s0 = C + zc0 * NQ2 + QX;
+    const LDSP T* s1 = C + zc1 * NQ2 + QX;
+    T v0[n], v1[n];
 #pragma unroll
-    for (int cy = 0; cy < 2; ++cy) {
-      const int a = y - cy * Q;
-      if (a < 0 || a > Q) continue;
-      const LDSP T* s0 = C + zc0 * NQ2 + cy * n * NQ + QX;
-      const LDSP T* s1 = C + zc1 * NQ2 + cy * n * NQ + QX;
-#pragma unroll
-      for (int k = 0; k < n; ++k) {
-        const T v = two ? s0[k * NQ] + s1[k * NQ] : s0[k * NQ];
-        acc += Bl[k * n + a] * v;
-      }
+    for (int k = 0; k < n; ++k) {
+      v0[k] = fma(t1, s1[k * NQ], s0[k * NQ]);
+      v1[k] = fma(t1, s1[(n + k) * NQ], s0[(n + k) * NQ]);
     }
-    A[r * NQ + QX] = acc;
+    T acc0 = Bl[a0] * v0[0], acc1 = Bl[a1] * v1[0];
+#pragma unroll
+    for (int k = 1; k < n; ++k) {
+      acc0 = fma(Bl[k * n + a0], v0[k], acc0);
+      acc1 = fma(Bl[k * n + a1], v1[k], acc1);
+    }
+    A[r * NQ + QX] = y < Q ? acc0 : (y > Q ? acc1 : acc0 + acc1);
   }
   __syncthreads();
   // 7. x^T, one interior row per item, handed to the epilogue with its
-  //    interior index (the caller's vector update is fused here)
+  //    interior index (the caller's vector update is fused here); both x
+  //    cells computed, as in step 6
 #pragma unroll 1
   for (int i = tid; i < mi * mi * mi; i += NT<T>) {
     const int xi = i % mi, line = i / mi;
     const int x = xi + 1;
+    const int a0 = x <= Q ? x : Q, a1 = x >= Q ? x - Q : 0;
     const LDSP T* src = A + line * NQ;
-    T acc = 0;
+    T acc0 = Bl[a0] * src[0], acc1 = Bl[a1] * src[n];
 #pragma unroll
-    for (int cx = 0; cx < 2; ++cx) {
-      const int a = x - cx * Q;
-      if (a < 0 || a > Q) continue;
-#pragma unroll
-      for (int k = 0; k < n; ++k) acc += Bl[k * n + a] * src[cx * n + k];
+    for (int k = 1; k < n; ++k) {
+      acc0 = fma(Bl[k * n + a0], src[k], acc0);
+      acc1 = fma(Bl[k * n + a1], src[n + k], acc1);
     }
-    epi(i, acc);
+    epi(i, x < Q ? acc0 : (x > Q ? acc1 : acc0 + acc1));
   }
   __syncthreads();
 }
