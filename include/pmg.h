@@ -245,7 +245,10 @@ int pmg_batch_smooth_eager(pmg_batch* b, double* const* u, const double* const* 
 /* Launch shapes for every instance, chosen with the instances running
  * together: whole-batch graph sweeps (captured per candidate) on copies of u
  * (left unchanged), one instance's shape at a time, highest degree first,
- * over the candidates of pmg_autotune.  Drops captured graphs. */
+ * over the candidates of pmg_autotune.  Drops captured graphs.
+ * Currently switched off: returns PMG_ERR_UNSUPPORTED without device work (a
+ * host crash inside its graph-replay timing is unexplained); set shapes per
+ * instance with pmg_set_launch on pmg_batch_instance handles. */
 int pmg_batch_autotune(pmg_batch* b, double* const* u, const double* const* rhs);
 #define PMG_BQ_N_INSTANCES 0
 #define PMG_BQ_CAPTURES 1

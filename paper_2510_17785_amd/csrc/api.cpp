@@ -1953,6 +1953,16 @@ int pmg_batch_smooth(pmg_batch* b, double* const* u, const double* const* rhs, i
 
 int pmg_batch_autotune(pmg_batch* b, double* const* u, const double* const* rhs) {
   if (!b || !u || !rhs) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  // Switched off: a host-side crash occurred inside this tuner's timing of
+  // graph replays and its cause has not been found.  The tuner below is
+  // kept as it was; per-instance shapes can be set with pmg_set_launch.
+  return fail(PMG_ERR_UNSUPPORTED,
+              "batch autotuning is switched off (an unexplained host crash during its graph-replay "
+              "timing); set launch shapes per instance with pmg_set_launch");
+}
+
+[[maybe_unused]] static int batch_autotune_graph_replays(pmg_batch* b, double* const* u,
+                                                         const double* const* rhs) {
   drop_graphs(b);  // launch shapes are baked into captured graphs
   int cands[kLaunchCandidates][2];
   PMG_TRY(launch_candidates(cands));
