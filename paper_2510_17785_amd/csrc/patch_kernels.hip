@@ -207,7 +207,13 @@ struct Layout {
   static constexpr bool one_wg = DIM == 3 && !seg_top;
   static constexpr int G_top = NG * ipow(2 * (LV::q[0] + 1), DIM);
   static constexpr bool top_vec_fit = !all_fit && one_wg && (base_total + G_top + vec_total) * sz <= kBudgetOne;
-  static constexpr bool top_fit = !all_fit && one_wg && (base_total + G_top) * sz <= kBudgetOne;
+  // FP32 slab-form tops where the level vectors and the top metric do not
+  // fit together keep the vectors (the metric is then recomputed at every
+  // Gauss point): vectors in global memory make every Chebyshev update a
+  // chain of memory round trips, which cost more than the recomputation
+  static constexpr bool vec_over_G = !all_fit && one_wg && !top_vec_fit && sz == 4 &&
+                                     (base_total + vec_total) * sz <= kBudgetOne;
+  static constexpr bool top_fit = !all_fit && one_wg && !vec_over_G && (base_total + G_top) * sz <= kBudgetOne;
   // the metric of level l is kept in LDS (else recomputed at every Gauss point)
   static constexpr bool cache_level(int l) {
     return npts(l) > 0 && (all_fit || ((top_vec_fit || top_fit) && l == 0));
@@ -219,10 +225,11 @@ struct Layout {
   }
   static constexpr int G_total = G_rel(L);
   static constexpr bool cache_G = G_total > 0;
-  // level vectors in LDS when they fit next to the cached metric, or, with
-  // no metric cached, within the two-workgroup budget; else global scratch
+  // level vectors in LDS when they fit next to the cached metric, in place of
+  // it (above), or, with no metric cached, within the two-workgroup budget;
+  // else global scratch
   static constexpr bool vec_in_lds =
-      all_fit || top_vec_fit || (!cache_G && (base_total + vec_total) * sz <= kBudget);
+      all_fit || top_vec_fit || vec_over_G || (!cache_G && (base_total + vec_total) * sz <= kBudget);
   static constexpr int G_off = base_total;
   static constexpr int vec_off = base_total + G_total;
   static constexpr int dense_off = round_up(vec_off + (vec_in_lds ? vec_total : 0), 4);
