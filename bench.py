@@ -306,8 +306,9 @@ def main(argv=None):
                          "(for profiler runs that must launch what a tuned run timed)")
     ap.add_argument("--train-patches", type=int, default=None,
                     help="random patches whose Lanczos bounds train the bound network "
-                         "(default 100000 for the 32^3 Q6 learned-bounds workload, else 6000)")
-    ap.add_argument("--train-epochs", type=int, default=30)
+                         "(default 100000 for the 32^3 Q6 learned-bounds workload, 50000 for the 32^3 Q7 "
+                         "workload, else 6000)")
+    ap.add_argument("--train-epochs", type=int, default=60)
     ap.add_argument("--only", choices=["fp32", "fp64"], default=None,
                     help="time one precision only (for profiler runs; prints no JSON line)")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -340,7 +341,7 @@ def main(argv=None):
     if w.name == "3d-n24-q8-batch":
         return bench_batch(args, w)
     if args.train_patches is None:
-        args.train_patches = 100000 if w.name == "3d-n32-q6-learned" else 6000
+        args.train_patches = {"3d-n32-q6-learned": 100000, "3d-n32-q7-jump": 50000}.get(w.name, 6000)
     X = synth.make_vertices(w.dim, w.n, w.alpha, w.mesh_seed)
     mu = synth.make_coefficients(w.dim, w.n, w.mu_log10, w.coef_seed)
     bh = synth.make_rhs(w.dim, w.n, w.p, w.rhs_seed)
