@@ -1894,21 +1894,66 @@ __device__ double mesh_vertex(const PatchArgs& a, const int* ii, int r) {
 
 // Patch geometry: 3^d vertices relative to the patch centre and 2^d cell
 // coefficients, from the mesh or from the arrays of independent patches.
-template <typename T, int DIM>
-__device__ void load_geometry(const PatchArgs& a, int patch, T* geo, T* mu) {
+// f(i) for the rows i = tid, tid + NTH, ... < n of this thread (n <= NMAX),
+// unrolled over the compile-time bound
+template <int NTH, int NMAX, class F>
+__device__ __forceinline__ void rows(int n, F f) {
+#pragma unroll
+  for (int j = 0; j < (NMAX + NTH - 1) / NTH; ++j) {
+    const int i = (int)threadIdx.x + j * NTH;
+    if (i < n) f(i);
+  }
+}
+
+// The same rows as st(i, ld(i)), with every load issued before any store.
+// Nothing is guarded: a slot past the last row loads and stores row n - 1
+// again (the value its owner stores too), so st must be a plain store of
+// what ld returned.  Guarded, each load would be moved into its row's
+// branch and wait for its data before the next one is issued; this way a
+// thread pays one memory round trip, not one per row.  n >= 1.
+template <int NTH, int NMAX, class LD, class ST>
+__device__ __forceinline__ void rows_ld_st(int n, LD ld, ST st) {
+  constexpr int IT = (NMAX + NTH - 1) / NTH;
+  using V = decltype(ld(0));
+  V v[IT];
+#pragma unroll
+  for (int j = 0; j < IT; ++j) {
+    const int i = (int)threadIdx.x + j * NTH;
+    v[j] = ld(i < n ? i : n - 1);
+  }
+#pragma unroll
+  for (int j = 0; j < IT; ++j) {
+    const int i = (int)threadIdx.x + j * NTH;
+    st(i < n ? i : n - 1, v[j]);
+  }
+}
+
+template <typename T, int DIM, int NTH = 0, class PG = T*>
+__device__ void load_geometry(const PatchArgs& a, int patch, PG geo, PG mu) {
   constexpr int nvert = ipow(3, DIM), ncell = ipow(2, DIM);
   const int tid = threadIdx.x;
+  // f(i) over the rows of this thread: with NTH > 0 (the block size, known
+  // at compile time) unrolled, so the loads of all rows can issue together
+  auto each = [&](auto nmax, int n, auto f) {
+    if constexpr (NTH > 0) {
+      rows<NTH, decltype(nmax)::value>(n, f);
+    } else {
+      for (int i = tid; i < n; i += blockDim.x) f(i);
+    }
+  };
+  using NV = std::integral_constant<int, nvert * DIM>;
+  using NC = std::integral_constant<int, ncell>;
   if (a.patch_geo) {
     const double* V = a.patch_geo + (int64_t)patch * nvert * DIM;
     constexpr int centre = (nvert - 1) / 2;
-    for (int i = tid; i < nvert * DIM; i += blockDim.x) geo[i] = T(V[i] - V[centre * DIM + i % DIM]);
-    for (int i = tid; i < ncell; i += blockDim.x) mu[i] = T(a.patch_mu[(int64_t)patch * ncell + i]);
+    each(NV{}, nvert * DIM, [&](int i) { geo[i] = T(V[i] - V[centre * DIM + i % DIM]); });
+    each(NC{}, ncell, [&](int i) { mu[i] = T(a.patch_mu[(int64_t)patch * ncell + i]); });
     return;
   }
   const int vlin = a.patch_vertex[patch];
   const int N1 = a.N + 1;
   const int vx = vlin % N1, vy = (vlin / N1) % N1, vz = DIM == 3 ? vlin / (N1 * N1) : 0;
-  for (int i = tid; i < nvert * DIM; i += blockDim.x) {
+  each(NV{}, nvert * DIM, [&](int i) {
     const int r = i % DIM, t = i / DIM;
     const int ii[3] = {vx - 1 + t % 3, vy - 1 + (t / 3) % 3, DIM == 3 ? vz - 1 + t / 9 : 0};
     bool inside = true;
@@ -1917,15 +1962,15 @@ __device__ void load_geometry(const PatchArgs& a, int patch, T* geo, T* mu) {
     if (DIM == 3) g += (int64_t)ii[2] * N1 * N1;
     const double x = inside ? a.verts[g * DIM + r] : mesh_vertex<DIM>(a, ii, r);
     geo[i] = T(x - a.verts[(int64_t)vlin * DIM + r]);
-  }
-  for (int i = tid; i < ncell; i += blockDim.x) {
+  });
+  each(NC{}, ncell, [&](int i) {
     const int ci[3] = {vx - 1 + (i & 1), vy - 1 + ((i >> 1) & 1), DIM == 3 ? vz - 1 + ((i >> 2) & 1) : 0};
     bool inside = true;
     for (int d = 0; d < DIM; ++d) inside = inside && ci[d] >= 0 && ci[d] < a.N;
     int64_t g = ci[0] + (int64_t)ci[1] * a.N;
     if (DIM == 3) g += (int64_t)ci[2] * a.N * a.N;
     mu[i] = inside ? T(a.mu[g]) : T(0);   // ghost cells of a boundary-vertex patch
-  }
+  });
 }
 
 __device__ __forceinline__ int patch_of_block(const PatchArgs& a) {
@@ -1936,34 +1981,46 @@ template <typename T, int DIM, class LV>
 __device__ void load_patch(const Ctx<T, DIM, LV>& c, const PatchArgs& a, int patch) {
   using Lay = Layout<T, DIM, LV>;
   constexpr int L = LV::count;
-  const int tid = threadIdx.x;
+  constexpr int NTH = NT<T>;
+  LDSP T* lds = lds_cast(c.lds);
   // tables
   const T* tab = tptr<T>(a.tab);
+#pragma unroll
   for (int l = 0; l < L; ++l) {
-    const int sz = tab_size(LV::q[l]);
-    for (int i = tid; i < sz; i += NT<T>) c.lds[Lay::tab_level_off(l) + i] = tab[l * kTabLevelStride + i];
+    const T* src = tab + l * kTabLevelStride;
+    LDSP T* dst = lds + Lay::tab_level_off(l);
+    rows_ld_st<NTH, tab_size(LV::q[0])>(
+        tab_size(LV::q[l]), [&](int i) { return src[i]; }, [&](int i, T v) { dst[i] = v; });
   }
+#pragma unroll
   for (int t = 0; t + 1 < L; ++t) {
-    const int sz = (2 * LV::q[t] - 1) * (2 * LV::q[t + 1] - 1);
-    for (int i = tid; i < sz; i += NT<T>)
-      c.lds[Lay::tab_transfer_off(t) + i] =
-          tab[kMaxLevels * kTabLevelStride + t * kTabTransferStride + i];
+    const T* src = tab + kMaxLevels * kTabLevelStride + t * kTabTransferStride;
+    LDSP T* dst = lds + Lay::tab_transfer_off(t);
+    rows_ld_st<NTH, (2 * LV::q[0] - 1) * (2 * LV::q[1] - 1)>(
+        (2 * LV::q[t] - 1) * (2 * LV::q[t + 1] - 1), [&](int i) { return src[i]; },
+        [&](int i, T v) { dst[i] = v; });
   }
-  load_geometry<T, DIM>(a, patch, c.geo(), c.mu());
-  const T* cheb = tptr<T>(a.cheb);
-  for (int i = tid; i < 2 * (L - 1); i += NT<T>) c.cheb()[i] = cheb[(int64_t)patch * 2 * (L - 1) + i];
+  load_geometry<T, DIM, NTH>(a, patch, lds_cast(c.geo()), lds_cast(c.mu()));
+  {
+    const T* src = tptr<T>(a.cheb) + (int64_t)patch * 2 * (L - 1);
+    LDSP T* dst = lds_cast(c.cheb());
+    rows_ld_st<NTH, 2 * kMaxLevels>(2 * (L - 1), [&](int i) { return src[i]; },
+                                    [&](int i, T v) { dst[i] = v; });
+  }
+#pragma unroll
   for (int l = 0; l < L; ++l) {
     const int sz = Lay::level_size(l);
     const T* src = tptr<T>(a.invdiag[l]) + (int64_t)patch * sz;
-    T* dst = c.dinv(l);
-    for (int i = tid; i < sz; i += NT<T>) dst[i] = src[i];
+    VecPtr<T, DIM, LV> dst = vp<T, DIM, LV>(c.dinv(l));
+    rows_ld_st<NTH, Lay::level_size(0)>(sz, [&](int i) { return src[i]; }, [&](int i, T v) { dst[i] = v; });
   }
+#pragma unroll
   for (int l = 0; l < L; ++l) {
     if (!Lay::dense_level(l)) continue;
     const int sz = Lay::level_size(l) * Lay::level_size(l);
     const T* src = tptr<T>(a.dense[l]) + (int64_t)patch * sz;
-    T* dst = c.dense(l);
-    for (int i = tid; i < sz; i += NT<T>) dst[i] = src[i];
+    LDSP T* dst = lds_cast(c.dense(l));
+    rows_ld_st<NTH, 32 * 32>(sz, [&](int i) { return src[i]; }, [&](int i, T v) { dst[i] = v; });
   }
   __syncthreads();
 }
@@ -1992,37 +2049,50 @@ __device__ __forceinline__ void patch_update(const PatchArgs& a, Ctx<T, DIM, LV>
     // gather u-bar_j (closure) and b_j (interior), equation gather; issued
     // first so that its global loads overlap those of the patch data
     patch_base<DIM>(a.patch_vertex[patch], a.N, a.p, base, M);
-    T* X = c.X();
+    LDSP T* X = lds_cast(c.X());
+    VecPtr<T, DIM, LV> rv = vp<T, DIM, LV>(r0);
+    auto st_x = [&](int idx, double v) { X[idx] = T(v); };
+    auto st_r = [&](int idx, double v) { rv[idx] = T(v); };
     if (pf == 0) {
-#pragma unroll 1
-      for (int idx = tid; idx < S0::closure; idx += NT<T>) {
-        const int x = idx % m, t = idx / m, y = t % m, z = DIM == 3 ? t / m : 0;
-        X[idx] = T(a.u[base + x + y * M + (int64_t)z * M * M]);
-      }
-#pragma unroll 1
-      for (int idx = tid; idx < N0; idx += NT<T>) {
-        const int x = idx % mi + 1, t = idx / mi, y = t % mi + 1, z = DIM == 3 ? t / mi + 1 : 0;
-        r0[idx] = T(a.b[base + x + y * M + (int64_t)z * M * M]);
-      }
+      rows_ld_st<NT<T>, S0::closure>(
+          S0::closure,
+          [&](int idx) {
+            const int x = idx % m, t = idx / m, y = t % m, z = DIM == 3 ? t / m : 0;
+            return a.u[base + x + y * M + (int64_t)z * M * M];
+          },
+          st_x);
+      rows_ld_st<NT<T>, N0>(
+          N0,
+          [&](int idx) {
+            const int x = idx % mi + 1, t = idx / mi, y = t % mi + 1, z = DIM == 3 ? t / mi + 1 : 0;
+            return a.b[base + x + y * M + (int64_t)z * M * M];
+          },
+          st_r);
     } else {
       // boundary-vertex patch: closure nodes outside the mesh read as zero
+      // (their loads go to node 0, a valid address, and are discarded)
       const int N1 = a.N + 1, vlin = a.patch_vertex[patch];
       const int g0[3] = {(vlin % N1 - 1) * a.p, ((vlin / N1) % N1 - 1) * a.p,
                          DIM == 3 ? (vlin / (N1 * N1) - 1) * a.p : 0};
-#pragma unroll 1
-      for (int idx = tid; idx < S0::closure; idx += NT<T>) {
-        const int x = idx % m, t = idx / m, y = t % m, z = DIM == 3 ? t / m : 0;
-        const bool in = g0[0] + x >= 0 && g0[0] + x < M && g0[1] + y >= 0 && g0[1] + y < M &&
-                        (DIM == 2 || (g0[2] + z >= 0 && g0[2] + z < M));
-        X[idx] = in ? T(a.u[base + x + y * M + (int64_t)z * M * M]) : T(0);
-      }
-#pragma unroll 1
-      for (int idx = tid; idx < N0; idx += NT<T>) {
-        const int x = idx % mi + 1, t = idx / mi, y = t % mi + 1, z = DIM == 3 ? t / mi + 1 : 0;
-        r0[idx] = interior_node<DIM>(pf, a.p, idx, nullptr)
-                      ? T(a.b[base + x + y * M + (int64_t)z * M * M])
-                      : T(0);
-      }
+      rows_ld_st<NT<T>, S0::closure>(
+          S0::closure,
+          [&](int idx) {
+            const int x = idx % m, t = idx / m, y = t % m, z = DIM == 3 ? t / m : 0;
+            const bool in = g0[0] + x >= 0 && g0[0] + x < M && g0[1] + y >= 0 && g0[1] + y < M &&
+                            (DIM == 2 || (g0[2] + z >= 0 && g0[2] + z < M));
+            const double v = a.u[in ? base + x + y * M + (int64_t)z * M * M : 0];
+            return in ? v : 0.0;
+          },
+          st_x);
+      rows_ld_st<NT<T>, N0>(
+          N0,
+          [&](int idx) {
+            const int x = idx % mi + 1, t = idx / mi, y = t % mi + 1, z = DIM == 3 ? t / mi + 1 : 0;
+            const bool in = interior_node<DIM>(pf, a.p, idx, nullptr);
+            const double v = a.b[in ? base + x + y * M + (int64_t)z * M * M : 0];
+            return in ? v : 0.0;
+          },
+          st_r);
     }
   }
   load_patch<T, DIM, LV>(c, a, patch);  // ends with a barrier: the gather is in place too
