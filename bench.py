@@ -37,13 +37,15 @@ MFMA_FP32_PEAK_TFLOPS = 157.3
 
 def mfma_flops_per_patch(dim, levels, k):
     """Algorithmic flops of one patch update that the FP32 kernels run on the
-    matrix cores: the top level's 1D interpolation contractions (the
-    2^d 8 d n^{d+1} part of f(q), counted 1 + 2k times) when the top degree
-    is 6 or 7 in 3D (slab-form top level); everything else is vector ALU."""
+    matrix cores: the top level's 1D interpolation contractions when the top
+    degree is 6 or 7 in 3D (slab-form top level).  Of the 2^d 8 d n^{d+1}
+    contraction flops of f(q), half are interpolations (d forward, d
+    transposed) and half collocation derivatives, which stay on the vector
+    ALUs; counted 1 + 2k times.  Everything else is vector ALU."""
     if dim != 3 or levels[0] not in (6, 7):
         return 0
     n = levels[0] + 1
-    return 2 ** dim * 8 * dim * n ** (dim + 1) * (1 + 2 * k)
+    return 2 ** dim * 4 * dim * n ** (dim + 1) * (1 + 2 * k)
 
 
 def mixed_peak(share):
