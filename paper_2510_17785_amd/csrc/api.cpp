@@ -165,6 +165,7 @@ struct pmg_handle {
   void* dense[kMaxLevels] = {nullptr};
   void* cheb = nullptr;
   void* vec_scratch = nullptr;
+  void* metric = nullptr;  // per patch: the metric the patch kernel keeps in LDS (see PatchArgs)
   int64_t vec_bytes = 0;  // bytes per block slot of vec_scratch
   int64_t vec_blocks = 0;
   std::vector<double> bounds;  // host copy, n_patches x (L-1) x 2
@@ -209,6 +210,7 @@ struct pmg_handle {
     a.trunc_inv = trunc_inv;
     a.grid = tune_grid;
     a.map_mode = tune_map;
+    a.metric = metric;
     return a;
   }
 };
@@ -218,7 +220,8 @@ namespace {
 void free_handle(pmg_handle* h) {
   if (!h) return;
   void* ptrs[] = {h->verts, h->mu,          h->patch_vertex, h->patch_geo, h->patch_mu,
-                  h->tab64, h->cheb,        h->vec_scratch,  h->trunc_index, h->trunc_inv};
+                  h->tab64, h->cheb,        h->vec_scratch,  h->trunc_index, h->trunc_inv,
+                  h->metric};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h->tab && h->tab != h->tab64) (void)hipFree(h->tab);  // FP64 handles share the tables
@@ -630,6 +633,18 @@ int setup_common(pmg_handle* h) {
   const size_t ncheb = (size_t)h->n_patches * (L - 1) * 2;
   if ((s = dev_alloc(&h->cheb, ncheb * h->tsize(), &h->device_bytes)) < 0) return cleanup(s);
   h->bounds.assign(ncheb, 0.0);
+  // the metric of the levels that keep it in LDS, once per patch of a mesh:
+  // the patch updates read it instead of recomputing it at every sweep
+  if (!h->patch_geo && var->metric_elems() > 0) {
+    const size_t cnt = (size_t)h->n_patches * var->metric_elems();
+    if ((s = dev_alloc(&h->metric, cnt * h->tsize(), &h->device_bytes)) < 0) return cleanup(s);
+    PatchArgs a = h->args();
+    a.metric = nullptr;  // computed by this launch
+    a.metric_out = h->metric;
+    a.grid = 0;
+    a.map_mode = 0;
+    if ((s = launch_chunks(h, kModeMetric, a, 0, h->n_patches)) < 0) return cleanup(s);
+  }
 
   if (h->bounds_kind == PMG_BOUNDS_LANCZOS) {
     double* dbounds = nullptr;

@@ -23,6 +23,7 @@ enum PatchMode : int {
   kModeResidual = 1,  // gather, evaluate, write the local residual
   kModeSolve = 2,     // read local residuals, local solve, write corrections
   kModeApply = 3,     // read interior vectors, apply one level operator
+  kModeMetric = 4,    // setup: compute the cached levels' metric, write it to metric_out
 };
 
 // Arguments of every per-patch kernel.  Pointers to T-valued arrays are
@@ -71,6 +72,11 @@ struct PatchArgs {
   // most this many workgroups, each taking several patches) and the
   // patch-to-workgroup mapping (0 linear, 1 XCD-aware ranges)
   int32_t grid, map_mode;
+  // metric G of the levels whose metric is kept in LDS, per patch (T,
+  // n_patches_total x metric elements, the LDS layout), computed once at
+  // setup by kModeMetric; null: computed in every patch update
+  const void* metric;
+  void* metric_out;
 };
 
 // One compiled (precision, dim, levels) variant of the patch kernels.
@@ -94,6 +100,9 @@ struct PatchVariant {
   // and the FP64 setup kernel that forms them from the matrix-free operator
   int dense_level[kMaxLevels];
   hipError_t (*launch_dense)(const PatchArgs& a, hipStream_t s);
+  // elements per patch of the metric kept in LDS (0: none), see
+  // PatchArgs::metric; kModeMetric writes them
+  int64_t (*metric_elems)();
 };
 
 const PatchVariant* find_variant(int precision, int dim, int n_levels, const int* levels);

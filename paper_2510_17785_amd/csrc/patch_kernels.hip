@@ -225,6 +225,13 @@ struct Layout {
   }
   static constexpr int G_total = G_rel(L);
   static constexpr bool cache_G = G_total > 0;
+  // some level that the V-cycle applies recomputes its metric at the Gauss
+  // points (from the per-cell Jacobian coefficients)
+  static constexpr bool needs_jc = [] {
+    for (int l = 0; l < L; ++l)
+      if (npts(l) > 0 && !cache_level(l)) return true;
+    return false;
+  }();
   // level vectors in LDS when they fit next to the cached metric, in place of
   // it (above), or, with no metric cached, within the two-workgroup budget;
   // else global scratch
@@ -439,6 +446,7 @@ struct Ctx {
   __device__ T* Gc(int l) const { return lds + Lay::G_off + Lay::G_rel(l); }
   __device__ T* dense(int l) const { return lds + Lay::dense_off + Lay::dense_rel(l); }
   bool dense_ok = false;  // dense level matrices loaded (not in the setup kernels)
+  bool metric_loaded = false;  // the cached metric was read from the setup's copy
   __device__ T* X() const { return lds + Lay::X_off; }
   __device__ T* Out() const { return lds + Lay::Out_off; }
   __device__ T* abuf() const { return lds + Lay::abuf_off; }
@@ -1407,8 +1415,18 @@ __device__ __forceinline__ void apply_level(const Ctx<T, DIM, LV>& c) {
 // Metric at every Gauss point of every level (when cached in LDS) and the
 // per-cell Jacobian coefficients; requires the geometry to be loaded.
 template <typename T, int DIM, class LV>
-__device__ void prepare_geometry(const Ctx<T, DIM, LV>& c) {
+__device__ void prepare_geometry(const Ctx<T, DIM, LV>& c, bool any_level = true) {
   using Lay = Layout<T, DIM, LV>;
+  if (c.metric_loaded) {
+    // the cached metric came from the setup; the Jacobian coefficients only
+    // serve levels that recompute theirs: those the V-cycle applies without
+    // a cached metric, or any level when any_level (a single level apply)
+    if (Lay::needs_jc || any_level) {
+      jacobian_coefficients<T, DIM>(c.geo(), c.jc());
+      __syncthreads();
+    }
+    return;
+  }
   jacobian_coefficients<T, DIM>(c.geo(), c.jc());
   __syncthreads();
   if constexpr (Lay::cache_G) {
@@ -2022,6 +2040,14 @@ __device__ void load_patch(const Ctx<T, DIM, LV>& c, const PatchArgs& a, int pat
     LDSP T* dst = lds_cast(c.dense(l));
     rows_ld_st<NTH, 32 * 32>(sz, [&](int i) { return src[i]; }, [&](int i, T v) { dst[i] = v; });
   }
+  if constexpr (Lay::cache_G) {
+    if (c.metric_loaded) {
+      const T* src = tptr<T>(a.metric) + (int64_t)patch * Lay::G_total;
+      LDSP T* dst = lds_cast(c.lds) + Lay::G_off;
+      rows_ld_st<NTH, Lay::G_total>(Lay::G_total, [&](int i) { return src[i]; },
+                                    [&](int i, T v) { dst[i] = v; });
+    }
+  }
   __syncthreads();
 }
 
@@ -2095,15 +2121,24 @@ __device__ __forceinline__ void patch_update(const PatchArgs& a, Ctx<T, DIM, LV>
           st_r);
     }
   }
+  c.metric_loaded = Lay::cache_G && MODE != kModeMetric && a.metric != nullptr;
   load_patch<T, DIM, LV>(c, a, patch);  // ends with a barrier: the gather is in place too
   c.dense_ok = true;
 #pragma unroll
   for (int l = 0; l < kMaxLevels; ++l)
     if (l < LV::count && Lay::dense_global(l))
       c.dglob[l] = tptr<T>(a.dense[l]) + (int64_t)patch * Lay::level_size(l) * Lay::level_size(l);
-  prepare_geometry<T, DIM, LV>(c);
+  prepare_geometry<T, DIM, LV>(c, MODE == kModeApply);
 
-  if constexpr (MODE == kModeApply) {
+  if constexpr (MODE == kModeMetric) {
+    // setup: keep this patch's metric for the patch updates
+    if constexpr (Lay::cache_G) {
+      T* dst = reinterpret_cast<T*>(a.metric_out) + (int64_t)patch * Lay::G_total;
+      const T* src = c.lds + Lay::G_off;
+      for (int i = tid; i < Lay::G_total; i += NT<T>) dst[i] = src[i];
+    }
+    return;
+  } else if constexpr (MODE == kModeApply) {
     // y = A_{j,q} x for the requested level
     auto run = [&](auto Lc) {
       constexpr int L = decltype(Lc)::value;
@@ -2716,6 +2751,7 @@ struct Variant {
   using Lay = Layout<T, DIM, LV>;
   static size_t lds_bytes(int) { return (size_t)Lay::lds_elems * sizeof(T); }
   static int64_t vec_elems() { return Lay::vec_in_lds ? 0 : (int64_t)Lay::vec_total; }
+  static int64_t metric_elems() { return Lay::cache_G ? (int64_t)Lay::G_total : 0; }
   template <int MODE, bool PERSIST>
   static hipError_t go(const PatchArgs& a, int g, size_t lds, hipStream_t s) {
     hipError_t e = allow_lds(patch_kernel<T, DIM, LV, MODE, PERSIST>, lds);
@@ -2737,6 +2773,7 @@ struct Variant {
       case kModeResidual: return go<kModeResidual, false>(a, g, lds, s);
       case kModeSolve: return go<kModeSolve, false>(a, g, lds, s);
       case kModeApply: return go<kModeApply, false>(a, g, lds, s);
+      case kModeMetric: return go<kModeMetric, false>(a, g, lds, s);
       default: return hipErrorInvalidValue;
     }
   }
@@ -2797,6 +2834,7 @@ PatchVariant make_variant() {
   v.launch = &V::launch;
   v.lds_bytes = &V::lds_bytes;
   v.vec_scratch_elems = &V::vec_elems;
+  v.metric_elems = &V::metric_elems;
   v.vec_scratch_elems64 = &Variant<double, DIM, LV>::vec_elems;
   // the FP64 setup kernels use the FP64 layout of the same level list
   v.launch_diag = &Variant<double, DIM, LV>::launch_diag;
@@ -2824,6 +2862,7 @@ PatchVariant make_variant_bf16() {
   v.launch = &V::launch;
   v.lds_bytes = &V::lds_bytes;
   v.vec_scratch_elems = &V::vec_elems;
+  v.metric_elems = &V::metric_elems;
   v.vec_scratch_elems64 = &Variant<double, DIM, LP>::vec_elems;
   return v;
 }
