@@ -447,6 +447,7 @@ struct Ctx {
   __device__ T* dense(int l) const { return lds + Lay::dense_off + Lay::dense_rel(l); }
   bool dense_ok = false;  // dense level matrices loaded (not in the setup kernels)
   bool metric_loaded = false;  // the cached metric was read from the setup's copy
+  bool geo_needed = true;      // the patch geometry is used (Jacobian or metric)
   __device__ T* X() const { return lds + Lay::X_off; }
   __device__ T* Out() const { return lds + Lay::Out_off; }
   __device__ T* abuf() const { return lds + Lay::abuf_off; }
@@ -2018,7 +2019,7 @@ __device__ void load_patch(const Ctx<T, DIM, LV>& c, const PatchArgs& a, int pat
         (2 * LV::q[t] - 1) * (2 * LV::q[t + 1] - 1), [&](int i) { return src[i]; },
         [&](int i, T v) { dst[i] = v; });
   }
-  load_geometry<T, DIM, NTH>(a, patch, lds_cast(c.geo()), lds_cast(c.mu()));
+  if (c.geo_needed) load_geometry<T, DIM, NTH>(a, patch, lds_cast(c.geo()), lds_cast(c.mu()));
   {
     const T* src = tptr<T>(a.cheb) + (int64_t)patch * 2 * (L - 1);
     LDSP T* dst = lds_cast(c.cheb());
@@ -2122,6 +2123,9 @@ __device__ __forceinline__ void patch_update(const PatchArgs& a, Ctx<T, DIM, LV>
     }
   }
   c.metric_loaded = Lay::cache_G && MODE != kModeMetric && a.metric != nullptr;
+  // with the metric loaded, the geometry only serves levels that recompute
+  // theirs (prepare_geometry computes the Jacobian coefficients for those)
+  c.geo_needed = !c.metric_loaded || Lay::needs_jc || MODE == kModeApply;
   load_patch<T, DIM, LV>(c, a, patch);  // ends with a barrier: the gather is in place too
   c.dense_ok = true;
 #pragma unroll
