@@ -225,6 +225,15 @@ struct Layout {
   }
   static constexpr int G_total = G_rel(L);
   static constexpr bool cache_G = G_total > 0;
+  // levels l .. L-1 all have at most 64 nodes and are stored dense (or are
+  // the coarsest), with the vectors in LDS: one wavefront can run their
+  // V-cycle alone (vcycle_small)
+  static constexpr bool small_from(int l) {
+    if (l >= L || !vec_in_lds) return false;
+    for (int i = l; i < L; ++i)
+      if (level_size(i) > 64 || !(i == L - 1 || dense_level(i))) return false;
+    return true;
+  }
   // some level that the V-cycle applies recomputes its metric at the Gauss
   // points (from the per-cell Jacobian coefficients)
   static constexpr bool needs_jc = [] {
@@ -1748,6 +1757,160 @@ __device__ __forceinline__ void prolong_add(const T* __restrict__ dc, T* __restr
   __syncthreads();
 }
 
+// LDS writes of this wavefront visible to all its lanes: the memory
+// operations of one wavefront complete in order, so only the compiler must
+// be kept from moving accesses across this point
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The V-cycle (Algorithm 2) from level L down, for levels of at most 64
+// nodes stored as dense matrices: run by wavefront 0 alone, lane i owning
+// row i, with the Chebyshev iterates in registers and wavefront-level syncs
+// between the steps (a workgroup barrier per step would leave the other
+// wavefronts idle at every one).  Same arithmetic, in the same order, as
+// vcycle and chebyshev: the dense products sum over j ascending, the
+// transfers contract x, then y, then z.  Leaves d_L in LDS.
+template <typename T, int DIM, class LV, int L>
+__device__ void vcycle_small(const Ctx<T, DIM, LV>& c, int k) {
+  using Lay = Layout<T, DIM, LV>;
+  constexpr int N = Lay::level_size(L);
+  static_assert(N <= 64, "one row per lane");
+  const int i = threadIdx.x;  // < 64
+  LDSP T* d = lds_cast(c.d(L));
+  const LDSP T* r = lds_cast(c.r(L));
+  const LDSP T* dinv = lds_cast(c.dinv(L));
+  if constexpr (L == LV::count - 1) {
+    if (i == 0) d[0] = dinv[0] * r[0];
+    wave_sync();
+    return;
+  } else {
+    if constexpr (L + 2 == LV::count) {
+      if (c.trunc) {
+        // exact solve of a boundary-vertex patch's lowest level (as in vcycle)
+        constexpr int q = LV::q[L], mi = 2 * q - 1;
+        int lo[3], nb[3];
+        for (int a = 0; a < 3; ++a) {
+          const int fl = a < DIM ? (c.pf >> (2 * a)) & 3 : 0;
+          lo[a] = (fl & 1) ? q + 1 : 1;
+          nb[a] = a < DIM ? (fl ? q - 1 : mi) : 1;
+        }
+        const int nu = nb[0] * nb[1] * nb[2];
+        auto full = [&](int u) {
+          const int ox = u % nb[0], oy = (u / nb[0]) % nb[1], oz = u / (nb[0] * nb[1]);
+          return (lo[0] + ox - 1) + mi * ((lo[1] + oy - 1) + (DIM == 3 ? mi * (lo[2] + oz - 1) : 0));
+        };
+        if (i < N) d[i] = T(0);
+        wave_sync();
+        if (i < nu) {
+          const double* row = c.trunc + (int64_t)i * nu;
+          double acc = 0;
+          for (int w = 0; w < nu; ++w) acc += row[w] * double(r[full(w)]);
+          d[full(i)] = T(acc);
+        }
+        wave_sync();
+        return;
+      }
+    }
+    const bool own = i < N;
+    const LDSP T* M = lds_cast(c.dense(L));
+    LDSP T* zb = lds_cast(c.z());    // broadcast buffer for the Chebyshev direction
+    LDSP T* rb = lds_cast(c.res());  // and for the residual
+    const T f = own ? r[i] : T(0), di = own ? dinv[i] : T(0);
+    const T theta = c.cheb()[2 * L], delta = c.cheb()[2 * L + 1];
+    const T sigma = theta / delta;
+    auto Av = [&](const LDSP T* v) {  // row i of the stored level matrix times v
+      T acc = 0;
+      if (own)
+        for (int j = 0; j < N; ++j) acc += M[i * N + j] * v[j];
+      return acc;
+    };
+    // Chebyshev-Jacobi with the iterates of row i in registers (as chebyshev)
+    auto smooth = [&](T& x, bool x_zero) {
+      T rho = T(1) / sigma, res, z;
+      if (x_zero) {
+        res = f;
+        z = di * f / theta;
+        x = 0;
+      } else {
+        if (own) d[i] = x;
+        wave_sync();
+        res = f - Av(d);
+        z = di * res * (T(1) / theta);
+        wave_sync();
+      }
+      for (int it = 0; it + 1 < k; ++it) {
+        const T rho_new = T(1) / (T(2) * sigma - rho);
+        const T c1 = rho_new * rho, c2 = T(2) * rho_new / delta;
+        if (own) zb[i] = z;
+        wave_sync();
+        const T az = Av(zb);
+        wave_sync();
+        x = x + z;
+        res = res - az;
+        z = c1 * z + c2 * di * res;
+        rho = rho_new;
+      }
+      x = x + z;
+    };
+    T x;
+    smooth(x, true);
+    // residual, restriction (x, then y, then z) to level L + 1
+    if (own) d[i] = x;
+    wave_sync();
+    const T res = f - Av(d);
+    if (own) rb[i] = res;
+    wave_sync();
+    constexpr int QF = LV::q[L], QC = LV::q[L + 1];
+    constexpr int mf = 2 * QF - 1, mc = 2 * QC - 1;
+    constexpr int NC = Lay::level_size(L + 1);
+    const LDSP T* P1 = lds_cast(c.tabP(L));
+    if (i < NC) {
+      const int ix = i % mc, iy = (i / mc) % mc, iz = DIM == 3 ? i / (mc * mc) : 0;
+      T acc = 0;
+      for (int cc = 0; cc < (DIM == 3 ? mf : 1); ++cc) {
+        T ay = 0;
+        for (int b = 0; b < mf; ++b) {
+          T ax = 0;
+          for (int a = 0; a < mf; ++a) ax += P1[a * mc + ix] * rb[(cc * mf + b) * mf + a];
+          ay += P1[b * mc + iy] * ax;
+        }
+        if (DIM == 3)
+          acc += P1[cc * mc + iz] * ay;
+        else
+          acc = ay;
+      }
+      lds_cast(c.r(L + 1))[i] = acc;
+    }
+    wave_sync();
+    vcycle_small<T, DIM, LV, L + 1>(c, k);
+    // prolongation and correction (x, then y, then z), post-smoothing
+    const LDSP T* dc = lds_cast(c.d(L + 1));
+    if (own) {
+      const int ax_ = i % mf, by = (i / mf) % mf, cz = DIM == 3 ? i / (mf * mf) : 0;
+      T acc = 0;
+      for (int kk = 0; kk < (DIM == 3 ? mc : 1); ++kk) {
+        T ay = 0;
+        for (int j = 0; j < mc; ++j) {
+          T ax = 0;
+          for (int ii = 0; ii < mc; ++ii) ax += P1[ax_ * mc + ii] * dc[(kk * mc + j) * mc + ii];
+          ay += P1[by * mc + j] * ax;
+        }
+        if (DIM == 3)
+          acc += P1[cz * mc + kk] * ay;
+        else
+          acc = ay;
+      }
+      x = x + acc;
+    }
+    smooth(x, false);
+    if (own) d[i] = x;
+    wave_sync();
+  }
+}
+
 // V-cycle at level L (Algorithm 2): pre-smooth, residual, restrict, recurse,
 // prolongate and correct, post-smooth; the coarsest level is solved exactly.
 template <typename T, int DIM, class LV, int L>
@@ -1806,7 +1969,16 @@ __device__ void vcycle(const Ctx<T, DIM, LV>& c, int k, bool d_zero) {
     apply_vec_epi<T, DIM, LV, L>(c, c.d(L),           // residual
                                  EpiResidual<T, PT>{vp<T, DIM, LV>(c.r(L)), vp<T, DIM, LV>(res)});
     restrict_vec<T, DIM, QF, QC>(res, c.r(L + 1), lds_cast(c.tabP(L)), lds_cast(c.abuf()));  // restriction
-    vcycle<T, DIM, LV, L + 1>(c, k, true);                               // recursion
+    if constexpr (Layout<T, DIM, LV>::small_from(L + 1)) {                // recursion
+      if (c.dense_ok) {
+        if (tid < 64) vcycle_small<T, DIM, LV, L + 1>(c, k);
+        __syncthreads();
+      } else {
+        vcycle<T, DIM, LV, L + 1>(c, k, true);
+      }
+    } else {
+      vcycle<T, DIM, LV, L + 1>(c, k, true);
+    }
     prolong_add<T, DIM, QF, QC>(c.d(L + 1), c.d(L), lds_cast(c.tabP(L)), lds_cast(c.abuf()));  // correction
     chebyshev<T, DIM, LV, L>(c, k, false);           // post-smoothing
   }
