@@ -1626,7 +1626,9 @@ __device__ __forceinline__ void chebyshev(const Ctx<T, DIM, LV>& c, int k, bool 
 // row-major (fine rows, coarse columns).
 
 // restriction: rc = (P1^T (x) ... (x) P1^T) rf
-template <typename T, int DIM, int QF, int QC>
+// STAGE: copy the fine vector into LDS first (it lives in global scratch);
+// without, rf is an LDS vector and is read in place.
+template <typename T, int DIM, int QF, int QC, bool STAGE = true>
 __device__ __forceinline__ void restrict_vec(const T* __restrict__ rf, T* __restrict__ rc,
                                              const LDSP T* __restrict__ P1, LDSP T* __restrict__ ab) {
   constexpr int mf = 2 * QF - 1, mc = 2 * QC - 1;
@@ -1634,10 +1636,15 @@ __device__ __forceinline__ void restrict_vec(const T* __restrict__ rf, T* __rest
   if constexpr (DIM == 3) {
     LDSP T* t1 = ab;                  // [c][b][i]: mf*mf*mc
     LDSP T* t2 = t1 + mf * mf * mc;   // [c][j][i]: mf*mc*mc
-    LDSP T* sf = t2 + mf * mc * mc;   // the fine vector, staged in LDS
+    const LDSP T* sf = nullptr;
+    if constexpr (!STAGE) sf = lds_cast(rf);
+    if constexpr (STAGE) {
+      LDSP T* st = t2 + mf * mc * mc;  // the fine vector, staged in LDS
 #pragma unroll 1
-    for (int idx = tid; idx < mf * mf * mf; idx += NT<T>) sf[idx] = rf[idx];
-    __syncthreads();
+      for (int idx = tid; idx < mf * mf * mf; idx += NT<T>) st[idx] = rf[idx];
+      __syncthreads();
+      sf = st;
+    }
 #pragma unroll 1
     for (int idx = tid; idx < mf * mf * mc; idx += NT<T>) {
       const int i = idx % mc, cb = idx / mc;
@@ -1666,10 +1673,15 @@ __device__ __forceinline__ void restrict_vec(const T* __restrict__ rf, T* __rest
     }
   } else {
     LDSP T* t1 = ab;            // [b][i]: mf*mc
-    LDSP T* sf = t1 + mf * mc;  // the fine vector, staged in LDS
+    const LDSP T* sf = nullptr;
+    if constexpr (!STAGE) sf = lds_cast(rf);
+    if constexpr (STAGE) {
+      LDSP T* st = t1 + mf * mc;  // the fine vector, staged in LDS
 #pragma unroll 1
-    for (int idx = tid; idx < mf * mf; idx += NT<T>) sf[idx] = rf[idx];
-    __syncthreads();
+      for (int idx = tid; idx < mf * mf; idx += NT<T>) st[idx] = rf[idx];
+      __syncthreads();
+      sf = st;
+    }
 #pragma unroll 1
     for (int idx = tid; idx < mf * mc; idx += NT<T>) {
       const int i = idx % mc, b = idx / mc;
@@ -1692,7 +1704,7 @@ __device__ __forceinline__ void restrict_vec(const T* __restrict__ rf, T* __rest
 }
 
 // prolongation and correction: df += (P1 (x) ... (x) P1) dc
-template <typename T, int DIM, int QF, int QC>
+template <typename T, int DIM, int QF, int QC, bool STAGE = true>
 __device__ __forceinline__ void prolong_add(const T* __restrict__ dc, T* __restrict__ df,
                                             const LDSP T* __restrict__ P1, LDSP T* __restrict__ ab) {
   constexpr int mf = 2 * QF - 1, mc = 2 * QC - 1;
@@ -1700,10 +1712,15 @@ __device__ __forceinline__ void prolong_add(const T* __restrict__ dc, T* __restr
   if constexpr (DIM == 3) {
     LDSP T* t1 = ab;                  // [k][j][a]: mc*mc*mf
     LDSP T* t2 = t1 + mc * mc * mf;   // [k][b][a]: mc*mf*mf
-    LDSP T* sc = t2 + mc * mf * mf;   // the coarse vector, staged in LDS
+    const LDSP T* sc = nullptr;
+    if constexpr (!STAGE) sc = lds_cast(dc);
+    if constexpr (STAGE) {
+      LDSP T* st = t2 + mc * mf * mf;  // the coarse vector, staged in LDS
 #pragma unroll 1
-    for (int idx = tid; idx < mc * mc * mc; idx += NT<T>) sc[idx] = dc[idx];
-    __syncthreads();
+      for (int idx = tid; idx < mc * mc * mc; idx += NT<T>) st[idx] = dc[idx];
+      __syncthreads();
+      sc = st;
+    }
 #pragma unroll 1
     for (int idx = tid; idx < mc * mc * mf; idx += NT<T>) {
       const int a = idx % mf, kj = idx / mf;
@@ -1732,10 +1749,15 @@ __device__ __forceinline__ void prolong_add(const T* __restrict__ dc, T* __restr
     }
   } else {
     LDSP T* t1 = ab;            // [j][a]: mc*mf
-    LDSP T* sc = t1 + mc * mf;  // the coarse vector, staged in LDS
+    const LDSP T* sc = nullptr;
+    if constexpr (!STAGE) sc = lds_cast(dc);
+    if constexpr (STAGE) {
+      LDSP T* st = t1 + mc * mf;  // the coarse vector, staged in LDS
 #pragma unroll 1
-    for (int idx = tid; idx < mc * mc; idx += NT<T>) sc[idx] = dc[idx];
-    __syncthreads();
+      for (int idx = tid; idx < mc * mc; idx += NT<T>) st[idx] = dc[idx];
+      __syncthreads();
+      sc = st;
+    }
 #pragma unroll 1
     for (int idx = tid; idx < mc * mf; idx += NT<T>) {
       const int a = idx % mf, j = idx / mf;
@@ -1968,7 +1990,8 @@ __device__ void vcycle(const Ctx<T, DIM, LV>& c, int k, bool d_zero) {
     T* res = c.res();
     apply_vec_epi<T, DIM, LV, L>(c, c.d(L),           // residual
                                  EpiResidual<T, PT>{vp<T, DIM, LV>(c.r(L)), vp<T, DIM, LV>(res)});
-    restrict_vec<T, DIM, QF, QC>(res, c.r(L + 1), lds_cast(c.tabP(L)), lds_cast(c.abuf()));  // restriction
+    constexpr bool STAGE = !Layout<T, DIM, LV>::vec_in_lds;
+    restrict_vec<T, DIM, QF, QC, STAGE>(res, c.r(L + 1), lds_cast(c.tabP(L)), lds_cast(c.abuf()));  // restriction
     if constexpr (Layout<T, DIM, LV>::small_from(L + 1)) {                // recursion
       if (c.dense_ok) {
         if (tid < 64) vcycle_small<T, DIM, LV, L + 1>(c, k);
@@ -1979,7 +2002,7 @@ __device__ void vcycle(const Ctx<T, DIM, LV>& c, int k, bool d_zero) {
     } else {
       vcycle<T, DIM, LV, L + 1>(c, k, true);
     }
-    prolong_add<T, DIM, QF, QC>(c.d(L + 1), c.d(L), lds_cast(c.tabP(L)), lds_cast(c.abuf()));  // correction
+    prolong_add<T, DIM, QF, QC, STAGE>(c.d(L + 1), c.d(L), lds_cast(c.tabP(L)), lds_cast(c.abuf()));  // correction
     chebyshev<T, DIM, LV, L>(c, k, false);           // post-smoothing
   }
 }
@@ -2044,6 +2067,18 @@ __device__ __forceinline__ bool interior_node(int f, int q, int idx, int* ci) {
   if (ci) *ci = c;
   return true;
 }
+
+// evaluate epilogue (equation main:4), fused into the segment operator's
+// last phase: r = b - A u-bar on the unmasked rows, zero on the masked rows
+// of a boundary-vertex patch
+template <typename T, int DIM, class PT>
+struct EpiEvaluate {
+  PT r;
+  int pf, p;
+  __device__ __forceinline__ void operator()(int i, T v) const {
+    r[i] = (pf == 0 || interior_node<DIM>(pf, p, i, nullptr)) ? r[i] - v : T(0);
+  }
+};
 
 // Mesh vertex at indices ii (each in -1 .. N+1), continued linearly across
 // the boundary for -1 and N+1 (ghost vertices: only a finite metric is
@@ -2339,10 +2374,18 @@ __device__ __forceinline__ void patch_update(const PatchArgs& a, Ctx<T, DIM, LV>
     if constexpr (MODE == kModeSmooth || MODE == kModeResidual) {
       // evaluate: r_j = b_j - Pi_j A-bar_j u-bar_j (equation main:4); masked
       // rows (boundary-vertex patches) are set to zero
-      apply_level<T, DIM, LV, 0>(c);
-      for (int i = tid; i < N0; i += NT<T>)
-        r0[i] = (pf == 0 || interior_node<DIM>(pf, a.p, i, nullptr)) ? r0[i] - c.Out()[i] : T(0);
-      __syncthreads();
+      if constexpr (Lay::use_seg(0)) {
+        using PT = VecPtr<T, DIM, LV>;
+        apply3seg<T, LV::q[0], true, Lay::cache_level(0)>(
+            lds_cast(c.X()), EpiEvaluate<T, DIM, PT>{vp<T, DIM, LV>(r0), pf, a.p}, lds_cast(c.abuf()),
+            lds_cast(c.tabB(0)), lds_cast(c.tabDc(0)), lds_cast(c.jc()), lds_cast(c.mu()),
+            lds_cast(c.Gc(0)));
+      } else {
+        apply_level<T, DIM, LV, 0>(c);
+        for (int i = tid; i < N0; i += NT<T>)
+          r0[i] = (pf == 0 || interior_node<DIM>(pf, a.p, i, nullptr)) ? r0[i] - c.Out()[i] : T(0);
+        __syncthreads();
+      }
       if constexpr (MODE == kModeResidual) {
         double* out = a.out + (int64_t)patch * N0;
         for (int i = tid; i < N0; i += NT<T>) out[i] = double(r0[i]);
