@@ -729,6 +729,9 @@ int patch_setup_impl(const pmg_mesh* mesh, const double* coeff, int p, const pmg
   const PatchVariant* var = nullptr;
   PMG_TRY(check_opts(o, dim, p, levels, L, var));
   PMG_TRY(check_mesh(dim, N, mesh->vertices, p));
+  for (size_t i = 0, nc = (size_t)ipow(N, dim); i < nc; ++i)
+    if (!(coeff[i] > 0.0) || !std::isfinite(coeff[i]))
+      return fail(PMG_ERR_INVALID_ARG, "coefficient of cell %zu is %g", i, coeff[i]);
   PMG_TRY(init_tables_once());
   pmg_handle* h = new_handle(o, dim, N, p, L, levels, var);
   auto cleanup = [&](int s) {
@@ -776,9 +779,6 @@ int patch_setup_impl(const pmg_mesh* mesh, const double* coeff, int p, const pmg
       (e = hipMemcpy(h->patch_vertex, order.data(), order.size() * sizeof(int32_t),
                      hipMemcpyHostToDevice)))
     return cleanup(fail(PMG_ERR_HIP, "upload: %s", hipGetErrorString(e)));
-  for (size_t i = 0; i < nc; ++i)
-    if (!(coeff[i] > 0.0) || !std::isfinite(coeff[i]))
-      return cleanup(fail(PMG_ERR_INVALID_ARG, "coefficient of cell %zu is %g", i, coeff[i]));
 
   if ((s = setup_common(h)) < 0) return cleanup(s);
   *out = h;

@@ -82,3 +82,55 @@ def test_network_file_rejected_before_device_work(tmp_path):
     wrong = tmp_path / "wrong.bin"
     wrong.write_bytes(b"NOTANET\x00" + b"\x00" * 64)
     assert lib.pmg_mlp_load(str(wrong).encode(), 64, None, ctypes.byref(h), ctypes.byref(mg)) == L.PMG_ERR_INVALID_ARG
+
+
+def test_mesh_size_and_degree_checked():
+    from paper_2510_17785_amd import _lib as L
+    X1 = synth.make_vertices(3, 1, 0.0, 1)
+    st, msg, h = _setup(3, 1, 2, X1, (2, 1))
+    assert st == L.PMG_ERR_INVALID_ARG and "at least 2 cells" in msg and h is None
+    X = synth.make_vertices(3, 4, 0.0, 1)
+    st, msg, _ = _setup(3, 4, 0, X, None)
+    assert st == L.PMG_ERR_INVALID_ARG and "degree" in msg
+
+
+@pytest.mark.parametrize("bad", [0.0, -1.0, float("nan"), float("inf")])
+def test_coefficients_checked_before_device_work(bad):
+    from paper_2510_17785_amd import _lib as L
+    from paper_2510_17785_amd.api import _mesh
+    lib = L.load()
+    X = synth.make_vertices(3, 4, 0.0, 1)
+    m, keep = _mesh(3, 4, X)
+    mu = np.ones(4 ** 3)
+    mu[37] = bad
+    o = L.PmgOpts()
+    L.check(lib.pmg_default_opts(ctypes.byref(o)))
+    o.n_levels = 3
+    for i, q in enumerate((4, 2, 1)):
+        o.levels[i] = q
+    h = ctypes.c_void_p()
+    st = lib.pmg_patch_setup(ctypes.byref(m), mu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 4,
+                             ctypes.byref(o), ctypes.byref(h))
+    assert st == L.PMG_ERR_INVALID_ARG and h.value is None
+    assert "coefficient of cell 37" in lib.pmg_last_error().decode()
+
+
+def test_independent_patch_and_batch_counts_checked():
+    from paper_2510_17785_amd import _lib as L
+    lib = L.load()
+    o = L.PmgOpts()
+    L.check(lib.pmg_default_opts(ctypes.byref(o)))
+    V, mu = synth.make_random_patches(3, 2, 0.2, (-1, 1), 3)
+    V = np.ascontiguousarray(V)
+    mu = np.ascontiguousarray(mu)
+    D = ctypes.POINTER(ctypes.c_double)
+    h = ctypes.c_void_p()
+    st = lib.pmg_patches_setup(3, 0, V.ctypes.data_as(D), mu.ctypes.data_as(D), 4, ctypes.byref(o),
+                               ctypes.byref(h))
+    assert st == L.PMG_ERR_INVALID_ARG and "patch count" in lib.pmg_last_error().decode()
+    mu[1, 3] = -2.0
+    st = lib.pmg_patches_setup(3, 2, V.ctypes.data_as(D), mu.ctypes.data_as(D), 4, ctypes.byref(o),
+                               ctypes.byref(h))
+    assert st == L.PMG_ERR_INVALID_ARG and "patch 1 cell 3" in lib.pmg_last_error().decode()
+    st = lib.pmg_batch_setup(None, None, None, 0, ctypes.byref(o), ctypes.byref(h))
+    assert st == L.PMG_ERR_INVALID_ARG and h.value is None
