@@ -19,7 +19,9 @@ Components, each formed explicitly:
     Methods for Sparse Linear Systems, 2nd ed., Algorithm 12.1) with D^{-1}
     applied to the residuals;
   * V-cycle: pre-smooth, residual, restrict, recurse, prolongate, correct,
-    post-smooth (Algorithm 2).
+    post-smooth (Algorithm 2);
+  * the local solver's measure of quality in Section 3.2: conjugate gradients
+    on the patch problem, preconditioned by one V-cycle.
 """
 from __future__ import annotations
 
@@ -161,3 +163,40 @@ class LocalSolver:
     def exact_solve(self, r):
         """The exact local solve (the limit of many V-cycles): LU of A_{j,p}."""
         return np.linalg.solve(self.A[0], r)
+
+    def pcg(self, b, rtol, maxit):
+        """CG on A_{j,p} x = b preconditioned by solve() (Section 3.2 measures
+        the local solver by the iterations of exactly this combination)."""
+        return pcg(lambda v: self.A[0] @ v, self.solve, b, rtol, maxit)
+
+
+def pcg(apply_A, precondition, b, rtol, maxit):
+    """Preconditioned conjugate gradients from x = 0 (Hestenes and Stiefel,
+    1952; Saad, Iterative Methods for Sparse Linear Systems, 2nd ed.,
+    Algorithm 9.1).  Stops after the first iteration k with
+    ||r_k|| <= rtol ||b||, or after maxit iterations.
+    Returns (x_k, k, ||r_k|| / ||b||); b = 0 gives (0, 0, 0)."""
+    x = np.zeros_like(b)
+    bnorm = np.linalg.norm(b)
+    if bnorm == 0.0:
+        return x, 0, 0.0
+    r = b.copy()
+    k = 0
+    if maxit <= 0:
+        return x, 0, 1.0
+    z = precondition(r)
+    p = z.copy()
+    rz = r @ z
+    while True:
+        Ap = apply_A(p)
+        alpha = rz / (p @ Ap)          # step length along p
+        x = x + alpha * p
+        r = r - alpha * Ap
+        k += 1
+        if np.linalg.norm(r) <= rtol * bnorm or k >= maxit:
+            break
+        z = precondition(r)
+        rz_new = r @ z
+        p = z + (rz_new / rz) * p      # next direction, A-conjugate to the previous ones
+        rz = rz_new
+    return x, k, np.linalg.norm(r) / bnorm

@@ -248,24 +248,64 @@ def test_paper_single_patch_pcg_counts():
         s = pmg.LocalSolver(fem.PatchGeometry(X, np.ones(2 ** d)), levels, cheb_degree=1)
         s.bounds = None
         s.intervals = [(0.5, 3.5)] * (len(levels) - 1)
-        A = s.A[0]
-        b = np.random.default_rng(p).standard_normal(A.shape[0])
-        x = np.zeros_like(b)
-        r = b.copy()
-        z = s.solve(r)
-        dd = z.copy()
-        rz = r @ z
-        for k in range(1, 101):
-            Ad = A @ dd
-            al = rz / (dd @ Ad)
-            x += al * dd
-            r -= al * Ad
-            if np.linalg.norm(r) <= 1e-8 * np.linalg.norm(b):
-                break
-            z = s.solve(r)
-            rz, rz_old = r @ z, rz
-            dd = z + (rz / rz_old) * dd
+        b = np.random.default_rng(p).standard_normal(s.A[0].shape[0])
+        x, k, rel = s.pcg(b, 1e-8, 100)
+        assert rel <= 1e-8
         assert 0.7 * iters <= k <= 1.3 * iters, (p, k)
+
+
+def _spd(n, eigs, seed):
+    Q, _ = np.linalg.qr(np.random.default_rng(seed).standard_normal((n, n)))
+    return (Q * np.asarray(eigs)) @ Q.T
+
+
+def test_pcg_reaches_the_direct_solution():
+    # a random SPD matrix of condition 1e3 with the Jacobi preconditioner:
+    # the returned x is the LU solution to within cond x rtol
+    eigs = np.geomspace(1.0, 1e3, 40)
+    A = _spd(40, eigs, 1) + np.diag(np.linspace(0, 5, 40))
+    b = np.random.default_rng(2).standard_normal(40)
+    x, k, rel = pmg.pcg(lambda v: A @ v, lambda r: r / np.diag(A), b, 1e-13, 500)
+    xs = np.linalg.solve(A, b)
+    assert rel <= 1e-13 and k < 500
+    assert np.linalg.norm(x - xs) <= 1e-9 * np.linalg.norm(xs)
+    assert abs(np.linalg.norm(b - A @ x) / np.linalg.norm(b) - rel) <= 1e-12
+
+
+def test_pcg_finite_termination():
+    # unpreconditioned CG ends in at most as many iterations as A has
+    # distinct eigenvalues (the Krylov space then holds the solution), and
+    # in one iteration with the exact inverse as preconditioner
+    A = _spd(30, np.repeat([1.0, 3.0, 7.0, 20.0], [5, 10, 8, 7]), 3)
+    b = np.random.default_rng(4).standard_normal(30)
+    _, k, rel = pmg.pcg(lambda v: A @ v, lambda r: r, b, 1e-10, 100)
+    assert k == 4 and rel <= 1e-10
+    Ainv = np.linalg.inv(A)
+    x, k, rel = pmg.pcg(lambda v: A @ v, lambda r: Ainv @ r, b, 1e-10, 100)
+    assert k == 1 and rel <= 1e-10
+    # maxit and a zero right-hand side
+    x, k, rel = pmg.pcg(lambda v: A @ v, lambda r: r, b, 0.0, 2)
+    assert k == 2 and 0 < rel < 1
+    x, k, rel = pmg.pcg(lambda v: A @ v, lambda r: r, np.zeros(30), 1e-10, 100)
+    assert k == 0 and rel == 0.0 and not x.any()
+    x, k, rel = pmg.pcg(lambda v: A @ v, lambda r: r, b, 1e-10, 0)
+    assert k == 0 and rel == 1.0 and not x.any()
+
+
+def test_pcg_of_the_local_solver_is_monotone_in_energy():
+    # CG minimises the A-norm of the error over growing Krylov spaces: the
+    # error energy of x_k never increases with k (distorted Q4 patch, the
+    # V-cycle as preconditioner)
+    s = _solver(3, (4, 2, 1), seed=7)
+    b = np.random.default_rng(8).standard_normal(s.A[0].shape[0])
+    xs = s.exact_solve(b)
+    prev = np.inf
+    for kmax in range(1, 8):
+        x, k, _ = s.pcg(b, 0.0, kmax)
+        e = x - xs
+        en = e @ (s.A[0] @ e)
+        assert k == kmax and en <= prev * (1 + 1e-12)
+        prev = en
 
 
 # ---------------------------------------------------------------------------
