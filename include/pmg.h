@@ -168,6 +168,28 @@ int pmg_patch_apply(pmg_handle* h, int32_t level, const double* x, double* y);
  * from zero on A_{j,p} d = r[j].  r, d: device, n_patches x (2p-1)^dim. */
 int pmg_patch_local_solve(pmg_handle* h, const double* r, double* d);
 
+/* Largest maxit that pmg_patch_pcg accepts (bounds the kernel's run time). */
+#define PMG_PCG_MAXIT_LIMIT 10000
+
+/* Batched patch CG, the measure of the local solver in Section 3.2: for every
+ * patch j, conjugate gradients on A_{j,p} x = b[j] from x = 0, preconditioned
+ * by N_MG V-cycles (Algorithm 2) with the handle's levels, Chebyshev degree
+ * and intervals (degree 1 on an interval with a + b = 4 is the paper's damped
+ * Jacobi, omega = 1/2).  A patch stops after the first iteration k with
+ * ||r_k|| <= rtol ||b[j]||, or after maxit; each patch runs its own count.
+ * b, x: device, n_patches x (2p-1)^dim FP64, interior x-fastest.
+ * iters: device, n_patches int32 (k; 0 if b[j] = 0 or maxit = 0);
+ * relres: device, n_patches FP64 (||r_k|| / ||b[j]||, 0 if b[j] = 0).
+ * Residuals are the updated ones of the recurrence, as in the method.
+ * FP64 handles only (PMG_ERR_UNSUPPORTED otherwise), and not for handles
+ * with boundary-vertex patches (PMG_ERR_UNSUPPORTED).  PMG_ERR_INVALID_ARG:
+ * null pointer, bounds not set, rtol negative or not finite, maxit outside
+ * 0..PMG_PCG_MAXIT_LIMIT.  The first call allocates the handle's work
+ * vectors (2 x n_patches x (2p-1)^dim FP64), kept until pmg_patch_destroy.
+ * Asynchronous on the handle's stream. */
+int pmg_patch_pcg(pmg_handle* h, const double* b, double* x, double rtol, int32_t maxit,
+                  int32_t* iters, double* relres);
+
 /* Inverse diagonal of A_{j,q} at level `level`: out device, n_patches x (2q-1)^dim. */
 int pmg_get_inv_diag(const pmg_handle* h, int32_t level, double* out);
 

@@ -153,6 +153,19 @@ class PatchSmoother:
         L.check(self._lib.pmg_patch_local_solve(self._h, _dptr(r), _dptr(d)))
         return d
 
+    def pcg(self, b: torch.Tensor, rtol: float = 1e-8, maxit: int = 200):
+        """pmg_patch_pcg: CG on every patch problem A_{j,p} x = b[j],
+        preconditioned by the V-cycle.  Returns device tensors (x, iterations
+        int32, ||r_k|| / ||b[j]||)."""
+        if tuple(b.shape) != (self.n_patches, self.level_sizes[0]):
+            raise ValueError("b must have shape (n_patches, top level size)")
+        x = torch.empty_like(b)
+        it = torch.empty(self.n_patches, dtype=torch.int32, device=b.device)
+        rel = torch.empty(self.n_patches, dtype=torch.float64, device=b.device)
+        L.check(self._lib.pmg_patch_pcg(self._h, _dptr(b), _dptr(x), float(rtol), int(maxit),
+                                        it.data_ptr(), _dptr(rel)))
+        return x, it, rel
+
     def inv_diag(self, level: int) -> torch.Tensor:
         out = torch.empty((self.n_patches, self.level_sizes[level]), dtype=torch.float64,
                           device="cuda")

@@ -166,6 +166,7 @@ struct pmg_handle {
   void* cheb = nullptr;
   void* vec_scratch = nullptr;
   void* metric = nullptr;  // per patch: the metric the patch kernel keeps in LDS (see PatchArgs)
+  double* pcg_work = nullptr;  // pmg_patch_pcg: residual and search direction per patch
   int64_t vec_bytes = 0;  // bytes per block slot of vec_scratch
   int64_t vec_blocks = 0;
   std::vector<double> bounds;  // host copy, n_patches x (L-1) x 2
@@ -221,7 +222,7 @@ void free_handle(pmg_handle* h) {
   if (!h) return;
   void* ptrs[] = {h->verts, h->mu,          h->patch_vertex, h->patch_geo, h->patch_mu,
                   h->tab64, h->cheb,        h->vec_scratch,  h->trunc_index, h->trunc_inv,
-                  h->metric};
+                  h->metric,  h->pcg_work};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h->tab && h->tab != h->tab64) (void)hipFree(h->tab);  // FP64 handles share the tables
@@ -1286,6 +1287,34 @@ int pmg_patch_local_solve(pmg_handle* h, const double* r, double* d) {
   a.in = r;
   a.out = d;
   return launch_chunks(h, kModeSolve, a, 0, h->n_patches);
+}
+
+int pmg_patch_pcg(pmg_handle* h, const double* b, double* x, double rtol, int32_t maxit,
+                  int32_t* iters, double* relres) {
+  if (!h || !b || !x || !iters || !relres) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  if (!h->bounds_valid) return fail(PMG_ERR_INVALID_ARG, "Chebyshev bounds not set");
+  if (!(rtol >= 0.0) || !std::isfinite(rtol)) return fail(PMG_ERR_INVALID_ARG, "rtol must be finite and >= 0");
+  if (maxit < 0 || maxit > PMG_PCG_MAXIT_LIMIT)
+    return fail(PMG_ERR_INVALID_ARG, "maxit %d outside 0..%d", maxit, PMG_PCG_MAXIT_LIMIT);
+  if (h->precision != PMG_FP64) return fail(PMG_ERR_UNSUPPORTED, "patch CG runs on FP64 handles only");
+  if (h->with_boundary)
+    return fail(PMG_ERR_UNSUPPORTED, "patch CG is not available with boundary-vertex patches");
+  if (!h->pcg_work) {
+    int s = dev_alloc(&h->pcg_work, (size_t)h->n_patches * 2 * h->level_size(0) * sizeof(double),
+                      &h->device_bytes);
+    if (s < 0) return s;
+  }
+  PatchArgs a = h->args();
+  a.in = b;
+  a.out = x;
+  a.pcg_rtol = rtol;
+  a.pcg_maxit = maxit;
+  a.pcg_work = h->pcg_work;
+  a.pcg_iters = iters;
+  a.pcg_relres = relres;
+  a.grid = 0;
+  a.map_mode = 0;
+  return launch_chunks(h, kModePcg, a, 0, h->n_patches);
 }
 
 int pmg_get_inv_diag(const pmg_handle* h, int32_t level, double* out) {

@@ -24,6 +24,7 @@ enum PatchMode : int {
   kModeSolve = 2,     // read local residuals, local solve, write corrections
   kModeApply = 3,     // read interior vectors, apply one level operator
   kModeMetric = 4,    // setup: compute the cached levels' metric, write it to metric_out
+  kModePcg = 5,       // FP64 only: CG on each patch problem, preconditioned by the V-cycle
 };
 
 // Arguments of every per-patch kernel.  Pointers to T-valued arrays are
@@ -77,6 +78,14 @@ struct PatchArgs {
   // setup by kModeMetric; null: computed in every patch update
   const void* metric;
   void* metric_out;
+  // kModePcg: in = b, out = x (n_patches_total x size_0 each); work holds the
+  // residual and search direction (2 x size_0 per patch); per patch the
+  // iterations taken and ||r_k|| / ||b||
+  double pcg_rtol;
+  int32_t pcg_maxit;
+  double* pcg_work;
+  int32_t* pcg_iters;
+  double* pcg_relres;
 };
 
 // One compiled (precision, dim, levels) variant of the patch kernels.

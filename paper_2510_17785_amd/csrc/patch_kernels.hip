@@ -2259,6 +2259,106 @@ __device__ void load_patch(const Ctx<T, DIM, LV>& c, const PatchArgs& a, int pat
   __syncthreads();
 }
 
+// Sum of v over the FP64 workgroup; every thread gets the same value (the
+// per-wave partials are added in one order).  red: NT<double> / 64 doubles.
+__device__ double block_sum(double v, double* red) {
+  using T = double;
+  // wavefront shuffle reduction, then across the waves of the block
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0;
+  for (int w = 0; w < NT<T> / 64; ++w) s += red[w];
+  __syncthreads();
+  return s;
+}
+
+// Conjugate gradients preconditioned by N_MG V-cycles from zero (Algorithm 2)
+// on one patch problem A_{j,p} x = b_j, from x = 0 (Hestenes and Stiefel; Saad,
+// Iterative Methods for Sparse Linear Systems, Algorithm 9.1).  Section 3.2
+// judges the local solver by the iterations of this method.  Stops after the
+// first iteration with ||r_k|| <= rtol ||b|| or after maxit iterations.
+// FP64: x, the residual and the search direction live in global memory (this
+// patch's rows; a row is touched by one thread only, so they need no
+// barrier), the operator input and the V-cycle vectors in the patch context.
+// Each exit test uses a workgroup sum that every thread holds, so all
+// threads leave the loop together.
+template <int DIM, class LV>
+__device__ void patch_pcg(const Ctx<double, DIM, LV>& c, const PatchArgs& a, int patch) {
+  using T = double;
+  constexpr int N = Layout<T, DIM, LV>::level_size(0);
+  const int tid = threadIdx.x;
+  double* red = c.abuf();  // unused between operator applications and V-cycles
+  const double* b = a.in + (int64_t)patch * N;
+  double* x = a.out + (int64_t)patch * N;
+  double* r = a.pcg_work + (int64_t)patch * 2 * N;
+  double* p = r + N;
+  T* r0 = c.r(0);         // V-cycle right-hand side
+  const T* d0 = c.d(0);   // V-cycle result
+  T* v = c.z();           // operator input
+  auto precondition = [&]() {
+    for (int it = 0; it < a.n_vcycles; ++it) vcycle<T, DIM, LV, 0>(c, a.cheb_degree, it == 0);
+    __syncthreads();
+  };
+  double bb = 0;
+  for (int i = tid; i < N; i += NT<T>) {
+    const double bi = b[i];
+    x[i] = 0.0;
+    r[i] = bi;
+    r0[i] = bi;
+    bb += bi * bi;
+  }
+  bb = block_sum(bb, red);
+  const double stop = a.pcg_rtol * a.pcg_rtol * bb;
+  double rr = bb;
+  int k = 0;
+  if (bb > 0.0 && a.pcg_maxit > 0) {
+    precondition();
+    double rz = 0;
+    for (int i = tid; i < N; i += NT<T>) {
+      const double zi = d0[i];
+      p[i] = zi;
+      rz += r[i] * zi;
+    }
+    rz = block_sum(rz, red);
+#pragma unroll 1
+    for (;;) {
+      for (int i = tid; i < N; i += NT<T>) v[i] = p[i];
+      __syncthreads();
+      apply_vec<T, DIM, LV, 0>(c, v);
+      const T* Ap = c.Out();
+      double pap = 0;
+      for (int i = tid; i < N; i += NT<T>) pap += p[i] * Ap[i];
+      pap = block_sum(pap, red);
+      const double alpha = rz / pap;
+      double rn = 0;
+      for (int i = tid; i < N; i += NT<T>) {
+        x[i] += alpha * p[i];
+        const double ri = r[i] - alpha * Ap[i];
+        r[i] = ri;
+        r0[i] = ri;
+        rn += ri * ri;
+      }
+      rr = block_sum(rn, red);
+      ++k;
+      if (rr <= stop || k >= a.pcg_maxit) break;
+      precondition();
+      double rzn = 0;
+      for (int i = tid; i < N; i += NT<T>) rzn += r[i] * d0[i];
+      rzn = block_sum(rzn, red);
+      const double beta = rzn / rz;
+      rz = rzn;
+      for (int i = tid; i < N; i += NT<T>) p[i] = d0[i] + beta * p[i];
+    }
+  }
+  if (tid == 0) {
+    a.pcg_iters[patch] = k;
+    a.pcg_relres[patch] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+  }
+}
+
 // One patch update (mode: smooth, residual, local solve or level apply).
 template <typename T, int DIM, class LV, int MODE>
 __device__ __forceinline__ void patch_update(const PatchArgs& a, Ctx<T, DIM, LV>& c, int patch) {
@@ -2348,6 +2448,9 @@ __device__ __forceinline__ void patch_update(const PatchArgs& a, Ctx<T, DIM, LV>
       const T* src = c.lds + Lay::G_off;
       for (int i = tid; i < Lay::G_total; i += NT<T>) dst[i] = src[i];
     }
+    return;
+  } else if constexpr (MODE == kModePcg) {
+    if constexpr (std::is_same<T, double>::value) patch_pcg<DIM, LV>(c, a, patch);
     return;
   } else if constexpr (MODE == kModeApply) {
     // y = A_{j,q} x for the requested level
@@ -2564,20 +2667,6 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t n) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
   return z ^ (z >> 31);
-}
-
-__device__ double block_sum(double v, double* red) {
-  using T = double;
-  // wavefront shuffle reduction, then across the waves of the block
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  double s = 0;
-  for (int w = 0; w < NT<T> / 64; ++w) s += red[w];
-  __syncthreads();
-  return s;
 }
 
 // number of eigenvalues of the symmetric tridiagonal (al, be) below x
@@ -2993,6 +3082,9 @@ struct Variant {
       case kModeSolve: return go<kModeSolve, false>(a, g, lds, s);
       case kModeApply: return go<kModeApply, false>(a, g, lds, s);
       case kModeMetric: return go<kModeMetric, false>(a, g, lds, s);
+      case kModePcg:
+        if constexpr (std::is_same<T, double>::value) return go<kModePcg, false>(a, g, lds, s);
+        return hipErrorInvalidValue;
       default: return hipErrorInvalidValue;
     }
   }

@@ -1,0 +1,140 @@
+"""Batched patch CG (pmg_patch_pcg) against the FP64 oracle's pcg: CG on
+every patch problem A_{j,p} x = b_j preconditioned by the local V-cycle, the
+measure of the local solver in Section 3.2.
+
+Cases: the paper's setting (undeformed 2D patches, degree-1 smoothing with
+omega = 1/2, p = 3 and 7), distorted 3D patches with Lanczos intervals and
+Chebyshev degree 3 (p = 4 and 7), the patches of a mesh handle, fixed
+iteration counts, and the degenerate inputs.
+
+Tolerances: FP64 throughout.  One apply and one V-cycle agree with the
+oracle to about 1e-13 relative; CG carries that through each iteration with
+growth of the order of the condition number of the preconditioned operator
+(below 10 here), so iterates agree to 1e-10 and the final relative residuals
+(at 1e-8) to 1e-4 of their value.  Iteration counts are equal unless an
+oracle residual lies within 1% of the stopping threshold, where a rounding
+difference may move the stop by one iteration (then +-1 is accepted).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import synth  # noqa: E402
+from oracle import fem, lanczos, pmg  # noqa: E402
+
+from gpu_common import case, oracle_solver, rel_err  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+OMEGA_HALF = (0.5, 3.5 / 1.1)   # lambda bounds whose interval is [0.5, 3.5]: theta = 2
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def _compare(solvers, b, x, it, rel, rtol, maxit):
+    x, it, rel = x.cpu().numpy(), it.cpu().numpy(), rel.cpu().numpy()
+    for j, s in enumerate(solvers):
+        xo, ko, ro = s.pcg(b[j], rtol, maxit)
+        near = False
+        if rtol > 0 and ko < maxit:
+            _, _, prev = s.pcg(b[j], 0.0, ko - 1) if ko > 1 else (None, 0, 1.0)
+            near = abs(ro / rtol - 1) < 0.01 or abs(prev / rtol - 1) < 0.01
+        if near:
+            assert abs(int(it[j]) - ko) <= 1, (j, it[j], ko)
+            continue
+        assert it[j] == ko, (j, it[j], ko)
+        assert rel_err(x[j], xo) <= 1e-10, j
+        assert abs(rel[j] - ro) <= 1e-4 * ro + 1e-15, (j, rel[j], ro)
+
+
+@pytest.mark.parametrize("p,levels", [(3, (3, 1)), (7, (7, 3, 1))])
+def test_paper_setting_2d(dev, p, levels):
+    from paper_2510_17785_amd import PatchBatch
+    n = 6
+    X, mu = synth.make_random_patches(2, n, 0.0, None, 5)
+    B = PatchBatch(2, p, X, mu, levels=levels, cheb_degree=1)
+    B.set_bounds(np.broadcast_to(np.array(OMEGA_HALF), (n, len(levels) - 1, 2)).copy())
+    b = np.random.default_rng(p).standard_normal((n, B.level_sizes[0]))
+    x, it, rel = B.pcg(torch.tensor(b, device=dev), 1e-8, 100)
+    solvers = []
+    for j in range(n):
+        s = pmg.LocalSolver(fem.PatchGeometry(X[j], mu[j]), levels, cheb_degree=1)
+        s.set_bounds([OMEGA_HALF] * (len(levels) - 1))
+        solvers.append(s)
+    _compare(solvers, b, x, it, rel, 1e-8, 100)
+    print(f"\n2D Q{p} omega = 1/2, levels {levels}: CG iterations {it.cpu().numpy().tolist()}")
+
+
+@pytest.mark.parametrize("p,levels,n", [(4, (4, 2, 1), 13), (7, (7, 3, 1), 2)])
+def test_distorted_3d_lanczos(dev, p, levels, n):
+    from paper_2510_17785_amd import PatchBatch
+    X, mu = synth.make_random_patches(3, n, 0.25, (-2, 2), 60 + p)
+    B = PatchBatch(3, p, X, mu, levels=levels, precision="fp64")
+    b = np.random.default_rng(70 + p).standard_normal((n, B.level_sizes[0]))
+    x, it, rel = B.pcg(torch.tensor(b, device=dev), 1e-8, 60)
+    solvers = []
+    for j in range(n):
+        s = pmg.LocalSolver(fem.PatchGeometry(X[j], mu[j]), levels)
+        s.set_bounds([lanczos.bounds(s.A[l], s.dinv[l], 12, 0, j, l) for l in range(len(levels) - 1)])
+        solvers.append(s)
+    _compare(solvers, b, x, it, rel, 1e-8, 60)
+    # fixed iteration count: every iterate compared, not only the stop
+    x, it, rel = B.pcg(torch.tensor(b, device=dev), 0.0, 3)
+    assert (it.cpu().numpy() == 3).all()
+    _compare(solvers, b, x, it, rel, 0.0, 3)
+
+
+def test_mesh_handle_patches(dev):
+    from paper_2510_17785_amd import PatchSmoother
+    w, p, levels, X, mu, _ = case("3d-n16-q4", 4)
+    S = PatchSmoother(w.dim, w.n, p, X, mu, levels=levels, precision="fp64")
+    b = np.random.default_rng(3).standard_normal((S.n_patches, S.level_sizes[0]))
+    x, it, rel = S.pcg(torch.tensor(b, device=dev), 1e-8, 50)
+    mesh = fem.Mesh(w.dim, w.n, X, mu)
+    verts = [int(v) for v in S.patch_vertices()]
+    n1 = w.n + 1
+    solvers = [oracle_solver(mesh, (v % n1, (v // n1) % n1, v // (n1 * n1)), levels) for v in verts]
+    _compare(solvers, b, x, it, rel, 1e-8, 50)
+
+
+def test_degenerate_inputs(dev):
+    from paper_2510_17785_amd import PatchBatch
+    X, mu = synth.make_random_patches(3, 3, 0.2, None, 9)
+    B = PatchBatch(3, 4, X, mu, levels=(4, 2, 1), precision="fp64")
+    b = np.random.default_rng(1).standard_normal((3, B.level_sizes[0]))
+    b[1] = 0.0
+    bt = torch.tensor(b, device=dev)
+    x, it, rel = B.pcg(bt, 1e-8, 50)
+    assert it[1].item() == 0 and rel[1].item() == 0.0 and not x[1].any()
+    assert (it[[0, 2]] > 0).all() and (rel[[0, 2]] <= 1e-8).all()
+    x, it, rel = B.pcg(bt, 1e-8, 0)
+    assert not x.any() and not it.any()
+    assert rel.cpu().numpy().tolist() == [1.0, 0.0, 1.0]
+    # a second call reuses the work vectors: same result bit for bit
+    x1, it1, rel1 = B.pcg(bt, 1e-8, 50)
+    x2, it2, rel2 = B.pcg(bt, 1e-8, 50)
+    assert torch.equal(x1, x2) and torch.equal(it1, it2) and torch.equal(rel1, rel2)
+
+
+def test_rejected_arguments(dev):
+    from paper_2510_17785_amd import PatchBatch, PatchSmoother
+    from paper_2510_17785_amd._lib import PmgError
+    X, mu = synth.make_random_patches(3, 2, 0.2, None, 9)
+    B = PatchBatch(3, 4, X, mu, levels=(4, 2, 1), precision="fp64")
+    b = torch.zeros((2, B.level_sizes[0]), dtype=torch.float64, device=dev)
+    for rtol, maxit in [(-1.0, 10), (float("nan"), 10), (float("inf"), 10), (1e-8, -1), (1e-8, 10001)]:
+        with pytest.raises(PmgError):
+            B.pcg(b, rtol, maxit)
+    B32 = PatchBatch(3, 4, X, mu, levels=(4, 2, 1), precision="fp32")
+    with pytest.raises(PmgError, match="FP64"):
+        B32.pcg(b, 1e-8, 10)
+    w, p, levels, Xm, mum, _ = case("3d-n16-q4", 4)
+    Sb = PatchSmoother(w.dim, w.n, p, Xm, mum, levels=levels, precision="fp64", with_boundary=True)
+    with pytest.raises(PmgError, match="boundary"):
+        Sb.pcg(torch.zeros((Sb.n_patches, Sb.level_sizes[0]), dtype=torch.float64, device=dev), 1e-8, 10)
