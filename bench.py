@@ -293,6 +293,133 @@ def cpu_baseline_batch(w, ps, levels, X, mu, bh, local, budget_s=12.0):
                       "patches of all four instances"}
 
 
+# Batched patch CG: independent 3D Q7 patches drawn like the patches of the
+# 32^3 Q7 jump mesh (perturbation 0.25 h, cell coefficients 10^U(-4, 4)), as
+# many as that mesh has interior vertices; FP64 local solver, Lanczos bounds.
+PCG_WORKLOAD = "3d-q7-jump-local-pcg"
+PCG_PATCHES, PCG_P, PCG_LEVELS, PCG_ALPHA, PCG_MU = 29791, 7, (7, 3, 1), 0.25, (-4.0, 4.0)
+PCG_RTOL, PCG_MAXIT, PCG_SEED = 1e-8, 200, 6000
+
+
+def bench_pcg(args):
+    """CG on every patch problem A_{j,p} x = b_j, preconditioned by one local
+    V-cycle (the measure of the local solver in Section 3.2), all patches in
+    one call of pmg_patch_pcg; a step is one such call on the whole batch.
+    Value: V-cycles per second (one V-cycle and one top-level apply per CG
+    iteration of each patch)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2510_17785_amd import PatchBatch
+
+    X, mu = synth.make_random_patches(3, PCG_PATCHES, PCG_ALPHA, PCG_MU, PCG_SEED)
+    dev = torch.device("cuda", 0)
+    t0 = time.perf_counter()
+    B = PatchBatch(3, PCG_P, X, mu, levels=PCG_LEVELS, precision="fp64")
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    N = B.level_sizes[0]
+    bh = np.random.default_rng(PCG_SEED + 1).standard_normal((PCG_PATCHES, N))
+    b = torch.tensor(bh, device=dev)
+    for _ in range(args.warmup):
+        B.pcg(b, PCG_RTOL, PCG_MAXIT)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    ev[0].record()
+    for s in range(args.steps):
+        x, it, rel = B.pcg(b, PCG_RTOL, PCG_MAXIT)
+        ev[s + 1].record()
+    torch.cuda.synchronize()
+    call_ms = [ev[s].elapsed_time(ev[s + 1]) for s in range(args.steps)]
+    ms = sum(call_ms) / args.steps
+    its = it.cpu().numpy()
+    rels = rel.cpu().numpy()
+    vcycles = int(its.sum())
+    F, _ = algorithmic_per_patch(3, PCG_LEVELS, 3, 8)
+    # per CG iteration: one V-cycle and one top-level apply (the F of a patch
+    # update, whose evaluate apply becomes the CG operator apply), two dot
+    # products and three vector updates (10 flops per entry)
+    F_iter = F + 10 * N
+    achieved = vcycles * F_iter / (ms / 1e3) / 1e12
+    print(f"# patch CG: {ms:.2f} ms per batch, iterations min {its.min()} median "
+          f"{int(np.median(its))} max {its.max()}, max relres {rels.max():.2e}", file=sys.stderr, flush=True)
+    out = {
+        "metric": "batched patch-CG V-cycles/s (CG preconditioned by the local V-cycle, FP64)",
+        "value": vcycles / (ms / 1e3),
+        "unit": "V-cycles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{PCG_WORKLOAD}: {PCG_PATCHES} independent 3D Q{PCG_P} vertex patches "
+                        f"perturbed by {PCG_ALPHA} h, cell mu=10^U{PCG_MU}, local levels "
+                        f"{'->'.join(map(str, PCG_LEVELS))}, Chebyshev degree 3, Lanczos bounds, "
+                        f"CG to {PCG_RTOL} relative residual (at most {PCG_MAXIT} iterations), "
+                        f"b ~ N(0,1)",
+            "patch_dofs": N,
+        },
+        "solves_per_s": PCG_PATCHES / (ms / 1e3),
+        "patch_dofs_per_s": PCG_PATCHES * N / (ms / 1e3),
+        "iterations": {"min": int(its.min()), "median": float(np.median(its)), "max": int(its.max()),
+                       "mean": float(its.mean())},
+        "max_relres": float(rels.max()),
+        "setup_s": setup_s,
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": VALU_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / VALU_PEAK_TFLOPS,
+            "traffic": None,
+            "kernel": f"patch_kernel<double,3,Levels<{','.join(map(str, PCG_LEVELS))}>,pcg>",
+            "algorithmic_flops_per_iteration": F_iter,
+            "v_cycles_per_launch": vcycles,
+            "avg_launch_ms": ms,
+        },
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_pcg(X, mu, bh)
+    B.close()
+    print(json.dumps(out))
+    return 0
+
+
+def cpu_baseline_pcg(X, mu, bh, budget_s=12.0):
+    """The oracle's patch CG on a bounded sample of the batch's patches
+    (patch matrices and Lanczos bounds untimed), in V-cycles per second."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import fem, lanczos, pmg
+
+    sample = [int(j) for j in np.random.default_rng(0).choice(len(X), 8, replace=False)]
+    with threadpool_limits(limits=1):
+        solvers = []
+        for j in sample:
+            s = pmg.LocalSolver(fem.PatchGeometry(X[j], mu[j]), PCG_LEVELS)
+            s.set_bounds([lanczos.bounds(s.A[l], s.dinv[l], 12, 0, j, l)
+                          for l in range(len(PCG_LEVELS) - 1)])
+            solvers.append(s)
+        vc, solves, t0 = 0, 0, time.perf_counter()
+        while True:
+            for s, j in zip(solvers, sample):
+                vc += s.pcg(bh[j], PCG_RTOL, PCG_MAXIT)[1]
+                solves += 1
+            if time.perf_counter() - t0 >= budget_s:
+                break
+        t = time.perf_counter() - t0
+    return {"value": vc / t, "unit": "V-cycles/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(sample)} of {len(X)} patches, {solves} oracle CG solves ({vc} V-cycles) "
+                      f"in {t:.1f} s (FP64 dense level matrices, setup untimed)"}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -339,6 +466,8 @@ def main(argv=None):
     import synth
     from paper_2510_17785_amd import GMGSolver, PatchSmoother
 
+    if args.workload == PCG_WORKLOAD:
+        return bench_pcg(args)
     w = synth.workload(args.workload)
     if w.name == "3d-n24-q8-batch":
         return bench_batch(args, w)
