@@ -420,6 +420,114 @@ def cpu_baseline_pcg(X, mu, bh, budget_s=12.0):
                       f"in {t:.1f} s (FP64 dense level matrices, setup untimed)"}
 
 
+STUDY_WORKLOAD = "local-solver-study"
+
+
+def bench_study(args):
+    """The single-patch study of Section 3.2 on the GPU (batched patch CG,
+    omega = 1/2 Jacobi V-cycle, levels from 1, 3, 7, CG to 1e-8 within 100
+    iterations): distortion 0..0.35 (2D) / 0..0.28 (3D), 20 patches per
+    value; a jump of 1..1e8 in one cell of an undeformed patch; a jump of
+    1e4 under distortion; p = 3 and 7 in 2D and 3D.  A step is the four
+    studies, one pmg_patch_pcg call each (the median call time of up to five
+    steps is used).  Value: V-cycles per second over all of them (small
+    batches: the GPU is far from full)."""
+    import numpy as np
+
+    from paper_2510_17785_amd.study import run_study
+
+    cases = [(2, 3), (2, 7), (3, 3), (3, 7)]
+    dists = {2: (0.0, 0.05, 0.1, 0.15, 0.2, 0.25, 0.3, 0.35), 3: (0.0, 0.05, 0.1, 0.15, 0.2, 0.25, 0.28)}
+    for _ in range(args.warmup):
+        run_study(3, 7, distortions=(0.1,), jumps=(1.0,), realizations=4)
+    tables, total_s, total_vc, flops = {}, 0.0, 0, 0.0
+    res = {}
+    steps = min(max(args.steps, 1), 5)   # each pass sets up four batches: at most five passes
+    for dim, p in cases:
+        secs = []
+        for _ in range(steps):
+            r = run_study(dim, p, distortions=dists[dim])
+            secs.append(r["seconds"])
+        r["seconds"] = float(np.median(secs))
+        res[(dim, p)] = r
+        total_s += r["seconds"]
+        total_vc += r["v_cycles"]
+        F, _ = algorithmic_per_patch(dim, r["levels"], 1, 8)
+        flops += r["v_cycles"] * (F + 10 * r["patch_dofs"])
+        tables[f"{dim}d-p{p}"] = [{k: v for k, v in row.items()} for row in r["rows"]]
+        print(f"# study {dim}D p={p}: {len(r['X'])} patches, {r['seconds'] * 1e3:.2f} ms, "
+              + "; ".join(f"{row['sweep']} {row['value']:g}: {row['mean_iterations']:.2f}"
+                          for row in r["rows"] if row["mean_iterations"] is not None),
+              file=sys.stderr, flush=True)
+    achieved = flops / total_s / 1e12
+    out = {
+        "metric": "local-solver study V-cycles/s (batched patch CG, omega=1/2 Jacobi V-cycle, FP64)",
+        "value": total_vc / total_s,
+        "unit": "V-cycles/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": total_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{STUDY_WORKLOAD}: single 2^d-cell patches, every vertex moved by delta h in a "
+                        f"random direction, one-cell jumps 1..1e8 and 1e4 with distortion, 20 per value, "
+                        f"p in (3, 7) for d in (2, 3), levels (3,1) / (7,3,1), degree-1 Chebyshev on "
+                        f"[0.5, 3.5], CG to 1e-8 within 100 iterations, b ~ N(0,1)",
+            "patches": {f"{d}d-p{p}": len(res[(d, p)]["X"]) for d, p in cases},
+        },
+        "tables": tables,
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": VALU_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / VALU_PEAK_TFLOPS,
+            "traffic": None,
+            "kernel": "patch_kernel<double,d,Levels<p,...,1>,pcg> for (d, p) in "
+                      + ", ".join(f"({d}, {p})" for d, p in cases),
+            "note": "a few hundred patches per call: latency-bound, far below a full GPU",
+        },
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_study(res[(3, 7)])
+    print(json.dumps(out, default=float))
+    return 0
+
+
+def cpu_baseline_study(r, budget_s=12.0):
+    """The oracle's patch CG on a sample of the 3D p = 7 study's patches
+    (patch matrices untimed), in V-cycles per second."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import fem, pmg
+    from paper_2510_17785_amd.study import OMEGA_HALF_BOUNDS
+
+    sample = [int(j) for j in np.random.default_rng(0).choice(len(r["X"]), 6, replace=False)]
+    with threadpool_limits(limits=1):
+        solvers = []
+        for j in sample:
+            s = pmg.LocalSolver(fem.PatchGeometry(r["X"][j], r["mu"][j]), r["levels"], cheb_degree=1)
+            s.set_bounds([OMEGA_HALF_BOUNDS] * (len(r["levels"]) - 1))
+            solvers.append(s)
+        vc, solves, t0 = 0, 0, time.perf_counter()
+        while True:
+            for s, j in zip(solvers, sample):
+                vc += s.pcg(r["b"][j], 1e-8, 100)[1]
+                solves += 1
+            if time.perf_counter() - t0 >= budget_s:
+                break
+        t = time.perf_counter() - t0
+    return {"value": vc / t, "unit": "V-cycles/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(sample)} of the {len(r['X'])} 3D p=7 study patches, {solves} oracle CG "
+                      f"solves ({vc} V-cycles) in {t:.1f} s (setup untimed)"}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -468,6 +576,8 @@ def main(argv=None):
 
     if args.workload == PCG_WORKLOAD:
         return bench_pcg(args)
+    if args.workload == STUDY_WORKLOAD:
+        return bench_study(args)
     w = synth.workload(args.workload)
     if w.name == "3d-n24-q8-batch":
         return bench_batch(args, w)

@@ -14,4 +14,5 @@ from .generators import (  # noqa: F401
     make_case,
     make_random_patch,
     make_random_patches,
+    make_sphere_distorted_patches,
 )

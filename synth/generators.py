@@ -315,3 +315,40 @@ def make_random_patches(dim: int, n: int, alpha: float, mu_log10, seed: int,
     else:
         mu = 10.0 ** rng.uniform(mu_log10[0], mu_log10[1], size=(n, 2 ** dim))
     return X, mu
+
+
+def make_sphere_distorted_patches(dim: int, n: int, delta: float, seed: int,
+                                  mu_cell: Optional[float] = None, det_floor: float = 0.01):
+    """n independent patches (2^dim cells of width h = 0.5, as
+    make_random_patches lays them out) whose 3^dim vertices are each moved
+    by delta h in a direction drawn uniformly on the unit sphere (a normalised
+    standard Gaussian vector): the distortion model of the single-patch study
+    in Section 3.2.  A patch with a cell whose sampled Jacobian determinant is
+    at most det_floor h^dim is redrawn from the continuing stream.
+    Coefficients: 1 in every cell, cell 0 set to mu_cell when given.
+    Returns (vertices (n, 3^dim, dim), mu (n, 2^dim))."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    h = 0.5
+    coords = _all_cells(dim, 3).astype(np.float64) * h
+    corners = _corner_rows(dim, 3, _all_cells(dim, 2))
+
+    def draw(k):
+        d = rng.standard_normal((k,) + coords.shape)
+        d /= np.linalg.norm(d, axis=-1, keepdims=True)
+        return coords[None] + delta * h * d
+
+    X = draw(n)
+    floor = det_floor * h ** dim
+    todo = np.arange(n)
+    for _ in range(10000):
+        dets = _min_jacobian_batched(X[todo][:, corners].reshape(-1, 2 ** dim, dim), dim).reshape(todo.size, -1)
+        todo = todo[dets.min(axis=1) <= floor]
+        if todo.size == 0:
+            break
+        X[todo] = draw(todo.size)
+    else:
+        raise RuntimeError("could not draw untangled patches")
+    mu = np.ones((n, 2 ** dim))
+    if mu_cell is not None:
+        mu[:, 0] = mu_cell
+    return X, mu
