@@ -428,21 +428,21 @@ def bench_study(args):
     omega = 1/2 Jacobi V-cycle, levels from 1, 3, 7, CG to 1e-8 within 100
     iterations): distortion 0..0.35 (2D) / 0..0.28 (3D), 20 patches per
     value; a jump of 1..1e8 in one cell of an undeformed patch; a jump of
-    1e4 under distortion; p = 3 and 7 in 2D and 3D.  A step is the four
-    studies, one pmg_patch_pcg call each (the median call time of up to five
-    steps is used).  Value: V-cycles per second over all of them (small
+    1e4 under distortion; p = 3, 7, 15 in 2D and 3, 7 in 3D.  A step is the
+    five studies, one pmg_patch_pcg call each (the median call time of up to
+    five steps is used).  Value: V-cycles per second over all of them (small
     batches: the GPU is far from full)."""
     import numpy as np
 
     from paper_2510_17785_amd.study import run_study
 
-    cases = [(2, 3), (2, 7), (3, 3), (3, 7)]
+    cases = [(2, 3), (2, 7), (2, 15), (3, 3), (3, 7)]
     dists = {2: (0.0, 0.05, 0.1, 0.15, 0.2, 0.25, 0.3, 0.35), 3: (0.0, 0.05, 0.1, 0.15, 0.2, 0.25, 0.28)}
     for _ in range(args.warmup):
         run_study(3, 7, distortions=(0.1,), jumps=(1.0,), realizations=4)
     tables, total_s, total_vc, flops = {}, 0.0, 0, 0.0
     res = {}
-    steps = min(max(args.steps, 1), 5)   # each pass sets up four batches: at most five passes
+    steps = min(max(args.steps, 1), 5)   # each pass sets up five batches: at most five passes
     for dim, p in cases:
         secs = []
         for _ in range(steps):
@@ -476,7 +476,7 @@ def bench_study(args):
         "config": {
             "workload": f"{STUDY_WORKLOAD}: single 2^d-cell patches, every vertex moved by delta h in a "
                         f"random direction, one-cell jumps 1..1e8 and 1e4 with distortion, 20 per value, "
-                        f"p in (3, 7) for d in (2, 3), levels (3,1) / (7,3,1), degree-1 Chebyshev on "
+                        f"p in (3, 7, 15) for d = 2 and (3, 7) for d = 3, levels (3,1) / (7,3,1) / (15,7,3,1), degree-1 Chebyshev on "
                         f"[0.5, 3.5], CG to 1e-8 within 100 iterations, b ~ N(0,1)",
             "patches": {f"{d}d-p{p}": len(res[(d, p)]["X"]) for d, p in cases},
         },

@@ -3180,7 +3180,8 @@ PatchVariant make_variant_bf16() {
 
 #define PMG_VARIANTS(T)                                                                        \
   make_variant<T, 2, 2, 1>(), make_variant<T, 2, 3, 1>(), make_variant<T, 2, 3, 2, 1>(),       \
-      make_variant<T, 2, 4, 2, 1>(), make_variant<T, 2, 7, 3, 1>(), make_variant<T, 3, 2, 1>(), \
+      make_variant<T, 2, 4, 2, 1>(), make_variant<T, 2, 7, 3, 1>(), make_variant<T, 2, 15, 7, 3, 1>(), \
+      make_variant<T, 3, 2, 1>(), \
       make_variant<T, 3, 3, 1>(), make_variant<T, 3, 3, 2, 1>(), make_variant<T, 3, 4, 2, 1>(), \
       make_variant<T, 3, 6, 3, 1>(), make_variant<T, 3, 7, 3, 1>(), make_variant<T, 3, 8, 4, 2, 1>()
 

@@ -2,7 +2,8 @@
 
 CG to a relative residual of 1e-8, preconditioned by one p-multigrid V-cycle
 with damped Jacobi smoothing (omega = 1/2: the degree-1 Chebyshev step on
-the interval [0.5, 3.5]) and the nested p-levels 1, 3, 7 (p_{k+1} = 2 p_k + 1),
+the interval [0.5, 3.5]) and the nested p-levels 1, 3, 7, 15
+(p_{k+1} = 2 p_k + 1),
 at most 100 iterations per patch.  For one (dim, p), three sweeps are run as
 one batch in one pmg_patch_pcg call:
 

@@ -3,7 +3,7 @@ every patch problem A_{j,p} x = b_j preconditioned by the local V-cycle, the
 measure of the local solver in Section 3.2.
 
 Cases: the paper's setting (undeformed 2D patches, degree-1 smoothing with
-omega = 1/2, p = 3 and 7), distorted 3D patches with Lanczos intervals and
+omega = 1/2, p = 3, 7 and 15), distorted 3D patches with Lanczos intervals and
 Chebyshev degree 3 (p = 4 and 7), the patches of a mesh handle, fixed
 iteration counts, and the degenerate inputs.
 
@@ -53,7 +53,7 @@ def _compare(solvers, b, x, it, rel, rtol, maxit):
         assert abs(rel[j] - ro) <= 1e-4 * ro + 1e-15, (j, rel[j], ro)
 
 
-@pytest.mark.parametrize("p,levels", [(3, (3, 1)), (7, (7, 3, 1))])
+@pytest.mark.parametrize("p,levels", [(3, (3, 1)), (7, (7, 3, 1)), (15, (15, 7, 3, 1))])
 def test_paper_setting_2d(dev, p, levels):
     from paper_2510_17785_amd import PatchBatch
     n = 6

@@ -47,12 +47,12 @@ def _oracle_counts(res, rtol=1e-8, maxit=100):
     return out
 
 
-@pytest.mark.parametrize("dim,p,reals", [(2, 3, 3), (2, 7, 3), (3, 3, 3), (3, 7, 1)])
+@pytest.mark.parametrize("dim,p,reals", [(2, 3, 3), (2, 7, 3), (2, 15, 1), (3, 3, 3), (3, 7, 1)])
 def test_study_matches_oracle(dev, dim, p, reals):
     from paper_2510_17785_amd.study import run_study
     dist = (0.0, 0.2, 0.35) if dim == 2 else (0.0, 0.15, 0.28)
     res = run_study(dim, p, distortions=dist, jumps=(1.0, 1e4, 1e8), realizations=reals, seed=50 + p)
-    assert res["levels"] == ((3, 1) if p == 3 else (7, 3, 1))
+    assert res["levels"] == {3: (3, 1), 7: (7, 3, 1), 15: (15, 7, 3, 1)}[p]
     for j, (k, r, near) in enumerate(_oracle_counts(res)):
         kg, rg = int(res["iterations"][j]), float(res["relres"][j])
         if near:
@@ -63,7 +63,7 @@ def test_study_matches_oracle(dev, dim, p, reals):
     assert all(row["not_converged"] == 0 for row in res["rows"])
 
 
-@pytest.mark.parametrize("p", [3, 7])
+@pytest.mark.parametrize("p", [3, 7, 15])
 def test_study_trends_2d(dev, p):
     from paper_2510_17785_amd.study import run_study
     dist = (0.0, 0.1, 0.2, 0.3, 0.35)
