@@ -20,6 +20,11 @@ Components, each formed explicitly:
     applied to the residuals;
   * V-cycle: pre-smooth, residual, restrict, recurse, prolongate, correct,
     post-smooth (Algorithm 2);
+  * the Cartesian-reinforced smoother (Section 3.1, smoothers): Richardson
+    steps d += omega P (r - A d) with P = D diag(A_b) A_b^{-1}, A_b the
+    operator of the undeformed Cartesian reference patch (unit cells,
+    coefficient 1) at the level's degree and D the level's inverse
+    diagonal; one step before and one after the coarse correction;
   * the local solver's measure of quality in Section 3.2: conjugate gradients
     on the patch problem, preconditioned by one V-cycle.
 """
@@ -103,6 +108,16 @@ def chebyshev(A, dinv, f, x, a, b, k, x_is_zero=False):
     return x
 
 
+def reference_patch_matrix(dim: int, q: int, ncell=None) -> np.ndarray:
+    """A_{b,q}: the degree-q operator of the undeformed Cartesian patch with
+    unit cells and coefficient 1 (the reference patch of the
+    Cartesian-reinforced smoother, Section 3.1), assembled like any patch."""
+    ncell = tuple(ncell) if ncell is not None else (2,) * dim
+    g = np.array(np.meshgrid(*([np.arange(3.0)] * dim), indexing="ij"))
+    X = np.stack([g[i].transpose(tuple(reversed(range(dim)))).reshape(-1) for i in range(dim)], 1)
+    return patch_matrix(PatchGeometry(X, np.ones(2 ** dim), ncell), q)
+
+
 def _level_size(patch: PatchGeometry, q: int) -> int:
     return int(np.prod([patch.ncell[i] * q - 1 for i in range(patch.dim)]))
 
@@ -116,7 +131,8 @@ class LocalSolver:
     """
 
     def __init__(self, patch: PatchGeometry, levels, bounds=None, cheb_degree=3,
-                 n_vcycles=1, safety=CHEB_SAFETY, rng=CHEB_RANGE):
+                 n_vcycles=1, safety=CHEB_SAFETY, rng=CHEB_RANGE, smoother="chebyshev",
+                 omega=0.5):
         self.patch = patch
         # a patch cut by the boundary has no interior node at low degrees
         # (q - 1 = 0 nodes along a one-cell direction at q = 1): the coarsest
@@ -130,6 +146,11 @@ class LocalSolver:
         self.P = [prolongation(self.levels[l], self.levels[l + 1], patch.ncell)
                   for l in range(len(self.levels) - 1)]
         self.chol = sla.cho_factor(self.A[-1], lower=True)
+        if smoother not in ("chebyshev", "cartesian"):
+            raise ValueError(smoother)
+        self.smoother, self.omega = smoother, omega
+        if smoother == "cartesian":
+            self.Ab = [reference_patch_matrix(patch.dim, q, patch.ncell) for q in self.levels[:-1]]
         self.bounds = None
         if bounds is not None:
             self.set_bounds(bounds)
@@ -144,14 +165,27 @@ class LocalSolver:
         if level == len(self.levels) - 1:
             return sla.cho_solve(self.chol, r)
         A, dinv = self.A[level], self.dinv[level]
-        a, b = self.intervals[level]
-        d = chebyshev(A, dinv, r, d, a, b, self.k, x_is_zero=d_is_zero)   # pre-smoothing
+        if self.smoother == "cartesian":
+            d = self.cartesian_step(level, r, d, d_is_zero)                # pre-smoothing
+        else:
+            a, b = self.intervals[level]
+            d = chebyshev(A, dinv, r, d, a, b, self.k, x_is_zero=d_is_zero)
         res = r - A @ d                                                    # residual
         rc = self.P[level].T @ res                                         # restriction
         e = self.vcycle(level + 1, np.zeros_like(rc), rc, d_is_zero=True)  # recursion
         d = d + self.P[level] @ e                                          # prolongation + correction
-        d = chebyshev(A, dinv, r, d, a, b, self.k)                         # post-smoothing
+        if self.smoother == "cartesian":
+            d = self.cartesian_step(level, r, d)                           # post-smoothing
+        else:
+            d = chebyshev(A, dinv, r, d, a, b, self.k)
         return d
+
+    def cartesian_step(self, level, r, d, d_is_zero=False):
+        """One Richardson step d += omega P (r - A d) with the
+        Cartesian-reinforced preconditioner P = D diag(A_b) A_b^{-1}."""
+        res = r if d_is_zero else r - self.A[level] @ d
+        Ab = self.Ab[level]
+        return d + self.omega * self.dinv[level] * np.diag(Ab) * np.linalg.solve(Ab, res)
 
     def solve(self, r):
         """d ~ A_{j,p}^{-1} r by n_vcycles V-cycles from d = 0."""

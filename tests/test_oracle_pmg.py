@@ -482,3 +482,100 @@ def test_coarse_coefficient_means(rule, expect):
     mu = np.array([1.0, 4.0, 16.0, 64.0, 1.0, 4.0, 16.0, 64.0])
     c = fem.Mesh(3, 2, X, mu).coarsen(rule)
     assert c.n == 1 and np.isclose(c.mu[0], expect, rtol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# Cartesian-reinforced smoother
+# ---------------------------------------------------------------------------
+
+def _cartesian_patch(dim, h, mu):
+    g = np.array(np.meshgrid(*([np.arange(3.0)] * dim), indexing="ij"))
+    X = np.stack([g[i].transpose(tuple(reversed(range(dim)))).reshape(-1) for i in range(dim)], 1) * h
+    return fem.PatchGeometry(X, np.full(2 ** dim, mu))
+
+
+def _two_cell_1d(q):
+    # 1D mass and stiffness of two unit cells, interior nodes only, built
+    # here from the GLL basis and the (q+1)-point Gauss rule directly
+    x, w = fe1d.gauss_rule(q + 1)
+    L = fe1d.lagrange_values(fe1d.gll_nodes(q), x)
+    D = fe1d.lagrange_derivatives(fe1d.gll_nodes(q), x)
+    Mc, Kc = (L * w) @ L.T, (D * w) @ D.T
+    M = np.zeros((2 * q + 1, 2 * q + 1))
+    K = np.zeros_like(M)
+    for c in range(2):
+        s = slice(c * q, c * q + q + 1)
+        M[s, s] += Mc
+        K[s, s] += Kc
+    return M[1:-1, 1:-1], K[1:-1, 1:-1]
+
+
+@pytest.mark.parametrize("dim,q", [(2, 1), (2, 3), (2, 7), (3, 2), (3, 3)])
+def test_reference_patch_matrix_is_a_kronecker_sum(dim, q):
+    # the reference patch operator is sum_i M x .. K_i .. x M (x fastest, so
+    # the x factor is the right-most Kronecker factor), which is what makes
+    # its fast diagonalisation exact
+    M, K = _two_cell_1d(q)
+    A = np.zeros((M.shape[0] ** dim,) * 2)
+    for i in range(dim):
+        T = np.ones((1, 1))
+        for j in range(dim):
+            T = np.kron(K if j == i else M, T)
+        A += T
+    assert np.abs(pmg.reference_patch_matrix(dim, q) - A).max() <= 1e-12 * np.abs(A).max()
+
+
+@pytest.mark.parametrize("dim,q", [(2, 3), (2, 7), (3, 3)])
+def test_cartesian_preconditioner_inverts_undeformed_patches(dim, q):
+    # on an undeformed patch of any cell size with one coefficient, A_j is a
+    # multiple of A_b and D diag(A_b) undoes that multiple: P A = I
+    s = pmg.LocalSolver(_cartesian_patch(dim, 0.37, 5.3), (q, 1), smoother="cartesian")
+    Ab = s.Ab[0]
+    PA = (s.dinv[0] * np.diag(Ab))[:, None] * np.linalg.solve(Ab, s.A[0])
+    assert np.abs(PA - np.eye(len(PA))).max() <= 1e-10
+    # a distorted patch: P A is no longer the identity
+    s2 = _solver(dim, (q, 1), seed=3)
+    s2 = pmg.LocalSolver(s2.patch, (q, 1), smoother="cartesian")
+    PA2 = (s2.dinv[0] * np.diag(s2.Ab[0]))[:, None] * np.linalg.solve(s2.Ab[0], s2.A[0])
+    assert np.abs(PA2 - np.eye(len(PA2))).max() > 1e-2
+
+
+@pytest.mark.parametrize("dim,levels", [(2, (3, 1)), (3, (3, 1)), (2, (7, 3, 1)), (3, (7, 3, 1)),
+                                        (2, (15, 7, 3, 1))])
+def test_cartesian_vcycle_cg_iterations_equal_level_count(dim, levels):
+    # with P = A^{-1} on every level and omega = 1/2, one V-cycle B gives
+    # B A = 3/4 on the A-orthogonal complement of the first coarse space,
+    # 1 - 1/4^k on the k-th complement below and 1 on the coarsest space:
+    # one distinct eigenvalue per level, so CG ends after exactly as many
+    # iterations as there are levels
+    s = pmg.LocalSolver(_cartesian_patch(dim, 0.5, 2.0), levels, smoother="cartesian")
+    b = np.random.default_rng(len(levels)).standard_normal(s.A[0].shape[0])
+    x, k, rel = s.pcg(b, 1e-12, 50)
+    assert k == len(levels) and rel <= 1e-12
+    # the spectrum of B A itself
+    n = s.A[0].shape[0]
+    BA = np.column_stack([s.solve(s.A[0][:, j]) for j in range(n)]) if n <= 400 else None
+    if BA is not None:
+        ev = np.sort(np.linalg.eigvals(BA).real)
+        expect = sorted({1.0 - 0.25 ** (len(levels) - 1 - l) if l < len(levels) - 1 else 1.0
+                         for l in range(len(levels))})
+        assert all(np.min(np.abs(ev - e)) <= 1e-10 for e in expect)
+        assert all(np.min(np.abs(np.array(expect) - e)) <= 1e-10 for e in ev)
+
+
+def test_cartesian_step_uses_the_reference_patch():
+    # on a distorted patch one step from zero is omega D diag(A_b) A_b^{-1} r
+    # with A_b the Kronecker sum of the 1D two-cell matrices (not the
+    # distorted patch's own operator)
+    M, K = _two_cell_1d(3)
+    Ab = np.kron(M, K) + np.kron(K, M)
+    s = pmg.LocalSolver(_solver(2, (3, 1), seed=3).patch, (3, 1), smoother="cartesian", omega=0.5)
+    r = np.random.default_rng(4).standard_normal(Ab.shape[0])
+    d = s.cartesian_step(0, r, np.zeros_like(r), d_is_zero=True)
+    expect = 0.5 * s.dinv[0] * np.diag(Ab) * np.linalg.solve(Ab, r)
+    assert np.abs(d - expect).max() <= 1e-12 * np.abs(expect).max()
+    # and from a nonzero start it acts on the residual r - A d
+    d0 = np.random.default_rng(5).standard_normal(Ab.shape[0])
+    d1 = s.cartesian_step(0, r, d0)
+    expect1 = d0 + 0.5 * s.dinv[0] * np.diag(Ab) * np.linalg.solve(Ab, r - s.A[0] @ d0)
+    assert np.abs(d1 - expect1).max() <= 1e-12 * np.abs(expect1).max()
