@@ -190,6 +190,25 @@ int pmg_patch_local_solve(pmg_handle* h, const double* r, double* d);
 int pmg_patch_pcg(pmg_handle* h, const double* b, double* x, double rtol, int32_t maxit,
                   int32_t* iters, double* relres);
 
+/* Local smoothers of the V-cycle (Section 3.1, smoothers). */
+#define PMG_SMOOTHER_CHEBYSHEV 0  /* Chebyshev-accelerated Jacobi (the default) */
+#define PMG_SMOOTHER_CARTESIAN 1  /* Cartesian-reinforced */
+
+/* Choose the local smoother.  PMG_SMOOTHER_CARTESIAN: one Richardson step
+ * d += omega P (r - A d) before and one after the coarse correction on every
+ * level above the coarsest, P = D diag(A_b) A_b^{-1} (Section 3.1), with D
+ * the inverse diagonal of the patch's level operator and A_b the operator of
+ * the two-cell Cartesian reference patch with unit cells and coefficient 1
+ * at the level's degree, inverted by fast diagonalisation of the 1D two-cell
+ * mass and stiffness matrices (tables formed in FP64 on the host at the first
+ * call, kept until pmg_patch_destroy).  It is used by pmg_patch_pcg only;
+ * with it set, pmg_patch_smooth(_colors), pmg_patch_local_solve and sweeps
+ * that use the handle return PMG_ERR_UNSUPPORTED.  FP64 handles of interior
+ * patches only (PMG_ERR_UNSUPPORTED otherwise).  PMG_ERR_INVALID_ARG: null
+ * handle, unknown kind, omega not finite and > 0 (ignored for Chebyshev).
+ * Synchronous (uploads the tables). */
+int pmg_set_smoother(pmg_handle* h, int32_t kind, double omega);
+
 /* Inverse diagonal of A_{j,q} at level `level`: out device, n_patches x (2q-1)^dim. */
 int pmg_get_inv_diag(const pmg_handle* h, int32_t level, double* out);
 

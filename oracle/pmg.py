@@ -151,6 +151,7 @@ class LocalSolver:
         self.smoother, self.omega = smoother, omega
         if smoother == "cartesian":
             self.Ab = [reference_patch_matrix(patch.dim, q, patch.ncell) for q in self.levels[:-1]]
+            self.Ab_chol = [sla.cho_factor(Ab, lower=True) for Ab in self.Ab]
         self.bounds = None
         if bounds is not None:
             self.set_bounds(bounds)
@@ -185,7 +186,7 @@ class LocalSolver:
         Cartesian-reinforced preconditioner P = D diag(A_b) A_b^{-1}."""
         res = r if d_is_zero else r - self.A[level] @ d
         Ab = self.Ab[level]
-        return d + self.omega * self.dinv[level] * np.diag(Ab) * np.linalg.solve(Ab, res)
+        return d + self.omega * self.dinv[level] * np.diag(Ab) * sla.cho_solve(self.Ab_chol[level], res)
 
     def solve(self, r):
         """d ~ A_{j,p}^{-1} r by n_vcycles V-cycles from d = 0."""

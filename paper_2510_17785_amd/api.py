@@ -166,6 +166,12 @@ class PatchSmoother:
                                         it.data_ptr(), _dptr(rel)))
         return x, it, rel
 
+    def set_smoother(self, kind: str = "chebyshev", omega: float = 0.5):
+        """pmg_set_smoother: "chebyshev" (default) or "cartesian" (the
+        Cartesian-reinforced smoother with damping omega; pmg_patch_pcg only)."""
+        k = {"chebyshev": L.PMG_SMOOTHER_CHEBYSHEV, "cartesian": L.PMG_SMOOTHER_CARTESIAN}[kind]
+        L.check(self._lib.pmg_set_smoother(self._h, k, float(omega)))
+
     def inv_diag(self, level: int) -> torch.Tensor:
         out = torch.empty((self.n_patches, self.level_sizes[level]), dtype=torch.float64,
                           device="cuda")

@@ -167,6 +167,11 @@ struct pmg_handle {
   void* vec_scratch = nullptr;
   void* metric = nullptr;  // per patch: the metric the patch kernel keeps in LDS (see PatchArgs)
   double* pcg_work = nullptr;  // pmg_patch_pcg: residual and search direction per patch
+  // local smoother: PMG_SMOOTHER_CHEBYSHEV, or PMG_SMOOTHER_CARTESIAN (pmg_patch_pcg
+  // only) with its damping and fast-diagonalisation tables (kFdmStride per level)
+  int smoother = PMG_SMOOTHER_CHEBYSHEV;
+  double omega = 0.5;
+  double* fdm_tab = nullptr;
   int64_t vec_bytes = 0;  // bytes per block slot of vec_scratch
   int64_t vec_blocks = 0;
   std::vector<double> bounds;  // host copy, n_patches x (L-1) x 2
@@ -222,7 +227,7 @@ void free_handle(pmg_handle* h) {
   if (!h) return;
   void* ptrs[] = {h->verts, h->mu,          h->patch_vertex, h->patch_geo, h->patch_mu,
                   h->tab64, h->cheb,        h->vec_scratch,  h->trunc_index, h->trunc_inv,
-                  h->metric,  h->pcg_work};
+                  h->metric,  h->pcg_work,     h->fdm_tab};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h->tab && h->tab != h->tab64) (void)hipFree(h->tab);  // FP64 handles share the tables
@@ -293,6 +298,8 @@ int time_launches(hipStream_t stream, int reps, F fn, float* ms) {
 // colours [c_begin, c_end) of a sweep (reversed for direction -1) on `stream`
 int smooth_on(pmg_handle* h, double* u, const double* b, int c_begin, int c_end, int direction,
               hipStream_t stream) {
+  if (h->smoother != PMG_SMOOTHER_CHEBYSHEV)
+    return fail(PMG_ERR_UNSUPPORTED, "the Cartesian-reinforced smoother is available in pmg_patch_pcg only");
   PatchArgs a = h->args();
   a.u = u;
   a.b = b;
@@ -1282,6 +1289,8 @@ int pmg_patch_apply(pmg_handle* h, int32_t level, const double* x, double* y) {
 
 int pmg_patch_local_solve(pmg_handle* h, const double* r, double* d) {
   if (!h || !r || !d) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  if (h->smoother != PMG_SMOOTHER_CHEBYSHEV)
+    return fail(PMG_ERR_UNSUPPORTED, "the Cartesian-reinforced smoother is available in pmg_patch_pcg only");
   if (!h->bounds_valid) return fail(PMG_ERR_INVALID_ARG, "Chebyshev bounds not set");
   PatchArgs a = h->args();
   a.in = r;
@@ -1292,7 +1301,8 @@ int pmg_patch_local_solve(pmg_handle* h, const double* r, double* d) {
 int pmg_patch_pcg(pmg_handle* h, const double* b, double* x, double rtol, int32_t maxit,
                   int32_t* iters, double* relres) {
   if (!h || !b || !x || !iters || !relres) return fail(PMG_ERR_INVALID_ARG, "null argument");
-  if (!h->bounds_valid) return fail(PMG_ERR_INVALID_ARG, "Chebyshev bounds not set");
+  const bool cart = h->smoother == PMG_SMOOTHER_CARTESIAN;
+  if (!cart && !h->bounds_valid) return fail(PMG_ERR_INVALID_ARG, "Chebyshev bounds not set");
   if (!(rtol >= 0.0) || !std::isfinite(rtol)) return fail(PMG_ERR_INVALID_ARG, "rtol must be finite and >= 0");
   if (maxit < 0 || maxit > PMG_PCG_MAXIT_LIMIT)
     return fail(PMG_ERR_INVALID_ARG, "maxit %d outside 0..%d", maxit, PMG_PCG_MAXIT_LIMIT);
@@ -1312,9 +1322,43 @@ int pmg_patch_pcg(pmg_handle* h, const double* b, double* x, double rtol, int32_
   a.pcg_work = h->pcg_work;
   a.pcg_iters = iters;
   a.pcg_relres = relres;
+  a.fdm_tab = h->fdm_tab;
+  a.fdm_omega = h->omega;
   a.grid = 0;
   a.map_mode = 0;
-  return launch_chunks(h, kModePcg, a, 0, h->n_patches);
+  return launch_chunks(h, cart ? kModePcgCart : kModePcg, a, 0, h->n_patches);
+}
+
+int pmg_set_smoother(pmg_handle* h, int32_t kind, double omega) {
+  if (!h) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  if (kind == PMG_SMOOTHER_CHEBYSHEV) {
+    h->smoother = kind;
+    return PMG_OK;
+  }
+  if (kind != PMG_SMOOTHER_CARTESIAN) return fail(PMG_ERR_INVALID_ARG, "unknown smoother %d", kind);
+  if (!(omega > 0.0) || !std::isfinite(omega)) return fail(PMG_ERR_INVALID_ARG, "omega must be finite and > 0");
+  if (h->precision != PMG_FP64)
+    return fail(PMG_ERR_UNSUPPORTED, "the Cartesian-reinforced smoother runs on FP64 handles only");
+  if (h->with_boundary)
+    return fail(PMG_ERR_UNSUPPORTED, "the Cartesian-reinforced smoother needs two cells per direction");
+  if (!h->fdm_tab) {
+    std::vector<double> tab((size_t)kMaxLevels * kFdmStride, 0.0);
+    for (int l = 0; l + 1 < h->L; ++l) {
+      const FdmTables f = fdm_tables(h->levels[l]);
+      double* dst = tab.data() + (size_t)l * kFdmStride;
+      std::copy(f.S.begin(), f.S.end(), dst);
+      std::copy(f.lam.begin(), f.lam.end(), dst + f.m * f.m);
+      std::copy(f.dM.begin(), f.dM.end(), dst + f.m * f.m + f.m);
+      std::copy(f.dK.begin(), f.dK.end(), dst + f.m * f.m + 2 * f.m);
+    }
+    int st = dev_alloc(&h->fdm_tab, tab.size() * sizeof(double), &h->device_bytes);
+    if (st < 0) return st;
+    hipError_t e = hipMemcpy(h->fdm_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(PMG_ERR_HIP, "smoother tables: %s", hipGetErrorString(e));
+  }
+  h->smoother = kind;
+  h->omega = omega;
+  return PMG_OK;
 }
 
 int pmg_get_inv_diag(const pmg_handle* h, int32_t level, double* out) {

@@ -161,4 +161,109 @@ void h_prolongation_1d(int nc, int p, std::vector<int>& first, std::vector<doubl
   }
 }
 
+FdmTables fdm_tables(int q) {
+  FdmTables f;
+  const int n = q + 1, m = 2 * q - 1;
+  f.m = m;
+  DegreeTables t = degree_tables(q);
+  // one cell: M_ab = sum_k w_k l_a(x_k) l_b(x_k), K_ab = sum_k w_k l_a'(x_k) l_b'(x_k);
+  // two cells share node q; the interior nodes are 1 .. 2q-1
+  std::vector<double> M2((2 * q + 1) * (2 * q + 1), 0.0), K2(M2.size(), 0.0);
+  for (int c = 0; c < 2; ++c)
+    for (int a = 0; a < n; ++a)
+      for (int b = 0; b < n; ++b) {
+        double mv = 0, kv = 0;
+        for (int k = 0; k < n; ++k) {
+          mv += t.wg[k] * t.B[k * n + a] * t.B[k * n + b];
+          kv += t.wg[k] * t.D[k * n + a] * t.D[k * n + b];
+        }
+        const int r = c * q + a, s2 = c * q + b;
+        M2[r * (2 * q + 1) + s2] += mv;
+        K2[r * (2 * q + 1) + s2] += kv;
+      }
+  std::vector<double> M(m * m), K(m * m);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) {
+      M[i * m + j] = M2[(i + 1) * (2 * q + 1) + (j + 1)];
+      K[i * m + j] = K2[(i + 1) * (2 * q + 1) + (j + 1)];
+    }
+  f.dM.resize(m);
+  f.dK.resize(m);
+  for (int i = 0; i < m; ++i) {
+    f.dM[i] = M[i * m + i];
+    f.dK[i] = K[i * m + i];
+  }
+  // Cholesky M = L L^T (M is symmetric positive definite)
+  std::vector<double> Lc(m * m, 0.0);
+  for (int j = 0; j < m; ++j) {
+    double d = M[j * m + j];
+    for (int k = 0; k < j; ++k) d -= Lc[j * m + k] * Lc[j * m + k];
+    Lc[j * m + j] = std::sqrt(d);
+    for (int i = j + 1; i < m; ++i) {
+      double v = M[i * m + j];
+      for (int k = 0; k < j; ++k) v -= Lc[i * m + k] * Lc[j * m + k];
+      Lc[i * m + j] = v / Lc[j * m + j];
+    }
+  }
+  // C = L^{-1} K L^{-T}: solve L Y = K, then L C^T = Y^T (C symmetric)
+  std::vector<double> Y(m * m), C(m * m);
+  for (int col = 0; col < m; ++col)
+    for (int i = 0; i < m; ++i) {
+      double v = K[i * m + col];
+      for (int k = 0; k < i; ++k) v -= Lc[i * m + k] * Y[k * m + col];
+      Y[i * m + col] = v / Lc[i * m + i];
+    }
+  for (int col = 0; col < m; ++col)
+    for (int i = 0; i < m; ++i) {
+      double v = Y[col * m + i];
+      for (int k = 0; k < i; ++k) v -= Lc[i * m + k] * C[col * m + k];
+      C[col * m + i] = v / Lc[i * m + i];
+    }
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < i; ++j) C[i * m + j] = C[j * m + i] = 0.5 * (C[i * m + j] + C[j * m + i]);
+  // cyclic Jacobi rotations (Golub and Van Loan, Algorithm 8.5.3): C = V diag(lam) V^T
+  std::vector<double> V(m * m, 0.0);
+  for (int i = 0; i < m; ++i) V[i * m + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0, tot = 0;
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) (i == j ? tot : off) += C[i * m + j] * C[i * m + j];
+    if (off <= 1e-30 * (tot + off)) break;
+    for (int p = 0; p < m - 1; ++p)
+      for (int r = p + 1; r < m; ++r) {
+        const double apr = C[p * m + r];
+        if (apr == 0.0) continue;
+        const double tau = (C[r * m + r] - C[p * m + p]) / (2.0 * apr);
+        const double tt = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+        const double cs = 1.0 / std::sqrt(1.0 + tt * tt), sn = tt * cs;
+        for (int k = 0; k < m; ++k) {  // C <- C J (columns p, r)
+          const double ckp = C[k * m + p], ckr = C[k * m + r];
+          C[k * m + p] = cs * ckp - sn * ckr;
+          C[k * m + r] = sn * ckp + cs * ckr;
+        }
+        for (int k = 0; k < m; ++k) {  // C <- J^T C (rows p, r)
+          const double cpk = C[p * m + k], crk = C[r * m + k];
+          C[p * m + k] = cs * cpk - sn * crk;
+          C[r * m + k] = sn * cpk + cs * crk;
+        }
+        for (int k = 0; k < m; ++k) {  // V <- V J
+          const double vkp = V[k * m + p], vkr = V[k * m + r];
+          V[k * m + p] = cs * vkp - sn * vkr;
+          V[k * m + r] = sn * vkp + cs * vkr;
+        }
+      }
+  }
+  f.lam.resize(m);
+  for (int k = 0; k < m; ++k) f.lam[k] = C[k * m + k];
+  // S = L^{-T} V: solve L^T S = V column by column
+  f.S.assign(m * m, 0.0);
+  for (int col = 0; col < m; ++col)
+    for (int i = m - 1; i >= 0; --i) {
+      double v = V[i * m + col];
+      for (int k = i + 1; k < m; ++k) v -= Lc[k * m + i] * f.S[k * m + col];
+      f.S[i * m + col] = v / Lc[i * m + i];
+    }
+  return f;
+}
+
 }  // namespace pmgi

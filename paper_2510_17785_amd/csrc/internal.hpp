@@ -25,7 +25,11 @@ enum PatchMode : int {
   kModeApply = 3,     // read interior vectors, apply one level operator
   kModeMetric = 4,    // setup: compute the cached levels' metric, write it to metric_out
   kModePcg = 5,       // FP64 only: CG on each patch problem, preconditioned by the V-cycle
+  kModePcgCart = 6,   // the same with the Cartesian-reinforced smoother in the V-cycle
 };
+
+// Per level of fdm tables: S (29 x 29 at most), lam, dM, dK (29 each).
+constexpr int kFdmStride = 29 * 29 + 3 * 29;
 
 // Arguments of every per-patch kernel.  Pointers to T-valued arrays are
 // void* here and cast inside the kernel.
@@ -86,6 +90,11 @@ struct PatchArgs {
   double* pcg_work;
   int32_t* pcg_iters;
   double* pcg_relres;
+  // Cartesian-reinforced smoother (kModePcgCart): fast-diagonalisation
+  // tables per smoothed level, kFdmStride doubles each (S row-major with
+  // column k the k-th eigenvector, then lam, dM, dK), and the damping omega
+  const double* fdm_tab;
+  double fdm_omega;
 };
 
 // One compiled (precision, dim, levels) variant of the patch kernels.

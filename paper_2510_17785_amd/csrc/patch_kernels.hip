@@ -457,6 +457,8 @@ struct Ctx {
   bool dense_ok = false;  // dense level matrices loaded (not in the setup kernels)
   bool metric_loaded = false;  // the cached metric was read from the setup's copy
   bool geo_needed = true;      // the patch geometry is used (Jacobian or metric)
+  const double* fdm = nullptr;  // Cartesian-reinforced smoother tables (kModePcgCart)
+  double omega = 0;
   __device__ T* X() const { return lds + Lay::X_off; }
   __device__ T* Out() const { return lds + Lay::Out_off; }
   __device__ T* abuf() const { return lds + Lay::abuf_off; }
@@ -1935,7 +1937,76 @@ __device__ void vcycle_small(const Ctx<T, DIM, LV>& c, int k) {
 
 // V-cycle at level L (Algorithm 2): pre-smooth, residual, restrict, recurse,
 // prolongate and correct, post-smooth; the coarsest level is solved exactly.
-template <typename T, int DIM, class LV, int L>
+// One pass of the fast diagonalisation along direction `dir` of an m^DIM
+// vector (x fastest): out_k = sum_a S[a][k] in_a (FWD, S^T) or
+// out_a = sum_k S[a][k] in_k (S).
+template <int DIM, int m, bool FWD>
+__device__ void fdm_pass(const double* in, double* out, const double* S, int dir) {
+  constexpr int N = ipow(m, DIM);
+  const int stride = dir == 0 ? 1 : (dir == 1 ? m : m * m);
+  for (int idx = threadIdx.x; idx < N; idx += NT<double>) {
+    const int i = (idx / stride) % m;
+    const int base = idx - i * stride;
+    double acc = 0;
+    for (int a = 0; a < m; ++a) acc += (FWD ? S[a * m + i] : S[i * m + a]) * in[base + a * stride];
+    out[idx] = acc;
+  }
+}
+
+// One Richardson step of the Cartesian-reinforced smoother (Section 3.1) on
+// level L: d += omega D diag(A_b) A_b^{-1} (r - A d), D the level's inverse
+// diagonal and A_b the operator of the two-cell Cartesian reference patch
+// (unit cells, coefficient 1), inverted by fast diagonalisation:
+// A_b^{-1} = S^(x d) diag(1 / sum_i lam_{k_i}) (S^T)^(x d).  FP64.
+template <int DIM, class LV, int L>
+__device__ void cartesian_step(const Ctx<double, DIM, LV>& c, bool d_zero) {
+  using T = double;
+  using PT = VecPtr<T, DIM, LV>;
+  constexpr int N = Layout<T, DIM, LV>::level_size(L);
+  constexpr int m = 2 * LV::q[L] - 1;
+  const double* S = c.fdm + L * kFdmStride;
+  const double* lam = S + m * m;
+  const double* dM = lam + m;
+  const double* dK = dM + m;
+  T* d = c.d(L);
+  const T* r = c.r(L);
+  const T* dinv = c.dinv(L);
+  T* u = c.res();
+  T* v = c.z();
+  if (d_zero) {
+    for (int i = threadIdx.x; i < N; i += NT<T>) u[i] = r[i];
+    __syncthreads();
+  } else {
+    apply_vec_epi<T, DIM, LV, L>(c, d, EpiResidual<T, PT>{vp<T, DIM, LV>(c.r(L)), vp<T, DIM, LV>(u)});
+  }
+  T* src = u;
+  T* dst = v;
+  for (int dir = 0; dir < DIM; ++dir) {
+    fdm_pass<DIM, m, true>(src, dst, S, dir);
+    __syncthreads();
+    T* t = src; src = dst; dst = t;
+  }
+  for (int i = threadIdx.x; i < N; i += NT<T>) {
+    const int k0 = i % m, k1 = (i / m) % m, k2 = DIM == 3 ? i / (m * m) : 0;
+    src[i] /= lam[k0] + lam[k1] + (DIM == 3 ? lam[k2] : 0.0);
+  }
+  __syncthreads();
+  for (int dir = 0; dir < DIM; ++dir) {
+    fdm_pass<DIM, m, false>(src, dst, S, dir);
+    __syncthreads();
+    T* t = src; src = dst; dst = t;
+  }
+  for (int i = threadIdx.x; i < N; i += NT<T>) {
+    const int a0 = i % m, a1 = (i / m) % m, a2 = DIM == 3 ? i / (m * m) : 0;
+    const double diag = DIM == 3 ? dK[a0] * dM[a1] * dM[a2] + dM[a0] * dK[a1] * dM[a2] + dM[a0] * dM[a1] * dK[a2]
+                                 : dK[a0] * dM[a1] + dM[a0] * dK[a1];
+    const double step = c.omega * dinv[i] * diag * src[i];
+    d[i] = d_zero ? step : d[i] + step;
+  }
+  __syncthreads();
+}
+
+template <typename T, int DIM, class LV, int L, bool CART = false>
 __device__ void vcycle(const Ctx<T, DIM, LV>& c, int k, bool d_zero) {
   constexpr int N = Layout<T, DIM, LV>::level_size(L);
   const int tid = threadIdx.x;
@@ -1986,13 +2057,16 @@ __device__ void vcycle(const Ctx<T, DIM, LV>& c, int k, bool d_zero) {
                             : mf * mc + mf * mf) <= Layout<T, DIM, LV>::abuf_elems,
                   "transfer temporaries exceed the work area");
     using PT = VecPtr<T, DIM, LV>;
-    chebyshev<T, DIM, LV, L>(c, k, d_zero);          // pre-smoothing
+    if constexpr (CART)                               // pre-smoothing
+      cartesian_step<DIM, LV, L>(c, d_zero);
+    else
+      chebyshev<T, DIM, LV, L>(c, k, d_zero);
     T* res = c.res();
     apply_vec_epi<T, DIM, LV, L>(c, c.d(L),           // residual
                                  EpiResidual<T, PT>{vp<T, DIM, LV>(c.r(L)), vp<T, DIM, LV>(res)});
     constexpr bool STAGE = !Layout<T, DIM, LV>::vec_in_lds;
     restrict_vec<T, DIM, QF, QC, STAGE>(res, c.r(L + 1), lds_cast(c.tabP(L)), lds_cast(c.abuf()));  // restriction
-    if constexpr (Layout<T, DIM, LV>::small_from(L + 1)) {                // recursion
+    if constexpr (!CART && Layout<T, DIM, LV>::small_from(L + 1)) {     // recursion
       if (c.dense_ok) {
         if (tid < 64) vcycle_small<T, DIM, LV, L + 1>(c, k);
         __syncthreads();
@@ -2000,10 +2074,13 @@ __device__ void vcycle(const Ctx<T, DIM, LV>& c, int k, bool d_zero) {
         vcycle<T, DIM, LV, L + 1>(c, k, true);
       }
     } else {
-      vcycle<T, DIM, LV, L + 1>(c, k, true);
+      vcycle<T, DIM, LV, L + 1, CART>(c, k, true);
     }
     prolong_add<T, DIM, QF, QC, STAGE>(c.d(L + 1), c.d(L), lds_cast(c.tabP(L)), lds_cast(c.abuf()));  // correction
-    chebyshev<T, DIM, LV, L>(c, k, false);           // post-smoothing
+    if constexpr (CART)                               // post-smoothing
+      cartesian_step<DIM, LV, L>(c, false);
+    else
+      chebyshev<T, DIM, LV, L>(c, k, false);
   }
 }
 
@@ -2285,7 +2362,7 @@ __device__ double block_sum(double v, double* red) {
 // barrier), the operator input and the V-cycle vectors in the patch context.
 // Each exit test uses a workgroup sum that every thread holds, so all
 // threads leave the loop together.
-template <int DIM, class LV>
+template <int DIM, class LV, bool CART>
 __device__ void patch_pcg(const Ctx<double, DIM, LV>& c, const PatchArgs& a, int patch) {
   using T = double;
   constexpr int N = Layout<T, DIM, LV>::level_size(0);
@@ -2299,7 +2376,7 @@ __device__ void patch_pcg(const Ctx<double, DIM, LV>& c, const PatchArgs& a, int
   const T* d0 = c.d(0);   // V-cycle result
   T* v = c.z();           // operator input
   auto precondition = [&]() {
-    for (int it = 0; it < a.n_vcycles; ++it) vcycle<T, DIM, LV, 0>(c, a.cheb_degree, it == 0);
+    for (int it = 0; it < a.n_vcycles; ++it) vcycle<T, DIM, LV, 0, CART>(c, a.cheb_degree, it == 0);
     __syncthreads();
   };
   double bb = 0;
@@ -2449,8 +2526,12 @@ __device__ __forceinline__ void patch_update(const PatchArgs& a, Ctx<T, DIM, LV>
       for (int i = tid; i < Lay::G_total; i += NT<T>) dst[i] = src[i];
     }
     return;
-  } else if constexpr (MODE == kModePcg) {
-    if constexpr (std::is_same<T, double>::value) patch_pcg<DIM, LV>(c, a, patch);
+  } else if constexpr (MODE == kModePcg || MODE == kModePcgCart) {
+    if constexpr (std::is_same<T, double>::value) {
+      c.fdm = a.fdm_tab;
+      c.omega = a.fdm_omega;
+      patch_pcg<DIM, LV, MODE == kModePcgCart>(c, a, patch);
+    }
     return;
   } else if constexpr (MODE == kModeApply) {
     // y = A_{j,q} x for the requested level
@@ -3084,6 +3165,9 @@ struct Variant {
       case kModeMetric: return go<kModeMetric, false>(a, g, lds, s);
       case kModePcg:
         if constexpr (std::is_same<T, double>::value) return go<kModePcg, false>(a, g, lds, s);
+        return hipErrorInvalidValue;
+      case kModePcgCart:
+        if constexpr (std::is_same<T, double>::value) return go<kModePcgCart, false>(a, g, lds, s);
         return hipErrorInvalidValue;
       default: return hipErrorInvalidValue;
     }

@@ -68,14 +68,21 @@ def study_patches(dim: int, distortions: Sequence[float], jumps: Sequence[float]
 def run_study(dim: int, p: int, distortions: Sequence[float] = (0.0, 0.05, 0.1, 0.15, 0.2, 0.25, 0.3),
               jumps: Sequence[float] = (1.0, 1e2, 1e4, 1e6, 1e8), fixed_jump: float = 1e4,
               realizations: int = 20, rtol: float = 1e-8, maxit: int = 100, seed: int = 7000,
-              device=None) -> Dict:
-    """Run the three sweeps for one (dim, p); returns the per-group rows, the
+              smoother: str = "jacobi", device=None) -> Dict:
+    """Run the three sweeps for one (dim, p) with the damped Jacobi
+    (`smoother="jacobi"`) or the Cartesian-reinforced smoother
+    (`"cartesian"`, omega = 1/2 as well); returns the per-group rows, the
     per-patch iteration counts and residuals, and the time of the CG call."""
     dev = torch.device("cuda", 0) if device is None else device
     levels = paper_levels(p)
     groups, X, mu = study_patches(dim, distortions, jumps, fixed_jump, realizations, seed)
     B = PatchBatch(dim, p, X, mu, levels=levels, precision="fp64", cheb_degree=1, bounds="fixed")
-    B.set_bounds(np.broadcast_to(np.array(OMEGA_HALF_BOUNDS), (B.n_patches, len(levels) - 1, 2)).copy())
+    if smoother == "cartesian":
+        B.set_smoother("cartesian", 0.5)
+    elif smoother == "jacobi":
+        B.set_bounds(np.broadcast_to(np.array(OMEGA_HALF_BOUNDS), (B.n_patches, len(levels) - 1, 2)).copy())
+    else:
+        raise ValueError(smoother)
     b = np.random.default_rng(seed + 300).standard_normal((B.n_patches, B.level_sizes[0]))
     bd = torch.tensor(b, device=dev)
     torch.cuda.synchronize()
@@ -93,6 +100,7 @@ def run_study(dim: int, p: int, distortions: Sequence[float] = (0.0, 0.05, 0.1, 
                      "min": int(k.min()), "max": int(k.max()),
                      "not_converged": int((~ok).sum())})
     B.close()
-    return {"dim": dim, "p": p, "levels": levels, "rows": rows, "iterations": its, "relres": rels,
+    return {"dim": dim, "p": p, "levels": levels, "smoother": smoother, "rows": rows,
+            "iterations": its, "relres": rels,
             "X": X, "mu": mu, "b": b, "groups": groups, "seconds": seconds,
             "patch_dofs": int(b.shape[1]), "v_cycles": int(its.sum())}

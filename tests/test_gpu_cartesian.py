@@ -1,0 +1,112 @@
+"""The Cartesian-reinforced smoother (Section 3.1) in the batched patch CG
+(pmg_set_smoother + pmg_patch_pcg) against the FP64 oracle.
+
+Parity: on undeformed patches with one coefficient the smoother inverts the
+level operators, so CG with one V-cycle ends after exactly as many
+iterations as there are levels (a closed form, see the oracle pins); there
+and on distorted and jump patches every converged patch's count equals the
+oracle's, its final relative residual agrees to 1e-4 of its value (with an
+absolute floor of 1e-13, the rounding level where CG terminates exactly) and,
+on undeformed patches, its solution to 1e-10 (FP64; a count may differ by
+one only where an oracle residual lies within 1% of the threshold).  Patches
+that do not converge within the iteration cap are compared by that status.
+
+Trends in 2D, as the paper states them: the smoother beats damped Jacobi
+on near-Cartesian patches, and fails on coefficient jumps beyond a modest
+contrast (the paper says roughly 1e2).  Checked as: from a jump of 1e3 in
+one cell, at least half of ten runs (one patch, ten right-hand sides; the
+preconditioner is not symmetric there, so convergence depends on the
+right-hand side) miss 1e-8 within 100 iterations, where damped Jacobi
+converges in all of them.  The oracle gives the same counts (7, 9, 6 of 10
+at p = 3 for 1e3, 1e4, 1e8; 9-10 at p = 7 and 15).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import synth  # noqa: E402
+from oracle import fem, pmg  # noqa: E402
+
+from gpu_common import rel_err  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def _levels(p):
+    return (p,) + tuple(q for q in (15, 7, 3, 1) if q < p)
+
+
+def _oracle(X, mu, levels, b, rtol, maxit):
+    s = pmg.LocalSolver(fem.PatchGeometry(X, mu), levels, smoother="cartesian", omega=0.5)
+    x, k, r = s.pcg(b, rtol, maxit)
+    near = False
+    if r <= rtol and k < maxit:
+        prev = s.pcg(b, 0.0, k - 1)[2] if k > 1 else 1.0
+        near = abs(r / rtol - 1) < 0.01 or abs(prev / rtol - 1) < 0.01
+    return x, k, r, near
+
+
+@pytest.mark.parametrize("dim,p", [(2, 3), (2, 7), (2, 15), (3, 3), (3, 7)])
+def test_undeformed_patches_one_iteration_per_level(dev, dim, p):
+    from paper_2510_17785_amd import PatchBatch
+    X, mu = synth.make_sphere_distorted_patches(dim, 3, 0.0, 11)
+    X = X * 0.37
+    mu = mu * 4.2
+    lv = _levels(p)
+    B = PatchBatch(dim, p, X, mu, levels=lv, precision="fp64", cheb_degree=1, bounds="fixed")
+    B.set_smoother("cartesian", 0.5)
+    b = np.random.default_rng(p).standard_normal((3, B.level_sizes[0]))
+    x, it, rel = B.pcg(torch.tensor(b, device=dev), 1e-12, 50)
+    x, it, rel = x.cpu().numpy(), it.cpu().numpy(), rel.cpu().numpy()
+    assert (it == len(lv)).all() and (rel <= 1e-12).all(), (it, rel)
+    for j in range(3):
+        xo, ko, _, _ = _oracle(X[j], mu[j], lv, b[j], 1e-12, 50)
+        assert ko == len(lv)
+        assert rel_err(x[j], xo) <= 1e-10, j
+
+
+@pytest.mark.parametrize("dim,p", [(2, 3), (2, 7), (3, 3)])
+def test_study_matches_oracle(dev, dim, p):
+    from paper_2510_17785_amd.study import run_study
+    res = run_study(dim, p, distortions=(0.0, 0.2), jumps=(1.0, 10.0, 1e4), realizations=2, seed=90 + p,
+                    smoother="cartesian", maxit=100)
+    for j in range(len(res["X"])):
+        xo, ko, ro, near = _oracle(res["X"][j], res["mu"][j], res["levels"], res["b"][j], 1e-8, 100)
+        kg, rg = int(res["iterations"][j]), float(res["relres"][j])
+        if ro > 1e-8:   # not converged in the oracle: not converged on the GPU either
+            assert kg == 100 and rg > 1e-8, (j, kg, rg, ro)
+        elif near:
+            assert abs(kg - ko) <= 1, (j, kg, ko)
+        else:
+            # residuals at exact termination are rounding noise: absolute floor
+            assert kg == ko and abs(rg - ro) <= 1e-4 * ro + 1e-13, (j, kg, ko, rg, ro)
+
+
+@pytest.mark.parametrize("p", [3, 7, 15])
+def test_trends_2d(dev, p):
+    from paper_2510_17785_amd.study import run_study
+    dist = (0.0, 0.1, 0.2)
+    jumps = (1.0, 1e3, 1e4, 1e8)
+    kw = dict(distortions=dist, jumps=jumps, realizations=10, maxit=100)
+    cart = {(r["sweep"], r["value"]): r for r in run_study(2, p, smoother="cartesian", **kw)["rows"]}
+    jac = {(r["sweep"], r["value"]): r for r in run_study(2, p, smoother="jacobi", **kw)["rows"]}
+    print(f"\n2D p={p} Cartesian-reinforced: distortion {dist} -> "
+          f"{[cart[('distortion', d)]['mean_iterations'] for d in dist]} (Jacobi "
+          f"{[jac[('distortion', d)]['mean_iterations'] for d in dist]}); jump {jumps} not converged "
+          f"{[cart[('jump', m)]['not_converged'] for m in jumps]} of 10")
+    assert cart[("distortion", 0.0)]["max"] == len(_levels(p))
+    for d in dist:   # better than Jacobi on near-Cartesian patches
+        assert cart[("distortion", d)]["not_converged"] == 0
+        assert cart[("distortion", d)]["mean_iterations"] < jac[("distortion", d)]["mean_iterations"]
+    assert cart[("jump", 1.0)]["not_converged"] == 0
+    for m in jumps[1:]:   # high contrast: most runs fail, where Jacobi converges in all
+        assert cart[("jump", m)]["not_converged"] >= 5
+        assert jac[("jump", m)]["not_converged"] == 0
