@@ -17,10 +17,12 @@ V-cycle, one smoothing step each way (Section 4): on the coarsest level an
 exact solve (dense Cholesky); otherwise
     u = sweep_forward(0, f);  r = f - A u;  u += P V(R r);  u = sweep_backward(u, f).
 Pre- and post-smoothing visit the patches in opposite orders, which keeps the
-preconditioner symmetric so that CG applies (the paper runs GMRES with one
-fixed order, Section 4).
+preconditioner symmetric so that CG applies.  With post_direction = +1 both
+sweeps use the same colour order, as the paper does (Section 4), and the
+preconditioner is not symmetric.
 
-Outer solver: preconditioned CG from x = 0, stopped at ||r_k|| <= rtol ||b||.
+Outer solvers: preconditioned CG, or GMRES with the preconditioner on the
+right (Section 4 runs GMRES), from x = 0, stopped at ||r_k|| <= rtol ||b||.
 """
 from __future__ import annotations
 
@@ -71,8 +73,9 @@ def prolongation_h(dim: int, nc: int, p: int) -> sp.csr_matrix:
 class GMG:
     def __init__(self, mesh: Mesh, p: int, levels, cheb_degree=3, n_vcycles=1,
                  lanczos_steps=12, seed=0, bounds=None, with_boundary=False,
-                 coarse_mean="arithmetic"):
+                 coarse_mean="arithmetic", post_direction=-1):
         self.dim, self.p = mesh.dim, p
+        self.post_direction = post_direction
         sizes = hierarchy_sizes(mesh.n)
         meshes = [mesh]
         while meshes[-1].n != sizes[0]:
@@ -103,7 +106,7 @@ class GMG:
         u = S.sweep(np.zeros_like(f), f, +1)
         r = f - self.A[level] @ u
         u = u + self.P[level - 1] @ self.vcycle(level - 1, self.P[level - 1].T @ r)
-        u = S.sweep(u, f, -1)
+        u = S.sweep(u, f, self.post_direction)
         return u
 
     def precondition(self, r):
@@ -134,3 +137,56 @@ class GMG:
             d = z + (rz_new / rz) * d
             rz = rz_new
         return x, maxit + 1, hist
+
+    def gmres(self, b, rtol=1e-8, maxit=100):
+        """GMRES preconditioned on the right by one V-cycle.  Returns
+        (x, iterations, relative residual); iterations = maxit + 1 signals no
+        convergence."""
+        return gmres(lambda v: self.A[-1] @ v, self.precondition, b, rtol, maxit)
+
+
+def gmres(apply_A, precondition, b, rtol, maxit):
+    """Flexible GMRES with the preconditioner on the right, from x = 0, no
+    restart (Saad, Iterative Methods for Sparse Linear Systems, 2nd ed.,
+    Algorithm 9.6): Arnoldi with modified Gram-Schmidt on A M^{-1}, Givens
+    rotations for the least-squares problem, x = Z y with z_j = M^{-1} v_j.
+    Stops after the first iteration k with ||b - A x_k|| <= rtol ||b|| (the
+    rotated right-hand side gives that norm), or after maxit.
+    Returns (x_k, k or maxit + 1, ||b - A x_k|| / ||b||)."""
+    n = b.shape[0]
+    beta = np.linalg.norm(b)
+    if beta == 0.0:
+        return np.zeros_like(b), 0, 0.0
+    V = [b / beta]
+    Z = []
+    H = np.zeros((maxit + 1, maxit))
+    cs, sn = np.zeros(maxit), np.zeros(maxit)
+    g = np.zeros(maxit + 1)
+    g[0] = beta
+    k_done = maxit + 1
+    for j in range(maxit):
+        Z.append(precondition(V[j]))
+        w = apply_A(Z[j])
+        for i in range(j + 1):                 # modified Gram-Schmidt
+            H[i, j] = w @ V[i]
+            w = w - H[i, j] * V[i]
+        H[j + 1, j] = np.linalg.norm(w)
+        V.append(w / H[j + 1, j] if H[j + 1, j] != 0.0 else w)
+        for i in range(j):                     # earlier rotations on the new column
+            hi = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+            H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+            H[i, j] = hi
+        den = np.hypot(H[j, j], H[j + 1, j])
+        cs[j], sn[j] = H[j, j] / den, H[j + 1, j] / den
+        H[j, j] = den
+        H[j + 1, j] = 0.0
+        g[j + 1] = -sn[j] * g[j]
+        g[j] = cs[j] * g[j]
+        if abs(g[j + 1]) <= rtol * beta:
+            k_done = j + 1
+            break
+    k = min(k_done, maxit)
+    y = sla.solve_triangular(H[:k, :k], g[:k])
+    x = sum(y[i] * Z[i] for i in range(k))
+    return x, k_done, abs(g[k]) / beta
+

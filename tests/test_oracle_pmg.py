@@ -579,3 +579,68 @@ def test_cartesian_step_uses_the_reference_patch():
     d1 = s.cartesian_step(0, r, d0)
     expect1 = d0 + 0.5 * s.dinv[0] * np.diag(Ab) * np.linalg.solve(Ab, r - s.A[0] @ d0)
     assert np.abs(d1 - expect1).max() <= 1e-12 * np.abs(expect1).max()
+
+
+# ---------------------------------------------------------------------------
+# GMRES and the paper's sweep order
+# ---------------------------------------------------------------------------
+
+def test_gmres_reaches_the_direct_solution_with_monotone_residuals():
+    rng = np.random.default_rng(11)
+    A = np.eye(40) * 4 + rng.standard_normal((40, 40))      # non-symmetric
+    b = rng.standard_normal(40)
+    x, k, rel = gmg.gmres(lambda v: A @ v, lambda r: r / np.diag(A), b, 1e-12, 40)
+    xs = np.linalg.solve(A, b)
+    assert k <= 40 and rel <= 1e-12
+    assert np.linalg.norm(x - xs) <= 1e-9 * np.linalg.norm(xs)
+    assert abs(np.linalg.norm(b - A @ x) / np.linalg.norm(b) - rel) <= 1e-12
+    # minimal residual over growing Krylov spaces: true residuals never increase
+    prev = np.inf
+    for kmax in range(1, 12):
+        x, _, _ = gmg.gmres(lambda v: A @ v, lambda r: r, b, 0.0, kmax)
+        res = np.linalg.norm(b - A @ x)
+        assert res <= prev * (1 + 1e-12)
+        prev = res
+
+
+def test_gmres_finite_termination():
+    # a diagonalisable matrix with 3 distinct eigenvalues: 3 iterations;
+    # the exact inverse as preconditioner: 1
+    rng = np.random.default_rng(12)
+    Q = rng.standard_normal((25, 25))
+    A = Q @ np.diag(np.repeat([1.0, 2.5, 6.0], [10, 8, 7])) @ np.linalg.inv(Q)
+    b = rng.standard_normal(25)
+    _, k, rel = gmg.gmres(lambda v: A @ v, lambda r: r, b, 1e-9, 50)
+    assert k == 3 and rel <= 1e-9
+    Ainv = np.linalg.inv(A)
+    _, k, rel = gmg.gmres(lambda v: A @ v, lambda r: Ainv @ r, b, 1e-9, 50)
+    assert k == 1
+    x, k, rel = gmg.gmres(lambda v: A @ v, lambda r: r, np.zeros(25), 1e-9, 50)
+    assert k == 0 and rel == 0.0 and not x.any()
+    _, k, rel = gmg.gmres(lambda v: A @ v, lambda r: r, b, 0.0, 2)
+    assert k == 3 and 0 < rel < 1      # maxit + 1: not converged
+
+
+def test_paper_order_vcycle_is_not_symmetric_and_gmres_converges():
+    w = synth.workload("2d-n8-q3")
+    X = synth.make_vertices(2, 4, 0.2, 5)
+    mesh = fem.Mesh(2, 4, X, np.ones(16))
+    G = gmg.GMG(mesh, 3, (3, 1), cheb_degree=1, post_direction=+1)
+    G1 = gmg.GMG(mesh, 3, (3, 1), cheb_degree=1, post_direction=-1)
+    n = G.A[-1].shape[0]
+    mask = fem.dirichlet_mask(2, 4, 3)
+    idx = np.flatnonzero(mask)[:12]
+    def mat(GG):
+        cols = []
+        for j in idx:
+            e = np.zeros(n); e[j] = 1.0
+            cols.append(GG.precondition(e)[idx])
+        return np.array(cols).T
+    B, B1 = mat(G), mat(G1)
+    assert np.abs(B1 - B1.T).max() <= 1e-10 * np.abs(B1).max()     # opposite orders: symmetric
+    assert np.abs(B - B.T).max() > 1e-4 * np.abs(B).max()          # one order: not symmetric
+    b = np.random.default_rng(3).standard_normal(n) * mask
+    x, k, rel = G.gmres(b, 1e-10, 50)
+    assert rel <= 1e-10 and k <= 50
+    xs = sla.solve(G.A[-1].toarray()[np.ix_(mask, mask)], b[mask])
+    assert np.abs(x[mask] - xs).max() <= 1e-8 * np.abs(xs).max()
