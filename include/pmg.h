@@ -321,6 +321,27 @@ int gmg_vcycle(gmg_handle* g, const double* r, double* z);
 int gmg_cg_solve(gmg_handle* g, double* x, const double* b, double rtol, int32_t maxit,
                  int32_t* iters, double* relres);
 
+/* Largest maxit that gmg_gmres_solve accepts. */
+#define PMG_GMRES_MAXIT_LIMIT 500
+
+/* Colour order of the post-smoothing sweep of the V-cycle: -1 (the default)
+ * reverses the pre-smoothing order, which keeps the preconditioner
+ * symmetric; +1 repeats it, as the paper does (Section 4), for GMRES.
+ * PMG_ERR_INVALID_ARG for other values. */
+int gmg_set_post_direction(gmg_handle* g, int32_t direction);
+
+/* GMRES from x = 0 with one V-cycle as right preconditioner (the outer
+ * solver of Section 4; flexible form, no restart: 2 maxit + 1 device vectors
+ * of the fine size, allocated at the first call that needs them and kept
+ * until gmg_destroy), until ||b - A x|| <= rtol ||b|| or maxit iterations.
+ * x, b: device FP64; iters, relres: host (may be NULL); iters = maxit + 1
+ * and PMG_WARN_NOT_CONVERGED when maxit is hit.  Synchronous.
+ * PMG_ERR_INVALID_ARG: null pointer, rtol not finite and > 0, maxit outside
+ * 1..PMG_GMRES_MAXIT_LIMIT; PMG_ERR_BREAKDOWN on a zero or non-finite
+ * rotation. */
+int gmg_gmres_solve(gmg_handle* g, double* x, const double* b, double rtol, int32_t maxit,
+                    int32_t* iters, double* relres);
+
 /* Number of mesh levels, or the smoother handle of level l (1 = coarsest
  * smoothed level, n_levels-1 = finest); the handle stays owned by g. */
 int gmg_query(const gmg_handle* g, int32_t what, int64_t* value);

@@ -413,6 +413,22 @@ class GMGSolver:
                                        ctypes.byref(it), ctypes.byref(rel)))
         return x, it.value, rel.value
 
+    def gmres(self, b: torch.Tensor, rtol: float = 1e-8, maxit: int = 100):
+        """gmg_gmres_solve: GMRES with one V-cycle as right preconditioner.
+        Returns (x, iterations, relative residual); iterations = maxit + 1
+        when it did not converge."""
+        x = torch.empty_like(b)
+        it = ctypes.c_int32()
+        rel = ctypes.c_double()
+        L.check(self._lib.gmg_gmres_solve(self._h, _dptr(x), _dptr(b), float(rtol), int(maxit),
+                                          ctypes.byref(it), ctypes.byref(rel)))
+        return x, it.value, rel.value
+
+    def set_post_direction(self, direction: int):
+        """gmg_set_post_direction: -1 (reversed, symmetric) or +1 (the
+        paper's same order)."""
+        L.check(self._lib.gmg_set_post_direction(self._h, int(direction)))
+
     def close(self):
         if getattr(self, "_h", None) is not None:
             L.check(self._lib.gmg_destroy(self._h))

@@ -910,6 +910,8 @@ struct gmg_handle {
   double* partial = nullptr;
   double* scal = nullptr;  // device scalars
   double* hscal = nullptr; // pinned host scalars
+  int post_dir = -1;       // colour order of the post-smoothing sweep (-1: reversed)
+  std::vector<double*> kv; // GMRES: Krylov basis and preconditioned vectors (grown on demand)
   int64_t len(int l) const {
     int64_t M = (int64_t)sizes[l] * p + 1;
     return dim == 3 ? M * M * M : M * M;
@@ -947,6 +949,7 @@ void free_gmg(gmg_handle* g) {
   fr(g->Ad);
   fr(g->partial);
   fr(g->scal);
+  for (auto* p : g->kv) fr(p);
   if (g->hscal) (void)hipHostFree(g->hscal);
   delete g;
 }
@@ -996,7 +999,7 @@ int vcycle(gmg_handle* g, int l, const double* f, double* u) {
   PMG_TRY(vcycle(g, l - 1, g->f[l - 1], g->u[l - 1]));
   PMG_TRY(h_transfer(g, l - 1, g->u[l - 1], t, false));
   HIP_TRY(launch_axpby(g->len(l), 1.0, t, 1.0, u, g->stream));
-  PMG_TRY(pmg_patch_smooth(S, u, f, -1));
+  PMG_TRY(pmg_patch_smooth(S, u, f, g->post_dir));
   return PMG_OK;
 }
 
@@ -1510,6 +1513,112 @@ int gmg_cg_solve(gmg_handle* g, double* x, const double* b, double rtol, int32_t
   if (relres) *relres = rel;
   g_last_error = "CG did not converge within maxit iterations";
   return PMG_WARN_NOT_CONVERGED;
+}
+
+int gmg_set_post_direction(gmg_handle* g, int32_t direction) {
+  if (!g) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  if (direction != 1 && direction != -1) return fail(PMG_ERR_INVALID_ARG, "direction must be +1 or -1");
+  g->post_dir = direction;
+  return PMG_OK;
+}
+
+int gmg_gmres_solve(gmg_handle* g, double* x, const double* b, double rtol, int32_t maxit, int32_t* iters,
+                    double* relres) {
+  if (!g || !x || !b) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(PMG_ERR_INVALID_ARG, "need a finite rtol > 0");
+  if (maxit < 1 || maxit > PMG_GMRES_MAXIT_LIMIT)
+    return fail(PMG_ERR_INVALID_ARG, "maxit %d outside 1..%d", maxit, PMG_GMRES_MAXIT_LIMIT);
+  const int lf = g->nlev - 1;
+  const int64_t n = g->len(lf);
+  hipStream_t s = g->stream;
+  // V_0 .. V_maxit (Arnoldi basis), then Z_0 .. Z_{maxit-1} (preconditioned)
+  const size_t need = 2 * (size_t)maxit + 1;
+  while (g->kv.size() < need) {
+    double* p = nullptr;
+    PMG_TRY(dev_alloc(&p, (size_t)n * sizeof(double), nullptr));
+    g->kv.push_back(p);
+  }
+  auto V = [&](int i) { return g->kv[i]; };
+  auto Z = [&](int i) { return g->kv[maxit + 1 + i]; };
+  auto scalar = [&](const double* a, const double* c, double* out) -> int {
+    PMG_TRY(dot(g, a, c, 0));
+    HIP_TRY(hipMemcpyAsync(g->hscal, g->scal, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *out = g->hscal[0];
+    return PMG_OK;
+  };
+  // x = 0; v_0 = b / ||b|| (Dirichlet entries of b are ignored)
+  HIP_TRY(hipMemsetAsync(x, 0, n * sizeof(double), s));
+  HIP_TRY(hipMemcpyAsync(V(0), b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(launch_mask_dirichlet(g->dim, g->M(lf), V(0), s));
+  double beta2 = 0;
+  PMG_TRY(scalar(V(0), V(0), &beta2));
+  const double beta = std::sqrt(beta2);
+  if (beta == 0.0) {
+    if (iters) *iters = 0;
+    if (relres) *relres = 0.0;
+    return PMG_OK;
+  }
+  HIP_TRY(launch_axpby(n, 0.0, V(0), 1.0 / beta, V(0), s));
+  // Arnoldi with modified Gram-Schmidt on A M^{-1}, Givens rotations on the
+  // Hessenberg matrix (Saad, Iterative Methods for Sparse Linear Systems,
+  // Algorithm 9.6, flexible GMRES, no restart)
+  std::vector<double> H((size_t)(maxit + 1) * maxit, 0.0), cs(maxit), sn(maxit), gv(maxit + 1, 0.0);
+  auto h = [&](int i, int j) -> double& { return H[(size_t)i * maxit + j]; };
+  gv[0] = beta;
+  int k_done = maxit + 1;
+  for (int j = 0; j < maxit; ++j) {
+    PMG_TRY(vcycle(g, lf, V(j), Z(j)));
+    PMG_TRY(global_apply(g, lf, Z(j), V(j + 1)));
+    for (int i = 0; i <= j; ++i) {
+      double hij = 0;
+      PMG_TRY(scalar(V(j + 1), V(i), &hij));
+      h(i, j) = hij;
+      HIP_TRY(launch_axpby(n, -hij, V(i), 1.0, V(j + 1), s));
+    }
+    double hn2 = 0;
+    PMG_TRY(scalar(V(j + 1), V(j + 1), &hn2));
+    const double hn = std::sqrt(hn2);
+    h(j + 1, j) = hn;
+    if (hn != 0.0) HIP_TRY(launch_axpby(n, 0.0, V(j + 1), 1.0 / hn, V(j + 1), s));
+    for (int i = 0; i < j; ++i) {
+      const double hi = cs[i] * h(i, j) + sn[i] * h(i + 1, j);
+      h(i + 1, j) = -sn[i] * h(i, j) + cs[i] * h(i + 1, j);
+      h(i, j) = hi;
+    }
+    const double den = std::hypot(h(j, j), h(j + 1, j));
+    if (!(den > 0.0) || !std::isfinite(den)) {
+      if (iters) *iters = j + 1;
+      return fail(PMG_ERR_BREAKDOWN, "GMRES breakdown at iteration %d", j + 1);
+    }
+    cs[j] = h(j, j) / den;
+    sn[j] = h(j + 1, j) / den;
+    h(j, j) = den;
+    h(j + 1, j) = 0.0;
+    gv[j + 1] = -sn[j] * gv[j];
+    gv[j] = cs[j] * gv[j];
+    if (std::fabs(gv[j + 1]) <= rtol * beta) {
+      k_done = j + 1;
+      break;
+    }
+  }
+  // x = Z y with H y = g (upper triangular, the first k rows)
+  const int k = std::min(k_done, (int)maxit);
+  std::vector<double> y(k);
+  for (int i = k - 1; i >= 0; --i) {
+    double v = gv[i];
+    for (int t = i + 1; t < k; ++t) v -= h(i, t) * y[t];
+    y[i] = v / h(i, i);
+  }
+  for (int i = 0; i < k; ++i) HIP_TRY(launch_axpby(n, y[i], Z(i), 1.0, x, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (iters) *iters = k_done;
+  if (relres) *relres = std::fabs(gv[k]) / beta;
+  if (k_done > maxit) {
+    g_last_error = "GMRES did not converge within maxit iterations";
+    return PMG_WARN_NOT_CONVERGED;
+  }
+  return PMG_OK;
 }
 
 int gmg_query(const gmg_handle* g, int32_t what, int64_t* value) {

@@ -15,4 +15,5 @@ from .generators import (  # noqa: F401
     make_random_patch,
     make_random_patches,
     make_sphere_distorted_patches,
+    make_sphere_distorted_mesh,
 )

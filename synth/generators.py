@@ -352,3 +352,42 @@ def make_sphere_distorted_patches(dim: int, n: int, delta: float, seed: int,
     if mu_cell is not None:
         mu[:, 0] = mu_cell
     return X, mu
+
+
+def make_sphere_distorted_mesh(dim: int, n: int, delta: float, seed: int,
+                               det_floor: float = 0.01, max_redraws: int = 10000) -> np.ndarray:
+    """Structured mesh of the unit square/cube with n cells per direction whose
+    interior vertices are each moved by delta h (h = 1/n, the length of every
+    edge at a vertex of the uniform mesh) in a direction drawn uniformly on
+    the unit sphere (a normalised standard Gaussian vector): the distortion
+    model of the global experiments in Section 4.  Draws happen for all
+    vertices in lexicographic order; boundary draws are discarded.  Cells whose
+    sampled Jacobian determinant falls to det_floor h^dim or below get the
+    directions of their interior vertices redrawn from the continuing stream,
+    until no such cell is left."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    h = 1.0 / n
+    n1 = n + 1
+    coords = _all_cells(dim, n1)
+    base = coords.astype(np.float64) * h
+    if delta == 0.0:
+        return base.copy()
+    interior = np.all((coords > 0) & (coords < n), axis=1)
+
+    def draw(k):
+        d = rng.standard_normal((k, dim))
+        return delta * h * d / np.linalg.norm(d, axis=1, keepdims=True)
+
+    disp = draw(base.shape[0])
+    disp[~interior] = 0.0
+    cells = _all_cells(dim, n)
+    corners = _corner_rows(dim, n1, cells)
+    floor = det_floor * h ** dim
+    for _ in range(max_redraws):
+        verts = base + disp
+        bad = np.flatnonzero(_min_jacobian_batched(verts[corners], dim) <= floor)
+        if bad.size == 0:
+            return verts
+        move = sorted({int(vi) for c in bad for vi in corners[c] if interior[vi]})
+        disp[move] = draw(len(move))
+    raise RuntimeError("could not draw a mesh without degenerate cells")

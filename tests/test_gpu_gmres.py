@@ -1,0 +1,132 @@
+"""GMRES with the GMG preconditioner and the paper's sweep order (Section 4)
+through the C ABI.
+
+Parity: on a small 2D mesh (8 x 8 cells, Q3, levels 3 -> 1, damped Jacobi
+omega = 1/2 as the local smoother, the same colour order before and after
+the coarse correction) the GPU's GMRES takes the oracle's iteration count
+and reaches its solution to 1e-9 (FP64; one V-cycle agrees to about 1e-13,
+and GMRES amplifies that by the conditioning of its small least-squares
+problems); CG with the symmetric order is unchanged.
+
+The paper's table (tests/golden/table2_gmres_jacobi_2d.txt, 2D, 32 x 32
+cells, p = 3, 7, 15, N_MG = 1, 2, 25, distortion 0..35%), with the patches
+of all vertices (boundary ones cut to their cells inside the domain): our
+counts are printed beside the paper's.  Asserted: at p = 3 within one
+iteration of the paper for N_MG = 1, 2; with nearly exact local solves
+(N_MG = 25) within two for every p; more local V-cycles never cost
+iterations; counts do not fall as the distortion grows (by more than one).
+Not asserted, and reported: at p = 7 and 15 with one or two local V-cycles
+our counts exceed the paper's (our single-patch counts at p = 15 are also
+higher, 27 against its roughly 23), so the gap lies in the local V-cycle,
+not in the global method, which matches the paper at N_MG = 25.  The setups
+differ where the paper leaves things open or chooses otherwise: the coarsest
+level is solved exactly here (the paper uses GMRES preconditioned by one
+patch sweep), and the distorted meshes are our own random draws of the
+paper's model.
+"""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import synth  # noqa: E402
+from oracle import fem, gmg  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+OMEGA_HALF = (0.5, 3.5 / 1.1)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def _levels(p):
+    return (p,) + tuple(q for q in (15, 7, 3, 1) if q < p)
+
+
+def _gpu_solver(dim, n, p, X, n_mg, post, with_boundary=False):
+    from paper_2510_17785_amd import GMGSolver
+    lv = _levels(p)
+    G = GMGSolver(dim, n, p, X, np.ones(n ** dim), levels=lv, precision="fp64", cheb_degree=1,
+                  n_vcycles=n_mg, bounds="fixed", with_boundary=with_boundary)
+    for l in range(1, G.n_mesh_levels):
+        S = G.smoother(l)
+        S.set_bounds(np.broadcast_to(np.array(OMEGA_HALF), (S.n_patches, len(lv) - 1, 2)).copy())
+    G.set_post_direction(post)
+    return G
+
+
+@pytest.mark.parametrize("post", [+1, -1])
+def test_gmres_matches_oracle(dev, post):
+    dim, n, p = 2, 8, 3
+    X = synth.make_sphere_distorted_mesh(dim, n, 0.25, 21)
+    G = _gpu_solver(dim, n, p, X, 1, post)
+    mask = fem.dirichlet_mask(dim, n, p)
+    b = np.random.default_rng(4).standard_normal(mask.size) * mask
+    x, it, rel = G.gmres(torch.tensor(b, device=dev), 1e-8, 100)
+    O = gmg.GMG(fem.Mesh(dim, n, X, np.ones(n ** dim)), p, _levels(p), cheb_degree=1, post_direction=post)
+    for S in O.smoothers[1:]:
+        for s in S.solvers.values():
+            s.set_bounds([OMEGA_HALF] * (len(_levels(p)) - 1))
+    xo, ko, ro = O.gmres(b, 1e-8, 100)
+    assert it == ko, (it, ko)
+    assert abs(rel - ro) <= 1e-4 * ro
+    xg = x.cpu().numpy()
+    assert np.abs(xg - xo).max() <= 1e-9 * np.abs(xo).max()
+    if post == -1:   # symmetric order: CG as before, and GMRES needs no more iterations than CG
+        _, it_cg, _ = G.cg(torch.tensor(b, device=dev), 1e-8, 100)
+        assert it <= it_cg
+
+
+def test_rejected_arguments(dev):
+    from paper_2510_17785_amd._lib import PmgError
+    X = synth.make_sphere_distorted_mesh(2, 4, 0.1, 3)
+    G = _gpu_solver(2, 4, 3, X, 1, +1)
+    b = torch.zeros(13 ** 2, dtype=torch.float64, device=dev)
+    for rtol, maxit in [(0.0, 10), (float("nan"), 10), (1e-8, 0), (1e-8, 501)]:
+        with pytest.raises(PmgError):
+            G.gmres(b, rtol, maxit)
+    with pytest.raises(PmgError):
+        G.set_post_direction(0)
+    x, it, rel = G.gmres(b, 1e-8, 10)
+    assert it == 0 and rel == 0.0 and not x.any()
+
+
+def test_paper_table_2d(dev):
+    path = os.path.join(os.path.dirname(__file__), "golden", "table2_gmres_jacobi_2d.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    n, dim = 32, 2
+    meshes = {d: synth.make_sphere_distorted_mesh(dim, n, d, 8000 + int(round(100 * d)))
+              for d in sorted({float(r[2]) for r in rows})}
+    out = []
+    for p_s, nmg_s, d_s, paper in rows:
+        p, n_mg, d, paper = int(p_s), int(nmg_s), float(d_s), int(paper)
+        G = _gpu_solver(dim, n, p, meshes[d], n_mg, +1, with_boundary=True)
+        mask = fem.dirichlet_mask(dim, n, p)
+        b = np.random.default_rng(p).standard_normal(mask.size) * mask
+        _, it, rel = G.gmres(torch.tensor(b, device=dev), 1e-8, 100)
+        G.close()
+        assert rel <= 1e-8
+        out.append((p, n_mg, d, it, paper))
+    print("\np N_MG delta: ours (paper)")
+    for p, n_mg, d, it, paper in out:
+        print(f"{p:2d} {n_mg:2d} {d:.2f}: {it} ({paper})")
+    ours = {(p, n_mg, d): it for p, n_mg, d, it, _ in out}
+    for p, n_mg, d, it, paper in out:
+        if p == 3 and n_mg < 25:
+            assert abs(it - paper) <= 1, (p, n_mg, d, it, paper)
+        if n_mg == 25:
+            assert abs(it - paper) <= 2, (p, n_mg, d, it, paper)
+    deltas = sorted(meshes)
+    for p in (3, 7, 15):
+        for d in deltas:
+            assert ours[(p, 25, d)] <= ours[(p, 2, d)] <= ours[(p, 1, d)], (p, d)
+        for n_mg in (1, 2, 25):
+            seq = [ours[(p, n_mg, d)] for d in deltas]
+            assert all(b >= a - 1 for a, b in zip(seq, seq[1:])), (p, n_mg, seq)
