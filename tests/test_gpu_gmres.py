@@ -98,6 +98,41 @@ def test_rejected_arguments(dev):
     assert it == 0 and rel == 0.0 and not x.any()
 
 
+def test_paper_table_3d(dev):
+    # the 3D columns (8^3 cells, p = 3 and 7): printed beside the paper's;
+    # asserted: within two iterations at p = 3, the N_MG ordering, and no
+    # fall with distortion by more than one
+    path = os.path.join(os.path.dirname(__file__), "golden", "table2_gmres_jacobi_3d.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    n, dim = 8, 3
+    meshes = {d: synth.make_sphere_distorted_mesh(dim, n, d, 8100 + int(round(100 * d)))
+              for d in sorted({float(r[2]) for r in rows})}
+    out = []
+    for p_s, nmg_s, d_s, paper in rows:
+        p, n_mg, d, paper = int(p_s), int(nmg_s), float(d_s), int(paper)
+        G = _gpu_solver(dim, n, p, meshes[d], n_mg, +1, with_boundary=True)
+        mask = fem.dirichlet_mask(dim, n, p)
+        b = np.random.default_rng(p).standard_normal(mask.size) * mask
+        _, it, rel = G.gmres(torch.tensor(b, device=dev), 1e-8, 100)
+        G.close()
+        assert rel <= 1e-8
+        out.append((p, n_mg, d, it, paper))
+    print("\n3D p N_MG delta: ours (paper)")
+    for p, n_mg, d, it, paper in out:
+        print(f"{p:2d} {n_mg:2d} {d:.2f}: {it} ({paper})")
+    ours = {(p, n_mg, d): it for p, n_mg, d, it, _ in out}
+    for p, n_mg, d, it, paper in out:
+        if p == 3:
+            assert abs(it - paper) <= 2, (p, n_mg, d, it, paper)
+    deltas = sorted(meshes)
+    for p in (3, 7):
+        for d in deltas:
+            assert ours[(p, 25, d)] <= ours[(p, 2, d)] <= ours[(p, 1, d)], (p, d)
+        for n_mg in (1, 2, 25):
+            seq = [ours[(p, n_mg, d)] for d in deltas]
+            assert all(b >= a - 1 for a, b in zip(seq, seq[1:])), (p, n_mg, seq)
+
+
 def test_paper_table_2d(dev):
     path = os.path.join(os.path.dirname(__file__), "golden", "table2_gmres_jacobi_2d.txt")
     rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
