@@ -123,6 +123,18 @@ class PatchSmoother:
         mask = self.solvers[v].patch.interior_mask(self.p)
         return b[inn] - (Abar @ u[clo])[mask]
 
+    def additive_sweep(self, u, b, theta):
+        """The additive variant: every patch's correction from the same
+        iterate u, u + theta sum_j Pi_j^T d_j with d_j the local V-cycle
+        solution for the local residual of u (all patches in one phase,
+        damped by theta); returns the updated copy of u."""
+        u = np.array(u, dtype=np.float64, copy=True)
+        corr = np.zeros_like(u)
+        for v in self.order:
+            d = self.solvers[v].solve(self.local_residual(v, u, b))
+            corr[self.idx[v][1]] += d
+        return u + theta * corr
+
     def sweep(self, u, b, direction=+1, exact=False):
         """One multiplicative sweep; returns the updated copy of u."""
         u = np.array(u, dtype=np.float64, copy=True)

@@ -366,6 +366,53 @@ def test_one_patch_mesh_exact_solve():
     assert np.linalg.norm((b - A @ u)[m]) <= 1e-12 * np.linalg.norm(b)
 
 
+def _additive_case(n=3, p=2, seed=10):
+    X = synth.make_vertices(2, n, 0.2, seed)
+    mesh = fem.Mesh(2, n, X, np.ones(n * n))
+    return mesh, PatchSmoother(mesh, p, (p, 1)), fem.dirichlet_operator(mesh, p), fem.dirichlet_mask(2, n, p)
+
+
+def test_additive_sweep_ignores_patch_order():
+    # every correction comes from the same iterate: any order, even across
+    # colours, gives the same result (the multiplicative sweep does not)
+    mesh, S, A, m = _additive_case(4)
+    b = np.random.default_rng(1).standard_normal(m.size) * m
+    u0 = np.random.default_rng(2).standard_normal(m.size) * m
+    a1, s1 = S.additive_sweep(u0, b, 0.5), S.sweep(u0, b)
+    S.order = list(reversed(S.order))
+    a2, s2 = S.additive_sweep(u0, b, 0.5), S.sweep(u0, b)
+    assert np.abs(a1 - a2).max() <= 1e-13 * np.abs(a1).max()
+    assert np.abs(s1 - s2).max() > 1e-6 * np.abs(s1).max()
+
+
+def test_additive_preconditioner_is_symmetric_and_linear():
+    # u = 0: the sweep is theta B b with B = sum_j Pi_j^T M_j Pi_j, M_j the
+    # (symmetric) local V-cycle: B is symmetric and linear in b
+    mesh, S, A, m = _additive_case(3)
+    idx = np.flatnonzero(m)
+    cols = []
+    for j in idx:
+        e = np.zeros(m.size); e[j] = 1.0
+        cols.append(S.additive_sweep(np.zeros(m.size), e, 0.7)[idx])
+    B = np.array(cols).T / 0.7
+    assert np.abs(B - B.T).max() <= 1e-11 * np.abs(B).max()
+    r = np.random.default_rng(3).standard_normal(m.size) * m
+    assert np.allclose(S.additive_sweep(np.zeros(m.size), r, 0.7)[idx], 0.7 * B @ r[idx], atol=1e-12)
+    # the exact solution is a fixed point
+    xs = np.zeros(m.size)
+    xs[idx] = np.linalg.solve(A.toarray()[np.ix_(idx, idx)], r[idx])
+    assert np.abs(S.additive_sweep(xs, r, 0.7) - xs).max() <= 1e-11 * np.abs(xs).max()
+
+
+def test_additive_equals_multiplicative_on_one_patch():
+    mesh, S, A, m = _additive_case(2, p=3)
+    b = np.random.default_rng(4).standard_normal(m.size) * m
+    u0 = np.random.default_rng(5).standard_normal(m.size) * m
+    assert np.allclose(S.additive_sweep(u0, b, 1.0), S.sweep(u0, b), atol=1e-13)
+    # the damping scales the correction
+    assert np.allclose(S.additive_sweep(u0, b, 0.4) - u0, 0.4 * (S.sweep(u0, b) - u0), atol=1e-13)
+
+
 # ---------------------------------------------------------------------------
 # global multigrid and CG
 # ---------------------------------------------------------------------------
