@@ -190,6 +190,18 @@ int pmg_patch_local_solve(pmg_handle* h, const double* r, double* d);
 int pmg_patch_pcg(pmg_handle* h, const double* b, double* x, double rtol, int32_t maxit,
                   int32_t* iters, double* relres);
 
+/* The additive variant of the patch smoother: every local residual from the
+ * same u (equation main:4), every local solve (equation main:5), then
+ * u += theta sum_j Pi_j^T d_j (equation scatter with damping theta), the
+ * corrections added colour by colour so that the sums are deterministic.
+ * u, b: device global vectors as for pmg_patch_smooth.  Work buffers of
+ * 2 x n_patches x (2p-1)^dim FP64 are allocated at the first call and kept
+ * until pmg_patch_destroy.  Mesh handles of interior-vertex patches only
+ * (PMG_ERR_UNSUPPORTED for independent patches or PMG_PATCH_WITH_BOUNDARY);
+ * PMG_ERR_INVALID_ARG: null pointer, theta not finite and > 0, bounds not
+ * set.  Asynchronous on the handle's stream. */
+int pmg_patch_smooth_additive(pmg_handle* h, double* u, const double* b, double theta);
+
 /* Local smoothers of the V-cycle (Section 3.1, smoothers). */
 #define PMG_SMOOTHER_CHEBYSHEV 0  /* Chebyshev-accelerated Jacobi (the default) */
 #define PMG_SMOOTHER_CARTESIAN 1  /* Cartesian-reinforced */

@@ -130,6 +130,10 @@ class PatchSmoother:
     def smooth(self, u: torch.Tensor, b: torch.Tensor, direction: int = 1):
         L.check(self._lib.pmg_patch_smooth(self._h, _dptr(u), _dptr(b), int(direction)))
 
+    def smooth_additive(self, u: torch.Tensor, b: torch.Tensor, theta: float):
+        """pmg_patch_smooth_additive: all patches from the same u, damped by theta."""
+        L.check(self._lib.pmg_patch_smooth_additive(self._h, _dptr(u), _dptr(b), float(theta)))
+
     def smooth_colors(self, u, b, c_begin, c_end):
         L.check(self._lib.pmg_patch_smooth_colors(self._h, _dptr(u), _dptr(b), int(c_begin),
                                                   int(c_end)))

@@ -172,6 +172,7 @@ struct pmg_handle {
   int smoother = PMG_SMOOTHER_CHEBYSHEV;
   double omega = 0.5;
   double* fdm_tab = nullptr;
+  double* add_buf = nullptr;  // additive smoother: local residuals and corrections per patch
   int64_t vec_bytes = 0;  // bytes per block slot of vec_scratch
   int64_t vec_blocks = 0;
   std::vector<double> bounds;  // host copy, n_patches x (L-1) x 2
@@ -227,7 +228,7 @@ void free_handle(pmg_handle* h) {
   if (!h) return;
   void* ptrs[] = {h->verts, h->mu,          h->patch_vertex, h->patch_geo, h->patch_mu,
                   h->tab64, h->cheb,        h->vec_scratch,  h->trunc_index, h->trunc_inv,
-                  h->metric,  h->pcg_work,     h->fdm_tab};
+                  h->metric,  h->pcg_work,     h->fdm_tab,      h->add_buf};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h->tab && h->tab != h->tab64) (void)hipFree(h->tab);  // FP64 handles share the tables
@@ -1330,6 +1331,26 @@ int pmg_patch_pcg(pmg_handle* h, const double* b, double* x, double rtol, int32_
   a.grid = 0;
   a.map_mode = 0;
   return launch_chunks(h, cart ? kModePcgCart : kModePcg, a, 0, h->n_patches);
+}
+
+int pmg_patch_smooth_additive(pmg_handle* h, double* u, const double* b, double theta) {
+  if (!h || !u || !b) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  if (!(theta > 0.0) || !std::isfinite(theta)) return fail(PMG_ERR_INVALID_ARG, "theta must be finite and > 0");
+  if (h->patch_geo) return fail(PMG_ERR_UNSUPPORTED, "independent patches have no global vector to smooth");
+  if (h->with_boundary)
+    return fail(PMG_ERR_UNSUPPORTED, "the additive smoother is available for interior-vertex patches only");
+  const int64_t n0 = h->level_size(0);
+  if (!h->add_buf) PMG_TRY(dev_alloc(&h->add_buf, (size_t)2 * h->n_patches * n0 * sizeof(double), &h->device_bytes));
+  double* r = h->add_buf;
+  double* d = r + (size_t)h->n_patches * n0;
+  // every local residual from the same u, every local solve, then the damped
+  // corrections colour by colour (disjoint interiors: no atomics, one order)
+  PMG_TRY(pmg_patch_residual(h, u, b, r));
+  PMG_TRY(pmg_patch_local_solve(h, r, d));
+  for (int c = 0; c < h->n_colors; ++c)
+    HIP_TRY(launch_patch_scatter(h->dim, h->N, h->p, h->patch_vertex, h->color_off[c],
+                                 h->color_off[c + 1] - h->color_off[c], d, theta, u, h->stream));
+  return PMG_OK;
 }
 
 int pmg_set_smoother(pmg_handle* h, int32_t kind, double omega) {

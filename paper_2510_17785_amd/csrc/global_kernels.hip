@@ -488,6 +488,45 @@ hipError_t launch_h_prolong_axis(int dim, int axis, const int* sizes_in, const i
   return hipGetLastError();
 }
 
+// u[global node of interior node i of patch j] += theta d[j][i] for the
+// patches begin .. begin + count - 1 (patch order; one colour, so their
+// interiors are disjoint and every node is written by one thread): the
+// scatter of the additive smoother, interior-vertex patches of a structured
+// mesh with N cells per direction at degree p, interiors x fastest.
+template <int DIM>
+__global__ void patch_scatter_kernel(int N, int p, const int32_t* vertex, int begin, int count,
+                                     const double* d, double theta, double* u) {
+  const int mi = 2 * p - 1;
+  const int64_t n0 = DIM == 3 ? (int64_t)mi * mi * mi : (int64_t)mi * mi;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)count * n0) return;
+  const int j = begin + (int)(t / n0);
+  const int i = (int)(t % n0);
+  const int N1 = N + 1;
+  const int64_t M = (int64_t)N * p + 1;
+  const int v = vertex[j];
+  const int vx = v % N1, vy = (v / N1) % N1, vz = DIM == 3 ? v / (N1 * N1) : 0;
+  const int x = i % mi + 1, y = (i / mi) % mi + 1, z = DIM == 3 ? i / (mi * mi) + 1 : 0;
+  int64_t g = (int64_t)(vx - 1) * p + x + M * ((int64_t)(vy - 1) * p + y);
+  if (DIM == 3) g += M * M * ((int64_t)(vz - 1) * p + z);
+  u[g] += theta * d[(int64_t)j * n0 + i];
+}
+
+hipError_t launch_patch_scatter(int dim, int N, int p, const int32_t* vertex, int begin, int count,
+                                const double* d, double theta, double* u, hipStream_t s) {
+  const int mi = 2 * p - 1;
+  const int64_t total = (int64_t)count * (dim == 3 ? (int64_t)mi * mi * mi : (int64_t)mi * mi);
+  if (total <= 0) return hipSuccess;
+  (void)hipGetLastError();
+  if (dim == 3)
+    hipLaunchKernelGGL(patch_scatter_kernel<3>, dim3(grid_for(total)), dim3(256), 0, s, N, p, vertex, begin,
+                       count, d, theta, u);
+  else
+    hipLaunchKernelGGL(patch_scatter_kernel<2>, dim3(grid_for(total)), dim3(256), 0, s, N, p, vertex, begin,
+                       count, d, theta, u);
+  return hipGetLastError();
+}
+
 hipError_t launch_mask_dirichlet(int dim, int M, double* x, hipStream_t s) {
   const int64_t total = dim == 3 ? (int64_t)M * M * M : (int64_t)M * M;
   (void)hipGetLastError();

@@ -144,6 +144,8 @@ hipError_t launch_h_prolong_axis(int dim, int axis, const int* sizes_in, const i
                                  const int* first, const double* w, int p, const double* in,
                                  double* out, int transpose, hipStream_t s);
 hipError_t launch_mask_dirichlet(int dim, int M, double* x, hipStream_t s);
+hipError_t launch_patch_scatter(int dim, int N, int p, const int32_t* vertex, int begin, int count,
+                                const double* d, double theta, double* u, hipStream_t s);
 hipError_t launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);
 hipError_t launch_xpay_to(int64_t n, const double* x, double a, const double* y, double* z,
                           hipStream_t s);
