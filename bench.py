@@ -640,6 +640,28 @@ def main(argv=None):
 
     if args.only:
         return 0
+    # the additive variant on the FP32 handle: residuals and local solves of
+    # all patches from one iterate in one launch each, then the damped
+    # scatter colour by colour
+    additive = None
+    if "fp32" in res:
+        S32 = res["fp32"]["S"]
+        u = torch.zeros_like(b)
+        for _ in range(args.warmup):
+            S32.smooth_additive(u, b, 0.5)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            S32.smooth_additive(u, b, 0.5)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_add = e0.elapsed_time(e1) / args.steps
+        additive = {"ms_per_step": ms_add, "value": res["fp32"]["dofs"] / (ms_add / 1e3), "unit": "DoF/s",
+                    "theta": 0.5, "note": "one additive sweep (all patches from one iterate), FP32 local "
+                                          "solver with learned bounds; convergence per sweep differs from "
+                                          "the multiplicative sweep"}
+        print(f"# fp32 additive: sweep {ms_add:.4f} ms", file=sys.stderr, flush=True)
     cg = {}
     if not args.no_cg:
         cg_variants = [("fp64_lanczos", "fp64", "lanczos"), ("fp32_learned", "fp32", "learned"),
@@ -715,6 +737,7 @@ def main(argv=None):
                   "ms_per_step": res[prec]["sweep_ms"],
                   "speedup_over_fp64": res["fp64"]["sweep_ms"] / res[prec]["sweep_ms"]}
            for prec in ("bf16", "bf16x3") if prec in res},
+        "additive_fp32": additive,
         "vcycles_per_s": r32["n_patches"] / (r32["sweep_ms"] / 1e3),
         "launch_shapes": {p: res[p]["launch"] for p in res},
         "setup_s": {f"{p}_{'lanczos' if p == 'fp64' else 'learned'}": res[p]["setup_s"] for p in res},
