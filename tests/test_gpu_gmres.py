@@ -165,3 +165,19 @@ def test_paper_table_2d(dev):
         for n_mg in (1, 2, 25):
             seq = [ours[(p, n_mg, d)] for d in deltas]
             assert all(b >= a - 1 for a, b in zip(seq, seq[1:])), (p, n_mg, seq)
+
+
+def test_gmres_fp32_local_solver_within_one_iteration(dev):
+    # FP32 local solves inside the FP64 GMRES: at most one iteration more
+    from paper_2510_17785_amd import GMGSolver
+    X = synth.make_sphere_distorted_mesh(3, 8, 0.25, 33)
+    mask = fem.dirichlet_mask(3, 8, 4)
+    b = torch.tensor(np.random.default_rng(5).standard_normal(mask.size) * mask, device=dev)
+    its = {}
+    for prec in ("fp64", "fp32"):
+        G = GMGSolver(3, 8, 4, X, np.ones(512), levels=(4, 2, 1), precision=prec)
+        G.set_post_direction(+1)
+        _, its[prec], rel = G.gmres(b, 1e-8, 100)
+        assert rel <= 1e-8
+        G.close()
+    assert its["fp32"] <= its["fp64"] + 1, its

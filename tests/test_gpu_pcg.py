@@ -138,3 +138,27 @@ def test_rejected_arguments(dev):
     Sb = PatchSmoother(w.dim, w.n, p, Xm, mum, levels=levels, precision="fp64", with_boundary=True)
     with pytest.raises(PmgError, match="boundary"):
         Sb.pcg(torch.zeros((Sb.n_patches, Sb.level_sizes[0]), dtype=torch.float64, device=dev), 1e-8, 10)
+
+
+@pytest.mark.parametrize("smoother", ["chebyshev", "cartesian"])
+def test_two_vcycles_per_preconditioning(dev, smoother):
+    # N_MG = 2: the preconditioner is two V-cycles, the second from the first's result
+    from paper_2510_17785_amd import PatchBatch
+    X, mu = synth.make_random_patches(2, 5, 0.2, None, 31)
+    lv = (7, 3, 1)
+    B = PatchBatch(2, 7, X, mu, levels=lv, precision="fp64", n_vcycles=2,
+                   cheb_degree=3 if smoother == "chebyshev" else 1,
+                   bounds="lanczos" if smoother == "chebyshev" else "fixed")
+    if smoother == "cartesian":
+        B.set_smoother("cartesian", 0.5)
+    b = np.random.default_rng(32).standard_normal((5, B.level_sizes[0]))
+    x, it, rel = B.pcg(torch.tensor(b, device=dev), 1e-8, 60)
+    solvers = []
+    for j in range(5):
+        if smoother == "cartesian":
+            s = pmg.LocalSolver(fem.PatchGeometry(X[j], mu[j]), lv, n_vcycles=2, smoother="cartesian")
+        else:
+            s = pmg.LocalSolver(fem.PatchGeometry(X[j], mu[j]), lv, n_vcycles=2)
+            s.set_bounds([lanczos.bounds(s.A[l], s.dinv[l], 12, 0, j, l) for l in range(2)])
+        solvers.append(s)
+    _compare(solvers, b, x, it, rel, 1e-8, 60)
