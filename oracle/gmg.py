@@ -17,7 +17,8 @@ V-cycle, one smoothing step each way (Section 4): on the coarsest level an
 exact solve (dense Cholesky); otherwise
     u = sweep_forward(0, f);  r = f - A u;  u += P V(R r);  u = sweep_backward(u, f).
 Pre- and post-smoothing visit the patches in opposite orders, which keeps the
-preconditioner symmetric so that CG applies.  With post_direction = +1 both
+preconditioner symmetric so that CG applies; with additive_theta set, both
+are additive sweeps with that damping (symmetric as well).  With post_direction = +1 both
 sweeps use the same colour order, as the paper does (Section 4), and the
 preconditioner is not symmetric.
 
@@ -73,9 +74,10 @@ def prolongation_h(dim: int, nc: int, p: int) -> sp.csr_matrix:
 class GMG:
     def __init__(self, mesh: Mesh, p: int, levels, cheb_degree=3, n_vcycles=1,
                  lanczos_steps=12, seed=0, bounds=None, with_boundary=False,
-                 coarse_mean="arithmetic", post_direction=-1):
+                 coarse_mean="arithmetic", post_direction=-1, additive_theta=None):
         self.dim, self.p = mesh.dim, p
         self.post_direction = post_direction
+        self.additive_theta = additive_theta
         sizes = hierarchy_sizes(mesh.n)
         meshes = [mesh]
         while meshes[-1].n != sizes[0]:
@@ -103,10 +105,11 @@ class GMG:
         if level == 0:
             return self.coarse_solve(f)
         S = self.smoothers[level]
-        u = S.sweep(np.zeros_like(f), f, +1)
+        th = self.additive_theta
+        u = S.sweep(np.zeros_like(f), f, +1) if th is None else S.additive_sweep(np.zeros_like(f), f, th)
         r = f - self.A[level] @ u
         u = u + self.P[level - 1] @ self.vcycle(level - 1, self.P[level - 1].T @ r)
-        u = S.sweep(u, f, self.post_direction)
+        u = S.sweep(u, f, self.post_direction) if th is None else S.additive_sweep(u, f, th)
         return u
 
     def precondition(self, r):

@@ -691,3 +691,23 @@ def test_paper_order_vcycle_is_not_symmetric_and_gmres_converges():
     assert rel <= 1e-10 and k <= 50
     xs = sla.solve(G.A[-1].toarray()[np.ix_(mask, mask)], b[mask])
     assert np.abs(x[mask] - xs).max() <= 1e-8 * np.abs(xs).max()
+
+
+def test_gmg_with_additive_smoothing_is_symmetric_and_solves():
+    X = synth.make_vertices(2, 4, 0.2, 6)
+    mesh = fem.Mesh(2, 4, X, np.ones(16))
+    G = gmg.GMG(mesh, 3, (3, 1), additive_theta=0.25)
+    n = G.A[-1].shape[0]
+    mask = fem.dirichlet_mask(2, 4, 3)
+    idx = np.flatnonzero(mask)[:15]
+    cols = []
+    for j in idx:
+        e = np.zeros(n); e[j] = 1.0
+        cols.append(G.precondition(e)[idx])
+    B = np.array(cols).T
+    assert np.abs(B - B.T).max() <= 1e-10 * np.abs(B).max()
+    b = np.random.default_rng(7).standard_normal(n) * mask
+    x, k, hist = G.cg(b, 1e-10, 200)
+    assert k <= 200 and hist[-1] <= 1e-10
+    xs = sla.solve(G.A[-1].toarray()[np.ix_(mask, mask)], b[mask])
+    assert np.abs(x[mask] - xs).max() <= 1e-8 * np.abs(xs).max()
