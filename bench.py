@@ -670,6 +670,8 @@ def main(argv=None):
             cg_variants += [("bf16_learned", "bf16", "learned"), ("bf16x3_learned", "bf16x3", "learned")]
         # one interval for every patch and level: the envelope of the Lanczos bounds
         cg_variants += [("fp32_fixed", "fp32", "fixed")]
+        # additive sweeps (damping 2^-d) as both smoothing steps
+        cg_variants += [("fp32_learned_additive", "fp32", "learned")]
         for key, prec, bsrc in cg_variants:
             t0 = time.perf_counter()
             G = GMGSolver(w.dim, w.n, w.p, X, mu, levels=w.levels, precision=prec,
@@ -684,6 +686,8 @@ def main(argv=None):
                     lam = S_l.bounds()
                     env = np.array([lam[..., 0].min(), lam[..., 1].max()])
                     S_l.set_bounds(np.broadcast_to(env, lam.shape).copy())
+            if key.endswith("_additive"):
+                G.set_additive(0.5 ** w.dim)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             x, it, rel = G.cg(b, rtol=w.rtol)

@@ -342,6 +342,13 @@ int gmg_cg_solve(gmg_handle* g, double* x, const double* b, double rtol, int32_t
  * PMG_ERR_INVALID_ARG for other values. */
 int gmg_set_post_direction(gmg_handle* g, int32_t direction);
 
+/* theta > 0: both smoothing steps of the V-cycle are additive sweeps
+ * (pmg_patch_smooth_additive) with damping theta, which keeps the
+ * preconditioner symmetric; theta = 0 (the default): multiplicative sweeps.
+ * Interior-vertex patch sets only (the sweeps return PMG_ERR_UNSUPPORTED
+ * otherwise).  PMG_ERR_INVALID_ARG: theta negative or not finite. */
+int gmg_set_additive(gmg_handle* g, double theta);
+
 /* GMRES from x = 0 with one V-cycle as right preconditioner (the outer
  * solver of Section 4; flexible form, no restart: 2 maxit + 1 device vectors
  * of the fine size, allocated at the first call that needs them and kept

@@ -53,6 +53,7 @@ EXPORTS = [
     "pmg_default_opts", "pmg_patch_setup", "pmg_patch_smooth", "pmg_patch_smooth_colors",
     "pmg_patch_residual", "pmg_patch_apply", "pmg_patch_local_solve", "pmg_patch_pcg",
     "pmg_set_smoother", "gmg_set_post_direction", "gmg_gmres_solve", "pmg_patch_smooth_additive",
+    "gmg_set_additive",
     "pmg_get_inv_diag",
     "pmg_get_bounds", "pmg_set_bounds", "pmg_get_patch_vertices", "pmg_query",
     "pmg_patch_destroy", "gmg_setup", "gmg_apply", "gmg_vcycle", "gmg_cg_solve", "gmg_query",
@@ -116,6 +117,7 @@ def load() -> ctypes.CDLL:
         "pmg_set_smoother": [P, i32, ctypes.c_double],
         "pmg_patch_smooth_additive": [P, P, P, ctypes.c_double],
         "gmg_set_post_direction": [P, i32],
+        "gmg_set_additive": [P, ctypes.c_double],
         "gmg_gmres_solve": [P, P, P, ctypes.c_double, i32, ctypes.POINTER(i32),
                             ctypes.POINTER(ctypes.c_double)],
         "pmg_get_inv_diag": [P, i32, P],

@@ -428,6 +428,10 @@ class GMGSolver:
                                           ctypes.byref(it), ctypes.byref(rel)))
         return x, it.value, rel.value
 
+    def set_additive(self, theta: float):
+        """gmg_set_additive: additive smoothing with damping theta (0: multiplicative)."""
+        L.check(self._lib.gmg_set_additive(self._h, float(theta)))
+
     def set_post_direction(self, direction: int):
         """gmg_set_post_direction: -1 (reversed, symmetric) or +1 (the
         paper's same order)."""

@@ -912,6 +912,7 @@ struct gmg_handle {
   double* scal = nullptr;  // device scalars
   double* hscal = nullptr; // pinned host scalars
   int post_dir = -1;       // colour order of the post-smoothing sweep (-1: reversed)
+  double add_theta = 0.0;  // > 0: additive sweeps with this damping instead of multiplicative ones
   std::vector<double*> kv; // GMRES: Krylov basis and preconditioned vectors (grown on demand)
   int64_t len(int l) const {
     int64_t M = (int64_t)sizes[l] * p + 1;
@@ -991,7 +992,10 @@ int vcycle(gmg_handle* g, int l, const double* f, double* u) {
   }
   pmg_handle* S = g->smoother[l];
   HIP_TRY(hipMemsetAsync(u, 0, g->len(l) * sizeof(double), g->stream));
-  PMG_TRY(pmg_patch_smooth(S, u, f, +1));
+  if (g->add_theta > 0.0)
+    PMG_TRY(pmg_patch_smooth_additive(S, u, f, g->add_theta));
+  else
+    PMG_TRY(pmg_patch_smooth(S, u, f, +1));
   // residual r = f - A u, restricted to level l-1
   double* t = g->t[l];
   PMG_TRY(global_apply(g, l, u, t));
@@ -1000,7 +1004,10 @@ int vcycle(gmg_handle* g, int l, const double* f, double* u) {
   PMG_TRY(vcycle(g, l - 1, g->f[l - 1], g->u[l - 1]));
   PMG_TRY(h_transfer(g, l - 1, g->u[l - 1], t, false));
   HIP_TRY(launch_axpby(g->len(l), 1.0, t, 1.0, u, g->stream));
-  PMG_TRY(pmg_patch_smooth(S, u, f, g->post_dir));
+  if (g->add_theta > 0.0)
+    PMG_TRY(pmg_patch_smooth_additive(S, u, f, g->add_theta));
+  else
+    PMG_TRY(pmg_patch_smooth(S, u, f, g->post_dir));
   return PMG_OK;
 }
 
@@ -1540,6 +1547,13 @@ int gmg_set_post_direction(gmg_handle* g, int32_t direction) {
   if (!g) return fail(PMG_ERR_INVALID_ARG, "null argument");
   if (direction != 1 && direction != -1) return fail(PMG_ERR_INVALID_ARG, "direction must be +1 or -1");
   g->post_dir = direction;
+  return PMG_OK;
+}
+
+int gmg_set_additive(gmg_handle* g, double theta) {
+  if (!g) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  if (!(theta >= 0.0) || !std::isfinite(theta)) return fail(PMG_ERR_INVALID_ARG, "theta must be finite and >= 0");
+  g->add_theta = theta;
   return PMG_OK;
 }
 

@@ -52,3 +52,22 @@ def test_additive_rejects(dev):
     Sb = PatchSmoother(w.dim, 4, p, X, mu, levels=levels, with_boundary=True)
     with pytest.raises(PmgError, match="interior"):
         Sb.smooth_additive(u, bt, 0.5)
+
+
+@pytest.mark.parametrize("dim,n,p,levels,theta", [(2, 8, 3, (3, 1), 0.25), (3, 4, 2, (2, 1), 0.125)])
+def test_gmg_cg_with_additive_smoothing(dev, dim, n, p, levels, theta):
+    # additive sweeps (damping theta) as both smoothing steps of the V-cycle:
+    # the oracle's CG iteration count and solution
+    import synth
+    from oracle import gmg
+    from paper_2510_17785_amd import GMGSolver
+    X = synth.make_vertices(dim, n, 0.2, 3)
+    mask = fem.dirichlet_mask(dim, n, p)
+    b = np.random.default_rng(1).standard_normal(mask.size) * mask
+    G = GMGSolver(dim, n, p, X, np.ones(n ** dim), levels=levels, precision="fp64")
+    G.set_additive(theta)
+    x, it, rel = G.cg(torch.tensor(b, device=dev), 1e-8, 200)
+    O = gmg.GMG(fem.Mesh(dim, n, X, np.ones(n ** dim)), p, levels, additive_theta=theta)
+    xo, ko, _ = O.cg(b, 1e-8, 200)
+    assert it == ko and rel <= 1e-8, (it, ko)
+    assert np.abs(x.cpu().numpy() - xo).max() <= 1e-9 * np.abs(xo).max()
