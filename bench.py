@@ -83,12 +83,12 @@ def algorithmic_per_patch(dim, levels, k, tsize):
     return F, B
 
 
-def measured_traffic(workload):
-    """HBM bytes per launch of the FP32 patch kernel from the committed
-    rocprofv3 counter summary, or None when the kernel source has changed
-    since the counters were taken."""
+def measured_traffic(workload, kernel="patch_kernel_fp32"):
+    """HBM bytes per launch of the patch kernel from the committed rocprofv3
+    counter summary profiles/<kernel>_<workload>.md, or None when the kernel
+    source has changed since the counters were taken."""
     import hashlib
-    prof = os.path.join(ROOT, "profiles", f"patch_kernel_fp32_{workload}.md")
+    prof = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md")
     src = os.path.join(ROOT, "paper_2510_17785_amd", "csrc", "patch_kernels.hip")
     if not os.path.exists(prof):
         return None
@@ -377,7 +377,7 @@ def bench_pcg(args):
             "peak": VALU_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / VALU_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(PCG_WORKLOAD, "patch_kernel_fp64"),
             "kernel": f"patch_kernel<double,3,Levels<{','.join(map(str, PCG_LEVELS))}>,pcg>",
             "algorithmic_flops_per_iteration": F_iter,
             "v_cycles_per_launch": vcycles,
