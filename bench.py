@@ -108,23 +108,25 @@ def has_bf16(w):
 
 
 def time_sweeps(S, u, b, steps, warmup, torch):
-    """Per-colour launch times (ms) over `steps` forward sweeps, recorded with
-    events on the stream the kernels run on."""
+    """`steps` forward sweeps timed with two events on the stream the kernels
+    run on, around all of them (an event between the colour launches would
+    add a gap of its own to every launch).  Per launch: the sweep time over
+    the colour count, which includes the short gaps between the dependent
+    launches (so it bounds the kernel's own duration from above)."""
     for _ in range(warmup):
         S.smooth(u, b, +1)
     torch.cuda.synchronize()
-    nc = S.n_colors
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(nc + 1)] for _ in range(steps)]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    for s in range(steps):
-        ev[s][0].record()
-        for c in range(nc):
-            S.smooth_colors(u, b, c, c + 1)
-            ev[s][c + 1].record()
+    e0.record()
+    for _ in range(steps):
+        S.smooth(u, b, +1)
+    e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    per_launch = [ev[s][c].elapsed_time(ev[s][c + 1]) for s in range(steps) for c in range(nc)]
-    sweep_ms = sum(ev[s][0].elapsed_time(ev[s][nc]) for s in range(steps)) / steps
+    sweep_ms = e0.elapsed_time(e1) / steps
+    nc = S.n_colors
+    per_launch = [sweep_ms / nc] * (steps * nc)
     return sweep_ms, per_launch, wall
 
 
