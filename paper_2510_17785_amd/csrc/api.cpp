@@ -2030,6 +2030,8 @@ struct pmg_batch {
 namespace {
 
 void drop_graphs(pmg_batch* b) {
+  // a replay of these graphs may still run on the stream: wait before destroying
+  if (b->exec[0] || b->exec[1]) (void)hipStreamSynchronize(b->stream);
   for (int d = 0; d < 2; ++d) {
     if (b->exec[d]) (void)hipGraphExecDestroy(b->exec[d]);
     if (b->graph[d]) (void)hipGraphDestroy(b->graph[d]);
@@ -2156,8 +2158,12 @@ int pmg_batch_smooth(pmg_batch* b, double* const* u, const double* const* rhs, i
   }
   hipError_t e;
   if (!b->exec[d] || b->bound[d] != ptrs) {
-    // (re)capture: the graph is bound to these vector addresses
-    if (b->exec[d]) (void)hipGraphExecDestroy(b->exec[d]);
+    // (re)capture: the graph is bound to these vector addresses; its last
+    // replay may still run on the stream, so wait before destroying it
+    if (b->exec[d]) {
+      if ((e = hipStreamSynchronize(b->stream))) return fail(PMG_ERR_HIP, "batch recapture: %s", hipGetErrorString(e));
+      (void)hipGraphExecDestroy(b->exec[d]);
+    }
     if (b->graph[d]) (void)hipGraphDestroy(b->graph[d]);
     b->exec[d] = nullptr;
     b->graph[d] = nullptr;

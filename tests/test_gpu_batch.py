@@ -99,6 +99,51 @@ def test_batch_graph_and_autotune_bitwise(dev):
     B.close()
 
 
+def test_batch_graph_replays_and_recapture_bitwise(dev):
+    # the sweeps of the test above without the launch-shape tuner: direct
+    # batch = each instance alone, graph replays (with host work and
+    # synchronisation between) = direct, new vector addresses captured again
+    # (the previous graph is destroyed only after its replay has finished)
+    from paper_2510_17785_amd import SmootherBatch
+    n = 6
+    X, mu, b, u0 = _inputs(n)
+    B = SmootherBatch(3, [n] * 4, PS, X, mu, precision="fp32")
+    bd = [torch.tensor(x, device=dev) for x in b]
+    ref = []
+    for k, S in enumerate(B.instances):
+        u = torch.tensor(u0[k], device=dev)
+        S.smooth(u, bd[k], +1)
+        S.smooth(u, bd[k], -1)
+        ref.append(u.clone())
+    us = [torch.tensor(x, device=dev) for x in u0]
+    B.smooth(us, bd, +1, graph=False)
+    B.smooth(us, bd, -1, graph=False)
+    for k in range(4):
+        assert torch.equal(us[k], ref[k]), PS[k]
+    for rep in range(3):
+        for k in range(4):
+            us[k].copy_(torch.tensor(u0[k], device=dev))
+        torch.cuda.synchronize()
+        B.smooth(us, bd, +1)
+        B.smooth(us, bd, -1)
+        torch.cuda.synchronize()
+        for k in range(4):
+            assert torch.equal(us[k], ref[k]), (rep, PS[k])
+    assert B.captures == 2 and B.replays == 4
+    # other addresses, queued right behind a replay: captured again
+    vs = [torch.tensor(x, device=dev) for x in u0]
+    for k in range(4):
+        us[k].copy_(vs[k])
+    B.smooth(us, bd, +1)
+    B.smooth(vs, bd, +1)
+    B.smooth(vs, bd, -1)
+    torch.cuda.synchronize()
+    assert B.captures == 4
+    for k in range(4):
+        assert torch.equal(vs[k], ref[k]), PS[k]
+    B.close()
+
+
 @pytest.mark.parametrize("k", range(4))
 def test_batch_instance_outer_cg(dev, k):
     from paper_2510_17785_amd import GMGSolver
