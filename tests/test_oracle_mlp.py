@@ -107,3 +107,41 @@ def test_training_reduces_loss_on_lanczos_labels():
     batches = [rng.permutation(48)[:16] for _ in range(300)]
     theta = mlp.train(theta, Xs, T, batches, lr=3e-3)
     assert mlp.loss(theta, Xs, T) < 0.2 * l0
+
+
+def _tanh(x):
+    # tanh from its definition through the exponential, independent of numpy's tanh
+    import math
+    e = math.exp(2.0 * x)
+    return (e - 1.0) / (e + 1.0)
+
+
+def test_forward_hand_computed_network():
+    # A 2-input, 2-output network whose weights route one chain through every
+    # layer: unit 0 of each hidden layer carries tanh(x0 - 0.5 x1 + 0.1), then
+    # tanh(0.8 h + 0.2), then tanh(-1.5 h), and the linear output layer reads
+    # y0 = 2 h3 + 0.5 and y1 = -h3 + (unit 1 of layer 3 = tanh(0) = 0) - 1.
+    # A dropped hidden layer, tanh on the output, a transposed weight matrix
+    # or a bias in the wrong place each change the printed values.
+    n_in, n_out = 2, 2
+    theta = np.zeros(mlp.n_params(n_in, n_out))
+    W1, b1, W2, b2, W3, b3, W4, b4 = mlp.unpack(theta, n_in, n_out)  # views into theta
+    W1[0, 0], W1[1, 0], b1[0] = 1.0, -0.5, 0.1
+    W2[0, 0], b2[0] = 0.8, 0.2
+    W3[0, 0] = -1.5
+    W4[0, 0], W4[0, 1], W4[1, 1] = 2.0, -1.0, 3.0
+    b4[0], b4[1] = 0.5, -1.0
+    X = np.array([[0.3, -0.4], [-1.2, 0.6], [0.0, 0.0]])
+    Y, (_, h1, h2, h3) = mlp.forward(theta, X, n_out)
+    for row, (x0, x1) in enumerate(X):
+        t1 = _tanh(x0 - 0.5 * x1 + 0.1)
+        t2 = _tanh(0.8 * t1 + 0.2)
+        t3 = _tanh(-1.5 * t2)
+        assert Y[row, 0] == pytest.approx(2.0 * t3 + 0.5, abs=1e-14)
+        assert Y[row, 1] == pytest.approx(-t3 + 3.0 * _tanh(0.0) - 1.0, abs=1e-14)
+        assert h1[row, 0] == pytest.approx(t1, abs=1e-15)
+        # every other hidden unit has zero weights and bias: tanh(0) = 0
+        assert np.all(h1[row, 1:] == 0) and np.all(h2[row, 1:] == 0) and np.all(h3[row, 1:] == 0)
+    # the first row, by hand: t1 = tanh(0.6), t2 = tanh(0.8 t1 + 0.2), t3 = tanh(-1.5 t2)
+    assert Y[0, 0] == pytest.approx(-0.8681209, abs=5e-7)
+    assert Y[0, 1] == pytest.approx(-0.3159396, abs=5e-7)

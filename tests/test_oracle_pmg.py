@@ -124,6 +124,67 @@ def test_chebyshev_error_polynomial():
         assert np.allclose(ck, tau * c0, atol=1e-9 * np.abs(c0).max())
 
 
+def _eigen_contraction(A, dinv, a, b, k):
+    """|tau_k(lambda)| of every eigenvector of D^{-1} A, measured by running
+    the smoother on the error e_0 = v (f = 0)."""
+    lam, V = sla.eigh(A, np.diag(1.0 / dinv))
+    out = []
+    for i in range(len(lam)):
+        xk = pmg.chebyshev(A, dinv, np.zeros(len(lam)), V[:, i], a, b, k)
+        out.append(np.linalg.norm(xk) / np.linalg.norm(V[:, i]))
+    return lam, np.array(out)
+
+
+def test_chebyshev_interval_targets_the_upper_spectrum():
+    # Reading R5: the interval [max(lam_min, b/rho), b], b = s lam_max, makes
+    # the degree-k smoother damp every eigenvector of D^{-1} A whose eigenvalue
+    # lies in [b/rho, lam_max] by at least the Chebyshev minimax factor
+    # 1/T_k((rho+1)/(rho-1)) (1/T_3(8/7) = 0.39334 for rho = 15) and amplify
+    # none.  A patch whose D^{-1} A has eigenvalues far below b/rho exercises
+    # the clamp: with a = lam_min instead, the polynomial equioscillates over
+    # the whole spectrum and leaves part of the upper range almost undamped.
+    A = fem.patch_matrix(_patch(2, seed=11), 4)
+    dinv = 1.0 / np.diag(A)
+    lam = sla.eigh(A, np.diag(np.diag(A)), eigvals_only=True)
+    a, b = pmg.chebyshev_interval(lam[0], lam[-1])
+    assert lam[0] < b / 15 / 2                     # the clamp is active here
+    k = 3
+    lam_v, tau = _eigen_contraction(A, dinv, a, b, k)
+    T3 = lambda x: 4 * x ** 3 - 3 * x
+    bound = 1.0 / T3(16.0 / 14.0)
+    assert bound == pytest.approx(0.39334, abs=1e-5)
+    upper = lam_v >= b / 15
+    assert upper.sum() >= 10
+    assert tau[upper].max() <= bound * (1 + 1e-9)
+    assert tau.max() <= 1.0 + 1e-12
+    # the factor is reached on the upper range (equioscillation), so the
+    # interval is no wider than it needs to be
+    assert tau[upper].max() >= 0.8 * bound
+
+
+def test_chebyshev_interval_uses_lambda_min_when_it_is_large():
+    # When the spectrum of D^{-1} A already lies inside [b/rho, b], the interval
+    # starts at lam_min, and every eigenvector is damped by the minimax factor
+    # of the tight interval, 1/T_k(theta/delta) with theta/delta =
+    # (s lam_max + lam_min)/(s lam_max - lam_min): 1/T_3(8/3) = 0.014738 for
+    # the spectrum [1, 2], far below the clamped interval's 0.393.
+    rng = np.random.default_rng(5)
+    n = 30
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.concatenate([[1.0, 2.0], rng.uniform(1.0, 2.0, n - 2)])
+    d = rng.uniform(0.5, 4.0, n)                    # D = diag(A)
+    M = Q @ np.diag(lam) @ Q.T                      # D^{-1/2} A D^{-1/2}
+    A = np.sqrt(d)[:, None] * M * np.sqrt(d)[None, :]
+    dinv = 1.0 / d                                  # scaling only: D^{-1} A ~ M
+    a, b = pmg.chebyshev_interval(1.0, 2.0)
+    assert a == pytest.approx(1.0)
+    _, tau = _eigen_contraction(A, dinv, a, b, 3)
+    T3 = lambda x: 4 * x ** 3 - 3 * x
+    bound = 1.0 / T3((2.2 + 1.0) / (2.2 - 1.0))
+    assert bound == pytest.approx(0.014738, abs=1e-6)
+    assert tau.max() <= bound * (1 + 1e-9)
+
+
 def test_chebyshev_degree_one_is_damped_jacobi():
     # k = 1 on an interval with a + b = 4 is the paper's Jacobi step with
     # omega = 1/2 (Section 3.1, smoothers; Section 3.2)
