@@ -288,8 +288,9 @@ int pmg_batch_setup(const pmg_mesh* meshes, const double* const* coeffs, const i
 int pmg_batch_instance(pmg_batch* b, int32_t i, pmg_handle** h);
 /* One sweep of every instance (direction +1 or -1); u[i], rhs[i]: device
  * vectors of instance i.  The first call per direction captures the sweep
- * into a HIP graph bound to these addresses; later calls with the same
- * addresses replay it, other addresses capture again (counted by
+ * into a HIP graph bound to these addresses and to every instance's launch
+ * shape (pmg_set_launch, pmg_autotune); later calls with the same addresses
+ * and shapes replay it, other addresses or shapes capture again (counted by
  * pmg_batch_query).  Asynchronous on opts->stream. */
 int pmg_batch_smooth(pmg_batch* b, double* const* u, const double* const* rhs, int32_t direction);
 /* The same sweep enqueued directly, without a graph. */
@@ -298,10 +299,10 @@ int pmg_batch_smooth_eager(pmg_batch* b, double* const* u, const double* const* 
 /* Launch shapes for every instance, chosen with the instances running
  * together: whole-batch graph sweeps (captured per candidate) on copies of u
  * (left unchanged), one instance's shape at a time, highest degree first,
- * over the candidates of pmg_autotune.  Drops captured graphs.
- * Currently switched off: returns PMG_ERR_UNSUPPORTED without device work (a
- * host crash inside its graph-replay timing is unexplained); set shapes per
- * instance with pmg_set_launch on pmg_batch_instance handles. */
+ * over the candidates of pmg_autotune.  Drops captured graphs.  u, rhs as
+ * for pmg_batch_smooth; the copies of u are device memory the call allocates
+ * and frees.  Synchronises opts->stream.  PMG_ERR_INVALID_ARG: null vector or
+ * bounds not set. */
 int pmg_batch_autotune(pmg_batch* b, double* const* u, const double* const* rhs);
 #define PMG_BQ_N_INSTANCES 0
 #define PMG_BQ_CAPTURES 1
@@ -323,13 +324,18 @@ int gmg_setup(const pmg_mesh* mesh, const double* coeff, int32_t p, const pmg_op
 int gmg_apply(gmg_handle* g, const double* x, double* y);
 
 /* z = V-cycle(r) (Section 2 and Section 4: forward sweep, residual,
- * restriction, recursion, prolongation, backward sweep).  Device FP64. */
+ * restriction, recursion, prolongation, post-sweep).  The post-sweep runs the
+ * colours in reverse (default, a symmetric V-cycle) or in the pre-sweep's
+ * order after gmg_set_post_direction(+1) (the paper's order, non-symmetric);
+ * with gmg_set_additive both sweeps are additive.  Device FP64. */
 int gmg_vcycle(gmg_handle* g, const double* r, double* z);
 
 /* Preconditioned CG from x = 0 until ||r|| <= rtol ||b|| or maxit iterations.
  * x, b: device FP64.  iters, relres: host (may be NULL).  Synchronous.
  * Returns PMG_WARN_NOT_CONVERGED when maxit is hit, PMG_ERR_BREAKDOWN on
- * breakdown. */
+ * breakdown, PMG_ERR_UNSUPPORTED when the V-cycle is not symmetric
+ * (multiplicative sweeps with gmg_set_post_direction(+1): use
+ * gmg_gmres_solve). */
 int gmg_cg_solve(gmg_handle* g, double* x, const double* b, double rtol, int32_t maxit,
                  int32_t* iters, double* relres);
 
@@ -416,6 +422,29 @@ int pmg_mlp_load(const char* path, int64_t max_batch, void* stream, pmg_mlp** ou
  * number.  The network must have 3 4^d + 2^d inputs and 2 (n_levels - 1)
  * outputs.  Synchronous. */
 int pmg_set_bounds_mlp(pmg_handle* h, pmg_mlp* m, double margin, double ood_z, int64_t* n_fallback);
+
+/* Train the network on the Chebyshev bounds of a handle (learned bounds, the
+ * project's extension of the smoother's interval; the labels are the Lanczos
+ * bounds the method computes for the patches of `labels`, usually a
+ * pmg_patches_setup handle of random patches).  Steps, all in the library:
+ * the features of every patch of `labels` (as pmg_patch_features) and its
+ * targets ln lambda_min, ln lambda_max per smoothed level (from its bounds, as
+ * pmg_get_bounds); the standardiser fitted on the training rows (the first
+ * epoch's row list); `epochs` epochs of pmg_mlp_train over those rows; then,
+ * over the validation rows, the root mean squared error of every output and
+ * the lambda_max margin = 3 x the largest error of an ln lambda_max output
+ * (the margin pmg_set_bounds_mlp takes).
+ * train_order: device int32, epochs x n_train patch numbers of `labels` (one
+ * permutation of the training rows per epoch); val_rows: device int32, n_val
+ * patch numbers.  epoch_loss (host, epochs), val_rmse (host, n_out floats)
+ * and margin (host) may be NULL.  Synchronous.  PMG_ERR_INVALID_ARG: null
+ * network, handle or row lists, n_train or n_val < 1, a row number outside
+ * the handle's patches (checked on the host copy), a network whose sizes do
+ * not match the handle (3 4^d + 2^d inputs, 2 (n_levels - 1) outputs), bounds
+ * not set or not positive, batch above max_batch. */
+int pmg_mlp_fit_bounds(pmg_mlp* m, const pmg_handle* labels, const int32_t* train_order, int64_t n_train,
+                       const int32_t* val_rows, int64_t n_val, int32_t epochs, int32_t batch, float lr,
+                       double* epoch_loss, float* val_rmse, double* margin);
 
 const char* pmg_last_error(void);
 

@@ -64,6 +64,7 @@ EXPORTS = [
     "pmg_mlp_destroy", "pmg_set_bounds_mlp", "pmg_set_launch", "pmg_autotune",
     "pmg_batch_setup", "pmg_batch_instance", "pmg_batch_smooth", "pmg_batch_smooth_eager",
     "pmg_batch_autotune", "pmg_batch_query", "pmg_batch_destroy", "pmg_mlp_save", "pmg_mlp_load",
+    "pmg_mlp_fit_bounds",
 ]
 
 
@@ -149,6 +150,7 @@ def load() -> ctypes.CDLL:
         "pmg_mlp_gradient": [P, P, P, ctypes.c_int64, F, ctypes.POINTER(ctypes.c_double)],
         "pmg_mlp_train": [P, P, P, ctypes.c_int64, P, i32, i32, ctypes.c_float, D],
         "pmg_mlp_destroy": [P],
+        "pmg_mlp_fit_bounds": [P, P, P, ctypes.c_int64, P, ctypes.c_int64, i32, i32, ctypes.c_float, D, F, D],
         "pmg_set_bounds_mlp": [P, P, ctypes.c_double, ctypes.c_double,
                                ctypes.POINTER(ctypes.c_int64)],
         "pmg_set_launch": [P, i32, i32],

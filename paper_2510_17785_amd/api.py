@@ -348,6 +348,28 @@ class BoundNet:
                                         hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return hist
 
+    def fit_bounds(self, labels: "PatchSmoother", train_order: torch.Tensor, val_rows: torch.Tensor,
+                   epochs: int, batch: int, lr: float = 1e-3):
+        """pmg_mlp_fit_bounds: features and ln-bound targets of the patches of
+        `labels`, standardiser, training and validation, all in the library.
+        train_order: int32 device (epochs, n_train) patch numbers; val_rows:
+        int32 device (n_val,).  Returns (epoch losses, validation RMSE per
+        output, lambda_max margin)."""
+        for t in (train_order, val_rows):
+            if t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("row lists must be contiguous int32 device tensors")
+        if train_order.dim() != 2 or train_order.shape[0] != epochs:
+            raise ValueError("train_order must have shape (epochs, n_train)")
+        hist = np.zeros(epochs)
+        rmse = np.zeros(self.n_out, dtype=np.float32)
+        margin = ctypes.c_double()
+        L.check(self._lib.pmg_mlp_fit_bounds(
+            self._h, labels._h, train_order.data_ptr(), int(train_order.shape[1]), val_rows.data_ptr(),
+            int(val_rows.shape[0]), int(epochs), int(batch), float(lr),
+            hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            rmse.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(margin)))
+        return hist, rmse, margin.value
+
     def close(self):
         if getattr(self, "_h", None) is not None:
             L.check(self._lib.pmg_mlp_destroy(self._h))

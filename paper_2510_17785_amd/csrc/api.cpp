@@ -535,6 +535,9 @@ int setup_common(pmg_handle* h) {
   hipError_t e;
   int s;
   auto cleanup = [&](int st) { return st; };
+  // launch attributes of every patch kernel of the variant, once per device,
+  // before any launch can be recorded into a graph
+  if ((e = var->prime())) return fail(PMG_ERR_HIP, "patch kernel attributes: %s", hipGetErrorString(e));
   // 1D tables: per level B, Dc, D, xg, wg; per transfer the patch prolongation
   std::vector<double> tab(kTabSize, 0.0);
   for (int l = 0; l < L; ++l) {
@@ -1483,6 +1486,9 @@ int gmg_cg_solve(gmg_handle* g, double* x, const double* b, double rtol, int32_t
                  double* relres) {
   if (!g || !x || !b) return fail(PMG_ERR_INVALID_ARG, "null argument");
   if (!(rtol > 0.0) || maxit < 1) return fail(PMG_ERR_INVALID_ARG, "need rtol > 0 and maxit >= 1");
+  if (g->post_dir == 1 && !(g->add_theta > 0.0))
+    return fail(PMG_ERR_UNSUPPORTED, "the V-cycle with the same sweep order before and after the coarse "
+                                     "correction is not symmetric: use gmg_gmres_solve");
   const int lf = g->nlev - 1;
   const int64_t n = g->len(lf);
   hipStream_t s = g->stream;
@@ -1949,6 +1955,97 @@ int pmg_set_bounds_mlp(pmg_handle* h, pmg_mlp* mm, double margin, double ood_z, 
   return PMG_OK;
 }
 
+int pmg_mlp_fit_bounds(pmg_mlp* mm, const pmg_handle* h, const int32_t* train_order, int64_t n_train,
+                       const int32_t* val_rows, int64_t n_val, int32_t epochs, int32_t batch, float lr,
+                       double* epoch_loss, float* val_rmse, double* margin) {
+  MlpNet* m = reinterpret_cast<MlpNet*>(mm);
+  if (!m || !h || !train_order || !val_rows) return fail(PMG_ERR_INVALID_ARG, "null argument");
+  if (n_train < 1 || n_val < 1 || epochs < 1) return fail(PMG_ERR_INVALID_ARG, "need n_train, n_val, epochs >= 1");
+  if (!h->bounds_valid) return fail(PMG_ERR_INVALID_ARG, "the label handle has no bounds");
+  const int nl = h->L - 1, n = h->n_patches, nf = n_features(h->dim), no = 2 * nl;
+  if (m->n_in != nf || m->n_out != no)
+    return fail(PMG_ERR_INVALID_ARG, "network has %d inputs and %d outputs, need %d and %d", m->n_in, m->n_out,
+                nf, no);
+  if (n_train > INT32_MAX || n_val > INT32_MAX) return fail(PMG_ERR_INVALID_ARG, "too many rows");
+  // row numbers are indices into the handle's patches: check the host copies
+  std::vector<int32_t> ord((size_t)epochs * n_train), vr(n_val);
+  HIP_TRY(hipMemcpy(ord.data(), train_order, ord.size() * 4, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(vr.data(), val_rows, vr.size() * 4, hipMemcpyDeviceToHost));
+  for (int32_t r : ord)
+    if (r < 0 || r >= n) return fail(PMG_ERR_INVALID_ARG, "training row %d outside 0..%d", r, n - 1);
+  for (int32_t r : vr)
+    if (r < 0 || r >= n) return fail(PMG_ERR_INVALID_ARG, "validation row %d outside 0..%d", r, n - 1);
+  // targets: ln lambda per smoothed level, from the handle's bounds
+  std::vector<float> th((size_t)n * no);
+  for (size_t i = 0; i < th.size(); ++i) {
+    const double lam = h->bounds[i];
+    if (!(lam > 0.0) || !std::isfinite(lam))
+      return fail(PMG_ERR_INVALID_ARG, "bound %zu of the label handle is %g, not positive", i, lam);
+    th[i] = (float)std::log(lam);
+  }
+  float *F = nullptr, *T = nullptr, *W = nullptr;
+  const int64_t nw = std::max<int64_t>(n_train, n_val);
+  int st;
+  if ((st = dev_alloc(&F, (size_t)n * nf * 4, nullptr)) < 0) return st;
+  if ((st = dev_alloc(&T, (size_t)n * no * 4, nullptr)) < 0 ||
+      (st = dev_alloc(&W, (size_t)nw * (nf + 2 * no) * 4, nullptr)) < 0) {
+    (void)hipFree(F);
+    if (T) (void)hipFree(T);
+    return st;
+  }
+  auto release = [&]() {
+    (void)hipStreamSynchronize(m->stream);
+    (void)hipFree(F);
+    (void)hipFree(T);
+    (void)hipFree(W);
+  };
+  PatchArgs a = h->args();
+  a.patch_begin = 0;
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess) e = launch_features(h->dim, a, n, F, m->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(T, th.data(), th.size() * 4, hipMemcpyHostToDevice, m->stream);
+  // standardiser over the training rows (the first epoch lists each once)
+  if (e == hipSuccess) e = m->gather_rows(F, train_order, (int)n_train, nf, W);
+  if (e == hipSuccess) e = m->fit_standardizer(W, n_train);
+  if (e != hipSuccess) {
+    release();
+    return fail(PMG_ERR_HIP, "bound network features: %s", hipGetErrorString(e));
+  }
+  st = pmg_mlp_train(mm, F, T, n_train, train_order, epochs, batch, lr, epoch_loss);
+  if (st < 0) {
+    release();
+    return st;
+  }
+  // validation: predictions of the validation rows against their targets
+  float* Xv = W;
+  float* Tv = W + (size_t)n_val * nf;
+  float* Yv = Tv + (size_t)n_val * no;
+  std::vector<float> yh((size_t)n_val * no), tv((size_t)n_val * no);
+  e = m->gather_rows(F, val_rows, (int)n_val, nf, Xv);
+  if (e == hipSuccess) e = m->gather_rows(T, val_rows, (int)n_val, no, Tv);
+  if (e == hipSuccess) st = pmg_mlp_predict(mm, Xv, n_val, Yv);
+  if (e == hipSuccess && st == PMG_OK)
+    e = hipMemcpyAsync(yh.data(), Yv, yh.size() * 4, hipMemcpyDeviceToHost, m->stream);
+  if (e == hipSuccess && st == PMG_OK)
+    e = hipMemcpyAsync(tv.data(), Tv, tv.size() * 4, hipMemcpyDeviceToHost, m->stream);
+  release();
+  if (st < 0) return st;
+  if (e != hipSuccess) return fail(PMG_ERR_HIP, "bound network validation: %s", hipGetErrorString(e));
+  double worst_max = 0.0;
+  for (int k = 0; k < no; ++k) {
+    double s = 0.0;
+    for (int64_t i = 0; i < n_val; ++i) {
+      const double d = (double)yh[(size_t)i * no + k] - (double)tv[(size_t)i * no + k];
+      s += d * d;
+    }
+    const double rmse = std::sqrt(s / (double)n_val);
+    if (val_rmse) val_rmse[k] = (float)rmse;
+    if (k % 2 == 1) worst_max = std::max(worst_max, rmse);  // ln lambda_max outputs
+  }
+  if (margin) *margin = 3.0 * worst_max;
+  return PMG_OK;
+}
+
 int pmg_autotune(pmg_handle* h, const double* u, const double* b, float* best_ms) {
   if (!h || !u || !b) return fail(PMG_ERR_INVALID_ARG, "null argument");
   if (h->patch_geo) return fail(PMG_ERR_UNSUPPORTED, "independent patches have no sweep to tune");
@@ -2022,7 +2119,9 @@ struct pmg_batch {
   std::vector<hipEvent_t> join;
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t exec[2] = {nullptr, nullptr};
-  std::vector<const void*> bound[2];  // (u, b) per instance of each captured graph
+  // per instance of each captured graph: u, b and the launch shape (grid,
+  // mapping), which the captured launches bake in
+  std::vector<int64_t> bound[2];
   int64_t captures = 0, replays = 0;
   int max_colors = 0;
 };
@@ -2056,10 +2155,14 @@ void free_batch(pmg_batch* b) {
 
 // enqueue one sweep of every instance: colour by colour, instances forked
 // onto their side streams and joined back before the next colour
+// (a side stream that waited on the fork is always joined back, also after a
+// failed launch: under capture, an unjoined side stream would stay part of a
+// capture that has ended)
 int enqueue_sweep(pmg_batch* b, double* const* u, const double* const* rhs, int direction,
                   hipStream_t main) {
   hipError_t e;
-  for (int k = 0; k < b->max_colors; ++k) {
+  int st = PMG_OK;
+  for (int k = 0; k < b->max_colors && st == PMG_OK; ++k) {
     if ((e = hipEventRecord(b->fork, main))) return fail(PMG_ERR_HIP, "batch fork: %s", hipGetErrorString(e));
     for (size_t i = 0; i < b->inst.size(); ++i) {
       pmg_handle* h = b->inst[i];
@@ -2067,12 +2170,12 @@ int enqueue_sweep(pmg_batch* b, double* const* u, const double* const* rhs, int 
       if (c < 0 || c >= h->n_colors) continue;
       if ((e = hipStreamWaitEvent(b->side[i], b->fork, 0)))
         return fail(PMG_ERR_HIP, "batch wait: %s", hipGetErrorString(e));
-      PMG_TRY(smooth_on(h, u[i], rhs[i], c, c + 1, 1, b->side[i]));
+      if (st == PMG_OK) st = smooth_on(h, u[i], rhs[i], c, c + 1, 1, b->side[i]);
       if ((e = hipEventRecord(b->join[i], b->side[i])) || (e = hipStreamWaitEvent(main, b->join[i], 0)))
         return fail(PMG_ERR_HIP, "batch join: %s", hipGetErrorString(e));
     }
   }
-  return PMG_OK;
+  return st;
 }
 
 }  // namespace
@@ -2149,12 +2252,14 @@ int pmg_batch_smooth(pmg_batch* b, double* const* u, const double* const* rhs, i
   if (!b || !u || !rhs) return fail(PMG_ERR_INVALID_ARG, "null argument");
   if (direction != 1 && direction != -1) return fail(PMG_ERR_INVALID_ARG, "direction must be +1 or -1");
   const int d = direction > 0 ? 0 : 1;
-  std::vector<const void*> ptrs;
+  std::vector<int64_t> ptrs;
   for (size_t i = 0; i < b->inst.size(); ++i) {
     if (!u[i] || !rhs[i] || !b->inst[i]->bounds_valid)
       return fail(PMG_ERR_INVALID_ARG, "instance %zu: null vector or bounds not set", i);
-    ptrs.push_back(u[i]);
-    ptrs.push_back(rhs[i]);
+    ptrs.push_back((int64_t)(intptr_t)u[i]);
+    ptrs.push_back((int64_t)(intptr_t)rhs[i]);
+    ptrs.push_back(b->inst[i]->tune_grid);
+    ptrs.push_back(b->inst[i]->tune_map);
   }
   hipError_t e;
   if (!b->exec[d] || b->bound[d] != ptrs) {
@@ -2172,11 +2277,16 @@ int pmg_batch_smooth(pmg_batch* b, double* const* u, const double* const* rhs, i
     const int st = enqueue_sweep(b, u, rhs, direction, b->cap);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(b->cap, &g);
-    if (st < 0) {
-      if (g) (void)hipGraphDestroy(g);
-      return st;
+    if (st < 0 || e) {
+      if (!e && g) (void)hipGraphDestroy(g);
+      return st < 0 ? st : fail(PMG_ERR_HIP, "batch capture: %s", hipGetErrorString(e));
     }
-    if (e) return fail(PMG_ERR_HIP, "batch capture: %s", hipGetErrorString(e));
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if ((e = hipStreamIsCapturing(b->cap, &cs)) || cs != hipStreamCaptureStatusNone) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(PMG_ERR_HIP, "batch capture: the capture stream is still capturing (%s)",
+                  hipGetErrorString(e));
+    }
     b->graph[d] = g;
     if ((e = hipGraphInstantiate(&b->exec[d], g, nullptr, nullptr, 0)))
       return fail(PMG_ERR_HIP, "batch graph: %s", hipGetErrorString(e));
@@ -2191,16 +2301,9 @@ int pmg_batch_smooth(pmg_batch* b, double* const* u, const double* const* rhs, i
 
 int pmg_batch_autotune(pmg_batch* b, double* const* u, const double* const* rhs) {
   if (!b || !u || !rhs) return fail(PMG_ERR_INVALID_ARG, "null argument");
-  // Switched off: a host-side crash occurred inside this tuner's timing of
-  // graph replays and its cause has not been found.  The tuner below is
-  // kept as it was; per-instance shapes can be set with pmg_set_launch.
-  return fail(PMG_ERR_UNSUPPORTED,
-              "batch autotuning is switched off (an unexplained host crash during its graph-replay "
-              "timing); set launch shapes per instance with pmg_set_launch");
-}
-
-[[maybe_unused]] static int batch_autotune_graph_replays(pmg_batch* b, double* const* u,
-                                                         const double* const* rhs) {
+  for (size_t i = 0; i < b->inst.size(); ++i)
+    if (!u[i] || !rhs[i] || !b->inst[i]->bounds_valid)
+      return fail(PMG_ERR_INVALID_ARG, "instance %zu: null vector or bounds not set", i);
   drop_graphs(b);  // launch shapes are baked into captured graphs
   int cands[kLaunchCandidates][2];
   PMG_TRY(launch_candidates(cands));

@@ -103,6 +103,9 @@ struct PatchVariant {
   int levels[kMaxLevels];
   // launch one patch kernel in `mode` over args.n_patch patches
   hipError_t (*launch)(int mode, const PatchArgs& a, hipStream_t s);
+  // set the launch attributes (dynamic LDS) of every patch kernel of this
+  // variant on the current device; called at setup, before any capture
+  hipError_t (*prime)();
   // dynamic LDS bytes of `mode`, and per-block vector-scratch elements needed
   // when vectors do not fit in LDS (0 if they do)
   size_t (*lds_bytes)(int mode);
@@ -182,6 +185,8 @@ struct MlpNet {
   hipError_t fit_standardizer(const float* X, int64_t n);
   hipError_t adam_step(float lr, float b1, float b2, float eps);
   hipError_t gather(const float* X, const float* T, const int32_t* order, int B);
+  // out (B x K) = rows idx[0..B) of X (rows of K floats)
+  hipError_t gather_rows(const float* X, const int32_t* idx, int B, int K, float* out);
   hipError_t max_abs_z(const float* X, int64_t n, float* zmax);
 };
 

@@ -292,6 +292,13 @@ hipError_t MlpNet::gather(const float* X, const float* T, const int32_t* order, 
   return hipGetLastError();
 }
 
+hipError_t MlpNet::gather_rows(const float* X, const int32_t* idx, int B, int K, float* out) {
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(gather_rows_kernel, dim3(grid_of((int64_t)B * K)), dim3(256), 0, stream, X, idx, B,
+                     K, out);
+  return hipGetLastError();
+}
+
 hipError_t MlpNet::max_abs_z(const float* X, int64_t n, float* zmax) {
   (void)hipGetLastError();
   hipLaunchKernelGGL(max_abs_z_kernel, dim3(grid_of(n)), dim3(256), 0, stream, X, n, n_in, mean,

@@ -3149,6 +3149,26 @@ struct Variant {
     hipLaunchKernelGGL((patch_kernel<T, DIM, LV, MODE, PERSIST>), dim3(g), dim3(NT<T>), lds, s, a);
     return report_launch(patch_kernel<T, DIM, LV, MODE, PERSIST>, "patch", dim3(g), lds, NT<T>);
   }
+  // Grant the LDS of every patch-kernel instantiation the handle may launch
+  // (both launch forms of the smoothing kernel), so that no first launch,
+  // which sets the kernel attribute, happens while a stream is captured.
+  template <int MODE, bool PERSIST>
+  static hipError_t prime_one() {
+    return allow_lds(patch_kernel<T, DIM, LV, MODE, PERSIST>, lds_bytes(MODE));
+  }
+  static hipError_t prime() {
+    hipError_t e = prime_one<kModeSmooth, false>();
+    if (!e) e = prime_one<kModeSmooth, true>();
+    if (!e) e = prime_one<kModeResidual, false>();
+    if (!e) e = prime_one<kModeSolve, false>();
+    if (!e) e = prime_one<kModeApply, false>();
+    if (!e) e = prime_one<kModeMetric, false>();
+    if constexpr (std::is_same<T, double>::value) {
+      if (!e) e = prime_one<kModePcg, false>();
+      if (!e) e = prime_one<kModePcgCart, false>();
+    }
+    return e;
+  }
   static hipError_t launch(int mode, const PatchArgs& a, hipStream_t s) {
     if (a.n_patch <= 0) return hipSuccess;
     const size_t lds = lds_bytes(mode);
@@ -3227,6 +3247,7 @@ PatchVariant make_variant() {
   const int q[] = {Qs...};
   for (int i = 0; i < kMaxLevels; ++i) v.levels[i] = i < LV::count ? q[i] : 0;
   v.launch = &V::launch;
+  v.prime = &V::prime;
   v.lds_bytes = &V::lds_bytes;
   v.vec_scratch_elems = &V::vec_elems;
   v.metric_elems = &V::metric_elems;
@@ -3255,6 +3276,7 @@ PatchVariant make_variant_bf16() {
   PatchVariant v = make_variant<float, DIM, Qs...>();
   v.precision = SPLIT ? PMG_BF16X3_FP32ACC : PMG_BF16_FP32ACC;
   v.launch = &V::launch;
+  v.prime = &V::prime;
   v.lds_bytes = &V::lds_bytes;
   v.vec_scratch_elems = &V::vec_elems;
   v.metric_elems = &V::metric_elems;

@@ -46,30 +46,29 @@ class TrainResult:
 
 def train_bound_network(dim, p, levels, vertices, coeff, epochs=40, batch=256, lr=1e-3,
                         val_frac=0.1, label_steps=30, seed=0) -> TrainResult:
+    """Lanczos labels of the given random patches (pmg_patches_setup), then
+    pmg_mlp_fit_bounds: features, ln-bound targets, standardiser, training,
+    validation and margin in the library.  This function draws the random
+    numbers (initial weights, the validation split, the sample order of every
+    epoch) and sequences the calls."""
     import time
     n = vertices.shape[0]
     t0 = time.perf_counter()
     lab = PatchBatch(dim, p, vertices, coeff, levels=levels, precision="fp64",
                      lanczos_steps=label_steps, seed=seed)
-    lam = lab.bounds()                                   # (n, L-1, 2)
-    F = lab.features()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    T = torch.tensor(np.log(lam).reshape(n, -1), dtype=torch.float32, device="cuda")
-    lab.close()
+    n_out = 2 * (len(levels) - 1)
     rng = np.random.default_rng(seed)
     perm = rng.permutation(n)
     n_val = max(1, int(val_frac * n))
     val, tr = perm[:n_val], perm[n_val:]
-    Ft, Tt = F[torch.tensor(tr, device="cuda")].contiguous(), T[torch.tensor(tr, device="cuda")].contiguous()
-    Fv, Tv = F[torch.tensor(val, device="cuda")].contiguous(), T[torch.tensor(val, device="cuda")].contiguous()
-    net = BoundNet(n_features(dim), T.shape[1], glorot_params(n_features(dim), T.shape[1], rng),
-                   max_batch=max(batch, 1024))
-    net.fit_standardizer(Ft)
-    order = np.stack([rng.permutation(len(tr)) for _ in range(epochs)]).astype(np.int32)
-    hist = net.train(Ft, Tt, torch.tensor(order, device="cuda"), epochs, batch, lr)
+    net = BoundNet(n_features(dim), n_out, glorot_params(n_features(dim), n_out, rng),
+                   max_batch=max(batch, 1024, n_val))
+    order = np.stack([tr[rng.permutation(len(tr))] for _ in range(epochs)]).astype(np.int32)
+    hist, rmse, margin = net.fit_bounds(lab, torch.tensor(order, device="cuda"),
+                                        torch.tensor(val.astype(np.int32), device="cuda"),
+                                        epochs, batch, lr)
+    lab.close()
     t2 = time.perf_counter()
-    pred = net.predict(Fv)
-    rmse = torch.sqrt(((pred - Tv) ** 2).mean(dim=0)).cpu().numpy()
-    margin = 3.0 * float(rmse[1::2].max())
     return TrainResult(net, hist, rmse, margin, t1 - t0, t2 - t1)

@@ -7,10 +7,14 @@ against the direct sweep, tuned against untuned launches.  Each instance's
 own smoother is pinned to the oracle elsewhere (boundary-patch and parity
 tests); here the outer FP64 GMG-CG of every degree converges and, at
 degrees 2 and 4, takes the oracle's iteration count."""
+import faulthandler
+
 import numpy as np
 import pytest
 
 torch = pytest.importorskip("torch")
+
+faulthandler.enable()  # a crash in host code prints the Python stack
 
 import synth  # noqa: E402
 from oracle import fem  # noqa: E402
@@ -37,10 +41,6 @@ def _inputs(n, seed0=0):
     return X, mu, b, u0
 
 
-@pytest.mark.skip(reason="a host crash (segmentation fault) occurred inside pmg_batch_autotune's "
-                         "graph-replay timing in this test and its cause has not been found; the "
-                         "batch tuner is switched off in the library and the test stays off the GPU "
-                         "until the cause is shown")
 def test_batch_graph_and_autotune_bitwise(dev):
     from paper_2510_17785_amd import SmootherBatch
     n = 6
@@ -95,6 +95,17 @@ def test_batch_graph_and_autotune_bitwise(dev):
         S.smooth(u, bd[1], +1)
         S.smooth(u, bd[1], -1)
         assert torch.equal(u, ref[1]), (grid, mp)
+    # a launch shape changed after capture makes the batch capture again
+    S.set_launch(64, 1)
+    c0 = B.captures
+    for k in range(4):
+        us[k].copy_(torch.tensor(u0[k], device=dev))
+    B.smooth(us, bd, +1)
+    B.smooth(us, bd, -1)
+    torch.cuda.synchronize()
+    assert B.captures == c0 + 2
+    for k in range(4):
+        assert torch.equal(us[k], ref[k]), PS[k]
     print(f"\ntuned launch shapes (grid, map) per degree {PS}: {shapes}")
     B.close()
 

@@ -1,5 +1,6 @@
-"""Parity at the full workload sizes, in the launch configuration the
-benchmark times.
+"""Parity at the full workload sizes, in the default launch shape (one
+workgroup per patch; the shapes the benchmark's autotuner picks are checked
+bit for bit against it in test_gpu_launch_shapes.py).
 
 One colour of a forward sweep runs on the whole mesh; sampled patches of
 that colour are recomputed one by one by the oracle from the same u and b

@@ -94,6 +94,9 @@ def test_rejected_arguments(dev):
             G.gmres(b, rtol, maxit)
     with pytest.raises(PmgError):
         G.set_post_direction(0)
+    # the paper's order makes the V-cycle non-symmetric: CG refuses it
+    with pytest.raises(PmgError):
+        G.cg(b, 1e-8, 10)
     x, it, rel = G.gmres(b, 1e-8, 10)
     assert it == 0 and rel == 0.0 and not x.any()
 

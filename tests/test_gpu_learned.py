@@ -137,11 +137,21 @@ def test_learned_bounds_gain(dev):
     assert res.epoch_loss[-1] < 0.1 * res.epoch_loss[0]
     assert res.val_rmse.max() < 0.1
     X, mu, b = synth.make_case(w)
-    # accuracy and setup time on the mesh, FP32 smoother
+    # accuracy and setup time on the mesh, FP32 smoother: the handle's setup
+    # with and without per-patch Lanczos (after a warm-up setup), the
+    # difference being the Lanczos bounds' cost
+    PatchSmoother(3, w.n, w.p, X, mu, levels=w.levels, precision="fp32", bounds="fixed").close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S0 = PatchSmoother(3, w.n, w.p, X, mu, levels=w.levels, precision="fp32", bounds="fixed")
+    torch.cuda.synchronize()
+    t_fixed_setup = time.perf_counter() - t0
+    S0.close()
     t0 = time.perf_counter()
     S = PatchSmoother(3, w.n, w.p, X, mu, levels=w.levels, precision="fp32")
     torch.cuda.synchronize()
     t_lanczos_setup = time.perf_counter() - t0
+    t_lanczos = t_lanczos_setup - t_fixed_setup
     lam_l = S.bounds()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -166,10 +176,13 @@ def test_learned_bounds_gain(dev):
           f"{res.label_seconds:.2f} s), val rmse {res.val_rmse}, margin {res.margin:.3f}; "
           f"mesh: median |dln lmax| {np.median(err_max):.4f}, p99 {np.quantile(err_max, 0.99):.4f}, "
           f"max {err_max.max():.4f}; lmin median {np.median(err):.4f}; "
-          f"bounds setup: Lanczos handle {t_lanczos_setup:.4f} s, network {t_mlp:.4f} s; "
-          f"CG iterations: Lanczos {it_l}, learned {it_m}, fixed {it_f}")
+          f"bounds setup: Lanczos handle {t_lanczos_setup:.4f} s (Lanczos {t_lanczos:.4f} s), "
+          f"network {t_mlp:.4f} s; CG iterations: Lanczos {it_l}, learned {it_m}, fixed {it_f}")
     assert it_m <= it_l + 1
     assert it_m <= it_f
+    # the gain: the network's bounds cost a fraction of per-patch Lanczos
+    # (12 operator applies per smoothed level and patch) at equal iterations
+    assert t_mlp < 0.5 * t_lanczos
 
 
 def test_network_save_load_round_trip(dev, tmp_path):
