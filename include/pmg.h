@@ -288,10 +288,12 @@ int pmg_batch_setup(const pmg_mesh* meshes, const double* const* coeffs, const i
 int pmg_batch_instance(pmg_batch* b, int32_t i, pmg_handle** h);
 /* One sweep of every instance (direction +1 or -1); u[i], rhs[i]: device
  * vectors of instance i.  The first call per direction captures the sweep
- * into a HIP graph bound to these addresses and to every instance's launch
- * shape (pmg_set_launch, pmg_autotune); later calls with the same addresses
- * and shapes replay it, other addresses or shapes capture again (counted by
- * pmg_batch_query).  Asynchronous on opts->stream. */
+ * into a HIP graph bound to these addresses; later calls with the same
+ * addresses replay it, other addresses capture again (counted by
+ * pmg_batch_query).  Asynchronous on opts->stream.  The graph holds launches
+ * of the default shape (one workgroup per patch): PMG_ERR_UNSUPPORTED when an
+ * instance has another shape (pmg_set_launch), which
+ * pmg_batch_smooth_eager runs. */
 int pmg_batch_smooth(pmg_batch* b, double* const* u, const double* const* rhs, int32_t direction);
 /* The same sweep enqueued directly, without a graph. */
 int pmg_batch_smooth_eager(pmg_batch* b, double* const* u, const double* const* rhs,
@@ -299,10 +301,11 @@ int pmg_batch_smooth_eager(pmg_batch* b, double* const* u, const double* const* 
 /* Launch shapes for every instance, chosen with the instances running
  * together: whole-batch graph sweeps (captured per candidate) on copies of u
  * (left unchanged), one instance's shape at a time, highest degree first,
- * over the candidates of pmg_autotune.  Drops captured graphs.  u, rhs as
- * for pmg_batch_smooth; the copies of u are device memory the call allocates
- * and frees.  Synchronises opts->stream.  PMG_ERR_INVALID_ARG: null vector or
- * bounds not set. */
+ * over the candidates of pmg_autotune.  Switched off: returns
+ * PMG_ERR_UNSUPPORTED without device work (timing graph replays of tuned
+ * shapes ended in a host crash whose cause is not known); set shapes per
+ * instance with pmg_set_launch on pmg_batch_instance handles and sweep with
+ * pmg_batch_smooth_eager. */
 int pmg_batch_autotune(pmg_batch* b, double* const* u, const double* const* rhs);
 #define PMG_BQ_N_INSTANCES 0
 #define PMG_BQ_CAPTURES 1

@@ -41,6 +41,11 @@ def _inputs(n, seed0=0):
     return X, mu, b, u0
 
 
+@pytest.mark.skip(reason="a host crash (segmentation fault) inside pmg_batch_autotune's timing of "
+                         "graph replays of tuned launch shapes occurred twice, the second time after "
+                         "the kernel attributes were set at setup and the capture error paths were "
+                         "fixed; its cause is not known, so the tuner and graphs of non-default "
+                         "shapes are switched off in the library and this test stays off the GPU")
 def test_batch_graph_and_autotune_bitwise(dev):
     from paper_2510_17785_amd import SmootherBatch
     n = 6
@@ -152,6 +157,38 @@ def test_batch_graph_replays_and_recapture_bitwise(dev):
     assert B.captures == 4
     for k in range(4):
         assert torch.equal(vs[k], ref[k]), PS[k]
+    B.close()
+
+
+def test_batch_eager_with_launch_shapes_and_graph_refusal(dev):
+    # hand-set launch shapes (persistent grids, XCD mapping) on the
+    # instances: the direct batch sweep gives the default shape's bits; the
+    # graph sweep refuses non-default shapes and the tuner is switched off,
+    # both without device work
+    from paper_2510_17785_amd import SmootherBatch
+    from paper_2510_17785_amd._lib import PmgError
+    n = 6
+    X, mu, b, u0 = _inputs(n)
+    B = SmootherBatch(3, [n] * 4, PS, X, mu, precision="fp32")
+    bd = [torch.tensor(x, device=dev) for x in b]
+    us = [torch.tensor(x, device=dev) for x in u0]
+    B.smooth(us, bd, +1, graph=False)
+    B.smooth(us, bd, -1, graph=False)
+    ref = [u.clone() for u in us]
+    for k, (grid, mp) in enumerate([(0, 1), (64, 1), (8, 0), (3, 0)]):
+        B.instances[k].set_launch(grid, mp)
+    for k in range(4):
+        us[k].copy_(torch.tensor(u0[k], device=dev))
+    B.smooth(us, bd, +1, graph=False)
+    B.smooth(us, bd, -1, graph=False)
+    torch.cuda.synchronize()
+    for k in range(4):
+        assert torch.equal(us[k], ref[k]), PS[k]
+    with pytest.raises(PmgError):
+        B.smooth(us, bd, +1, graph=True)
+    with pytest.raises(PmgError):
+        B.autotune(us, bd)
+    assert B.captures == 0
     B.close()
 
 
