@@ -190,6 +190,24 @@ int pmg_patch_local_solve(pmg_handle* h, const double* r, double* d);
 int pmg_patch_pcg(pmg_handle* h, const double* b, double* x, double rtol, int32_t maxit,
                   int32_t* iters, double* relres);
 
+/* Largest work memory of pmg_patch_pcg_noalloc: 64 MiB per GPU. */
+#define PMG_PCG_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* pmg_patch_pcg for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and results, with the per-patch residual and search
+ * direction (2 x top-level size x n_patches doubles) in a library-owned
+ * device array of PMG_PCG_SCRATCH_BYTES per GPU instead of a buffer the
+ * handle allocates on its first pmg_patch_pcg call.  The call allocates and
+ * frees nothing.  Arguments, layout and errors as pmg_patch_pcg; in addition
+ * PMG_ERR_INVALID_ARG when the work exceeds PMG_PCG_SCRATCH_BYTES (the
+ * message gives both sizes), before any device work.  Every call on a GPU
+ * shares that GPU's array: calls that overlap on one GPU (other streams or
+ * threads) race, and the caller must order them.  The array keeps the last
+ * call's contents; the kernel writes every entry it reads. */
+int pmg_patch_pcg_noalloc(pmg_handle* h, const double* b, double* x, double rtol, int32_t maxit,
+                          int32_t* iters, double* relres);
+
 /* The additive variant of the patch smoother: every local residual from the
  * same u (equation main:4), every local solve (equation main:5), then
  * u += theta sum_j Pi_j^T d_j (equation scatter with damping theta), the

@@ -64,7 +64,7 @@ EXPORTS = [
     "pmg_mlp_destroy", "pmg_set_bounds_mlp", "pmg_set_launch", "pmg_autotune",
     "pmg_batch_setup", "pmg_batch_instance", "pmg_batch_smooth", "pmg_batch_smooth_eager",
     "pmg_batch_autotune", "pmg_batch_query", "pmg_batch_destroy", "pmg_mlp_save", "pmg_mlp_load",
-    "pmg_mlp_fit_bounds",
+    "pmg_mlp_fit_bounds", "pmg_patch_pcg_noalloc",
 ]
 
 
@@ -115,6 +115,7 @@ def load() -> ctypes.CDLL:
         "pmg_patch_apply": [P, i32, P, P],
         "pmg_patch_local_solve": [P, P, P],
         "pmg_patch_pcg": [P, P, P, ctypes.c_double, i32, P, P],
+        "pmg_patch_pcg_noalloc": [P, P, P, ctypes.c_double, i32, P, P],
         "pmg_set_smoother": [P, i32, ctypes.c_double],
         "pmg_patch_smooth_additive": [P, P, P, ctypes.c_double],
         "gmg_set_post_direction": [P, i32],

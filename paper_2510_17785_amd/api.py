@@ -170,6 +170,21 @@ class PatchSmoother:
                                         it.data_ptr(), _dptr(rel)))
         return x, it, rel
 
+    def pcg_noalloc(self, b: torch.Tensor, x: torch.Tensor, iters: torch.Tensor, relres: torch.Tensor,
+                    rtol: float = 1e-8, maxit: int = 200):
+        """pmg_patch_pcg_noalloc: pcg into caller-provided outputs, with no
+        device allocation in the library (its work memory is a fixed
+        per-GPU array)."""
+        n = (self.n_patches, self.level_sizes[0])
+        if tuple(b.shape) != n or tuple(x.shape) != n:
+            raise ValueError("b and x must have shape (n_patches, top level size)")
+        if iters.dtype != torch.int32 or tuple(iters.shape) != (self.n_patches,) or not iters.is_cuda:
+            raise ValueError("iters must be an int32 device tensor of n_patches entries")
+        if tuple(relres.shape) != (self.n_patches,):
+            raise ValueError("relres must have n_patches entries")
+        L.check(self._lib.pmg_patch_pcg_noalloc(self._h, _dptr(b), _dptr(x), float(rtol), int(maxit),
+                                                iters.data_ptr(), _dptr(relres)))
+
     def set_smoother(self, kind: str = "chebyshev", omega: float = 0.5):
         """pmg_set_smoother: "chebyshev" (default) or "cartesian" (the
         Cartesian-reinforced smoother with damping omega; pmg_patch_pcg only)."""

@@ -1350,6 +1350,21 @@ int pcg_launch(pmg_handle* h, const double* b, double* x, double rtol, int32_t m
 
 }  // namespace
 
+int pmg_patch_pcg_noalloc(pmg_handle* h, const double* b, double* x, double rtol, int32_t maxit,
+                          int32_t* iters, double* relres) {
+  PMG_TRY(pcg_checks(h, b, x, rtol, maxit, iters, relres));
+  const size_t need = (size_t)h->n_patches * 2 * h->level_size(0) * sizeof(double);
+  if (need > PMG_PCG_SCRATCH_BYTES)
+    return fail(PMG_ERR_INVALID_ARG, "patch CG work of %zu bytes (%d patches of %d unknowns) exceeds the "
+                                     "%zu bytes of pmg_patch_pcg_noalloc", need, h->n_patches,
+                h->level_size(0), (size_t)PMG_PCG_SCRATCH_BYTES);
+  double* work = nullptr;
+  size_t have = 0;
+  HIP_TRY(pcg_scratch(&work, &have));
+  if (need > have) return fail(PMG_ERR_INVALID_ARG, "patch CG work of %zu bytes exceeds %zu", need, have);
+  return pcg_launch(h, b, x, rtol, maxit, iters, relres, work);
+}
+
 int pmg_patch_pcg(pmg_handle* h, const double* b, double* x, double rtol, int32_t maxit,
                   int32_t* iters, double* relres) {
   PMG_TRY(pcg_checks(h, b, x, rtol, maxit, iters, relres));

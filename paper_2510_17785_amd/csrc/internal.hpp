@@ -131,6 +131,9 @@ const PatchVariant* find_variant(int precision, int dim, int n_levels, const int
 hipError_t launch_features(int dim, const PatchArgs& a, int n_patch, float* out, hipStream_t s);
 // Fill the per-degree 1D tables in constant memory of the current device.
 hipError_t init_constant_tables();
+// Device address and size of the current device's work array of
+// pmg_patch_pcg_noalloc (looked up once per device, never allocated).
+hipError_t pcg_scratch(double** ptr, size_t* bytes);
 std::string list_variants();
 
 // Global (h-level) FP64 kernels.

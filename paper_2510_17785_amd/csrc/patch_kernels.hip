@@ -3313,6 +3313,33 @@ hipError_t launch_features(int dim, const PatchArgs& a, int n_patch, float* out,
   return hipGetLastError();
 }
 
+// Device work memory of pmg_patch_pcg_noalloc (the residual and search
+// direction of every patch of the call), one array per GPU, held until the
+// process ends.  Host code never uses the name `scratch` as an address: the
+// device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kPcgScratchDoubles = PMG_PCG_SCRATCH_BYTES / sizeof(double);
+static __device__ __align__(256) double scratch[kPcgScratchDoubles];
+
+hipError_t pcg_scratch(double** ptr, size_t* bytes) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static double* addr[kMaxDevices] = {nullptr};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = static_cast<double*>(p);
+  }
+  *ptr = addr[dev];
+  *bytes = kPcgScratchDoubles * sizeof(double);
+  return hipSuccess;
+}
+
 hipError_t init_constant_tables() {
   std::vector<double> t64(kConstTab, 0.0);
   for (int q = 1; q <= kMaxDegree; ++q) {
