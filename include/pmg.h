@@ -228,15 +228,17 @@ int pmg_patch_smooth_additive(pmg_handle* h, double* u, const double* b, double 
  * d += omega P (r - A d) before and one after the coarse correction on every
  * level above the coarsest, P = D diag(A_b) A_b^{-1} (Section 3.1), with D
  * the inverse diagonal of the patch's level operator and A_b the operator of
- * the two-cell Cartesian reference patch with unit cells and coefficient 1
- * at the level's degree, inverted by fast diagonalisation of the 1D two-cell
- * mass and stiffness matrices (tables formed in FP64 on the host at the first
- * call, kept until pmg_patch_destroy).  It is used by pmg_patch_pcg only;
- * with it set, pmg_patch_smooth(_colors), pmg_patch_local_solve and sweeps
- * that use the handle return PMG_ERR_UNSUPPORTED.  FP64 handles of interior
- * patches only (PMG_ERR_UNSUPPORTED otherwise).  PMG_ERR_INVALID_ARG: null
- * handle, unknown kind, omega not finite and > 0 (ignored for Chebyshev).
- * Synchronous (uploads the tables). */
+ * the Cartesian reference patch with unit cells, coefficient 1 and the
+ * patch's own cell count per direction (one where the domain boundary cuts
+ * the patch) at the level's degree, inverted by fast diagonalisation of the
+ * 1D mass and stiffness matrices (tables formed in FP64 on the host at the
+ * first call, stored in the handle's precision, kept until
+ * pmg_patch_destroy).  Used by the sweeps (pmg_patch_smooth(_colors), the
+ * GMG smoothers, batch sweeps) and by pmg_patch_pcg; pmg_patch_local_solve
+ * and the additive sweep return PMG_ERR_UNSUPPORTED with it set.  Chebyshev
+ * bounds are not needed for it.  PMG_ERR_INVALID_ARG: null handle, unknown
+ * kind, omega not finite and > 0 (ignored for Chebyshev).  Synchronous
+ * (uploads the tables). */
 int pmg_set_smoother(pmg_handle* h, int32_t kind, double omega);
 
 /* Inverse diagonal of A_{j,q} at level `level`: out device, n_patches x (2q-1)^dim. */

@@ -74,7 +74,8 @@ def prolongation_h(dim: int, nc: int, p: int) -> sp.csr_matrix:
 class GMG:
     def __init__(self, mesh: Mesh, p: int, levels, cheb_degree=3, n_vcycles=1,
                  lanczos_steps=12, seed=0, bounds=None, with_boundary=False,
-                 coarse_mean="arithmetic", post_direction=-1, additive_theta=None):
+                 coarse_mean="arithmetic", post_direction=-1, additive_theta=None,
+                 smoother="chebyshev", omega=0.5):
         self.dim, self.p = mesh.dim, p
         self.post_direction = post_direction
         self.additive_theta = additive_theta
@@ -90,7 +91,8 @@ class GMG:
             bl = "lanczos" if bounds is None else bounds[li]
             self.smoothers.append(PatchSmoother(m, p, levels, cheb_degree, n_vcycles, bl,
                                                 lanczos_steps, seed, global_matrix=self.A[li],
-                                                with_boundary=with_boundary))
+                                                with_boundary=with_boundary, smoother=smoother,
+                                                omega=omega))
         mask = dirichlet_mask(self.dim, self.meshes[0].n, p)
         self.coarse_mask = mask
         Ac = self.A[0].toarray()[np.ix_(mask, mask)]

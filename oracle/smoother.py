@@ -82,7 +82,8 @@ class PatchSmoother:
 
     def __init__(self, mesh: Mesh, p: int, levels, cheb_degree=3, n_vcycles=1,
                  bounds="lanczos", lanczos_steps=12, seed=0, global_matrix=None,
-                 keep_closure=False, vertices=None, with_boundary=False):
+                 keep_closure=False, vertices=None, with_boundary=False, smoother="chebyshev",
+                 omega=0.5):
         self.mesh, self.p, self.levels = mesh, p, tuple(levels)
         self.dim, self.n = mesh.dim, mesh.n
         self.order = patch_order(self.dim, self.n, with_boundary)
@@ -95,14 +96,18 @@ class PatchSmoother:
         self.A = global_matrix
         for v in self.order:
             P = mesh.patch(v)
-            s = LocalSolver(P, self.levels, cheb_degree=cheb_degree, n_vcycles=n_vcycles)
-            if bounds == "lanczos":
+            s = LocalSolver(P, self.levels, cheb_degree=cheb_degree, n_vcycles=n_vcycles,
+                            smoother=smoother, omega=omega)
+            if smoother == "cartesian":
+                b = None                 # the Cartesian-reinforced smoother uses no interval
+            elif bounds == "lanczos":
                 vlin = sum(v[i] * (self.n + 1) ** i for i in range(self.dim))
                 b = [lanczos.bounds(s.A[l], s.dinv[l], lanczos_steps, seed, vlin, l)
                      for l in range(len(s.levels) - 1)]
             else:
                 b = bounds[v]
-            s.set_bounds(b)
+            if b is not None:
+                s.set_bounds(b)
             self.solvers[v] = s
             self.idx[v] = patch_indices(v, p, self.n, self.dim)
             if keep_closure and global_matrix is None:

@@ -167,11 +167,11 @@ struct pmg_handle {
   void* vec_scratch = nullptr;
   void* metric = nullptr;  // per patch: the metric the patch kernel keeps in LDS (see PatchArgs)
   double* pcg_work = nullptr;  // pmg_patch_pcg: residual and search direction per patch
-  // local smoother: PMG_SMOOTHER_CHEBYSHEV, or PMG_SMOOTHER_CARTESIAN (pmg_patch_pcg
-  // only) with its damping and fast-diagonalisation tables (kFdmStride per level)
+  // local smoother: PMG_SMOOTHER_CHEBYSHEV, or PMG_SMOOTHER_CARTESIAN with its
+  // damping and fast-diagonalisation tables (kFdmStride per level, in T)
   int smoother = PMG_SMOOTHER_CHEBYSHEV;
   double omega = 0.5;
-  double* fdm_tab = nullptr;
+  void* fdm_tab = nullptr;  // T, kMaxLevels x kFdmStride
   double* add_buf = nullptr;  // additive smoother: local residuals and corrections per patch
   int64_t vec_bytes = 0;  // bytes per block slot of vec_scratch
   int64_t vec_blocks = 0;
@@ -299,14 +299,16 @@ int time_launches(hipStream_t stream, int reps, F fn, float* ms) {
 // colours [c_begin, c_end) of a sweep (reversed for direction -1) on `stream`
 int smooth_on(pmg_handle* h, double* u, const double* b, int c_begin, int c_end, int direction,
               hipStream_t stream) {
-  if (h->smoother != PMG_SMOOTHER_CHEBYSHEV)
-    return fail(PMG_ERR_UNSUPPORTED, "the Cartesian-reinforced smoother is available in pmg_patch_pcg only");
+  const bool cart = h->smoother == PMG_SMOOTHER_CARTESIAN;
   PatchArgs a = h->args();
   a.u = u;
   a.b = b;
+  a.fdm_tab = h->fdm_tab;
+  a.fdm_omega = h->omega;
   for (int k = c_begin; k < c_end; ++k) {
     const int c = direction > 0 ? k : c_end - 1 - (k - c_begin);
-    PMG_TRY(launch_chunks(h, kModeSmooth, a, h->color_off[c], h->color_off[c + 1], stream));
+    PMG_TRY(launch_chunks(h, cart ? kModeSmoothCart : kModeSmooth, a, h->color_off[c], h->color_off[c + 1],
+                          stream));
   }
   return PMG_OK;
 }
@@ -1264,7 +1266,8 @@ int pmg_patch_smooth_colors(pmg_handle* h, double* u, const double* b, int32_t c
                             int32_t c_end) {
   if (!h || !u || !b) return fail(PMG_ERR_INVALID_ARG, "null argument");
   if (h->patch_geo) return fail(PMG_ERR_UNSUPPORTED, "independent patches have no global vector to smooth");
-  if (!h->bounds_valid) return fail(PMG_ERR_INVALID_ARG, "Chebyshev bounds not set");
+  if (h->smoother == PMG_SMOOTHER_CHEBYSHEV && !h->bounds_valid)
+    return fail(PMG_ERR_INVALID_ARG, "Chebyshev bounds not set");
   if (c_begin < 0 || c_end > h->n_colors || c_begin > c_end)
     return fail(PMG_ERR_INVALID_ARG, "colour range [%d, %d) outside [0, %d)", c_begin, c_end, h->n_colors);
   return smooth_on(h, u, b, c_begin, c_end, 1, h->stream);
@@ -1304,7 +1307,7 @@ int pmg_patch_apply(pmg_handle* h, int32_t level, const double* x, double* y) {
 int pmg_patch_local_solve(pmg_handle* h, const double* r, double* d) {
   if (!h || !r || !d) return fail(PMG_ERR_INVALID_ARG, "null argument");
   if (h->smoother != PMG_SMOOTHER_CHEBYSHEV)
-    return fail(PMG_ERR_UNSUPPORTED, "the Cartesian-reinforced smoother is available in pmg_patch_pcg only");
+    return fail(PMG_ERR_UNSUPPORTED, "the batched local solve runs the Chebyshev smoother only");
   if (!h->bounds_valid) return fail(PMG_ERR_INVALID_ARG, "Chebyshev bounds not set");
   PatchArgs a = h->args();
   a.in = r;
@@ -1404,23 +1407,43 @@ int pmg_set_smoother(pmg_handle* h, int32_t kind, double omega) {
   }
   if (kind != PMG_SMOOTHER_CARTESIAN) return fail(PMG_ERR_INVALID_ARG, "unknown smoother %d", kind);
   if (!(omega > 0.0) || !std::isfinite(omega)) return fail(PMG_ERR_INVALID_ARG, "omega must be finite and > 0");
-  if (h->precision != PMG_FP64)
-    return fail(PMG_ERR_UNSUPPORTED, "the Cartesian-reinforced smoother runs on FP64 handles only");
-  if (h->with_boundary)
-    return fail(PMG_ERR_UNSUPPORTED, "the Cartesian-reinforced smoother needs two cells per direction");
   if (!h->fdm_tab) {
+    // per smoothed level: the tables of a two-cell direction, then those of a
+    // one-cell direction embedded at the low and at the high interior nodes
+    // of the two-cell numbering (identity, lam = 1 and zero diagonals on the
+    // other nodes, which are masked in a cut patch)
     std::vector<double> tab((size_t)kMaxLevels * kFdmStride, 0.0);
     for (int l = 0; l + 1 < h->L; ++l) {
-      const FdmTables f = fdm_tables(h->levels[l]);
-      double* dst = tab.data() + (size_t)l * kFdmStride;
-      std::copy(f.S.begin(), f.S.end(), dst);
-      std::copy(f.lam.begin(), f.lam.end(), dst + f.m * f.m);
-      std::copy(f.dM.begin(), f.dM.end(), dst + f.m * f.m + f.m);
-      std::copy(f.dK.begin(), f.dK.end(), dst + f.m * f.m + 2 * f.m);
+      const int q = h->levels[l], m = 2 * q - 1;
+      for (int type = 0; type < 3; ++type) {
+        const FdmTables f = fdm_tables(q, type == 0 ? 2 : 1);
+        const int off = type == 2 ? q : 0;  // first embedded node
+        double* S = tab.data() + (size_t)l * kFdmStride + type * kFdmTypeStride;
+        double* lam = S + m * m;
+        double* dM = lam + m;
+        double* dK = dM + m;
+        for (int i = 0; i < m; ++i) {
+          S[i * m + i] = 1.0;
+          lam[i] = 1.0;
+        }
+        for (int i = 0; i < f.m; ++i) {
+          for (int j = 0; j < f.m; ++j) S[(off + i) * m + off + j] = f.S[i * f.m + j];
+          lam[off + i] = f.lam[i];
+          dM[off + i] = f.dM[i];
+          dK[off + i] = f.dK[i];
+        }
+      }
     }
-    int st = dev_alloc(&h->fdm_tab, tab.size() * sizeof(double), &h->device_bytes);
+    const size_t ts = h->tsize();
+    int st = dev_alloc(&h->fdm_tab, tab.size() * ts, &h->device_bytes);
     if (st < 0) return st;
-    hipError_t e = hipMemcpy(h->fdm_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice);
+    hipError_t e;
+    if (h->precision == PMG_FP64) {
+      e = hipMemcpy(h->fdm_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice);
+    } else {
+      std::vector<float> t32(tab.begin(), tab.end());
+      e = hipMemcpy(h->fdm_tab, t32.data(), t32.size() * sizeof(float), hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) return fail(PMG_ERR_HIP, "smoother tables: %s", hipGetErrorString(e));
   }
   h->smoother = kind;

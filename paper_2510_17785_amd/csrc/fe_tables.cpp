@@ -161,15 +161,16 @@ void h_prolongation_1d(int nc, int p, std::vector<int>& first, std::vector<doubl
   }
 }
 
-FdmTables fdm_tables(int q) {
+FdmTables fdm_tables(int q, int ncell) {
   FdmTables f;
-  const int n = q + 1, m = 2 * q - 1;
+  const int n = q + 1, m = ncell * q - 1, nt = ncell * q + 1;
   f.m = m;
+  if (m <= 0) return f;
   DegreeTables t = degree_tables(q);
   // one cell: M_ab = sum_k w_k l_a(x_k) l_b(x_k), K_ab = sum_k w_k l_a'(x_k) l_b'(x_k);
-  // two cells share node q; the interior nodes are 1 .. 2q-1
-  std::vector<double> M2((2 * q + 1) * (2 * q + 1), 0.0), K2(M2.size(), 0.0);
-  for (int c = 0; c < 2; ++c)
+  // neighbouring cells share a node; the interior nodes are 1 .. ncell q - 1
+  std::vector<double> M2(nt * nt, 0.0), K2(M2.size(), 0.0);
+  for (int c = 0; c < ncell; ++c)
     for (int a = 0; a < n; ++a)
       for (int b = 0; b < n; ++b) {
         double mv = 0, kv = 0;
@@ -178,14 +179,14 @@ FdmTables fdm_tables(int q) {
           kv += t.wg[k] * t.D[k * n + a] * t.D[k * n + b];
         }
         const int r = c * q + a, s2 = c * q + b;
-        M2[r * (2 * q + 1) + s2] += mv;
-        K2[r * (2 * q + 1) + s2] += kv;
+        M2[r * nt + s2] += mv;
+        K2[r * nt + s2] += kv;
       }
   std::vector<double> M(m * m), K(m * m);
   for (int i = 0; i < m; ++i)
     for (int j = 0; j < m; ++j) {
-      M[i * m + j] = M2[(i + 1) * (2 * q + 1) + (j + 1)];
-      K[i * m + j] = K2[(i + 1) * (2 * q + 1) + (j + 1)];
+      M[i * m + j] = M2[(i + 1) * nt + (j + 1)];
+      K[i * m + j] = K2[(i + 1) * nt + (j + 1)];
     }
   f.dM.resize(m);
   f.dK.resize(m);

@@ -43,10 +43,12 @@ std::vector<double> patch_prolongation_1d(int p, int q, int ncell);
 // in columns first[g] .. first[g] + p, values w[g*(p+1) + t].
 void h_prolongation_1d(int nc, int p, std::vector<int>& first, std::vector<double>& w);
 
-// Fast diagonalisation of the degree-q operator of the two-cell Cartesian
-// reference patch (unit cells, coefficient 1), the A_b of the
-// Cartesian-reinforced smoother (Section 3.1).  M, K: the 1D two-cell mass
-// and stiffness matrices on the m = 2q-1 interior nodes; S (m x m, row-major,
+// Fast diagonalisation of the degree-q operator of the Cartesian reference
+// patch with `ncell` unit cells per direction (2 for an interior vertex, 1
+// along a direction where the boundary cuts the patch), coefficient 1: the
+// A_b of the Cartesian-reinforced smoother (Section 3.1).  M, K: the 1D mass
+// and stiffness matrices on the m = ncell q - 1 interior nodes (m = 0: empty
+// tables); S (m x m, row-major,
 // column k the k-th eigenvector) and lam solve K S = M S diag(lam) with
 // S^T M S = I, so that A_b = sum_i M (x) .. K_i .. (x) M has the inverse
 // S^(x d) diag(1 / sum_i lam_{k_i}) (S^T)^(x d); dM, dK are the diagonals of
@@ -55,6 +57,6 @@ struct FdmTables {
   int m = 0;
   std::vector<double> S, lam, dM, dK;
 };
-FdmTables fdm_tables(int q);
+FdmTables fdm_tables(int q, int ncell = 2);
 
 }  // namespace pmgi

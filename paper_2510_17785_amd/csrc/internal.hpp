@@ -26,10 +26,15 @@ enum PatchMode : int {
   kModeMetric = 4,    // setup: compute the cached levels' metric, write it to metric_out
   kModePcg = 5,       // FP64 only: CG on each patch problem, preconditioned by the V-cycle
   kModePcgCart = 6,   // the same with the Cartesian-reinforced smoother in the V-cycle
+  kModeSmoothCart = 7,  // kModeSmooth with the Cartesian-reinforced smoother in the V-cycle
 };
 
-// Per level of fdm tables: S (29 x 29 at most), lam, dM, dK (29 each).
-constexpr int kFdmStride = 29 * 29 + 3 * 29;
+// Per level of fdm tables, three direction types (a direction with two
+// cells; one cell whose interior nodes are the low ones 1 .. q-1; one cell
+// with the high ones q+1 .. 2q-1, both embedded in the two-cell numbering),
+// each: S (29 x 29 at most), lam, dM, dK (29 each).
+constexpr int kFdmTypeStride = 29 * 29 + 3 * 29;
+constexpr int kFdmStride = 3 * kFdmTypeStride;
 
 // Arguments of every per-patch kernel.  Pointers to T-valued arrays are
 // void* here and cast inside the kernel.
@@ -90,10 +95,11 @@ struct PatchArgs {
   double* pcg_work;
   int32_t* pcg_iters;
   double* pcg_relres;
-  // Cartesian-reinforced smoother (kModePcgCart): fast-diagonalisation
-  // tables per smoothed level, kFdmStride doubles each (S row-major with
-  // column k the k-th eigenvector, then lam, dM, dK), and the damping omega
-  const double* fdm_tab;
+  // Cartesian-reinforced smoother (kModePcgCart, kModeSmoothCart):
+  // fast-diagonalisation tables per smoothed level, kFdmStride elements of T
+  // each (per direction type: S row-major with column k the k-th
+  // eigenvector, then lam, dM, dK), and the damping omega
+  const void* fdm_tab;
   double fdm_omega;
 };
 

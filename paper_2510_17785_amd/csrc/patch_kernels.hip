@@ -58,6 +58,14 @@ __device__ __forceinline__ const LDSP T* lds_cast(const T* p) {
   return (const LDSP T*)p;
 }
 
+// Wavefront-level sync: the LDS writes of this wavefront's lanes are visible
+// to its other lanes afterwards (no workgroup barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // 1D tables of every degree 1..kMaxDegree, B (n x n), Dc (n x n), D (n x n),
 // Gauss points and weights, in constant memory: they depend on the degree
 // only, and reads at compile-time offsets become scalar loads.
@@ -457,7 +465,7 @@ struct Ctx {
   bool dense_ok = false;  // dense level matrices loaded (not in the setup kernels)
   bool metric_loaded = false;  // the cached metric was read from the setup's copy
   bool geo_needed = true;      // the patch geometry is used (Jacobian or metric)
-  const double* fdm = nullptr;  // Cartesian-reinforced smoother tables (kModePcgCart)
+  const T* fdm = nullptr;  // Cartesian-reinforced smoother tables (kModePcgCart, kModeSmoothCart)
   double omega = 0;
   __device__ T* X() const { return lds + Lay::X_off; }
   __device__ T* Out() const { return lds + Lay::Out_off; }
@@ -1784,11 +1792,6 @@ __device__ __forceinline__ void prolong_add(const T* __restrict__ dc, T* __restr
 // LDS writes of this wavefront visible to all its lanes: the memory
 // operations of one wavefront complete in order, so only the compiler must
 // be kept from moving accesses across this point
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // The V-cycle (Algorithm 2) from level L down, for levels of at most 64
 // nodes stored as dense matrices: run by wavefront 0 alone, lane i owning
@@ -1940,14 +1943,17 @@ __device__ void vcycle_small(const Ctx<T, DIM, LV>& c, int k) {
 // One pass of the fast diagonalisation along direction `dir` of an m^DIM
 // vector (x fastest): out_k = sum_a S[a][k] in_a (FWD, S^T) or
 // out_a = sum_k S[a][k] in_k (S).
-template <int DIM, int m, bool FWD>
-__device__ void fdm_pass(const double* in, double* out, const double* S, int dir) {
+// One pass of the fast diagonalisation along direction dir: out = S^T in
+// (FWD) or S in along that direction, with the direction's own table (the
+// type of the direction: two cells, or one cell at the low or high nodes).
+template <typename T, int DIM, int m, bool FWD>
+__device__ void fdm_pass(const T* in, T* out, const T* S, int dir) {
   constexpr int N = ipow(m, DIM);
   const int stride = dir == 0 ? 1 : (dir == 1 ? m : m * m);
-  for (int idx = threadIdx.x; idx < N; idx += NT<double>) {
+  for (int idx = threadIdx.x; idx < N; idx += NT<T>) {
     const int i = (idx / stride) % m;
     const int base = idx - i * stride;
-    double acc = 0;
+    T acc = 0;
     for (int a = 0; a < m; ++a) acc += (FWD ? S[a * m + i] : S[i * m + a]) * in[base + a * stride];
     out[idx] = acc;
   }
@@ -1955,25 +1961,32 @@ __device__ void fdm_pass(const double* in, double* out, const double* S, int dir
 
 // One Richardson step of the Cartesian-reinforced smoother (Section 3.1) on
 // level L: d += omega D diag(A_b) A_b^{-1} (r - A d), D the level's inverse
-// diagonal and A_b the operator of the two-cell Cartesian reference patch
-// (unit cells, coefficient 1), inverted by fast diagonalisation:
-// A_b^{-1} = S^(x d) diag(1 / sum_i lam_{k_i}) (S^T)^(x d).  FP64.
-template <int DIM, class LV, int L>
-__device__ void cartesian_step(const Ctx<double, DIM, LV>& c, bool d_zero) {
-  using T = double;
+// diagonal and A_b the operator of the Cartesian reference patch with unit
+// cells and coefficient 1 and the patch's own cell count per direction
+// (one along a direction the boundary cuts), inverted by fast
+// diagonalisation: A_b^{-1} = S^(x d) diag(1 / sum_i lam_{k_i}) (S^T)^(x d).
+// A one-cell direction's tables are embedded in the two-cell numbering of
+// the masked patch layout (identity and lam = 1 on the masked nodes, whose
+// values stay zero).
+template <typename T, int DIM, class LV, int L>
+__device__ void cartesian_step(const Ctx<T, DIM, LV>& c, bool d_zero) {
   using PT = VecPtr<T, DIM, LV>;
   constexpr int N = Layout<T, DIM, LV>::level_size(L);
   constexpr int m = 2 * LV::q[L] - 1;
-  const double* S = c.fdm + L * kFdmStride;
-  const double* lam = S + m * m;
-  const double* dM = lam + m;
-  const double* dK = dM + m;
+  // per direction: the table of its type (0: two cells; 1: one cell, low
+  // nodes, the high side cut; 2: one cell, high nodes, the low side cut)
+  const T* tab[3];
+  for (int i = 0; i < 3; ++i) {
+    const int fl = i < DIM ? (c.pf >> (2 * i)) & 3 : 0;
+    const int type = (fl & 1) ? 2 : ((fl & 2) ? 1 : 0);
+    tab[i] = c.fdm + L * kFdmStride + type * kFdmTypeStride;
+  }
   T* d = c.d(L);
-  const T* r = c.r(L);
   const T* dinv = c.dinv(L);
   T* u = c.res();
   T* v = c.z();
   if (d_zero) {
+    const T* r = c.r(L);
     for (int i = threadIdx.x; i < N; i += NT<T>) u[i] = r[i];
     __syncthreads();
   } else {
@@ -1982,25 +1995,32 @@ __device__ void cartesian_step(const Ctx<double, DIM, LV>& c, bool d_zero) {
   T* src = u;
   T* dst = v;
   for (int dir = 0; dir < DIM; ++dir) {
-    fdm_pass<DIM, m, true>(src, dst, S, dir);
+    fdm_pass<T, DIM, m, true>(src, dst, tab[dir], dir);
     __syncthreads();
     T* t = src; src = dst; dst = t;
   }
   for (int i = threadIdx.x; i < N; i += NT<T>) {
     const int k0 = i % m, k1 = (i / m) % m, k2 = DIM == 3 ? i / (m * m) : 0;
-    src[i] /= lam[k0] + lam[k1] + (DIM == 3 ? lam[k2] : 0.0);
+    src[i] /= tab[0][m * m + k0] + tab[1][m * m + k1] + (DIM == 3 ? tab[2][m * m + k2] : T(0));
   }
   __syncthreads();
   for (int dir = 0; dir < DIM; ++dir) {
-    fdm_pass<DIM, m, false>(src, dst, S, dir);
+    fdm_pass<T, DIM, m, false>(src, dst, tab[dir], dir);
     __syncthreads();
     T* t = src; src = dst; dst = t;
   }
   for (int i = threadIdx.x; i < N; i += NT<T>) {
     const int a0 = i % m, a1 = (i / m) % m, a2 = DIM == 3 ? i / (m * m) : 0;
-    const double diag = DIM == 3 ? dK[a0] * dM[a1] * dM[a2] + dM[a0] * dK[a1] * dM[a2] + dM[a0] * dM[a1] * dK[a2]
-                                 : dK[a0] * dM[a1] + dM[a0] * dK[a1];
-    const double step = c.omega * dinv[i] * diag * src[i];
+    const T m0 = tab[0][m * m + m + a0], k0 = tab[0][m * m + 2 * m + a0];
+    const T m1 = tab[1][m * m + m + a1], k1 = tab[1][m * m + 2 * m + a1];
+    T diag;
+    if constexpr (DIM == 3) {
+      const T m2 = tab[2][m * m + m + a2], k2 = tab[2][m * m + 2 * m + a2];
+      diag = k0 * m1 * m2 + m0 * k1 * m2 + m0 * m1 * k2;
+    } else {
+      diag = k0 * m1 + m0 * k1;
+    }
+    const T step = T(c.omega) * dinv[i] * diag * src[i];
     d[i] = d_zero ? step : d[i] + step;
   }
   __syncthreads();
@@ -2058,7 +2078,7 @@ __device__ void vcycle(const Ctx<T, DIM, LV>& c, int k, bool d_zero) {
                   "transfer temporaries exceed the work area");
     using PT = VecPtr<T, DIM, LV>;
     if constexpr (CART)                               // pre-smoothing
-      cartesian_step<DIM, LV, L>(c, d_zero);
+      cartesian_step<T, DIM, LV, L>(c, d_zero);
     else
       chebyshev<T, DIM, LV, L>(c, k, d_zero);
     T* res = c.res();
@@ -2078,7 +2098,7 @@ __device__ void vcycle(const Ctx<T, DIM, LV>& c, int k, bool d_zero) {
     }
     prolong_add<T, DIM, QF, QC, STAGE>(c.d(L + 1), c.d(L), lds_cast(c.tabP(L)), lds_cast(c.abuf()));  // correction
     if constexpr (CART)                               // post-smoothing
-      cartesian_step<DIM, LV, L>(c, false);
+      cartesian_step<T, DIM, LV, L>(c, false);
     else
       chebyshev<T, DIM, LV, L>(c, k, false);
   }
@@ -2442,6 +2462,9 @@ __device__ __forceinline__ void patch_update(const PatchArgs& a, Ctx<T, DIM, LV>
   using Lay = Layout<T, DIM, LV>;
   using S0 = Sh<DIM, LV::q[0]>;
   const int tid = threadIdx.x;
+  // the smoothing modes: local solves with Chebyshev or Cartesian-reinforced smoothing
+  constexpr bool SMOOTH = MODE == kModeSmooth || MODE == kModeSmoothCart;
+  constexpr bool CART = MODE == kModeSmoothCart;
   const int pf = patch_flags<DIM>(a, patch);
   c.pf = pf;
   c.trunc = nullptr;
@@ -2456,7 +2479,7 @@ __device__ __forceinline__ void patch_update(const PatchArgs& a, Ctx<T, DIM, LV>
   constexpr int m = S0::m, mi = S0::mi;
   T* r0 = c.r(0);
   int base = 0, M = 0;
-  if constexpr (MODE == kModeSmooth || MODE == kModeResidual) {
+  if constexpr (SMOOTH || MODE == kModeResidual) {
     // gather u-bar_j (closure) and b_j (interior), equation gather; issued
     // first so that its global loads overlap those of the patch data
     patch_base<DIM>(a.patch_vertex[patch], a.N, a.p, base, M);
@@ -2528,7 +2551,7 @@ __device__ __forceinline__ void patch_update(const PatchArgs& a, Ctx<T, DIM, LV>
     return;
   } else if constexpr (MODE == kModePcg || MODE == kModePcgCart) {
     if constexpr (std::is_same<T, double>::value) {
-      c.fdm = a.fdm_tab;
+      c.fdm = tptr<T>(a.fdm_tab);
       c.omega = a.fdm_omega;
       patch_pcg<DIM, LV, MODE == kModePcgCart>(c, a, patch);
     }
@@ -2555,7 +2578,7 @@ __device__ __forceinline__ void patch_update(const PatchArgs& a, Ctx<T, DIM, LV>
       if (a.level == 3) run(std::integral_constant<int, 3>{});
     return;
   } else {
-    if constexpr (MODE == kModeSmooth || MODE == kModeResidual) {
+    if constexpr (SMOOTH || MODE == kModeResidual) {
       // evaluate: r_j = b_j - Pi_j A-bar_j u-bar_j (equation main:4); masked
       // rows (boundary-vertex patches) are set to zero
       if constexpr (Lay::use_seg(0)) {
@@ -2581,9 +2604,13 @@ __device__ __forceinline__ void patch_update(const PatchArgs& a, Ctx<T, DIM, LV>
       __syncthreads();
     }
     // local solve: N_MG V-cycles from zero (equation main:5)
-    for (int it = 0; it < a.n_vcycles; ++it) vcycle<T, DIM, LV, 0>(c, a.cheb_degree, it == 0);
+    if constexpr (CART) {
+      c.fdm = tptr<T>(a.fdm_tab);
+      c.omega = a.fdm_omega;
+    }
+    for (int it = 0; it < a.n_vcycles; ++it) vcycle<T, DIM, LV, 0, CART>(c, a.cheb_degree, it == 0);
     const T* d0 = c.d(0);
-    if constexpr (MODE == kModeSmooth) {
+    if constexpr (SMOOTH) {
       // scatter-add in FP64 (equation scatter); interiors of one colour are disjoint
   #pragma unroll 1
     for (int idx = tid; idx < N0; idx += NT<T>) {
@@ -3163,6 +3190,8 @@ struct Variant {
     if (!e) e = prime_one<kModeSolve, false>();
     if (!e) e = prime_one<kModeApply, false>();
     if (!e) e = prime_one<kModeMetric, false>();
+    if (!e) e = prime_one<kModeSmoothCart, false>();
+    if (!e) e = prime_one<kModeSmoothCart, true>();
     if constexpr (std::is_same<T, double>::value) {
       if (!e) e = prime_one<kModePcg, false>();
       if (!e) e = prime_one<kModePcgCart, false>();
@@ -3173,12 +3202,14 @@ struct Variant {
     if (a.n_patch <= 0) return hipSuccess;
     const size_t lds = lds_bytes(mode);
     // persistent grids for smoothing only; other modes: one workgroup per patch
-    const bool persist = mode == kModeSmooth && a.grid > 0 && a.grid < a.n_patch;
+    const bool persist = (mode == kModeSmooth || mode == kModeSmoothCart) && a.grid > 0 && a.grid < a.n_patch;
     int g = persist ? a.grid : a.n_patch;
     if (a.map_mode == 1) g = (g + 7) / 8 * 8;  // whole rounds over the 8 XCDs
     switch (mode) {
       case kModeSmooth:
         return persist ? go<kModeSmooth, true>(a, g, lds, s) : go<kModeSmooth, false>(a, g, lds, s);
+      case kModeSmoothCart:
+        return persist ? go<kModeSmoothCart, true>(a, g, lds, s) : go<kModeSmoothCart, false>(a, g, lds, s);
       case kModeResidual: return go<kModeResidual, false>(a, g, lds, s);
       case kModeSolve: return go<kModeSolve, false>(a, g, lds, s);
       case kModeApply: return go<kModeApply, false>(a, g, lds, s);

@@ -648,6 +648,57 @@ def test_cartesian_preconditioner_inverts_undeformed_patches(dim, q):
     assert np.abs(PA2 - np.eye(len(PA2))).max() > 1e-2
 
 
+@pytest.mark.parametrize("dim,q,ncell", [(2, 3, (1, 2)), (2, 4, (2, 1)), (3, 3, (1, 2, 1)), (3, 2, (2, 2, 1))])
+def test_cartesian_preconditioner_inverts_cut_undeformed_patches(dim, q, ncell):
+    # a patch of a boundary vertex keeps its cells inside the domain (one per
+    # cut direction); its reference patch has the same cell counts, so on an
+    # undeformed mesh P A = I there too, and the reference operator is the
+    # Kronecker sum of the 1D matrices of one or two cells per direction
+    P = _cartesian_patch(dim, 0.25, 3.0)
+    P = fem.PatchGeometry(P.verts, P.mu, ncell)
+    Ab = pmg.reference_patch_matrix(dim, q, ncell)
+    Aj = fem.patch_matrix(P, q)
+    PA = (np.diag(Ab) / np.diag(Aj))[:, None] * np.linalg.solve(Ab, Aj)
+    assert np.abs(PA - np.eye(len(PA))).max() <= 1e-10
+    M2, K2 = _two_cell_1d(q)
+    M1, K1 = M2[:q - 1, :q - 1], K2[:q - 1, :q - 1]     # one cell: its interior nodes 1 .. q-1
+    # (the first cell's block of the two-cell matrices holds exactly the one-cell ones)
+    x, w = fe1d.gauss_rule(q + 1)
+    L = fe1d.lagrange_values(fe1d.gll_nodes(q), x)
+    assert np.allclose(M1, ((L * w) @ L.T)[1:-1, 1:-1], atol=1e-14)
+    A = np.zeros_like(Ab)
+    for i in range(dim):
+        T = np.ones((1, 1))
+        for j in range(dim):
+            Mj, Kj = (M2, K2) if ncell[j] == 2 else (M1, K1)
+            T = np.kron(Kj if j == i else Mj, T)
+        A += T
+    assert np.abs(Ab - A).max() <= 1e-12 * np.abs(A).max()
+
+
+def test_cartesian_sweep_on_undeformed_mesh_reduces_the_error_by_four():
+    # on a one-patch mesh (N = 2) with an undeformed patch, the sweep is one
+    # V-cycle with the exact level inverses as smoothers: levels (q, 1) give
+    # B A the eigenvalues 3/4 and 1, so the error propagation I - B A has
+    # 1/4 and 0 and a sweep from zero reduces the energy norm of the error by
+    # at least 4 (equality on the fine complement)
+    mesh = fem.Mesh(2, 2, _cartesian_patch(2, 0.5, 1.0).verts, np.ones(4))
+    S = PatchSmoother(mesh, 3, (3, 1), smoother="cartesian", omega=0.5)
+    A = fem.dirichlet_operator(mesh, 3).toarray()
+    mask = fem.dirichlet_mask(2, 2, 3)
+    Ai = A[np.ix_(mask, mask)]
+    rng = np.random.default_rng(2)
+    b = np.zeros(mask.size)
+    b[mask] = rng.standard_normal(mask.sum())
+    xs = np.zeros(mask.size)
+    xs[mask] = np.linalg.solve(Ai, b[mask])
+    u = S.sweep(np.zeros_like(b), b, +1)
+    e0, e1 = xs[mask], (xs - u)[mask]
+    ratio = np.sqrt(e1 @ Ai @ e1 / (e0 @ Ai @ e0))
+    assert ratio <= 0.25 + 1e-12
+    assert ratio >= 0.2                  # not an exact solve
+
+
 @pytest.mark.parametrize("dim,levels", [(2, (3, 1)), (3, (3, 1)), (2, (7, 3, 1)), (3, (7, 3, 1)),
                                         (2, (15, 7, 3, 1))])
 def test_cartesian_vcycle_cg_iterations_equal_level_count(dim, levels):
