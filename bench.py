@@ -12,7 +12,13 @@ network (trained first, on the GPU, on Lanczos labels of random patches of
 the same distribution); the plain FP64 local solver with per-patch Lanczos
 bounds is timed beside it.  The comparison holds only if the outer GMG-CG
 iteration count of the FP32+learned solver stays within one of the FP64
-one; both counts are reported.  One JSON line is printed.
+one; both counts are reported.  One JSON line is printed; the default run
+adds the same record for the 32^3 Q7 jump workload (the matrix cores on the
+hot path) under "secondary".  Each record carries the roofline of the FP32
+smoothing kernel (against the 157.3 TFLOP/s FP32 peak, with the fraction of
+what unpacked vector instructions can issue beside it) and the oracle's
+sweep timed on the host, on all usable cores (up to 16 worker processes)
+and on one, in processes forked before the GPU is used.
 """
 from __future__ import annotations
 
@@ -28,8 +34,13 @@ if ROOT not in sys.path:
 
 # Peak figures of MI355X used for the roofline fraction.
 HBM_PEAK_GBS = 8000.0
-# FP32 / FP64 FMA on the vector ALUs without packed FP32 (packed FP32 is
-# disabled in these kernels): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz.
+# FP32: 157.3 TFLOP/s on the vector ALUs (256 CUs x 4 SIMDs x 16 lanes x 2
+# FP32 per lane with packed instructions x 2 flop x 2.4 GHz) and on the
+# matrix cores alike; FP64: 78.6 TFLOP/s (no packed form).
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+# What the FP32 kernels here can issue on the vector ALUs: packed FP32 is
+# disabled in them, so one FP32 FMA per lane and cycle (78.6 TFLOP/s).
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # Dense FP32 matrix-core peak (v_mfma_f32_16x16x4_f32).
 MFMA_FP32_PEAK_TFLOPS = 157.3
@@ -130,42 +141,92 @@ def time_sweeps(S, u, b, steps, warmup, torch):
     return sweep_ms, per_launch, wall
 
 
-def cpu_baseline(w, X, mu, b, budget_s=12.0):
-    """The oracle's sweep timed on a bounded sample of patches (setup of the
-    sample untimed), extrapolated to a full sweep."""
+def host_info():
+    """Host cores this process may use and the CPU model."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return cores, model
+
+
+def _oracle_sweep_worker(job):
+    """One worker of the multi-core oracle baseline: the oracle's sweep over a
+    set of patches of one colour (independent updates), repeated for the
+    budget; returns (patch updates, seconds).  Setup untimed."""
+    dim, n, p, levels, X, mu, b, verts, budget_s = job
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     from oracle import fem
-    from oracle.smoother import PatchSmoother, patch_order
-
-    order = patch_order(w.dim, w.n)
-    rng = np.random.default_rng(0)
-    # the oracle assembles dense patch matrices: fewer sample patches at high degree
-    sample_n = min(96 if w.p <= 4 else 8, len(order))
-    pick = sorted(rng.choice(len(order), sample_n, replace=False))
-    sample = [order[i] for i in pick]
-    mesh = fem.Mesh(w.dim, w.n, X, mu)
+    from oracle.smoother import PatchSmoother
     with threadpool_limits(limits=1):
-        S = PatchSmoother(mesh, w.p, w.levels, keep_closure=True, vertices=sample)
+        S = PatchSmoother(fem.Mesh(dim, n, X, mu), p, levels, keep_closure=True, vertices=verts)
         u = np.zeros_like(b)
-        reps = 0
-        t0 = time.perf_counter()
+
+        def updates():
+            # the oracle sweep's steps per patch (local residual, V-cycle,
+            # scatter) on one vector: the sweep's copy of the whole vector is
+            # paid once per sweep, not once per sampled patch
+            for v in S.order:
+                u[S.idx[v][1]] += S.solvers[v].solve(S.local_residual(v, u, b))
+
+        updates()
+        reps, t0 = 0, time.perf_counter()
         while True:
-            u = S.sweep(u, b, +1)
+            updates()
             reps += 1
             if time.perf_counter() - t0 >= budget_s:
                 break
-        t = time.perf_counter() - t0
-    t_sweep = t / reps * len(order) / sample_n
+        return reps * len(verts), time.perf_counter() - t0
+
+
+def cpu_baseline(w, X, mu, b, budget_s=8.0, max_workers=16):
+    """The oracle's sweep (FP64 dense level matrices, setup untimed) timed on
+    the host: on all usable cores (a process pool, each worker updating its
+    own patches of one colour, which are independent) and on one core; the
+    rate of patch updates is extrapolated to a full sweep.  Runs in worker
+    processes forked before the GPU is touched."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    from oracle.smoother import patch_order, vertex_color
+
+    cores, model = host_info()
+    workers = max(1, min(cores, max_workers))
+    order = patch_order(w.dim, w.n)
+    colour0 = [v for v in order if vertex_color(v) == 0]
+    rng = np.random.default_rng(0)
+    per = 12 if w.p <= 4 else 2         # the oracle assembles dense patch matrices
+    pick = [colour0[i] for i in rng.choice(len(colour0), min(len(colour0), per * workers), replace=False)]
+    chunks = [pick[k::workers] for k in range(workers)]
+    jobs = [(w.dim, w.n, w.p, w.levels, X, mu, b, c, budget_s) for c in chunks if c]
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(len(jobs)) as pool:
+        res = pool.map(_oracle_sweep_worker, jobs)
+    wall = time.perf_counter() - t0
+    rate_all = sum(r[0] / r[1] for r in res)          # concurrent workers: rates add
+    one = _oracle_sweep_worker((w.dim, w.n, w.p, w.levels, X, mu, b, pick[:per], budget_s))
+    rate_one = one[0] / one[1]
+    n_patch = len(order)
     return {
-        "value": w.n_interior_dofs / t_sweep,
+        "value": w.n_interior_dofs * rate_all / n_patch,
         "unit": "DoF/s",
-        "cores": 1,
+        "cores": len(jobs),
         "kind": "oracle",
-        "sample": f"{sample_n} of {len(order)} patches of the same mesh, {reps} oracle sweeps "
-                  f"in {t:.1f} s (FP64 dense level matrices, setup untimed), extrapolated "
-                  f"to all patches",
+        "sample": f"{len(pick)} patches of colour 0 of the same mesh in {len(jobs)} worker processes "
+                  f"(one core each), {sum(r[0] for r in res)} patch updates in {budget_s:.0f} s "
+                  f"each ({wall:.1f} s with setup); extrapolated to all {n_patch} patches of a sweep",
+        "one_core": {"value": w.n_interior_dofs * rate_one / n_patch, "unit": "DoF/s", "cores": 1,
+                     "sample": f"{per} patches, {one[0]} patch updates in {one[1]:.1f} s"},
+        "host": {"nproc": os.cpu_count(), "usable_cores": cores, "cpu_model": model},
     }
 
 
@@ -244,9 +305,10 @@ def bench_batch(args, w):
         "roofline": {
             "bound": "alu",
             "achieved": achieved,
-            "peak": VALU_PEAK_TFLOPS,
+            "peak": FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s",
-            "frac": achieved / VALU_PEAK_TFLOPS,
+            "frac": achieved / FP32_PEAK_TFLOPS,
+            "valu_issue_frac": achieved / VALU_PEAK_TFLOPS,
             "traffic": None,
             "kernel": "patch_kernel<float,3,Levels<p...>,smooth> for p = 2, 4, 6, 8",
             "algorithmic_flops_per_sweep": F,
@@ -294,6 +356,9 @@ def cpu_baseline_batch(w, ps, levels, X, mu, bh, local, budget_s=12.0):
             "sample": "; ".join(desc) + " (oracle sweeps, setup untimed), extrapolated to all "
                       "patches of all four instances"}
 
+
+DEFAULT_WORKLOAD = "3d-n16-q4"
+SECOND_WORKLOAD = "3d-n32-q7-jump"
 
 # Batched patch CG: independent 3D Q7 patches drawn like the patches of the
 # 32^3 Q7 jump mesh (perturbation 0.25 h, cell coefficients 10^U(-4, 4)), as
@@ -376,9 +441,9 @@ def bench_pcg(args):
         "roofline": {
             "bound": "alu",
             "achieved": achieved,
-            "peak": VALU_PEAK_TFLOPS,
+            "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
-            "frac": achieved / VALU_PEAK_TFLOPS,
+            "frac": achieved / FP64_PEAK_TFLOPS,
             "traffic": measured_traffic(PCG_WORKLOAD, "patch_kernel_fp64"),
             "kernel": f"patch_kernel<double,3,Levels<{','.join(map(str, PCG_LEVELS))}>,pcg>",
             "algorithmic_flops_per_iteration": F_iter,
@@ -492,9 +557,9 @@ def bench_study(args):
         "roofline": {
             "bound": "alu",
             "achieved": achieved,
-            "peak": VALU_PEAK_TFLOPS,
+            "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
-            "frac": achieved / VALU_PEAK_TFLOPS,
+            "frac": achieved / FP64_PEAK_TFLOPS,
             "traffic": None,
             "kernel": "patch_kernel<double,d,Levels<p,...,1>,pcg> for (d, p) in "
                       + ", ".join(f"({d}, {p})" for d, p in cases),
@@ -613,9 +678,11 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="3d-n16-q4")
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-cg", action="store_true", help="skip the outer CG iteration check")
+    ap.add_argument("--no-second", action="store_true",
+                    help="skip the second record (the 32^3 Q7 jump workload) of the default run")
     ap.add_argument("--no-tune", action="store_true",
                     help="time the default launch shape (one workgroup per patch)")
     ap.add_argument("--launch", action="append", default=[],
@@ -648,11 +715,7 @@ def main(argv=None):
               "does not have)", file=sys.stderr)
         return 2
 
-    import numpy as np
-    import torch
-
     import synth
-    from paper_2510_17785_amd import GMGSolver, PatchSmoother
 
     if args.workload == PCG_WORKLOAD:
         return bench_pcg(args)
@@ -663,11 +726,49 @@ def main(argv=None):
     w = synth.workload(args.workload)
     if w.name == "3d-n24-q8-batch":
         return bench_batch(args, w)
-    if args.train_patches is None:
-        args.train_patches = {"3d-n32-q6-learned": 100000, "3d-n32-q7-jump": 50000}.get(w.name, 6000)
-    X = synth.make_vertices(w.dim, w.n, w.alpha, w.mesh_seed)
-    mu = synth.make_coefficients(w.dim, w.n, w.mu_log10, w.coef_seed)
-    bh = synth.make_rhs(w.dim, w.n, w.p, w.rhs_seed)
+    # the 32^3 Q7 jump workload (matrix cores on the hot path) as a second
+    # record of the default run
+    second = synth.workload(SECOND_WORKLOAD) if (args.workload == DEFAULT_WORKLOAD and not args.only
+                                                  and not args.no_second) else None
+    cases = [(w, synth.make_case(w))] + ([(second, synth.make_case(second))] if second else [])
+    # the CPU baselines first, in processes forked before the GPU is touched
+    cpu = {}
+    if not args.no_cpu and not args.only:
+        for wk, (X, mu, bh) in cases:
+            cpu[wk.name] = cpu_baseline(wk, X, mu, bh)
+            print(f"# cpu oracle {wk.name}: {cpu[wk.name]['value']:.3e} DoF/s on {cpu[wk.name]['cores']} "
+                  f"cores, {cpu[wk.name]['one_core']['value']:.3e} on one", file=sys.stderr, flush=True)
+    out = None
+    for k, (wk, (X, mu, bh)) in enumerate(cases):
+        rec = bench_sweep(args, wk, X, mu, bh, secondary=k > 0)
+        if rec is None:
+            return 0
+        if wk.name in cpu:
+            rec["cpu_baseline"] = cpu[wk.name]
+        if out is None:
+            out = rec
+        else:
+            out.setdefault("secondary", []).append(rec)
+    print(json.dumps(out))
+    return 0
+
+
+def bench_sweep(args, w, X, mu, bh, secondary=False):
+    """Sweeps of one mesh workload: FP32 local solver with learned bounds (the
+    headline) against FP64 with Lanczos bounds (plus the BF16-input forms where
+    they exist), the additive variant, the outer GMG-CG iteration check and the
+    roofline of the FP32 kernel.  Returns the record (None for --only)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2510_17785_amd import GMGSolver, PatchSmoother
+
+    steps = args.steps if not secondary else max(5, min(args.steps, 10))
+    if args.train_patches is None or secondary:
+        train_patches = {"3d-n32-q6-learned": 100000, "3d-n32-q7-jump": 50000}.get(w.name, 6000)
+    else:
+        train_patches = args.train_patches
     dev = torch.device("cuda", 0)
     b = torch.tensor(bh, device=dev)
 
@@ -675,14 +776,14 @@ def main(argv=None):
     train = {}
     if args.only != "fp64":
         from paper_2510_17785_amd.learned import train_bound_network
-        Xt, mut = synth.make_random_patches(w.dim, args.train_patches, w.alpha, w.mu_log10, 4000 + w.cfg)
+        Xt, mut = synth.make_random_patches(w.dim, train_patches, w.alpha, w.mu_log10, 4000 + w.cfg)
         tr = train_bound_network(w.dim, w.p, w.levels, Xt, mut, epochs=args.train_epochs, batch=256,
                                  lr=2e-3, seed=1)
         net = tr
-        train = {"patches": args.train_patches, "epochs": args.train_epochs,
+        train = {"patches": train_patches, "epochs": args.train_epochs,
                  "label_s": tr.label_seconds, "train_s": tr.train_seconds,
                  "val_rmse_ln": [float(x) for x in tr.val_rmse], "margin_ln": tr.margin}
-        print(f"# bound network: labels {tr.label_seconds:.2f} s, training {tr.train_seconds:.2f} s, "
+        print(f"# {w.name} bound network: labels {tr.label_seconds:.2f} s, training {tr.train_seconds:.2f} s, "
               f"val rmse {tr.val_rmse}", file=sys.stderr, flush=True)
 
     def learned(S):
@@ -707,20 +808,31 @@ def main(argv=None):
             S.set_launch(int(fixed[0][1]), int(fixed[0][2]))
         elif not args.no_tune:
             S.autotune(u, b)
-        sweep_ms, per_launch, wall = time_sweeps(S, u, b, args.steps, args.warmup, torch)
+        tuned_equal = None
+        if tuple(S.launch) != (0, 0):
+            # the timed shape gives the default shape's bits (one colour)
+            shape = tuple(S.launch)
+            u1, u2 = torch.zeros_like(b), torch.zeros_like(b)
+            S.smooth_colors(u1, b, 0, 1)
+            S.set_launch(0, 0)
+            S.smooth_colors(u2, b, 0, 1)
+            S.set_launch(*shape)
+            torch.cuda.synchronize()
+            tuned_equal = bool(torch.equal(u1, u2))
+        sweep_ms, per_launch, wall = time_sweeps(S, u, b, steps, args.warmup, torch)
         res[prec] = dict(S=S, setup_s=setup_s, sweep_ms=sweep_ms, per_launch=per_launch,
                          dofs=S.n_interior_dofs, n_patches=S.n_patches, fallback=fallback,
-                         launch=list(S.launch))
-        print(f"# {prec}+{bsrc}: sweep {sweep_ms:.4f} ms, setup {setup_s:.3f} s, "
-              f"{S.n_interior_dofs * 1e3 / sweep_ms:.3e} DoF/s", file=sys.stderr, flush=True)
+                         launch=list(S.launch), tuned_equal=tuned_equal)
+        print(f"# {w.name} {prec}+{bsrc}: sweep {sweep_ms:.4f} ms, setup {setup_s:.3f} s, "
+              f"{S.n_interior_dofs * 1e3 / sweep_ms:.3e} DoF/s, launch {S.launch}", file=sys.stderr, flush=True)
 
     if args.only:
-        return 0
+        return None
     # the additive variant on the FP32 handle: residuals and local solves of
     # all patches from one iterate in one launch each, then the damped
     # scatter colour by colour
     additive = None
-    if "fp32" in res:
+    if "fp32" in res and not secondary:
         S32 = res["fp32"]["S"]
         u = torch.zeros_like(b)
         for _ in range(args.warmup):
@@ -728,11 +840,11 @@ def main(argv=None):
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        for _ in range(args.steps):
+        for _ in range(steps):
             S32.smooth_additive(u, b, 0.5)
         e1.record()
         torch.cuda.synchronize()
-        ms_add = e0.elapsed_time(e1) / args.steps
+        ms_add = e0.elapsed_time(e1) / steps
         additive = {"ms_per_step": ms_add, "value": res["fp32"]["dofs"] / (ms_add / 1e3), "unit": "DoF/s",
                     "theta": 0.5, "note": "one additive sweep (all patches from one iterate), FP32 local "
                                           "solver with learned bounds; convergence per sweep differs from "
@@ -740,14 +852,18 @@ def main(argv=None):
         print(f"# fp32 additive: sweep {ms_add:.4f} ms", file=sys.stderr, flush=True)
     cg = {}
     if not args.no_cg:
-        cg_variants = [("fp64_lanczos", "fp64", "lanczos"), ("fp32_learned", "fp32", "learned"),
-                       ("fp32_lanczos", "fp32", "lanczos")]
+        cg_variants = [("fp64_lanczos", "fp64", "lanczos"), ("fp32_learned", "fp32", "learned")]
+        if not secondary:
+            cg_variants += [("fp32_lanczos", "fp32", "lanczos")]
         if has_bf16(w):
-            cg_variants += [("bf16_learned", "bf16", "learned"), ("bf16x3_learned", "bf16x3", "learned")]
-        # one interval for every patch and level: the envelope of the Lanczos bounds
-        cg_variants += [("fp32_fixed", "fp32", "fixed")]
-        # additive sweeps (damping 2^-d) as both smoothing steps
-        cg_variants += [("fp32_learned_additive", "fp32", "learned")]
+            cg_variants += [("bf16x3_learned", "bf16x3", "learned")]
+            if not secondary:
+                cg_variants += [("bf16_learned", "bf16", "learned")]
+        if not secondary:
+            # one interval for every patch and level: the envelope of the Lanczos bounds
+            cg_variants += [("fp32_fixed", "fp32", "fixed")]
+            # additive sweeps (damping 2^-d) as both smoothing steps
+            cg_variants += [("fp32_learned_additive", "fp32", "learned")]
         for key, prec, bsrc in cg_variants:
             t0 = time.perf_counter()
             G = GMGSolver(w.dim, w.n, w.p, X, mu, levels=w.levels, precision=prec,
@@ -773,27 +889,28 @@ def main(argv=None):
             if bsrc == "learned":
                 cg[key]["lanczos_fallback_patches"] = nfb
             G.close()
-            print(f"# cg {key}: {it} iterations, relres {rel:.2e}", file=sys.stderr, flush=True)
+            print(f"# {w.name} cg {key}: {it} iterations, relres {rel:.2e}", file=sys.stderr, flush=True)
         cg["fp32_learned_within_one_of_fp64"] = (cg["fp32_learned"]["iterations"]
                                                  <= cg["fp64_lanczos"]["iterations"] + 1)
 
     r32 = res["fp32"]
     F, B = algorithmic_per_patch(w.dim, w.levels, 3, 4)
-    total_launch_ms = float(np.sum(r32["per_launch"])) / args.steps
+    total_launch_ms = float(np.sum(r32["per_launch"])) / steps
     n_launch = r32["S"].n_colors
     avg_launch_s = total_launch_ms / n_launch / 1e3
     patches_per_launch = r32["n_patches"] / n_launch
     achieved = F * patches_per_launch / avg_launch_s / 1e12
     mshare = mfma_flops_per_patch(w.dim, w.levels, 3) / F
-    peak = mixed_peak(mshare)
     value = r32["dofs"] / (r32["sweep_ms"] / 1e3)
     value64 = res["fp64"]["dofs"] / (res["fp64"]["sweep_ms"] / 1e3)
+    persistent = 0 < r32["launch"][0] < max(r32["S"].color_offsets[c + 1] - r32["S"].color_offsets[c]
+                                            for c in range(r32["S"].n_colors))
     out = {
         "metric": "patch-smoother DoF/s: FP32-MFMA+learned vs FP64 plain, same outer CG iters",
         "value": value,
         "unit": "DoF/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
         "ms_per_step": r32["sweep_ms"],
         "higher_is_better": True,
@@ -820,20 +937,23 @@ def main(argv=None):
         "additive_fp32": additive,
         "vcycles_per_s": r32["n_patches"] / (r32["sweep_ms"] / 1e3),
         "launch_shapes": {p: res[p]["launch"] for p in res},
+        "tuned_shape_equals_default_bitwise": {p: res[p]["tuned_equal"] for p in res},
         "setup_s": {f"{p}_{'lanczos' if p == 'fp64' else 'learned'}": res[p]["setup_s"] for p in res},
         "learned_bounds": dict(train, lanczos_fallback_patches=res["fp32"]["fallback"]),
         "outer_cg": cg,
         "roofline": {
             "bound": "mfma" if mshare > 0.5 else "alu",
             "achieved": achieved,
-            "peak": peak,
+            "peak": FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s",
-            "frac": achieved / peak,
+            "frac": achieved / FP32_PEAK_TFLOPS,
             "traffic": measured_traffic(w.name),
-            "peak_parts": {"valu_fp32": VALU_PEAK_TFLOPS, "mfma_fp32": MFMA_FP32_PEAK_TFLOPS,
-                           "mfma_flop_share": mshare},
+            "valu_issue_frac": achieved / mixed_peak(mshare),
+            "peak_parts": {"fp32_peak": FP32_PEAK_TFLOPS, "valu_fp32_unpacked": VALU_PEAK_TFLOPS,
+                           "mfma_fp32": MFMA_FP32_PEAK_TFLOPS, "mfma_flop_share": mshare,
+                           "issuable_peak": mixed_peak(mshare)},
             "kernel": f"patch_kernel<float,{w.dim},Levels<{','.join(map(str, w.levels))}>,smooth,"
-                      f"{'persistent' if 0 < r32['launch'][0] < max(r32['S'].color_offsets[c + 1] - r32['S'].color_offsets[c] for c in range(r32['S'].n_colors)) else 'one workgroup per patch'}>",
+                      f"{'persistent' if persistent else 'one workgroup per patch'}>",
             "launch_shape": r32["launch"],
             "algorithmic_flops_per_patch": F,
             "algorithmic_bytes_per_patch": B,
@@ -842,10 +962,9 @@ def main(argv=None):
             "hbm_frac": B * patches_per_launch / avg_launch_s / 1e9 / HBM_PEAK_GBS,
         },
     }
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, X, mu, bh)
-    print(json.dumps(out))
-    return 0
+    for r in res.values():
+        r["S"].close()
+    return out
 
 
 if __name__ == "__main__":
