@@ -21,4 +21,7 @@ so that each step can be checked against the paper by eye:
   lanczos   -- eigenvalue bounds of D^{-1}A for the Chebyshev interval
   gmg       -- h-transfers, the global V-cycle and the outer CG (Section 2, Section 4)
   mlp       -- the bound-predicting network, forward/backward/Adam in FP64
+  simplex   -- simplicial patches (3 quadrilaterals / 4 hexahedra around a
+               vertex, Section 3.2): numbering, level matrices, transfers and
+               their V-cycle
 """

@@ -16,4 +16,6 @@ from .generators import (  # noqa: F401
     make_random_patches,
     make_sphere_distorted_patches,
     make_sphere_distorted_mesh,
+    simplex_patch,
+    make_simplex_patches,
 )

@@ -391,3 +391,88 @@ def make_sphere_distorted_mesh(dim: int, n: int, delta: float, seed: int,
         move = sorted({int(vi) for c in bad for vi in corners[c] if interior[vi]})
         disp[move] = draw(len(move))
     raise RuntimeError("could not draw a mesh without degenerate cells")
+
+
+def simplex_patch(dim: int):
+    """The undeformed simplicial vertex patch (Section 3.2): a triangle cut into
+    3 quadrilaterals (2D) or a tetrahedron cut into 4 hexahedra (3D) around its
+    centroid, the patch vertex.  Unit edge length; vertices in this order:
+      2D: corners T0, T1, T2 (counter-clockwise), edge midpoints M01, M12,
+          M20, centroid C  (7 vertices);
+      3D: corners T0..T3 (positively oriented), edge midpoints M01, M02, M03,
+          M12, M13, M23, face centroids F012, F013, F023, F123, centroid C
+          (15 vertices).
+    Cell k belongs to corner Tk; its corners are listed x fastest (corner
+    sum_i b_i 2^i), corner 0 being Tk and the last one C; the edge (2D) or
+    face (3D) midpoints follow in the order that makes the cell map
+    positively oriented.  Returns (vertices (nv, dim), cells (dim + 1,
+    2^dim) int), the cell corner lists indexing the vertices."""
+    if dim == 2:
+        T = np.array([[0.0, 0.0], [1.0, 0.0], [0.5, np.sqrt(3.0) / 2.0]])
+        M = np.array([(T[0] + T[1]) / 2, (T[1] + T[2]) / 2, (T[2] + T[0]) / 2])
+        C = T.mean(axis=0)
+        V = np.vstack([T, M, C[None]])
+        cells = np.array([[k, 3 + k, 3 + (k + 2) % 3, 6] for k in range(3)], dtype=np.int64)
+        return V, cells
+    if dim != 3:
+        raise ValueError("dim must be 2 or 3")
+    T = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.5, np.sqrt(3.0) / 2.0, 0.0],
+                  [0.5, np.sqrt(3.0) / 6.0, np.sqrt(2.0 / 3.0)]])
+    pairs = [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]
+    triples = [(0, 1, 2), (0, 1, 3), (0, 2, 3), (1, 2, 3)]
+    M = np.array([(T[i] + T[j]) / 2 for i, j in pairs])
+    F = np.array([(T[i] + T[j] + T[k]) / 3 for i, j, k in triples])
+    C = T.mean(axis=0)
+    V = np.vstack([T, M, F, C[None]])
+    mid = {pr: 4 + i for i, pr in enumerate(pairs)}
+    cen = {tr: 10 + i for i, tr in enumerate(triples)}
+    cells = []
+    for k in range(4):
+        a, b, c = [j for j in range(4) if j != k]
+        e = lambda j: mid[tuple(sorted((k, j)))]
+        f = lambda i, j: cen[tuple(sorted((k, i, j)))]
+        if np.linalg.det(np.array([V[e(a)] - V[k], V[e(b)] - V[k], V[e(c)] - V[k]])) < 0:
+            b, c = c, b
+        cells.append([k, e(a), e(b), f(a, b), e(c), f(a, c), f(b, c), 14])
+    return V, np.array(cells, dtype=np.int64)
+
+
+def make_simplex_patches(dim: int, n: int, delta: float, seed: int,
+                         mu_cell: Optional[float] = None, det_floor: float = 0.01):
+    """n simplicial patches (simplex_patch) whose vertices are each moved by
+    delta h in a direction drawn uniformly on the unit sphere, h the shortest
+    edge of the undeformed patch (the centroid's edges); a patch with a cell
+    whose sampled Jacobian determinant is at most det_floor h^dim is redrawn
+    from the continuing stream (the paper excludes degenerate patches,
+    Section 3.2).  Coefficients 1, cell 0 set to mu_cell when given.
+    Returns (vertices (n, nv, dim), cells (dim + 1, 2^dim), mu (n, dim + 1))."""
+    V, cells = simplex_patch(dim)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    edges = set()
+    for c in cells:
+        for b in range(2 ** dim):
+            for i in range(dim):
+                if not (b >> i) & 1:
+                    edges.add(tuple(sorted((int(c[b]), int(c[b | (1 << i)])))))
+    h = min(float(np.linalg.norm(V[i] - V[j])) for i, j in edges)
+
+    def draw(k):
+        d = rng.standard_normal((k,) + V.shape)
+        d /= np.linalg.norm(d, axis=-1, keepdims=True)
+        return V[None] + delta * h * d
+
+    X = draw(n)
+    floor = det_floor * h ** dim
+    todo = np.arange(n)
+    for _ in range(10000):
+        dets = _min_jacobian_batched(X[todo][:, cells].reshape(-1, 2 ** dim, dim), dim).reshape(todo.size, -1)
+        todo = todo[dets.min(axis=1) <= floor]
+        if todo.size == 0:
+            break
+        X[todo] = draw(todo.size)
+    else:
+        raise RuntimeError("could not draw untangled simplicial patches")
+    mu = np.ones((n, len(cells)))
+    if mu_cell is not None:
+        mu[:, 0] = mu_cell
+    return X, cells, mu
