@@ -469,6 +469,62 @@ int pmg_mlp_fit_bounds(pmg_mlp* m, const pmg_handle* labels, const int32_t* trai
                        const int32_t* val_rows, int64_t n_val, int32_t epochs, int32_t batch, float lr,
                        double* epoch_loss, float* val_rmse, double* margin);
 
+/* Simplicial vertex patches (Section 3.2: patches of 3 quadrilaterals in 2D
+ * and 4 hexahedra in 3D around one vertex, the cells of a triangle or a
+ * tetrahedron cut around its centroid).  A patch is nv vertices (7 in 2D: 3
+ * corners, 3 edge midpoints, the centroid; 15 in 3D: 4 corners, 6 edge
+ * midpoints, 4 face centroids, the centroid) and dim + 1 multilinear cells
+ * given by their corner lists (x fastest, corner 0 a corner of the simplex,
+ * the last corner the centroid; every cell positively oriented).  The
+ * unknowns are the nodes of the conforming degree-q space off the patch
+ * boundary (a node is on the boundary when a local index is 0); they are
+ * numbered in order of first appearance over the cells in order, the nodes
+ * of a cell x fastest: 3(q-1)^2 + 3(q-1) + 1 in 2D and 4(q-1)^3 + 6(q-1)^2 +
+ * 4(q-1) + 1 in 3D.  The local solver is the p-multigrid V-cycle of
+ * Algorithm 2 with rediscretised level operators, the embedding of the
+ * degree-q space into the degree-p one as prolongation and its transpose as
+ * restriction, Chebyshev-Jacobi smoothing and the exact solve at degree 1
+ * (the centroid alone).  FP64. */
+typedef struct pmg_simplex pmg_simplex;
+/* The numbering of the unknowns at degree q for a cell list (host, no
+ * device work): codes (host, (dim+1) x (q+1)^dim) receives 2 g + f for the
+ * cell node holding unknown g (f = 1 in the first cell holding it), -1 on the
+ * boundary; count the number of unknowns.  PMG_ERR_INVALID_ARG: null
+ * pointer, dim, q outside 1..15, a corner outside the vertex list. */
+int pmg_simplex_numbering(int32_t dim, const int32_t* cells, int32_t q, int32_t* codes, int32_t* count);
+/* n patches: verts (host, n x nv x dim), cells (host, (dim+1) x 2^dim, one
+ * list for all patches), coeff (host, n x (dim+1) cell coefficients), degree
+ * p.  opts: precision PMG_FP64 and bounds PMG_BOUNDS_FIXED (intervals from
+ * pmg_simplex_set_bounds) only, else PMG_ERR_UNSUPPORTED; n_levels = 0 takes
+ * p followed by the members of 1, 3, 7, 15 below it (the paper's nested
+ * degrees); kernels exist for 2D levels (3,1), (7,3,1), (15,7,3,1) and 3D
+ * (3,1), (7,3,1) (PMG_ERR_UNSUPPORTED otherwise).  Computes the inverse
+ * diagonal of every level on the device.  PMG_ERR_INVALID_ARG: null pointer,
+ * dim, n, bad level list, non-positive coefficient, cells that do not form a
+ * simplicial patch; PMG_ERR_DEGENERATE: a cell with det J <= 0 at a corner or
+ * a Gauss point.  Synchronises opts->stream. */
+int pmg_simplex_setup(int32_t dim, int64_t n, const double* verts, const int32_t* cells, const double* coeff,
+                      int32_t p, const pmg_opts* opts, pmg_simplex** out);
+/* PMG_Q_N_PATCHES, PMG_Q_N_LEVELS, PMG_Q_DEVICE_BYTES, PMG_Q_LEVEL_DEGREE + l,
+ * PMG_Q_LEVEL_SIZE + l (unknowns per patch at level l). */
+int pmg_simplex_query(const pmg_simplex* s, int32_t what, int64_t* value);
+/* lam: host, n x (n_levels - 1) x 2 bounds of D^{-1} A per smoothed level;
+ * intervals as for pmg_set_bounds. */
+int pmg_simplex_set_bounds(pmg_simplex* s, const double* lam);
+/* out: device, n x size_level (FP64 inverse diagonal of level `level`). */
+int pmg_simplex_get_inv_diag(const pmg_simplex* s, int32_t level, double* out);
+/* y = A_level x per patch; x, y device n x size_level.  Asynchronous. */
+int pmg_simplex_apply(pmg_simplex* s, int32_t level, const double* x, double* y);
+/* d = N_MG V-cycles from zero on r per patch; device n x size_0.  Asynchronous. */
+int pmg_simplex_local_solve(pmg_simplex* s, const double* r, double* d);
+/* CG on every A_p x = b preconditioned by the V-cycle, as pmg_patch_pcg:
+ * b, x device n x size_0; iters (int32) and relres device, n each.
+ * PMG_ERR_INVALID_ARG: null pointer, bounds not set, rtol not finite and
+ * >= 0, maxit outside 0..PMG_PCG_MAXIT_LIMIT.  Asynchronous. */
+int pmg_simplex_pcg(pmg_simplex* s, const double* b, double* x, double rtol, int32_t maxit, int32_t* iters,
+                    double* relres);
+int pmg_simplex_destroy(pmg_simplex* s);
+
 const char* pmg_last_error(void);
 
 #ifdef __cplusplus

@@ -8,8 +8,9 @@ The compute path is libpmg.so (HIP kernels, built in-tree by
 streams.  Importing this package does not load the library; constructing a
 solver does, and fails loudly when it is missing.
 """
-from .api import (BoundNet, GMGSolver, PatchBatch, PatchSmoother, SmootherBatch,  # noqa: F401
-                  n_features)
+from .api import (BoundNet, GMGSolver, PatchBatch, PatchSmoother, SimplexBatch,  # noqa: F401
+                  SmootherBatch, n_features, simplex_numbering)
 from . import _lib  # noqa: F401
 
-__all__ = ["PatchSmoother", "PatchBatch", "SmootherBatch", "BoundNet", "GMGSolver", "n_features"]
+__all__ = ["PatchSmoother", "PatchBatch", "SmootherBatch", "SimplexBatch", "BoundNet", "GMGSolver",
+           "n_features", "simplex_numbering"]

@@ -65,6 +65,9 @@ EXPORTS = [
     "pmg_batch_setup", "pmg_batch_instance", "pmg_batch_smooth", "pmg_batch_smooth_eager",
     "pmg_batch_autotune", "pmg_batch_query", "pmg_batch_destroy", "pmg_mlp_save", "pmg_mlp_load",
     "pmg_mlp_fit_bounds", "pmg_patch_pcg_noalloc",
+    "pmg_simplex_numbering", "pmg_simplex_setup", "pmg_simplex_query", "pmg_simplex_set_bounds",
+    "pmg_simplex_get_inv_diag", "pmg_simplex_apply", "pmg_simplex_local_solve", "pmg_simplex_pcg",
+    "pmg_simplex_destroy",
 ]
 
 
@@ -116,6 +119,16 @@ def load() -> ctypes.CDLL:
         "pmg_patch_local_solve": [P, P, P],
         "pmg_patch_pcg": [P, P, P, ctypes.c_double, i32, P, P],
         "pmg_patch_pcg_noalloc": [P, P, P, ctypes.c_double, i32, P, P],
+        "pmg_simplex_numbering": [i32, ctypes.POINTER(i32), i32, ctypes.POINTER(i32), ctypes.POINTER(i32)],
+        "pmg_simplex_setup": [i32, ctypes.c_int64, D, ctypes.POINTER(i32), D, i32, ctypes.POINTER(PmgOpts),
+                              ctypes.POINTER(P)],
+        "pmg_simplex_query": [P, i32, ctypes.POINTER(ctypes.c_int64)],
+        "pmg_simplex_set_bounds": [P, D],
+        "pmg_simplex_get_inv_diag": [P, i32, P],
+        "pmg_simplex_apply": [P, i32, P, P],
+        "pmg_simplex_local_solve": [P, P, P],
+        "pmg_simplex_pcg": [P, P, P, ctypes.c_double, i32, P, P],
+        "pmg_simplex_destroy": [P],
         "pmg_set_smoother": [P, i32, ctypes.c_double],
         "pmg_patch_smooth_additive": [P, P, P, ctypes.c_double],
         "gmg_set_post_direction": [P, i32],

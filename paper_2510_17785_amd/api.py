@@ -554,3 +554,96 @@ class SmootherBatch:
             self.close()
         except Exception:
             pass
+
+
+def simplex_numbering(dim: int, cells, q: int):
+    """pmg_simplex_numbering: (codes (dim+1, (q+1)^dim) with 2 g + first-holder
+    flag or -1, number of unknowns); host only."""
+    lib = L.load()
+    c = np.ascontiguousarray(cells, dtype=np.int32)
+    codes = np.zeros((dim + 1, (q + 1) ** dim), dtype=np.int32)
+    cnt = ctypes.c_int32()
+    L.check(lib.pmg_simplex_numbering(int(dim), c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(q),
+                                      codes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(cnt)))
+    return codes, cnt.value
+
+
+class SimplexBatch:
+    """pmg_simplex_*: independent simplicial vertex patches (vertices (n, nv,
+    dim), cells (dim+1, 2^dim), coefficients (n, dim+1))."""
+
+    def __init__(self, dim: int, p: int, vertices, cells, coeff, levels: Sequence[int] = None,
+                 cheb_degree: int = 3, n_vcycles: int = 1, cheb_safety: float = 1.1,
+                 cheb_range: float = 15.0, stream=None):
+        self._lib = L.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("SimplexBatch needs a GPU")
+        v = np.ascontiguousarray(vertices, dtype=np.float64)
+        c = np.ascontiguousarray(cells, dtype=np.int32)
+        mu = np.ascontiguousarray(coeff, dtype=np.float64)
+        n = v.shape[0]
+        nv = 7 if dim == 2 else 15
+        if v.shape != (n, nv, dim) or c.shape != (dim + 1, 2 ** dim) or mu.shape != (n, dim + 1):
+            raise ValueError("vertices (n, nv, dim), cells (dim+1, 2^dim), coefficients (n, dim+1) expected")
+        o = _opts(levels, "fp64", cheb_degree, n_vcycles, "fixed", 12, cheb_safety, cheb_range, 0, stream)
+        h = ctypes.c_void_p()
+        L.check(self._lib.pmg_simplex_setup(int(dim), int(n), v.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                            c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                            mu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(p),
+                                            ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self.dim, self.n_patches = dim, n
+        self.n_levels = self.query(L.PMG_Q_N_LEVELS)
+        self.levels = [self.query(L.PMG_Q_LEVEL_DEGREE + l) for l in range(self.n_levels)]
+        self.level_sizes = [self.query(L.PMG_Q_LEVEL_SIZE + l) for l in range(self.n_levels)]
+
+    def query(self, what: int) -> int:
+        v = ctypes.c_int64()
+        L.check(self._lib.pmg_simplex_query(self._h, int(what), ctypes.byref(v)))
+        return v.value
+
+    def set_bounds(self, lam) -> None:
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        if lam.shape != (self.n_patches, self.n_levels - 1, 2):
+            raise ValueError("bounds must have shape (n_patches, n_levels - 1, 2)")
+        L.check(self._lib.pmg_simplex_set_bounds(self._h, lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+
+    def inv_diag(self, level: int) -> torch.Tensor:
+        out = torch.empty((self.n_patches, self.level_sizes[level]), dtype=torch.float64, device="cuda")
+        L.check(self._lib.pmg_simplex_get_inv_diag(self._h, int(level), _dptr(out)))
+        return out
+
+    def apply(self, level: int, x: torch.Tensor) -> torch.Tensor:
+        if tuple(x.shape) != (self.n_patches, self.level_sizes[level]):
+            raise ValueError("x must have shape (n_patches, level size)")
+        y = torch.empty_like(x)
+        L.check(self._lib.pmg_simplex_apply(self._h, int(level), _dptr(x), _dptr(y)))
+        return y
+
+    def local_solve(self, r: torch.Tensor) -> torch.Tensor:
+        if tuple(r.shape) != (self.n_patches, self.level_sizes[0]):
+            raise ValueError("r must have shape (n_patches, top level size)")
+        d = torch.empty_like(r)
+        L.check(self._lib.pmg_simplex_local_solve(self._h, _dptr(r), _dptr(d)))
+        return d
+
+    def pcg(self, b: torch.Tensor, rtol: float = 1e-8, maxit: int = 200):
+        if tuple(b.shape) != (self.n_patches, self.level_sizes[0]):
+            raise ValueError("b must have shape (n_patches, top level size)")
+        x = torch.empty_like(b)
+        it = torch.empty(self.n_patches, dtype=torch.int32, device=b.device)
+        rel = torch.empty(self.n_patches, dtype=torch.float64, device=b.device)
+        L.check(self._lib.pmg_simplex_pcg(self._h, _dptr(b), _dptr(x), float(rtol), int(maxit),
+                                          it.data_ptr(), _dptr(rel)))
+        return x, it, rel
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            L.check(self._lib.pmg_simplex_destroy(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

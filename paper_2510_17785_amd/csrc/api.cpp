@@ -31,6 +31,16 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
+}  // namespace
+
+// the thread-local message of pmg_last_error, for the other translation units
+int pmgi::set_error(int code, const char* msg) {
+  g_last_error = msg;
+  return code;
+}
+
+namespace {
+
 #define HIP_TRY(expr)                                                                  \
   do {                                                                                 \
     hipError_t e_ = (expr);                                                            \

@@ -133,6 +133,51 @@ struct PatchVariant {
 };
 
 const PatchVariant* find_variant(int precision, int dim, int n_levels, const int* levels);
+
+// Simplicial vertex patches (simplex_kernels.hip): a triangle cut into 3
+// quadrilaterals (2D) or a tetrahedron cut into 4 hexahedra (3D) around its
+// centroid.  Unknowns per patch at degree q: the cells' interiors, the
+// faces and edges they share, and the centroid.
+constexpr __host__ __device__ int simplex_unknowns(int dim, int q) {
+  return dim == 2 ? 3 * (q - 1) * (q - 1) + 3 * (q - 1) + 1
+                  : 4 * (q - 1) * (q - 1) * (q - 1) + 6 * (q - 1) * (q - 1) + 4 * (q - 1) + 1;
+}
+constexpr int kSimplexThreads = 256;
+enum SimplexMode : int {
+  kSimplexDiag = 0,   // setup: inverse diagonal of level `level`
+  kSimplexApply = 1,  // y = A_level x per patch
+  kSimplexSolve = 2,  // N_MG V-cycles from zero
+  kSimplexPcg = 3,    // CG preconditioned by the V-cycle
+};
+struct SimplexArgs {
+  int32_t n_patch, patch_begin;
+  const double* geo;        // per patch: (dim+1) cells x 2^dim corners x dim, then (dim+1) mu
+  int32_t geo_stride;
+  const int32_t* gat[kMaxLevels];  // per level: (dim+1) x (q+1)^dim codes 2 g + owner, -1 boundary
+  const double* tab;        // per level B, E (n x n), xg, wg (n); per transfer P1 (nf x nc)
+  const double* dinv[kMaxLevels];  // per level: n_patch_total x size
+  const double* cheb;       // n_patch_total x (L-1) x 2: theta, delta
+  int32_t cheb_degree, n_vcycles;
+  const double* in;
+  double* out;
+  int32_t level;
+  double rtol;
+  int32_t maxit;
+  double* work;             // CG: 2 x size_0 per patch
+  int32_t* iters;
+  double* relres;
+};
+struct SimplexVariant {
+  int dim, n_levels;
+  int levels[kMaxLevels];
+  hipError_t (*launch)(int mode, const SimplexArgs& a, hipStream_t s);
+  hipError_t (*prime)();
+  size_t lds_bytes;
+  int cell_nodes;
+};
+const SimplexVariant* find_simplex_variant(int dim, int n_levels, const int* levels);
+// Set the message pmg_last_error returns; returns code.
+int set_error(int code, const char* msg);
 // Features of every patch for the bound-predicting network (n x nf floats).
 hipError_t launch_features(int dim, const PatchArgs& a, int n_patch, float* out, hipStream_t s);
 // Fill the per-degree 1D tables in constant memory of the current device.

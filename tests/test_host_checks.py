@@ -134,3 +134,41 @@ def test_independent_patch_and_batch_counts_checked():
     assert st == L.PMG_ERR_INVALID_ARG and "patch 1 cell 3" in lib.pmg_last_error().decode()
     st = lib.pmg_batch_setup(None, None, None, 0, ctypes.byref(o), ctypes.byref(h))
     assert st == L.PMG_ERR_INVALID_ARG and h.value is None
+
+
+@pytest.mark.parametrize("dim,q", [(2, 1), (2, 2), (2, 3), (2, 7), (2, 15), (3, 1), (3, 2), (3, 3), (3, 5), (3, 7)])
+def test_simplex_numbering_matches_the_oracle(dim, q):
+    # the library numbers the unknowns of a simplicial patch topologically
+    # (entities named by their vertices), the oracle by node position on a
+    # distorted patch: both must give the same unknown for every cell node
+    # and the same first holder (no GPU: host code only)
+    import synth
+    from oracle import simplex
+    from paper_2510_17785_amd import simplex_numbering
+    X, cells, _ = synth.make_simplex_patches(dim, 1, 0.2, 11)
+    codes, count = simplex_numbering(dim, cells, q)
+    gather, n = simplex.numbering(X[0], cells, q)
+    assert count == n
+    assert np.array_equal(np.where(codes >= 0, codes >> 1, -1), gather)
+    first = np.zeros_like(codes)
+    seen = set()
+    for c in range(dim + 1):
+        for a in range(codes.shape[1]):
+            g = gather[c, a]
+            if g >= 0 and g not in seen:
+                seen.add(g)
+                first[c, a] = 1
+    assert np.array_equal(np.where(codes >= 0, codes & 1, 0), first)
+
+
+def test_simplex_numbering_rejects_bad_cells():
+    import synth
+    from paper_2510_17785_amd import simplex_numbering
+    from paper_2510_17785_amd._lib import PmgError
+    _, cells = synth.simplex_patch(2)
+    bad = cells.copy()
+    bad[0, 0] = 9
+    with pytest.raises(PmgError):
+        simplex_numbering(2, bad, 3)
+    with pytest.raises(PmgError):
+        simplex_numbering(2, cells, 0)
