@@ -528,7 +528,9 @@ def bench_study(args):
             print(f"# study {dim}D p={p} {sm}: {len(r['X'])} patches, {r['seconds'] * 1e3:.2f} ms, "
                   + "; ".join(f"{row['sweep']} {row['value']:g}: "
                               + (f"{row['mean_iterations']:.2f}" if row["mean_iterations"] is not None else "-")
-                              + (f" ({row['not_converged']} not converged)" if row["not_converged"] else "")
+                              + (f" ({row['not_converged']} not converged: sentinel mean "
+                                 f"{row['mean_with_sentinel']:.0f}, off the paper's axes)"
+                                 if row["not_converged"] else "")
                               for row in r["rows"]),
                   file=sys.stderr, flush=True)
     achieved = flops / total_s / 1e12

@@ -214,10 +214,11 @@ int pmg_patch_pcg_noalloc(pmg_handle* h, const double* b, double* x, double rtol
  * corrections added colour by colour so that the sums are deterministic.
  * u, b: device global vectors as for pmg_patch_smooth.  Work buffers of
  * 2 x n_patches x (2p-1)^dim FP64 are allocated at the first call and kept
- * until pmg_patch_destroy.  Mesh handles of interior-vertex patches only
- * (PMG_ERR_UNSUPPORTED for independent patches or PMG_PATCH_WITH_BOUNDARY);
- * PMG_ERR_INVALID_ARG: null pointer, theta not finite and > 0, bounds not
- * set.  Asynchronous on the handle's stream. */
+ * until pmg_patch_destroy.  Mesh handles (PMG_ERR_UNSUPPORTED for
+ * independent patches); with PMG_PATCH_WITH_BOUNDARY the masked nodes of the
+ * boundary-vertex patches are not scattered.  PMG_ERR_INVALID_ARG: null
+ * pointer, theta not finite and > 0, bounds not set.  Asynchronous on the
+ * handle's stream. */
 int pmg_patch_smooth_additive(pmg_handle* h, double* u, const double* b, double theta);
 
 /* Local smoothers of the V-cycle (Section 3.1, smoothers). */

@@ -1393,8 +1393,6 @@ int pmg_patch_smooth_additive(pmg_handle* h, double* u, const double* b, double 
   if (!h || !u || !b) return fail(PMG_ERR_INVALID_ARG, "null argument");
   if (!(theta > 0.0) || !std::isfinite(theta)) return fail(PMG_ERR_INVALID_ARG, "theta must be finite and > 0");
   if (h->patch_geo) return fail(PMG_ERR_UNSUPPORTED, "independent patches have no global vector to smooth");
-  if (h->with_boundary)
-    return fail(PMG_ERR_UNSUPPORTED, "the additive smoother is available for interior-vertex patches only");
   const int64_t n0 = h->level_size(0);
   if (!h->add_buf) PMG_TRY(dev_alloc(&h->add_buf, (size_t)2 * h->n_patches * n0 * sizeof(double), &h->device_bytes));
   double* r = h->add_buf;

@@ -507,9 +507,11 @@ __global__ void patch_scatter_kernel(int N, int p, const int32_t* vertex, int be
   const int v = vertex[j];
   const int vx = v % N1, vy = (v / N1) % N1, vz = DIM == 3 ? v / (N1 * N1) : 0;
   const int x = i % mi + 1, y = (i / mi) % mi + 1, z = DIM == 3 ? i / (mi * mi) + 1 : 0;
-  int64_t g = (int64_t)(vx - 1) * p + x + M * ((int64_t)(vy - 1) * p + y);
-  if (DIM == 3) g += M * M * ((int64_t)(vz - 1) * p + z);
-  u[g] += theta * d[(int64_t)j * n0 + i];
+  const int64_t gx = (int64_t)(vx - 1) * p + x, gy = (int64_t)(vy - 1) * p + y,
+                gz = DIM == 3 ? (int64_t)(vz - 1) * p + z : 0;
+  // nodes of a boundary-vertex patch on or beyond the boundary are masked
+  if (gx <= 0 || gx >= M - 1 || gy <= 0 || gy >= M - 1 || (DIM == 3 && (gz <= 0 || gz >= M - 1))) return;
+  u[gx + M * gy + M * M * gz] += theta * d[(int64_t)j * n0 + i];
 }
 
 hipError_t launch_patch_scatter(int dim, int N, int p, const int32_t* vertex, int begin, int count,

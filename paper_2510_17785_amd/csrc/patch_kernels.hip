@@ -467,6 +467,14 @@ struct Ctx {
   bool geo_needed = true;      // the patch geometry is used (Jacobian or metric)
   const T* fdm = nullptr;  // Cartesian-reinforced smoother tables (kModePcgCart, kModeSmoothCart)
   double omega = 0;
+  // FP64 inverse of the coarsest level's 1 x 1 matrix (interior patches of
+  // FP32 handles): the coarse solve runs in FP64 in every precision
+  double coarse_inv = 0;
+  // d = A^{-1} r on the coarsest level of an interior patch
+  __device__ T coarse_solve(T r, T dinv) const {
+    if constexpr (sizeof(T) == 8) return dinv * r;
+    else return T(coarse_inv * double(r));
+  }
   __device__ T* X() const { return lds + Lay::X_off; }
   __device__ T* Out() const { return lds + Lay::Out_off; }
   __device__ T* abuf() const { return lds + Lay::abuf_off; }
@@ -1810,7 +1818,7 @@ __device__ void vcycle_small(const Ctx<T, DIM, LV>& c, int k) {
   const LDSP T* r = lds_cast(c.r(L));
   const LDSP T* dinv = lds_cast(c.dinv(L));
   if constexpr (L == LV::count - 1) {
-    if (i == 0) d[0] = dinv[0] * r[0];
+    if (i == 0) d[0] = c.coarse_solve(r[0], dinv[0]);
     wave_sync();
     return;
   } else {
@@ -2036,7 +2044,7 @@ __device__ void vcycle(const Ctx<T, DIM, LV>& c, int k, bool d_zero) {
     T* d = c.d(L);
     const T* r = c.r(L);
     const T* dinv = c.dinv(L);
-    if (tid == 0) d[0] = dinv[0] * r[0];
+    if (tid == 0) d[0] = c.coarse_solve(r[0], dinv[0]);
     __syncthreads();
   } else {
     if constexpr (L + 2 == LV::count) {
@@ -2468,6 +2476,7 @@ __device__ __forceinline__ void patch_update(const PatchArgs& a, Ctx<T, DIM, LV>
   const int pf = patch_flags<DIM>(a, patch);
   c.pf = pf;
   c.trunc = nullptr;
+  if constexpr (sizeof(T) == 4) c.coarse_inv = a.invdiag64[LV::count - 1][patch];
   if (pf && a.trunc_index) {
     const int k = a.trunc_index[patch];
     // one slot holds the largest unmasked box, a face patch's

@@ -25,18 +25,22 @@ def dev():
     return torch.device("cuda", 0)
 
 
+@pytest.mark.parametrize("boundary", [False, True])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("name,n,p,levels", [("2d-n8-q3", 6, 3, (3, 2, 1)), ("3d-n16-q4", 4, 4, (4, 2, 1)),
                                              ("3d-n32-q7-jump", 3, 7, (7, 3, 1))])
-def test_additive_sweep_matches_oracle(dev, name, n, p, levels, precision):
+def test_additive_sweep_matches_oracle(dev, name, n, p, levels, precision, boundary):
     from paper_2510_17785_amd import PatchSmoother
     w, p, levels, X, mu, b = case(name, n, p, levels)
-    S = PatchSmoother(w.dim, n, p, X, mu, levels=levels, precision=precision)
+    S = PatchSmoother(w.dim, n, p, X, mu, levels=levels, precision=precision, with_boundary=boundary)
     u0 = np.random.default_rng(7).standard_normal(b.shape) * fem.dirichlet_mask(w.dim, n, p)
     u = torch.tensor(u0, device=dev)
     S.smooth_additive(u, torch.tensor(b, device=dev), 0.6)
-    ref = OracleSmoother(fem.Mesh(w.dim, n, X, mu), p, levels).additive_sweep(u0, b, 0.6)
+    ref = OracleSmoother(fem.Mesh(w.dim, n, X, mu), p, levels,
+                         with_boundary=boundary).additive_sweep(u0, b, 0.6)
     assert rel_err(u.cpu().numpy() - u0, ref - u0) <= TOL[precision]
+    # Dirichlet nodes stay zero
+    assert np.all(u.cpu().numpy()[fem.dirichlet_mask(w.dim, n, p) == 0] == 0)
 
 
 def test_additive_rejects(dev):
@@ -49,9 +53,7 @@ def test_additive_rejects(dev):
     for theta in (0.0, -1.0, float("nan")):
         with pytest.raises(PmgError):
             S.smooth_additive(u, bt, theta)
-    Sb = PatchSmoother(w.dim, 4, p, X, mu, levels=levels, with_boundary=True)
-    with pytest.raises(PmgError, match="interior"):
-        Sb.smooth_additive(u, bt, 0.5)
+
 
 
 @pytest.mark.parametrize("dim,n,p,levels,theta", [(2, 8, 3, (3, 1), 0.25), (3, 4, 2, (2, 1), 0.125)])

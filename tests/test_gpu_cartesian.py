@@ -110,3 +110,11 @@ def test_trends_2d(dev, p):
     for m in jumps[1:]:   # high contrast: most runs fail, where Jacobi converges in all
         assert cart[("jump", m)]["not_converged"] >= 5
         assert jac[("jump", m)]["not_converged"] == 0
+    # the paper's means: a failed run enters with the sentinel, so the point
+    # leaves the axes; without failures they are the plain means
+    from paper_2510_17785_amd.study import SENTINEL_ITERATIONS
+    for r in list(cart.values()) + list(jac.values()):
+        if r["not_converged"]:
+            assert r["mean_with_sentinel"] >= SENTINEL_ITERATIONS * r["not_converged"] / r["patches"]
+        else:
+            assert r["mean_with_sentinel"] == pytest.approx(r["mean_iterations"], rel=1e-12)
