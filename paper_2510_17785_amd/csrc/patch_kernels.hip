@@ -254,6 +254,12 @@ struct Layout {
   // else global scratch
   static constexpr bool vec_in_lds =
       all_fit || top_vec_fit || vec_over_G || (!cache_G && (base_total + vec_total) * sz <= kBudget);
+  // FP32 slab-form tops that keep the level vectors in LDS instead of the
+  // metric read the top level's metric from the setup's copy in global
+  // memory (per patch NG x npts(0) values, the LDS layout) when the handle
+  // has one, instead of recomputing it at every Gauss point
+  static constexpr bool G_global = vec_over_G && npts(0) > 0;
+  static constexpr int G_glob_elems = G_global ? NG * npts(0) : 0;
   static constexpr int G_off = base_total;
   static constexpr int vec_off = base_total + G_total;
   static constexpr int dense_off = round_up(vec_off + (vec_in_lds ? vec_total : 0), 4);
@@ -433,6 +439,7 @@ struct Ctx {
   const double* trunc = nullptr;
   int pf = 0;  // boundary flags of the patch (see patch_flags)
   const T* dglob[kMaxLevels] = {nullptr};  // this patch's dense matrices in global memory
+  const T* Gg = nullptr;  // this patch's top-level metric in global memory (Layout::G_global)
   __device__ const T* gB(int l) const { return gtab + l * kTabLevelStride; }
   __device__ const T* gDc(int l) const {
     const int n = LV::q[l] + 1;
@@ -883,7 +890,9 @@ __device__ __forceinline__ void mm_phase(int ncols, MatF mat, InF in, OutF out) 
 // The slab-form operator (apply3) with its six interpolation contractions
 // (x, y, z and their transposes) on the matrix cores; the collocation
 // derivatives and the flux G grad stay in FP32 on the vector ALUs.
-template <int Q, bool CACHE, int MODE>
+// GM: where the metric comes from (0 recomputed at every Gauss point from
+// the Jacobian coefficients, 1 the LDS cache Gc, 2 the global copy Gg).
+template <int Q, int GM, int MODE>
 __device__ __noinline__ void apply3mm(const LDSP float* __restrict__ X, LDSP float* __restrict__ Out,
                                       LDSP float* __restrict__ ab, const LDSP float* __restrict__ Bt,
                                       const LDSP float* __restrict__ Dc,
@@ -891,7 +900,8 @@ __device__ __noinline__ void apply3mm(const LDSP float* __restrict__ X, LDSP flo
                                       const LDSP float* __restrict__ wg,
                                       const LDSP float* __restrict__ jc,
                                       const LDSP float* __restrict__ mu,
-                                      const LDSP float* __restrict__ Gc) {
+                                      const LDSP float* __restrict__ Gc,
+                                      const float* __restrict__ Gg) {
   using T = float;
   using SH = Sh<3, Q>;
   constexpr int n = SH::n, m = SH::m, mi = SH::mi, NQ = SH::NQ, S = SH::S, NQ2 = NQ * NQ;
@@ -952,10 +962,14 @@ __device__ __noinline__ void apply3mm(const LDSP float* __restrict__ X, LDSP flo
         gz += dz[a] * czr[a * NQ2];
       }
       T G[6];
-      if constexpr (CACHE) {
+      if constexpr (GM == 1) {
         const int gp = cz * S + idx;
 #pragma unroll
         for (int c = 0; c < 6; ++c) G[c] = Gc[c * 2 * S + gp];
+      } else if constexpr (GM == 2) {
+        const int gp = cz * S + idx;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) G[c] = Gg[c * 2 * S + gp];
       } else {
         const int cell = cz * 4 + cy * 2 + cx;
         metric3c<T>(jc + cell * 36, xg[kx], xg[ky], xg[kz], mu[cell] * wg[kx] * wg[ky] * wg[kz], G);
@@ -1425,9 +1439,15 @@ __device__ __forceinline__ void apply_level(const Ctx<T, DIM, LV>& c) {
     static_assert(4 * Sh<3, Q>::S <= Layout<T, DIM, LV>::abuf_elems,
                   "slab buffers exceed the work area");
     constexpr int MODE = !LV::bf16 ? kMmF32 : (LV::split ? kMmBf16x3 : kMmBf16);
-    apply3mm<Q, CACHE, MODE>(lds_cast(c.X()), lds_cast(c.Out()), lds_cast(c.abuf()), lds_cast(c.tabB(L)),
-                       lds_cast(c.tabDc(L)), lds_cast(c.tabXg(L)), lds_cast(c.tabWg(L)),
-                       lds_cast(c.jc()), lds_cast(c.mu()), lds_cast(c.Gc(L)));
+    if (Layout<T, DIM, LV>::G_global && c.Gg)
+      apply3mm<Q, 2, MODE>(lds_cast(c.X()), lds_cast(c.Out()), lds_cast(c.abuf()), lds_cast(c.tabB(L)),
+                           lds_cast(c.tabDc(L)), lds_cast(c.tabXg(L)), lds_cast(c.tabWg(L)),
+                           lds_cast(c.jc()), lds_cast(c.mu()), lds_cast(c.Gc(L)), c.Gg);
+    else
+      apply3mm<Q, CACHE ? 1 : 0, MODE>(lds_cast(c.X()), lds_cast(c.Out()), lds_cast(c.abuf()),
+                                       lds_cast(c.tabB(L)), lds_cast(c.tabDc(L)), lds_cast(c.tabXg(L)),
+                                       lds_cast(c.tabWg(L)), lds_cast(c.jc()), lds_cast(c.mu()),
+                                       lds_cast(c.Gc(L)), nullptr);
   } else if constexpr (DIM == 3) {
     static_assert(4 * Sh<3, Q>::S <= Layout<T, DIM, LV>::abuf_elems,
                   "slab buffers exceed the work area");
@@ -2539,6 +2559,9 @@ __device__ __forceinline__ void patch_update(const PatchArgs& a, Ctx<T, DIM, LV>
     }
   }
   c.metric_loaded = Lay::cache_G && MODE != kModeMetric && a.metric != nullptr;
+  c.Gg = (Lay::G_global && MODE != kModeMetric && a.metric)
+             ? tptr<T>(a.metric) + (int64_t)patch * Lay::G_glob_elems
+             : nullptr;
   // with the metric loaded, the geometry only serves levels that recompute
   // theirs (prepare_geometry computes the Jacobian coefficients for those)
   c.geo_needed = !c.metric_loaded || Lay::needs_jc || MODE == kModeApply;
@@ -2556,6 +2579,21 @@ __device__ __forceinline__ void patch_update(const PatchArgs& a, Ctx<T, DIM, LV>
       T* dst = reinterpret_cast<T*>(a.metric_out) + (int64_t)patch * Lay::G_total;
       const T* src = c.lds + Lay::G_off;
       for (int i = tid; i < Lay::G_total; i += NT<T>) dst[i] = src[i];
+    } else if constexpr (Lay::G_global && DIM == 3) {
+      // the top level's metric at every Gauss point, in the LDS-cache layout
+      constexpr int n = LV::q[0] + 1, NQ = 2 * n, NP = Lay::npts(0);
+      T* dst = reinterpret_cast<T*>(a.metric_out) + (int64_t)patch * Lay::G_glob_elems;
+      const T* xg = c.tabXg(0);
+      const T* wg = c.tabWg(0);
+      for (int pt = tid; pt < NP; pt += NT<T>) {
+        const int QX = pt % NQ, QY = (pt / NQ) % NQ, QZ = pt / (NQ * NQ);
+        const int cx = QX >= n, cy = QY >= n, cz = QZ >= n;
+        const int kx = QX - cx * n, ky = QY - cy * n, kz = QZ - cz * n;
+        const int cell = cz * 4 + cy * 2 + cx;
+        T G[6];
+        metric3c<T>(c.jc() + cell * 36, xg[kx], xg[ky], xg[kz], c.mu()[cell] * wg[kx] * wg[ky] * wg[kz], G);
+        for (int g = 0; g < 6; ++g) dst[g * NP + pt] = G[g];
+      }
     }
     return;
   } else if constexpr (MODE == kModePcg || MODE == kModePcgCart) {
@@ -3176,7 +3214,9 @@ struct Variant {
   using Lay = Layout<T, DIM, LV>;
   static size_t lds_bytes(int) { return (size_t)Lay::lds_elems * sizeof(T); }
   static int64_t vec_elems() { return Lay::vec_in_lds ? 0 : (int64_t)Lay::vec_total; }
-  static int64_t metric_elems() { return Lay::cache_G ? (int64_t)Lay::G_total : 0; }
+  static int64_t metric_elems() {
+    return Lay::cache_G ? (int64_t)Lay::G_total : (int64_t)Lay::G_glob_elems;
+  }
   template <int MODE, bool PERSIST>
   static hipError_t go(const PatchArgs& a, int g, size_t lds, hipStream_t s) {
     hipError_t e = allow_lds(patch_kernel<T, DIM, LV, MODE, PERSIST>, lds);
