@@ -57,6 +57,13 @@ template <typename T>
 __device__ __forceinline__ const LDSP T* lds_cast(const T* p) {
   return (const LDSP T*)p;
 }
+// the same for global memory: global (not flat) loads, which count against
+// the vector-memory counter only, so waits for LDS reads do not wait for them
+#define GLBP __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const GLBP T* glb_cast(const T* p) {
+  return (const GLBP T*)p;
+}
 
 // Wavefront-level sync: the LDS writes of this wavefront's lanes are visible
 // to its other lanes afterwards (no workgroup barrier).
@@ -901,7 +908,7 @@ __device__ __noinline__ void apply3mm(const LDSP float* __restrict__ X, LDSP flo
                                       const LDSP float* __restrict__ jc,
                                       const LDSP float* __restrict__ mu,
                                       const LDSP float* __restrict__ Gc,
-                                      const float* __restrict__ Gg) {
+                                      const GLBP float* __restrict__ Gg) {
   using T = float;
   using SH = Sh<3, Q>;
   constexpr int n = SH::n, m = SH::m, mi = SH::mi, NQ = SH::NQ, S = SH::S, NQ2 = NQ * NQ;
@@ -920,6 +927,19 @@ __device__ __noinline__ void apply3mm(const LDSP float* __restrict__ X, LDSP flo
   auto Bc = [&](int k, int a) -> T { return (k < n && a < n) ? Bt[k * n + a] : T(0); };
 #pragma unroll 1
   for (int cz = 0; cz < 2; ++cz) {
+    // the slab's metric from global memory, loaded before the contractions
+    // so that its latency hides behind them
+    constexpr int kGIt = GM == 2 ? (S + NT<T> - 1) / NT<T> : 1;
+    T Gp[kGIt][6];
+    if constexpr (GM == 2) {
+#pragma unroll
+      for (int it = 0; it < kGIt; ++it) {
+        const int idx = tid + it * NT<T>;
+        const int gp = cz * S + (idx < S ? idx : 0);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) Gp[it][c] = Gg[c * 2 * S + gp];
+      }
+    }
     // x: A[zl][y][QX] = sum_x Bp[QX][x] X[cz Q + zl][y][x]
     mm_phase<MODE>(
         n * m, Bp,
@@ -944,8 +964,7 @@ __device__ __noinline__ void apply3mm(const LDSP float* __restrict__ X, LDSP flo
         });
     __syncthreads();
     // reference gradients by collocation, then the flux G grad (FP32)
-#pragma unroll 1
-    for (int idx = tid; idx < S; idx += NT<T>) {
+    auto flux = [&](int idx, auto metric) {
       const int QX = idx % NQ, t = idx / NQ, QY = t % NQ, kz = t / NQ;
       const int cx = QX >= n, kx = QX - cx * n, cy = QY >= n, ky = QY - cy * n;
       const LDSP T* dx = Dc + kx * n;
@@ -962,21 +981,34 @@ __device__ __noinline__ void apply3mm(const LDSP float* __restrict__ X, LDSP flo
         gz += dz[a] * czr[a * NQ2];
       }
       T G[6];
-      if constexpr (GM == 1) {
-        const int gp = cz * S + idx;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) G[c] = Gc[c * 2 * S + gp];
-      } else if constexpr (GM == 2) {
-        const int gp = cz * S + idx;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) G[c] = Gg[c * 2 * S + gp];
-      } else {
-        const int cell = cz * 4 + cy * 2 + cx;
-        metric3c<T>(jc + cell * 36, xg[kx], xg[ky], xg[kz], mu[cell] * wg[kx] * wg[ky] * wg[kz], G);
-      }
+      metric(G, cx, cy, kx, ky, kz);
       A[idx] = G[0] * gx + G[1] * gy + G[2] * gz;
       Bf[idx] = G[1] * gx + G[3] * gy + G[4] * gz;
       Dd[idx] = G[2] * gx + G[4] * gy + G[5] * gz;
+    };
+    if constexpr (GM == 2) {
+#pragma unroll
+      for (int it = 0; it < kGIt; ++it) {
+        const int idx = tid + it * NT<T>;
+        if (idx < S)
+          flux(idx, [&](T* G, int, int, int, int, int) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) G[c] = Gp[it][c];
+          });
+      }
+    } else {
+#pragma unroll 1
+      for (int idx = tid; idx < S; idx += NT<T>)
+        flux(idx, [&](T* G, int cx, int cy, int kx, int ky, int kz) {
+          if constexpr (GM == 1) {
+            const int gp = cz * S + idx;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) G[c] = Gc[c * 2 * S + gp];
+          } else {
+            const int cell = cz * 4 + cy * 2 + cx;
+            metric3c<T>(jc + cell * 36, xg[kx], xg[ky], xg[kz], mu[cell] * wg[kx] * wg[ky] * wg[kz], G);
+          }
+        });
     }
     __syncthreads();
     // transposed collocation: C = Dc^T F (FP32)
@@ -1442,7 +1474,7 @@ __device__ __forceinline__ void apply_level(const Ctx<T, DIM, LV>& c) {
     if (Layout<T, DIM, LV>::G_global && c.Gg)
       apply3mm<Q, 2, MODE>(lds_cast(c.X()), lds_cast(c.Out()), lds_cast(c.abuf()), lds_cast(c.tabB(L)),
                            lds_cast(c.tabDc(L)), lds_cast(c.tabXg(L)), lds_cast(c.tabWg(L)),
-                           lds_cast(c.jc()), lds_cast(c.mu()), lds_cast(c.Gc(L)), c.Gg);
+                           lds_cast(c.jc()), lds_cast(c.mu()), lds_cast(c.Gc(L)), glb_cast(c.Gg));
     else
       apply3mm<Q, CACHE ? 1 : 0, MODE>(lds_cast(c.X()), lds_cast(c.Out()), lds_cast(c.abuf()),
                                        lds_cast(c.tabB(L)), lds_cast(c.tabDc(L)), lds_cast(c.tabXg(L)),
