@@ -899,8 +899,14 @@ __device__ __forceinline__ void mm_phase(int ncols, MatF mat, InF in, OutF out) 
 // derivatives and the flux G grad stay in FP32 on the vector ALUs.
 // GM: where the metric comes from (0 recomputed at every Gauss point from
 // the Jacobian coefficients, 1 the LDS cache Gc, 2 the global copy Gg).
-template <int Q, int GM, int MODE>
-__device__ __noinline__ void apply3mm(const LDSP float* __restrict__ X, LDSP float* __restrict__ Out,
+// VIN: the input is an interior vector with a zero patch boundary (read in
+// place), else the closure values X.  epi(i, (A x)_i) is called once per
+// interior row, in the last phase: rows of the z-plane that both cell layers
+// share are summed in Out first (at their own rows).  An epilogue may
+// change the input vector at row i: the second layer reads only its own
+// planes, none of which the first layer's epilogue calls touch.
+template <int Q, int GM, int MODE, bool VIN, class Epi>
+__device__ __noinline__ void apply3mm(const LDSP float* __restrict__ X, Epi epi, LDSP float* __restrict__ Out,
                                       LDSP float* __restrict__ ab, const LDSP float* __restrict__ Bt,
                                       const LDSP float* __restrict__ Dc,
                                       const LDSP float* __restrict__ xg,
@@ -943,7 +949,15 @@ __device__ __noinline__ void apply3mm(const LDSP float* __restrict__ X, LDSP flo
     // x: A[zl][y][QX] = sum_x Bp[QX][x] X[cz Q + zl][y][x]
     mm_phase<MODE>(
         n * m, Bp,
-        [&](int x, int j) -> T { return x < m ? X[(cz * Q + j / m) * m * m + (j % m) * m + x] : T(0); },
+        [&](int x, int j) -> T {
+          const int zc = cz * Q + j / m, y = j % m;
+          if constexpr (VIN) {
+            const bool in = x >= 1 && x < m - 1 && y >= 1 && y < m - 1 && zc >= 1 && zc < m - 1;
+            return in ? X[((zc - 1) * mi + (y - 1)) * mi + (x - 1)] : T(0);
+          } else {
+            return x < m ? X[zc * m * m + y * m + x] : T(0);
+          }
+        },
         [&](int QX, int j, T v) {
           if (QX < NQ) A[j * NQ + QX] = v;
         });
@@ -1055,11 +1069,14 @@ __device__ __noinline__ void apply3mm(const LDSP float* __restrict__ X, LDSP flo
         [&](int xi, int j, T v) {
           if (xi < mi) {
             const int zl = zl0 + j / mi, yi = j % mi;
-            LDSP T* o = Out + ((cz * Q + zl - 1) * mi + yi) * mi + xi;
-            if (cz == 1 && zl == 0)
-              *o += v;
-            else
+            const int zz = cz * Q + zl - 1, row = (zz * mi + yi) * mi + xi;
+            LDSP T* o = Out + row;  // rows of the shared plane zz = Q - 1
+            if (zz != Q - 1)
+              epi(row, v);
+            else if (cz == 0)
               *o = v;
+            else
+              epi(row, *o + v);
           }
         });
     __syncthreads();
@@ -1449,6 +1466,32 @@ __device__ __noinline__ void apply2(const T* __restrict__ X, T* __restrict__ Out
   }
 }
 
+// FP32 slab-form level on the matrix cores (apply3mm): input x (closure
+// values, or with VIN an interior vector with zero boundary), epi(i, (A x)_i)
+template <typename T, int DIM, class LV, int L>
+constexpr bool slab_mm() {
+  return DIM == 3 && std::is_same<T, float>::value && L == 0 && LV::q[L] <= 7 &&
+         !Layout<T, DIM, LV>::use_seg(L) && !Layout<T, DIM, LV>::use_quarter(L);
+}
+template <typename T, int DIM, class LV, int L, bool VIN, class Epi>
+__device__ __forceinline__ void apply_slab_mm(const Ctx<T, DIM, LV>& c, const T* x, Epi epi) {
+  if constexpr (slab_mm<T, DIM, LV, L>()) {
+    constexpr int Q = LV::q[L];
+    static_assert(4 * Sh<3, Q>::S <= Layout<T, DIM, LV>::abuf_elems, "slab buffers exceed the work area");
+    constexpr int MODE = !LV::bf16 ? kMmF32 : (LV::split ? kMmBf16x3 : kMmBf16);
+    constexpr int GM0 = Layout<T, DIM, LV>::cache_level(L) ? 1 : 0;
+    if (Layout<T, DIM, LV>::G_global && c.Gg)
+      apply3mm<Q, 2, MODE, VIN>(lds_cast(x), epi, lds_cast(c.Out()), lds_cast(c.abuf()), lds_cast(c.tabB(L)),
+                                lds_cast(c.tabDc(L)), lds_cast(c.tabXg(L)), lds_cast(c.tabWg(L)),
+                                lds_cast(c.jc()), lds_cast(c.mu()), lds_cast(c.Gc(L)), glb_cast(c.Gg));
+    else
+      apply3mm<Q, GM0, MODE, VIN>(lds_cast(x), epi, lds_cast(c.Out()), lds_cast(c.abuf()),
+                                  lds_cast(c.tabB(L)), lds_cast(c.tabDc(L)), lds_cast(c.tabXg(L)),
+                                  lds_cast(c.tabWg(L)), lds_cast(c.jc()), lds_cast(c.mu()), lds_cast(c.Gc(L)),
+                                  nullptr);
+  }
+}
+
 template <typename T, int DIM, class LV, int L>
 __device__ __forceinline__ void apply_level(const Ctx<T, DIM, LV>& c) {
   constexpr int Q = LV::q[L];
@@ -1470,16 +1513,7 @@ __device__ __forceinline__ void apply_level(const Ctx<T, DIM, LV>& c) {
     // (BF16 or split-BF16 operands for those variants, FP32 operands else)
     static_assert(4 * Sh<3, Q>::S <= Layout<T, DIM, LV>::abuf_elems,
                   "slab buffers exceed the work area");
-    constexpr int MODE = !LV::bf16 ? kMmF32 : (LV::split ? kMmBf16x3 : kMmBf16);
-    if (Layout<T, DIM, LV>::G_global && c.Gg)
-      apply3mm<Q, 2, MODE>(lds_cast(c.X()), lds_cast(c.Out()), lds_cast(c.abuf()), lds_cast(c.tabB(L)),
-                           lds_cast(c.tabDc(L)), lds_cast(c.tabXg(L)), lds_cast(c.tabWg(L)),
-                           lds_cast(c.jc()), lds_cast(c.mu()), lds_cast(c.Gc(L)), glb_cast(c.Gg));
-    else
-      apply3mm<Q, CACHE ? 1 : 0, MODE>(lds_cast(c.X()), lds_cast(c.Out()), lds_cast(c.abuf()),
-                                       lds_cast(c.tabB(L)), lds_cast(c.tabDc(L)), lds_cast(c.tabXg(L)),
-                                       lds_cast(c.tabWg(L)), lds_cast(c.jc()), lds_cast(c.mu()),
-                                       lds_cast(c.Gc(L)), nullptr);
+    apply_slab_mm<T, DIM, LV, L, false>(c, c.X(), EpiStore<T, LDSP T*>{lds_cast(c.Out())});
   } else if constexpr (DIM == 3) {
     static_assert(4 * Sh<3, Q>::S <= Layout<T, DIM, LV>::abuf_elems,
                   "slab buffers exceed the work area");
@@ -1634,6 +1668,14 @@ __device__ __forceinline__ void apply_vec_epi(const Ctx<T, DIM, LV>& c, const T*
     apply3seg<T, Q, false, Lay::cache_level(L)>(lds_cast(v), epi, lds_cast(c.abuf()), lds_cast(c.tabB(L)),
                                          lds_cast(c.tabDc(L)), lds_cast(c.jc()), lds_cast(c.mu()),
                                          lds_cast(c.Gc(L)));
+  } else if constexpr (slab_mm<T, DIM, LV, L>() && Lay::vec_in_lds) {
+    // input read in place; the epilogue in a pass of its own (in the last
+    // phase it would raise the operator's registers past the file)
+    apply_slab_mm<T, DIM, LV, L, true>(c, v, EpiStore<T, LDSP T*>{lds_cast(c.Out())});
+    constexpr int N = Lay::level_size(L);
+#pragma unroll 1
+    for (int i = threadIdx.x; i < N; i += NT<T>) epi(i, c.Out()[i]);
+    __syncthreads();
   } else {
     load_closure<T, DIM, Q>(c.X(), v);
     apply_level<T, DIM, LV, L>(c);
