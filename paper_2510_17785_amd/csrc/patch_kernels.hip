@@ -223,9 +223,10 @@ struct Layout {
   static constexpr int G_top = NG * ipow(2 * (LV::q[0] + 1), DIM);
   static constexpr bool top_vec_fit = !all_fit && one_wg && (base_total + G_top + vec_total) * sz <= kBudgetOne;
   // FP32 slab-form tops where the level vectors and the top metric do not
-  // fit together keep the vectors (the metric is then recomputed at every
-  // Gauss point): vectors in global memory make every Chebyshev update a
-  // chain of memory round trips, which cost more than the recomputation
+  // fit together keep the vectors in LDS (the metric is then read from its
+  // setup copy in global memory, or recomputed at every Gauss point where
+  // there is none): vectors in global memory make every Chebyshev update a
+  // chain of memory round trips, which cost more than either
   static constexpr bool vec_over_G = !all_fit && one_wg && !top_vec_fit && sz == 4 &&
                                      (base_total + vec_total) * sz <= kBudgetOne;
   static constexpr bool top_fit = !all_fit && one_wg && !vec_over_G && (base_total + G_top) * sz <= kBudgetOne;
@@ -261,11 +262,12 @@ struct Layout {
   // else global scratch
   static constexpr bool vec_in_lds =
       all_fit || top_vec_fit || vec_over_G || (!cache_G && (base_total + vec_total) * sz <= kBudget);
-  // FP32 slab-form tops that keep the level vectors in LDS instead of the
-  // metric read the top level's metric from the setup's copy in global
-  // memory (per patch NG x npts(0) values, the LDS layout) when the handle
-  // has one, instead of recomputing it at every Gauss point
-  static constexpr bool G_global = vec_over_G && npts(0) > 0;
+  // FP32 slab-form tops on the matrix cores (degree 7 at most) that keep the
+  // level vectors in LDS instead of the metric read the top level's metric
+  // from the setup's copy in global memory (per patch NG x npts(0) values,
+  // the LDS layout) when the handle has one, instead of recomputing it at
+  // every Gauss point
+  static constexpr bool G_global = vec_over_G && npts(0) > 0 && LV::q[0] <= 7 && !use_quarter(0);
   static constexpr int G_glob_elems = G_global ? NG * npts(0) : 0;
   static constexpr int G_off = base_total;
   static constexpr int vec_off = base_total + G_total;
