@@ -316,9 +316,32 @@ def bench_batch(args, w):
                     "(cut patches cost their share of cells)",
         },
     }
+    B.close()
+    if not args.no_cg:
+        # each instance's own outer CG at its full size (GMG with boundary
+        # patches on 24^3, 12^3, 6^3 and the dense coarse solve on 3^3):
+        # FP32 local solver against FP64, the +1 iteration rule
+        from paper_2510_17785_amd import GMGSolver
+        cg = {}
+        for k, p in enumerate(ps):
+            row = {}
+            for prec in ("fp64", "fp32"):
+                t0 = time.perf_counter()
+                G = GMGSolver(3, n, p, X[k], mu[k], precision=prec, with_boundary=True)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                _, it, rel = G.cg(bd[k], rtol=1e-8)
+                t2 = time.perf_counter()
+                G.close()
+                row[prec] = {"iterations": it, "relres": rel, "setup_s": t1 - t0, "solve_s": t2 - t1}
+            row["fp32_within_one"] = row["fp32"]["iterations"] <= row["fp64"]["iterations"] + 1
+            cg[str(p)] = row
+            print(f"# batch instance p={p} outer CG on {n}^3: FP64 {row['fp64']['iterations']}, "
+                  f"FP32 {row['fp32']['iterations']} iterations (setup {row['fp64']['setup_s']:.1f} s / "
+                  f"{row['fp32']['setup_s']:.1f} s)", file=sys.stderr, flush=True)
+        out["outer_cg"] = cg
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_batch(w, ps, levels, X, mu, bh, local)
-    B.close()
     print(json.dumps(out))
     return 0
 

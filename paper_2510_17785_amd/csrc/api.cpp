@@ -1033,44 +1033,95 @@ int dot(gmg_handle* g, const double* x, const double* y, int slot) {
   return PMG_OK;
 }
 
-// dense SPD inverse through the Cholesky factor (host, FP64)
+// Run f(i) for i in [lo, hi) on all host threads, rows dealt round-robin
+// (the triangular loops below give row i work proportional to i).
+template <class F>
+void parallel_rows(int lo, int hi, F f) {
+  const int nt = (int)std::max(1u, std::min(std::thread::hardware_concurrency(), 64u));
+  if (hi - lo < 2 * nt) {
+    for (int i = lo; i < hi; ++i) f(i);
+    return;
+  }
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nt; ++t)
+    pool.emplace_back([&, t]() {
+      for (int i = lo + t; i < hi; i += nt) f(i);
+    });
+  for (auto& th : pool) th.join();
+}
+
+// Dense SPD inverse through the Cholesky factor (host, FP64, all host
+// threads): A = L L^T by blocked right-looking elimination (row-major, lower
+// triangle in place), W = L^{-1} column by column, A^{-1} = W^T W.  Every
+// inner loop is a dot product over contiguous memory.
 int spd_inverse(std::vector<double>& A, int n) {
-  // A = L L^T (lower, in place)
-  for (int j = 0; j < n; ++j) {
-    double d = A[(size_t)j * n + j];
-    for (int k = 0; k < j; ++k) d -= A[(size_t)j * n + k] * A[(size_t)j * n + k];
-    if (!(d > 0.0)) return fail(PMG_ERR_BREAKDOWN, "coarse matrix not SPD at row %d", j);
-    d = std::sqrt(d);
-    A[(size_t)j * n + j] = d;
-    for (int i = j + 1; i < n; ++i) {
-      double s = A[(size_t)i * n + j];
-      const double* ai = &A[(size_t)i * n];
-      const double* aj = &A[(size_t)j * n];
-      for (int k = 0; k < j; ++k) s -= ai[k] * aj[k];
-      A[(size_t)i * n + j] = s / d;
+  constexpr int kB = 64;
+  auto a = [&](int i, int j) -> double& { return A[(size_t)i * n + j]; };
+  int bad = -1;
+  for (int k0 = 0; k0 < n && bad < 0; k0 += kB) {
+    const int k1 = std::min(n, k0 + kB);
+    // diagonal block (the columns before k0 are already eliminated)
+    for (int j = k0; j < k1 && bad < 0; ++j) {
+      double d = a(j, j);
+      for (int k = k0; k < j; ++k) d -= a(j, k) * a(j, k);
+      if (!(d > 0.0)) {
+        bad = j;
+        break;
+      }
+      d = std::sqrt(d);
+      a(j, j) = d;
+      for (int i = j + 1; i < k1; ++i) {
+        double v = a(i, j);
+        for (int k = k0; k < j; ++k) v -= a(i, k) * a(j, k);
+        a(i, j) = v / d;
+      }
     }
+    if (bad >= 0) break;
+    // the panel below it, then the trailing lower triangle
+    parallel_rows(k1, n, [&](int i) {
+      double* ai = &a(i, 0);
+      for (int j = k0; j < k1; ++j) {
+        const double* aj = &a(j, 0);
+        double v = ai[j];
+        for (int k = k0; k < j; ++k) v -= ai[k] * aj[k];
+        ai[j] = v / aj[j];
+      }
+    });
+    parallel_rows(k1, n, [&](int i) {
+      double* ai = &a(i, 0);
+      for (int j = k1; j <= i; ++j) {
+        const double* aj = &a(j, 0);
+        double v = 0;
+        for (int k = k0; k < k1; ++k) v += ai[k] * aj[k];
+        ai[j] -= v;
+      }
+    });
   }
-  // W = L^{-1} (lower), then A^{-1} = W^T W
-  std::vector<double> W((size_t)n * n, 0.0);
-  for (int c = 0; c < n; ++c) {
-    W[(size_t)c * n + c] = 1.0 / A[(size_t)c * n + c];
+  if (bad >= 0) return fail(PMG_ERR_BREAKDOWN, "coarse matrix not SPD at row %d", bad);
+  // Wt[c][i] = (L^{-1})[i][c] for i >= c: forward substitution per column c
+  std::vector<double> Wt((size_t)n * n, 0.0);
+  parallel_rows(0, n, [&](int c) {
+    double* w = &Wt[(size_t)c * n];
+    w[c] = 1.0 / a(c, c);
     for (int i = c + 1; i < n; ++i) {
-      double s = 0;
-      for (int k = c; k < i; ++k) s -= A[(size_t)i * n + k] * W[(size_t)k * n + c];
-      W[(size_t)i * n + c] = s / A[(size_t)i * n + i];
+      const double* ai = &a(i, 0);
+      double v = 0;
+      for (int k = c; k < i; ++k) v -= ai[k] * w[k];
+      w[i] = v / ai[i];
     }
-  }
-  std::vector<double> inv((size_t)n * n, 0.0);
-  for (int k = 0; k < n; ++k) {
-    const double* wk = &W[(size_t)k * n];
-    for (int i = 0; i <= k; ++i) {
-      const double wki = wk[i];
-      if (wki == 0.0) continue;
-      double* row = &inv[(size_t)i * n];
-      for (int j = 0; j <= k; ++j) row[j] += wki * wk[j];
+  });
+  // A^{-1}[i][j] = sum_{k >= max(i, j)} W[k][i] W[k][j], symmetric
+  parallel_rows(0, n, [&](int i) {
+    const double* wi = &Wt[(size_t)i * n];
+    for (int j = 0; j <= i; ++j) {
+      const double* wj = &Wt[(size_t)j * n];
+      double v = 0;
+      for (int k = i; k < n; ++k) v += wi[k] * wj[k];
+      A[(size_t)i * n + j] = v;
     }
-  }
-  A.swap(inv);
+  });
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j) A[(size_t)j * n + i] = A[(size_t)i * n + j];
   return PMG_OK;
 }
 

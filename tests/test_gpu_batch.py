@@ -212,3 +212,22 @@ def test_batch_instance_outer_cg(dev, k):
         assert it64 == ito
         assert np.abs(x.cpu().numpy() - xo).max() <= 1e-10 * np.abs(xo).max()
     print(f"\ndegree {p}: outer CG iterations FP64 {it64}, FP32 {it32}")
+
+
+def test_batch_instance_outer_cg_fullsize(dev):
+    """The degree-6 instance at its full 24^3 size (GMG levels 24^3, 12^3,
+    6^3 and the dense coarse solve of the 17^3 unknowns on 3^3): FP32 local
+    solver within one outer iteration of FP64."""
+    from paper_2510_17785_amd import GMGSolver
+    w = synth.workload("3d-n24-q8-batch")
+    k, p, n = 2, 6, w.n
+    X = synth.make_vertices(3, n, w.alpha, w.mesh_seed + k)
+    b = torch.tensor(synth.make_rhs(3, n, p, w.rhs_seed + k), device=dev)
+    its = {}
+    for prec in ("fp64", "fp32"):
+        G = GMGSolver(3, n, p, X, np.ones(n ** 3), precision=prec, with_boundary=True)
+        _, its[prec], rel = G.cg(b, rtol=1e-8)
+        G.close()
+        assert rel <= 1e-8, (prec, rel)
+    print(f"\n24^3 Q6 instance: outer CG iterations {its}")
+    assert its["fp32"] <= its["fp64"] + 1
