@@ -311,7 +311,8 @@ int pmg_batch_instance(pmg_batch* b, int32_t i, pmg_handle** h);
  * vectors of instance i.  The first call per direction captures the sweep
  * into a HIP graph bound to these addresses; later calls with the same
  * addresses replay it, other addresses capture again (counted by
- * pmg_batch_query).  Asynchronous on opts->stream.  The graph holds launches
+ * pmg_batch_query), and so does a change of an instance's smoother
+ * (pmg_set_smoother).  Asynchronous on opts->stream.  The graph holds launches
  * of the default shape (one workgroup per patch): PMG_ERR_UNSUPPORTED when an
  * instance has another shape (pmg_set_launch), which
  * pmg_batch_smooth_eager runs. */

@@ -2382,6 +2382,12 @@ int pmg_batch_smooth(pmg_batch* b, double* const* u, const double* const* rhs, i
     ptrs.push_back((int64_t)(intptr_t)rhs[i]);
     ptrs.push_back(b->inst[i]->tune_grid);
     ptrs.push_back(b->inst[i]->tune_map);
+    // the smoother (kernel mode, tables and damping are captured too)
+    ptrs.push_back(b->inst[i]->smoother);
+    int64_t om = 0;
+    std::memcpy(&om, &b->inst[i]->omega, sizeof(om));
+    ptrs.push_back(om);
+    ptrs.push_back((int64_t)(intptr_t)b->inst[i]->fdm_tab);
   }
   hipError_t e;
   if (!b->exec[d] || b->bound[d] != ptrs) {

@@ -157,6 +157,19 @@ def test_batch_graph_replays_and_recapture_bitwise(dev):
     assert B.captures == 4
     for k in range(4):
         assert torch.equal(vs[k], ref[k]), PS[k]
+    # an instance's smoother changed after capture: the same addresses are
+    # captured again, and the graph sweep equals the direct one
+    B.instances[1].set_smoother("cartesian", 0.5)
+    es = [torch.tensor(x, device=dev) for x in u0]
+    B.smooth(es, bd, +1, graph=False)
+    for k in range(4):
+        vs[k].copy_(torch.tensor(u0[k], device=dev))
+    torch.cuda.synchronize()
+    B.smooth(vs, bd, +1)
+    torch.cuda.synchronize()
+    assert B.captures == 5
+    for k in range(4):
+        assert torch.equal(vs[k], es[k]), PS[k]
     B.close()
 
 
