@@ -13,7 +13,9 @@ so that each step can be checked against the paper by eye:
 
   fe1d      -- Gauss-Lobatto-Legendre nodes, Gauss-Legendre rule, Lagrange basis
   fem       -- multilinear cell maps, element matrices of a(u,v)=int mu grad u.grad v
-               (Section 2, bilinear form), patch and global assembly
+               (Section 2, bilinear form), patch and global assembly, coarse
+               meshes (coefficient means, or box-wise coefficients integrated
+               by the octant rule)
   pmg       -- p-transfers, level operators, Chebyshev-Jacobi smoothing and the
                local p-multigrid V-cycle (Section 3.1, Algorithm 2)
   smoother  -- vertex patches, colouring and the multiplicative sweep

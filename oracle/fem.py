@@ -85,17 +85,65 @@ def jacobians(X: np.ndarray, points: np.ndarray) -> np.ndarray:
     return np.einsum("ecr,kcs->ekrs", X, dN)
 
 
+@functools.lru_cache(maxsize=None)
+def subcell_gradients(q: int, dim: int, s: int, sub: tuple):
+    """The degree-q tensor basis of a cell and its reference gradients at
+    the Gauss points of the sub-box sub of its reference cube cut into s^dim
+    boxes (q+1 points per direction in each, weights scaled by 1/s per
+    direction): the composite rule of a coarse cell whose coefficient is
+    piecewise constant on those boxes.  Same returns as reference_gradients."""
+    nodes = fe1d.gll_nodes(q)
+    xg, wg = fe1d.gauss_rule(q + 1)
+    per = [((sub[i] + xg) / s, wg / s) for i in range(dim)]
+    Ls = [fe1d.lagrange_values(nodes, per[i][0]) for i in range(dim)]
+    Ds = [fe1d.lagrange_derivatives(nodes, per[i][0]) for i in range(dim)]
+    idx = _multi(q + 1, dim)
+    npt = len(idx)
+    grad = np.zeros((npt, npt, dim))
+    w = np.zeros(npt)
+    pts = np.zeros((npt, dim))
+    for k, kk in enumerate(idx):
+        w[k] = np.prod([per[i][1][kk[i]] for i in range(dim)])
+        pts[k] = [per[i][0][kk[i]] for i in range(dim)]
+        for a, aa in enumerate(idx):
+            for i in range(dim):
+                val = 1.0
+                for j in range(dim):
+                    val *= Ds[j][aa[j], kk[j]] if j == i else Ls[j][aa[j], kk[j]]
+                grad[k, a, i] = val
+    return grad, w, pts
+
+
 def element_matrices(X: np.ndarray, mu: np.ndarray, q: int) -> np.ndarray:
     """Element matrices of a(.,.) for a batch of cells.
 
-    X : (ncell, 2^dim, dim) corner coordinates, mu : (ncell,) coefficients.
+    X : (ncell, 2^dim, dim) corner coordinates, mu : (ncell,) coefficients,
+    or (ncell, s^dim) coefficients constant on the s^dim boxes of each cell's
+    reference cube (x fastest), integrated box by box with the q+1-point
+    Gauss rule (the octant rule of coarse cells).
     Returns (ncell, n^dim, n^dim) with n = q+1, rows/columns in reference
     tensor order.
     """
     X = np.asarray(X, dtype=np.float64)
-    ncell, _, dim = X.shape
-    grad, w, pts = reference_gradients(q, dim)
-    npt, nb, _ = grad.shape
+    mu = np.asarray(mu, dtype=np.float64)
+    dim = X.shape[2]
+    if mu.ndim == 2:
+        s = int(round(mu.shape[1] ** (1.0 / dim)))
+        if s ** dim != mu.shape[1]:
+            raise ValueError("box coefficients must come in s^dim per cell")
+        out = 0.0
+        for b, sub in enumerate(_multi(s, dim)):
+            out = out + _element_matrices_rule(X, mu[:, b], subcell_gradients(q, dim, s, sub))
+        return out
+    return _element_matrices_rule(X, mu, reference_gradients(q, dim))
+
+
+def _element_matrices_rule(X: np.ndarray, mu: np.ndarray, rule) -> np.ndarray:
+    """sum_k mu w_k (J_k^{-T} grad phi_a) . (J_k^{-T} grad phi_b) det J_k over
+    the points of the rule (grad, w, pts)."""
+    ncell = X.shape[0]
+    grad, w, pts = rule
+    npt, nb, dim = grad.shape
     out = np.zeros((ncell, nb, nb))
     J = jacobians(X, pts)                           # (ncell, npt, d, d)
     detJ = np.linalg.det(J)
@@ -124,7 +172,8 @@ class PatchGeometry:
             the vertex at offset t in {0,1,2}^dim); in a direction with only
             one cell (a patch cut by the domain boundary) only offsets 0, 1
             are used
-    mu    : (2^dim,) coefficient of cell c = sum c_i 2^i
+    mu    : (2^dim,) coefficient of cell c = sum c_i 2^i, or (2^dim, s^dim)
+            coefficients per box of each cell (see element_matrices)
     ncell : cells per direction, each 1 or 2 (2 for a vertex in the interior)
     """
 
@@ -242,7 +291,7 @@ class Mesh:
             if all(t[i] <= nc[i] for i in range(self.dim)):
                 verts[sum(t[i] * 3 ** i for i in range(self.dim))] = \
                     self.vertex([st[i] + t[i] for i in range(self.dim)])
-        mu = np.zeros(2 ** self.dim)
+        mu = np.zeros((2 ** self.dim,) + self.mu.shape[1:])
         for c in _multi(2, self.dim):
             if all(c[i] < nc[i] for i in range(self.dim)):
                 mu[sum(c[i] * 2 ** i for i in range(self.dim))] = \
@@ -252,12 +301,28 @@ class Mesh:
     def coarsen(self, rule: str = "arithmetic") -> "Mesh":
         """Parent mesh with n/2 cells: vertices are the fine vertices with even
         indices (topological nesting, Section 2); a parent cell's coefficient
-        is the arithmetic, geometric or harmonic mean of its 2^dim children."""
+        is the arithmetic, geometric or harmonic mean of its 2^dim children,
+        or with rule "octant" the children's coefficients themselves, kept
+        per box of the parent's reference cube (s^dim boxes after k
+        coarsenings, s = 2^k: the finest cells' coefficients), which
+        element_matrices integrates box by box."""
         if self.n % 2:
             raise ValueError("odd mesh cannot be coarsened")
         nc = self.n // 2
         verts = np.array([self.vertex([2 * v[i] for i in range(self.dim)])
                           for v in _multi(nc + 1, self.dim)])
+        if rule == "octant":
+            fine = self.mu if self.mu.ndim == 2 else self.mu[:, None]
+            s = int(round(fine.shape[1] ** (1.0 / self.dim)))
+            mu = np.zeros((nc ** self.dim, (2 * s) ** self.dim))
+            for e in _multi(nc, self.dim):
+                ei = sum(e[i] * nc ** i for i in range(self.dim))
+                for c in _multi(2, self.dim):
+                    child = sum((2 * e[i] + c[i]) * self.n ** i for i in range(self.dim))
+                    for t in _multi(s, self.dim):
+                        box = sum((c[i] * s + t[i]) * (2 * s) ** i for i in range(self.dim))
+                        mu[ei, box] = fine[child, sum(t[i] * s ** i for i in range(self.dim))]
+            return Mesh(self.dim, nc, verts, mu)
         means = {"arithmetic": lambda x: np.mean(x),
                  "geometric": lambda x: np.exp(np.mean(np.log(x))),
                  "harmonic": lambda x: 1.0 / np.mean(1.0 / np.asarray(x))}

@@ -592,6 +592,54 @@ def test_coarse_coefficient_means(rule, expect):
     assert c.n == 1 and np.isclose(c.mu[0], expect, rtol=1e-14)
 
 
+def _affine_mesh(dim, n, mu, skew=0.0):
+    # a uniform mesh of the unit box sheared by an affine map: every cell
+    # and every coarse cell is affine, so the coarse spaces are nested
+    g = np.array(np.meshgrid(*([np.arange(n + 1)] * dim), indexing="ij"))
+    X = np.stack([g[i].transpose(tuple(reversed(range(dim)))).reshape(-1)
+                  for i in range(dim)], axis=1) / n
+    X[:, 0] += skew * X[:, dim - 1]
+    return fem.Mesh(dim, n, X, mu)
+
+
+@pytest.mark.parametrize("dim,p,n,levels", [(2, 3, 4, 1), (2, 2, 8, 2), (3, 2, 4, 1), (3, 1, 4, 2)])
+def test_octant_coarse_operator_is_galerkin_on_affine_meshes(dim, p, n, levels):
+    # reading R11: a coarse cell integrates box by box with its descendants'
+    # coefficients; on affine nested meshes that is exactly the Galerkin
+    # product P^T A_fine P (the integrand is a polynomial on every box),
+    # over one and two coarsenings, for coefficients jumping by 1e6
+    mu = 10.0 ** np.random.default_rng(dim + n).uniform(-3, 3, n ** dim)
+    fine = _affine_mesh(dim, n, mu, skew=0.3)
+    A = fem.dirichlet_operator(fine, p)
+    mesh, nc = fine, n
+    for _ in range(levels):
+        nc //= 2
+        mesh = mesh.coarsen("octant")
+        P = gmg.prolongation_h(dim, nc, p)
+        A = (P.T @ A @ P).tocsr()
+    Ac = fem.dirichlet_operator(mesh, p)
+    assert mesh.n == nc and mesh.mu.shape == (nc ** dim, (n // nc) ** dim)
+    assert abs(Ac - A).max() <= 1e-11 * abs(A).max()
+    # the arithmetic mean does not give it
+    Aa = fem.dirichlet_operator(_affine_mesh(dim, n, mu, skew=0.3).coarsen("arithmetic"), p) \
+        if levels == 1 else None
+    if Aa is not None:
+        assert abs(Aa - A).max() > 1e-3 * abs(A).max()
+
+
+def test_octant_rule_with_equal_box_coefficients_is_the_cell_rule():
+    # boxes of one coefficient on a distorted mesh: the composite rule and the
+    # cell rule differ only by quadrature error, which vanishes for an
+    # undistorted cell and stays small on a distorted one
+    dim, p, n = 2, 3, 4
+    X = synth.make_vertices(dim, n, 0.2, 3)
+    mu = np.full(n ** dim, 2.5)
+    A1 = fem.dirichlet_operator(fem.Mesh(dim, n, X, mu).coarsen("arithmetic"), p)
+    A2 = fem.dirichlet_operator(fem.Mesh(dim, n, X, mu).coarsen("octant"), p)
+    rel = abs(A1 - A2).max() / abs(A1).max()
+    assert 0 < rel < 1e-2
+
+
 # ---------------------------------------------------------------------------
 # Cartesian-reinforced smoother
 # ---------------------------------------------------------------------------
