@@ -156,10 +156,14 @@ struct Layout {
   // buffers fit 40 KB at the top degree (else the two-slab form)
   static constexpr int P0 = ipow(2 * (LV::q[0] + 1), DIM);
   static constexpr bool seg_top = DIM == 3 && 4 * P0 * (int)sizeof(T) <= 40 * 1024;
+  // FP64 degree-7 tops keep the level vectors in LDS: the top level then
+  // works in quarter-slabs and its inverse diagonal is read from global memory
+  static constexpr bool f64_vec = sizeof(T) == 8 && DIM == 3 && LV::q[0] == 7;
+  static constexpr bool dinv0_global = f64_vec;
   // where four full slabs would take more than 64 KB, the top level works in
   // quarter-slabs (n x n x NQ buffers)
   static constexpr bool quarter_top =
-      DIM == 3 && !seg_top && 4 * S0::S * (int)sizeof(T) > 64 * 1024;
+      DIM == 3 && !seg_top && (4 * S0::S * (int)sizeof(T) > 64 * 1024 || f64_vec);
   static constexpr int abuf_elems =
       seg_top ? 4 * P0 : (quarter_top ? 4 * S0::n * S0::n * S0::NQ : 4 * S0::S);
   static constexpr bool use_seg(int l) {
@@ -173,7 +177,7 @@ struct Layout {
   // vectors: r_l, d_l, dinv_l per level, then res and z at the top size
   static constexpr int vec_r(int l) {
     int o = 0;
-    for (int i = 0; i < l; ++i) o += 3 * level_size(i);
+    for (int i = 0; i < l; ++i) o += (dinv0_global && i == 0 ? 2 : 3) * level_size(i);
     return o;
   }
   static constexpr int vec_d(int l) { return vec_r(l) + level_size(l); }
@@ -261,7 +265,8 @@ struct Layout {
   // it (above), or, with no metric cached, within the two-workgroup budget;
   // else global scratch
   static constexpr bool vec_in_lds =
-      all_fit || top_vec_fit || vec_over_G || (!cache_G && (base_total + vec_total) * sz <= kBudget);
+      all_fit || top_vec_fit || vec_over_G || (!cache_G && (base_total + vec_total) * sz <= kBudget) ||
+      (f64_vec && !cache_G && (base_total + vec_total) * sz <= kBudgetOne);
   // FP32 slab-form tops on the matrix cores (degree 7 at most) that keep the
   // level vectors in LDS instead of the metric read the top level's metric
   // from the setup's copy in global memory (per patch NG x npts(0) values,
@@ -273,6 +278,7 @@ struct Layout {
   static constexpr int vec_off = base_total + G_total;
   static constexpr int dense_off = round_up(vec_off + (vec_in_lds ? vec_total : 0), 4);
   static constexpr int lds_elems = dense_off + dense_total;
+  static_assert(!f64_vec || vec_in_lds, "FP64 degree-7 level vectors must fit in LDS");
 };
 
 // ---------------------------------------------------------------------------
@@ -496,7 +502,9 @@ struct Ctx {
   __device__ T* abuf() const { return lds + Lay::abuf_off; }
   __device__ T* r(int l) const { return vec + Lay::vec_r(l); }
   __device__ T* d(int l) const { return vec + Lay::vec_d(l); }
-  __device__ T* dinv(int l) const { return vec + Lay::vec_dinv(l); }
+  // top level's inverse diagonal in global memory (Layout::dinv0_global)
+  T* dinv0 = nullptr;
+  __device__ T* dinv(int l) const { return (Lay::dinv0_global && l == 0) ? dinv0 : vec + Lay::vec_dinv(l); }
   __device__ T* res() const { return vec + Lay::vec_res; }
   __device__ T* z() const { return vec + Lay::vec_z; }
 };
@@ -1118,9 +1126,10 @@ struct EpiResidual {  // res = f - A x
   PT f, res;
   __device__ __forceinline__ void operator()(int i, T v) const { res[i] = f[i] - v; }
 };
-template <typename T, class PT>
+template <typename T, class PT, class DT = PT>
 struct EpiChebStart {  // res = f - A x, z = D^{-1} res / theta
-  PT f, res, z, dinv;
+  PT f, res, z;
+  DT dinv;
   T inv_theta;
   __device__ __forceinline__ void operator()(int i, T v) const {
     const T r = f[i] - v;
@@ -1128,9 +1137,10 @@ struct EpiChebStart {  // res = f - A x, z = D^{-1} res / theta
     z[i] = dinv[i] * r * inv_theta;
   }
 };
-template <typename T, class PT>
+template <typename T, class PT, class DT = PT>
 struct EpiChebStep {  // x += z, res -= A z, z = c1 z + c2 D^{-1} res
-  PT x, res, z, dinv;
+  PT x, res, z;
+  DT dinv;
   T c1, c2;
   __device__ __forceinline__ void operator()(int i, T v) const {
     const T zi = z[i];
@@ -1706,7 +1716,9 @@ __device__ __forceinline__ void chebyshev(const Ctx<T, DIM, LV>& c, int k, bool 
   PT x = vp<T, DIM, LV>(c.d(L));
   PT res = vp<T, DIM, LV>(c.res());
   PT z = vp<T, DIM, LV>(c.z());
-  PT dinv = vp<T, DIM, LV>(c.dinv(L));
+  // the top level's inverse diagonal may live in global memory
+  using DT = typename std::conditional<Layout<T, DIM, LV>::dinv0_global && L == 0, const T*, PT>::type;
+  DT dinv = (DT)c.dinv(L);
   const T theta = c.cheb()[2 * L], delta = c.cheb()[2 * L + 1];
   const T sigma = theta / delta;
   T rho = T(1) / sigma;
@@ -1722,13 +1734,13 @@ __device__ __forceinline__ void chebyshev(const Ctx<T, DIM, LV>& c, int k, bool 
     __syncthreads();
   } else {
     // r_0 = f - A x, z_0 = D^{-1} r_0 / theta
-    apply_vec_epi<T, DIM, LV, L>(c, c.d(L), EpiChebStart<T, PT>{f, res, z, dinv, T(1) / theta});
+    apply_vec_epi<T, DIM, LV, L>(c, c.d(L), EpiChebStart<T, PT, DT>{f, res, z, dinv, T(1) / theta});
   }
   for (int it = 0; it + 1 < k; ++it) {
     // x += z_i, r_{i+1} = r_i - A z_i, z_{i+1} = c1 z_i + c2 D^{-1} r_{i+1}
     const T rho_new = T(1) / (T(2) * sigma - rho);
     apply_vec_epi<T, DIM, LV, L>(c, c.z(),
-                                 EpiChebStep<T, PT>{x, res, z, dinv, rho_new * rho, T(2) * rho_new / delta});
+                                 EpiChebStep<T, PT, DT>{x, res, z, dinv, rho_new * rho, T(2) * rho_new / delta});
     rho = rho_new;
   }
 #pragma unroll 1
@@ -2436,6 +2448,7 @@ __device__ void load_patch(const Ctx<T, DIM, LV>& c, const PatchArgs& a, int pat
   }
 #pragma unroll
   for (int l = 0; l < L; ++l) {
+    if (Lay::dinv0_global && l == 0) continue;  // read in place (Ctx::dinv0)
     const int sz = Lay::level_size(l);
     const T* src = tptr<T>(a.invdiag[l]) + (int64_t)patch * sz;
     VecPtr<T, DIM, LV> dst = vp<T, DIM, LV>(c.dinv(l));
@@ -2573,6 +2586,8 @@ __device__ __forceinline__ void patch_update(const PatchArgs& a, Ctx<T, DIM, LV>
   c.pf = pf;
   c.trunc = nullptr;
   if constexpr (sizeof(T) == 4) c.coarse_inv = a.invdiag64[LV::count - 1][patch];
+  if constexpr (Lay::dinv0_global)
+    c.dinv0 = const_cast<T*>(tptr<T>(a.invdiag[0])) + (int64_t)patch * Lay::level_size(0);
   if (pf && a.trunc_index) {
     const int k = a.trunc_index[patch];
     // one slot holds the largest unmasked box, a face patch's
@@ -3045,7 +3060,9 @@ __global__ __launch_bounds__(NT<double>) void lanczos_kernel(PatchArgs a) {
       for (int i = tid; i < sz; i += NT<T>) c.lds[Lay::tab_level_off(l) + i] = tab[l * kTabLevelStride + i];
     }
     load_geometry<T, DIM>(a, patch, c.geo(), c.mu());
+    if constexpr (Lay::dinv0_global) c.dinv0 = const_cast<double*>(a.invdiag64[0]) + (int64_t)patch * Lay::level_size(0);
     for (int l = 0; l < LV::count; ++l) {
+      if (Lay::dinv0_global && l == 0) continue;
       const int sz = Lay::level_size(l);
       const double* src = a.invdiag64[l] + (int64_t)patch * sz;
       for (int i = tid; i < sz; i += NT<T>) c.dinv(l)[i] = src[i];
