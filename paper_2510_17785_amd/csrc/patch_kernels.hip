@@ -680,7 +680,7 @@ __device__ __noinline__ void apply3(const LDSP T* __restrict__ X, LDSP T* __rest
 // n x NQ x NQ (for degrees whose full slabs do not fit LDS next to the rest
 // of the patch).  Out is cleared first and every quarter adds its part.
 template <typename T, int Q, bool CACHE>
-__device__ __noinline__ void apply3q(const LDSP T* __restrict__ X, LDSP T* __restrict__ Out,
+__device__ __forceinline__ void apply3q(const LDSP T* __restrict__ X, LDSP T* __restrict__ Out,
                                      LDSP T* __restrict__ ab, const LDSP T* __restrict__ Bt,
                                      const LDSP T* __restrict__ Dc, const LDSP T* __restrict__ xg,
                                      const LDSP T* __restrict__ wg, const LDSP T* __restrict__ jc,
