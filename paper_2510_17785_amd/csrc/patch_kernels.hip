@@ -1372,7 +1372,7 @@ __device__ __noinline__ void apply3seg(const LDSP T* __restrict__ in, Epi epi,
 }
 
 template <typename T, int Q, bool CACHE>
-__device__ __noinline__ void apply2(const T* __restrict__ X, T* __restrict__ Out, T* __restrict__ ab,
+__device__ __forceinline__ void apply2(const T* __restrict__ X, T* __restrict__ Out, T* __restrict__ ab,
                        const T* __restrict__ Bt, const T* __restrict__ Dc, const T* __restrict__ xg,
                        const T* __restrict__ wg, const T* __restrict__ jc, const T* __restrict__ mu,
                        const T* __restrict__ Gc) {
