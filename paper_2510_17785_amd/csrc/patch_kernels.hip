@@ -1152,7 +1152,7 @@ struct EpiChebStep {  // x += z, res -= A z, z = c1 z + c2 D^{-1} res
 };
 
 template <typename T, int Q, bool CLOSURE_IN, bool CACHE, class Epi>
-__device__ __noinline__ void apply3seg(const LDSP T* __restrict__ in, Epi epi,
+__device__ __forceinline__ void apply3seg_body(const LDSP T* __restrict__ in, Epi epi,
                                        LDSP T* __restrict__ ab, const LDSP T* __restrict__ Bl,
                                        const LDSP T* __restrict__ Dcl,
                                        const LDSP T* __restrict__ jc, const LDSP T* __restrict__ mu,
@@ -1369,6 +1369,27 @@ __device__ __noinline__ void apply3seg(const LDSP T* __restrict__ in, Epi epi,
     epi(i, x < Q ? acc0 : (x > Q ? acc1 : acc0 + acc1));
   }
   __syncthreads();
+}
+
+// FP32 patches take the segment operator inline (their kernels are held to
+// 128 registers so that two patches share a CU); FP64 patches call it out of
+// line, which measured faster for them.
+template <typename T, int Q, bool CLOSURE_IN, bool CACHE, class Epi>
+__device__ __noinline__ void apply3seg_call(const LDSP T* __restrict__ in, Epi epi, LDSP T* __restrict__ ab,
+                                            const LDSP T* __restrict__ Bl, const LDSP T* __restrict__ Dcl,
+                                            const LDSP T* __restrict__ jc, const LDSP T* __restrict__ mu,
+                                            const LDSP T* __restrict__ Gc) {
+  apply3seg_body<T, Q, CLOSURE_IN, CACHE>(in, epi, ab, Bl, Dcl, jc, mu, Gc);
+}
+template <typename T, int Q, bool CLOSURE_IN, bool CACHE, class Epi>
+__device__ __forceinline__ void apply3seg(const LDSP T* __restrict__ in, Epi epi, LDSP T* __restrict__ ab,
+                                          const LDSP T* __restrict__ Bl, const LDSP T* __restrict__ Dcl,
+                                          const LDSP T* __restrict__ jc, const LDSP T* __restrict__ mu,
+                                          const LDSP T* __restrict__ Gc) {
+  if constexpr (sizeof(T) == 4)
+    apply3seg_body<T, Q, CLOSURE_IN, CACHE>(in, epi, ab, Bl, Dcl, jc, mu, Gc);
+  else
+    apply3seg_call<T, Q, CLOSURE_IN, CACHE>(in, epi, ab, Bl, Dcl, jc, mu, Gc);
 }
 
 template <typename T, int Q, bool CACHE>
@@ -2784,8 +2805,15 @@ __device__ __forceinline__ int work_item(const PatchArgs& a, int b, int k, int G
 // that each take several patches in turn (PERSIST true: a separate
 // instantiation, since the loop raises register use); the mapping is a
 // launch parameter.
+// FP32 segment-form patches, one workgroup per patch: at least four waves
+// per SIMD (128 registers), so that two patches share a CU as their LDS
+// allows (the persistent form's loop would spill at that limit)
+template <typename T, int DIM, class LV, bool PERSIST>
+constexpr int seg_min_waves() {
+  return DIM == 3 && sizeof(T) == 4 && !PERSIST && Layout<T, DIM, LV>::seg_top ? 4 : 1;
+}
 template <typename T, int DIM, class LV, int MODE, bool PERSIST>
-__global__ __launch_bounds__(NT<T>) void patch_kernel(PatchArgs a) {
+__global__ __launch_bounds__(NT<T>, (seg_min_waves<T, DIM, LV, PERSIST>())) void patch_kernel(PatchArgs a) {
   using Lay = Layout<T, DIM, LV>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   Ctx<T, DIM, LV> c;
