@@ -94,18 +94,28 @@ def algorithmic_per_patch(dim, levels, k, tsize):
     return F, B
 
 
+def kernel_source_digest():
+    """sha256 prefix of the patch-kernel sources: patch_kernels.hpp, then
+    patch_kernels.hip and the patch_variants_*.hip files in name order."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2510_17785_amd", "csrc")
+    names = ["patch_kernels.hpp"] + sorted(f for f in os.listdir(csrc)
+                                           if f.startswith("patch_") and f.endswith(".hip"))
+    h = hashlib.sha256()
+    for f in names:
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def measured_traffic(workload, kernel="patch_kernel_fp32"):
     """HBM bytes per launch of the patch kernel from the committed rocprofv3
     counter summary profiles/<kernel>_<workload>.md, or None when the kernel
     source has changed since the counters were taken."""
-    import hashlib
     prof = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md")
-    src = os.path.join(ROOT, "paper_2510_17785_amd", "csrc", "patch_kernels.hip")
     if not os.path.exists(prof):
         return None
     text = open(prof).read()
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if f"`{digest}`" not in text:
+    if f"`{kernel_source_digest()}`" not in text:
         return None
     for line in text.splitlines():
         if line.startswith("TRAFFIC_BYTES_PER_LAUNCH"):

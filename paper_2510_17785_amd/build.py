@@ -34,6 +34,8 @@ def sources():
     for f in sorted(os.listdir(CSRC)):
         if f.endswith(".hip") or f.endswith(".cpp"):
             out.append(os.path.join(CSRC, f))
+    # the patch-kernel variant files take the longest: start them first
+    out.sort(key=lambda f: not os.path.basename(f).startswith("patch_variants_"))
     return out
 
 
