@@ -101,8 +101,9 @@ __device__ __forceinline__ const T* ctab() {
     return c_tab32;
 }
 
-// Threads per patch workgroup: 8 waves for FP32 (about 100 VGPRs, two
-// workgroups per CU), 4 waves for FP64 (about 230 VGPRs).
+// Threads per patch workgroup: 8 waves for FP32 (segment-form tops held to
+// 128 VGPRs so that two workgroups share a CU; the slab-form tops take up to
+// 256 and one CU each), 4 waves for FP64 (up to 256 VGPRs).
 template <typename T>
 constexpr int NT = sizeof(T) == 4 ? 512 : 256;
 
