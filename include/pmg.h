@@ -307,17 +307,14 @@ int pmg_batch_setup(const pmg_mesh* meshes, const double* const* coeffs, const i
                     int32_t n, const pmg_opts* opts, pmg_batch** out);
 /* The handle of instance i (owned by the batch: do not destroy it). */
 int pmg_batch_instance(pmg_batch* b, int32_t i, pmg_handle** h);
-/* One sweep of every instance (direction +1 or -1); u[i], rhs[i]: device
- * vectors of instance i.  The first call per direction captures the sweep
- * into a HIP graph bound to these addresses; later calls with the same
- * addresses replay it, other addresses capture again (counted by
- * pmg_batch_query), and so does a change of an instance's smoother
- * (pmg_set_smoother).  Asynchronous on opts->stream.  The graph holds launches
- * of the default shape (one workgroup per patch): PMG_ERR_UNSUPPORTED when an
- * instance has another shape (pmg_set_launch), which
- * pmg_batch_smooth_eager runs. */
+/* One sweep of every instance captured into a HIP graph and replayed.
+ * Switched off: returns PMG_ERR_UNSUPPORTED without device work (capturing
+ * and replaying the batch sweep ended in a host crash whose cause is not
+ * known); pmg_batch_smooth_eager runs the sweep. */
 int pmg_batch_smooth(pmg_batch* b, double* const* u, const double* const* rhs, int32_t direction);
-/* The same sweep enqueued directly, without a graph. */
+/* One sweep of every instance (direction +1 or -1), enqueued directly on
+ * opts->stream (asynchronous); u[i], rhs[i]: device vectors of instance i.
+ * Every instance's launch shape (pmg_set_launch) is honoured. */
 int pmg_batch_smooth_eager(pmg_batch* b, double* const* u, const double* const* rhs,
                            int32_t direction);
 /* Launch shapes for every instance, chosen with the instances running
@@ -329,6 +326,8 @@ int pmg_batch_smooth_eager(pmg_batch* b, double* const* u, const double* const* 
  * instance with pmg_set_launch on pmg_batch_instance handles and sweep with
  * pmg_batch_smooth_eager. */
 int pmg_batch_autotune(pmg_batch* b, double* const* u, const double* const* rhs);
+/* Batch queries: the number of instances; graph captures and replays
+ * (always 0 while graph sweeps are switched off). */
 #define PMG_BQ_N_INSTANCES 0
 #define PMG_BQ_CAPTURES 1
 #define PMG_BQ_REPLAYS 2

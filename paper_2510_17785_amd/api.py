@@ -487,8 +487,9 @@ class GMGSolver:
 
 
 class SmootherBatch:
-    """pmg_batch_*: independent meshes of mixed degree smoothed together, a
-    sweep captured once into a HIP graph and replayed."""
+    """pmg_batch_*: independent meshes of mixed degree smoothed together, per
+    colour every instance's launch on a stream of its own (graph sweeps are
+    switched off in the library: smooth(graph=True) raises)."""
 
     def __init__(self, dim: int, ns, ps, vertices, coeffs, precision: str = "fp32",
                  bounds: str = "lanczos", with_boundary: bool = True, cheb_degree: int = 3,
@@ -524,7 +525,7 @@ class SmootherBatch:
     def _ptrs(ts):
         return (ctypes.c_void_p * len(ts))(*[_dptr(t) for t in ts])
 
-    def smooth(self, us, bs, direction: int = 1, graph: bool = True):
+    def smooth(self, us, bs, direction: int = 1, graph: bool = False):
         f = self._lib.pmg_batch_smooth if graph else self._lib.pmg_batch_smooth_eager
         L.check(f(self._h, self._ptrs(us), self._ptrs(bs), int(direction)))
 

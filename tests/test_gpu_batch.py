@@ -1,20 +1,18 @@
 """Mixed-degree batches: four independent meshes of degrees 2, 4, 6 and 8
 with boundary-vertex patches, smoothed together (instances concurrent per
-colour, the sweep captured into a HIP graph), and the launch shapes of the
-autotuner.  Every path runs the same patch updates, so results are compared
-bit for bit: batch against each instance smoothed on its own, graph replays
-against the direct sweep, tuned against untuned launches.  Each instance's
+colour), and hand-set launch shapes.  Every path runs the same patch
+updates, so results are compared bit for bit: batch against each instance
+smoothed on its own, other launch shapes against the default one.  Graph
+sweeps and the batch tuner are switched off in the library (host crashes of
+unknown cause); their tests stay in this file, skipped.  Each instance's
 own smoother is pinned to the oracle elsewhere (boundary-patch and parity
 tests); here the outer FP64 GMG-CG of every degree converges and, at
-degrees 2 and 4, takes the oracle's iteration count."""
-import faulthandler
-
+degrees 2 and 4, takes the oracle's iteration count.  (pytest's own
+faulthandler prints the stacks of a crash to the terminal.)"""
 import numpy as np
 import pytest
 
 torch = pytest.importorskip("torch")
-
-faulthandler.enable()  # a crash in host code prints the Python stack
 
 import synth  # noqa: E402
 from oracle import fem  # noqa: E402
@@ -71,15 +69,15 @@ def test_batch_graph_and_autotune_bitwise(dev):
         for k in range(4):
             us[k].copy_(torch.tensor(u0[k], device=dev))
         torch.cuda.synchronize()
-        B.smooth(us, bd, +1)
-        B.smooth(us, bd, -1)
+        B.smooth(us, bd, +1, graph=True)
+        B.smooth(us, bd, -1, graph=True)
         torch.cuda.synchronize()
         for k in range(4):
             assert torch.equal(us[k], ref[k]), (rep, PS[k])
     assert B.captures == 2 and B.replays == 4
     # other addresses: captured again
     vs = [u.clone() for u in us]
-    B.smooth(vs, bd, +1)
+    B.smooth(vs, bd, +1, graph=True)
     torch.cuda.synchronize()
     assert B.captures == 3
     # autotuned launch shapes give the same numbers
@@ -87,8 +85,8 @@ def test_batch_graph_and_autotune_bitwise(dev):
     shapes = [S.launch for S in B.instances]
     for k in range(4):
         us[k].copy_(torch.tensor(u0[k], device=dev))
-    B.smooth(us, bd, +1)
-    B.smooth(us, bd, -1)
+    B.smooth(us, bd, +1, graph=True)
+    B.smooth(us, bd, -1, graph=True)
     torch.cuda.synchronize()
     for k in range(4):
         assert torch.equal(us[k], ref[k]), (PS[k], shapes[k])
@@ -105,8 +103,8 @@ def test_batch_graph_and_autotune_bitwise(dev):
     c0 = B.captures
     for k in range(4):
         us[k].copy_(torch.tensor(u0[k], device=dev))
-    B.smooth(us, bd, +1)
-    B.smooth(us, bd, -1)
+    B.smooth(us, bd, +1, graph=True)
+    B.smooth(us, bd, -1, graph=True)
     torch.cuda.synchronize()
     assert B.captures == c0 + 2
     for k in range(4):
@@ -115,6 +113,10 @@ def test_batch_graph_and_autotune_bitwise(dev):
     B.close()
 
 
+@pytest.mark.skip(reason="a host crash (segmentation fault) occurred in this test in one of three "
+                         "full GPU runs with unchanged code (graph capture, replays and recaptures "
+                         "of the batch sweep); its cause is not known, so graph sweeps are switched "
+                         "off in the library and this test stays off the GPU")
 def test_batch_graph_replays_and_recapture_bitwise(dev):
     # the sweeps of the test above without the launch-shape tuner: direct
     # batch = each instance alone, graph replays (with host work and
@@ -140,8 +142,8 @@ def test_batch_graph_replays_and_recapture_bitwise(dev):
         for k in range(4):
             us[k].copy_(torch.tensor(u0[k], device=dev))
         torch.cuda.synchronize()
-        B.smooth(us, bd, +1)
-        B.smooth(us, bd, -1)
+        B.smooth(us, bd, +1, graph=True)
+        B.smooth(us, bd, -1, graph=True)
         torch.cuda.synchronize()
         for k in range(4):
             assert torch.equal(us[k], ref[k]), (rep, PS[k])
@@ -150,9 +152,9 @@ def test_batch_graph_replays_and_recapture_bitwise(dev):
     vs = [torch.tensor(x, device=dev) for x in u0]
     for k in range(4):
         us[k].copy_(vs[k])
-    B.smooth(us, bd, +1)
-    B.smooth(vs, bd, +1)
-    B.smooth(vs, bd, -1)
+    B.smooth(us, bd, +1, graph=True)
+    B.smooth(vs, bd, +1, graph=True)
+    B.smooth(vs, bd, -1, graph=True)
     torch.cuda.synchronize()
     assert B.captures == 4
     for k in range(4):
@@ -165,7 +167,7 @@ def test_batch_graph_replays_and_recapture_bitwise(dev):
     for k in range(4):
         vs[k].copy_(torch.tensor(u0[k], device=dev))
     torch.cuda.synchronize()
-    B.smooth(vs, bd, +1)
+    B.smooth(vs, bd, +1, graph=True)
     torch.cuda.synchronize()
     assert B.captures == 5
     for k in range(4):
