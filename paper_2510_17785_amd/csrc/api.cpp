@@ -2221,8 +2221,7 @@ int pmg_set_launch(pmg_handle* h, int32_t grid, int32_t map_mode) {
 // ---------------------------------------------------------------------------
 // batches of independent instances (meshes of their own, mixed degrees):
 // a sweep runs colour by colour, the instances of one colour concurrently on
-// one stream each, and is captured once into a HIP graph that later calls
-// replay
+// one stream each, joined before the next colour
 // ---------------------------------------------------------------------------
 
 struct pmg_batch {
