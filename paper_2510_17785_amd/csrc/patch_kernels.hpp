@@ -81,6 +81,17 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// The value v holds in lane j of the wavefront (j uniform).
+__device__ __forceinline__ float lane_value(float v, int j) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+}
+__device__ __forceinline__ double lane_value(double v, int j) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), j);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), j);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // 1D tables of every degree 1..kMaxDegree, B (n x n), Dc (n x n), D (n x n),
 // Gauss points and weights, in constant memory: they depend on the degree
 // only, and reads at compile-time offsets become scalar loads.
@@ -1988,17 +1999,24 @@ __device__ void vcycle_small(const Ctx<T, DIM, LV>& c, int k) {
       }
     }
     const bool own = i < N;
-    const LDSP T* M = lds_cast(c.dense(L));
-    LDSP T* zb = lds_cast(c.z());    // broadcast buffer for the Chebyshev direction
-    LDSP T* rb = lds_cast(c.res());  // and for the residual
+    LDSP T* rb = lds_cast(c.res());  // the residual, for the restriction
     const T f = own ? r[i] : T(0), di = own ? dinv[i] : T(0);
     const T theta = c.cheb()[2 * L], delta = c.cheb()[2 * L + 1];
     const T sigma = theta / delta;
-    auto Av = [&](const LDSP T* v) {  // row i of the stored level matrix times v
+    // row i of the stored level matrix, held in registers for the whole
+    // visit; a product takes the vector's entries from their lanes
+    // (readlane), so no LDS round trip or wavefront sync is needed
+    T Mrow[N];
+    {
+      const LDSP T* M = lds_cast(c.dense(L));
+#pragma unroll
+      for (int j = 0; j < N; ++j) Mrow[j] = own ? M[i * N + j] : T(0);
+    }
+    auto Av = [&](T v) {  // row i times the vector whose entry j lane j holds
       T acc = 0;
-      if (own)
-        for (int j = 0; j < N; ++j) acc += M[i * N + j] * v[j];
-      return acc;
+#pragma unroll
+      for (int j = 0; j < N; ++j) acc += Mrow[j] * lane_value(v, j);
+      return own ? acc : T(0);
     };
     // Chebyshev-Jacobi with the iterates of row i in registers (as chebyshev)
     auto smooth = [&](T& x, bool x_zero) {
@@ -2008,19 +2026,13 @@ __device__ void vcycle_small(const Ctx<T, DIM, LV>& c, int k) {
         z = di * f / theta;
         x = 0;
       } else {
-        if (own) d[i] = x;
-        wave_sync();
-        res = f - Av(d);
+        res = f - Av(x);
         z = di * res * (T(1) / theta);
-        wave_sync();
       }
       for (int it = 0; it + 1 < k; ++it) {
         const T rho_new = T(1) / (T(2) * sigma - rho);
         const T c1 = rho_new * rho, c2 = T(2) * rho_new / delta;
-        if (own) zb[i] = z;
-        wave_sync();
-        const T az = Av(zb);
-        wave_sync();
+        const T az = Av(z);
         x = x + z;
         res = res - az;
         z = c1 * z + c2 * di * res;
@@ -2031,9 +2043,7 @@ __device__ void vcycle_small(const Ctx<T, DIM, LV>& c, int k) {
     T x;
     smooth(x, true);
     // residual, restriction (x, then y, then z) to level L + 1
-    if (own) d[i] = x;
-    wave_sync();
-    const T res = f - Av(d);
+    const T res = f - Av(x);
     if (own) rb[i] = res;
     wave_sync();
     constexpr int QF = LV::q[L], QC = LV::q[L + 1];
